@@ -1,0 +1,216 @@
+"""Pins of the oracle's Lanczos/TRL (Alg. 10), observables (Sec. 3.6, 4.2),
+S^-_q (Alg. 11) and continued fraction (Eq. (cfe)) against dense
+diagonalisation, Kronecker-product spin operators on the full 2^N space, sum
+rules, closed forms and the exact resolvent."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import native as nat
+from oracle.cns import F
+from oracle.hamiltonian import bonds_1based, gen_full_ham
+from oracle.lanczos import lanczos, trl, diag_tri, lowest_distinct, ritz
+from oracle.observables import sz, corr_zz, corr_pm, positions, structure_factors, all_tuples
+from oracle.translation import Geometry, mk_list, gen_full_ham_sym_adapt, expand_to_u1
+from oracle.dynamics import smq_to_vec, smq_u1, continued_fraction
+from oracle.rng import splitmix64, start_vector
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build():
+    nat.build(force=False)
+
+
+def test_splitmix64_reference_outputs():
+    g = json.load(open(os.path.join(GOLD, "splitmix64.json")))
+    assert [str(splitmix64(1234567, i)) for i in range(3)] == g["seed_1234567"]
+    assert hex(splitmix64(0, 0)) == g["seed_0_first_hex"]
+    v = start_vector(1234567, np.arange(3), complex_=False)
+    assert np.all((v >= -1) & (v < 1))
+    assert v[0] == 2.0 * (6457827717110365317 >> 11) / 2.0 ** 53 - 1.0
+
+
+# ---------------------------------------------------------------- full-space operators
+def full_ops(N):
+    """s^z_i, s^+_i as 2^N x 2^N matrices; bit i of the basis index set = site i down."""
+    I = np.eye(2)
+    sz1 = np.diag([0.5, -0.5])       # basis (up, down)
+    sp1 = np.array([[0, 1], [0, 0]], dtype=float)   # |up><down|
+
+    def site(op, i):
+        out = np.array([[1.0]])
+        for s in range(N - 1, -1, -1):          # site N-1 is the most significant bit
+            out = np.kron(out, op if s == i else I)
+        return out
+    return [site(sz1, i) for i in range(N)], [site(sp1, i) for i in range(N)]
+
+
+def test_observables_against_kronecker_operators():
+    lat = wl.with_disorder(wl.chain(8), seed=11)
+    N, K = 8, 3
+    SZ, SP = full_ops(N)
+    H = sum(j * 0.5 * (SP[i] @ SP[k].T + SP[i].T @ SP[k]) + jz * SZ[i] @ SZ[k]
+            for i, k, j, jz in zip(lat.bi, lat.bj, lat.jxy, lat.jz))
+    # sector states: popcount K, ascending index order == rank order
+    idx = [m for m in range(1 << N) if bin(m).count("1") == K]
+    Hs = H[np.ix_(idx, idx)]
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    assert np.abs(Hs - gen_full_ham(N, K, bonds)).max() < 1e-14
+    e, U = np.linalg.eigh(Hs)
+    phi = U[:, 0]
+    full = np.zeros(1 << N)
+    full[idx] = phi
+    ref_sz = np.array([full @ SZ[i] @ full for i in range(N)])
+    ref_zz = np.array([[full @ SZ[i] @ SZ[j] @ full for j in range(N)] for i in range(N)])
+    ref_pm = np.array([[full @ SP[i] @ SP[j].T @ full for j in range(N)] for i in range(N)])
+    assert np.abs(sz(phi, N, K) - ref_sz).max() < 1e-13
+    assert np.abs(corr_zz(phi, N, K) - ref_zz).max() < 1e-13
+    assert np.abs(corr_pm(phi, N, K) - ref_pm).max() < 1e-13
+    # energy identity
+    E = sum(j * 0.5 * (ref_pm[i, k] + ref_pm[k, i]) + jz * ref_zz[i, k]
+            for i, k, j, jz in zip(lat.bi, lat.bj, lat.jxy, lat.jz))
+    assert E == pytest.approx(e[0], abs=1e-12)
+    # S^-_q by definition vs Kronecker
+    pos = positions(N, 1, 1)
+    q = np.array([2 * np.pi * 3 / N, 0, 0])
+    Smq = sum(np.exp(-1j * q[0] * pos[r, 0]) * SP[r].T for r in range(N)) / math.sqrt(N)
+    out_full = Smq @ full
+    idx1 = [m for m in range(1 << N) if bin(m).count("1") == K + 1]
+    assert np.abs(smq_u1(N, K, pos, q, phi.astype(complex)) - out_full[idx1]).max() < 1e-14
+
+
+def test_sum_rules_u1_and_k():
+    lat = wl.square(4)
+    N, K = 16, 3
+    M = N / 2 - K
+    geo = Geometry(*lat.dims)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    pos = positions(*lat.dims)
+    qs = [2 * np.pi * np.array([kx / 4, ky / 4, 0]) for (kx, ky, kz) in wl.all_momenta(lat)]
+    for Kv in [(0, 0, 0), (1, 2, 0)]:
+        s, R = mk_list(geo, K, Kv)
+        e, U = np.linalg.eigh(gen_full_ham_sym_adapt(geo, K, bonds, s, R, Kv))
+        u1 = expand_to_u1(geo, K, s, R, Kv, U[:, 0])
+        szv = sz(u1, N, K)
+        assert szv.sum() == pytest.approx(M, abs=1e-12)
+        assert np.abs(szv - M / N).max() < 1e-12            # translation invariant
+        zz = corr_zz(u1, N, K)
+        pm = corr_pm(u1, N, K)
+        assert np.abs(zz.sum(axis=1) - M * szv).max() < 1e-12
+        sf = structure_factors(zz, pm, szv, pos, np.array(qs))
+        assert sf[:, 0].sum() == pytest.approx(N / 4, abs=1e-10)
+        assert sf[0, 0] == pytest.approx(M * M / N, abs=1e-10)   # q = 0 longitudinal part
+        assert sf[:, 1].sum() == pytest.approx(N - K, abs=1e-10)
+        E = sum(j * (zz[i, k] * 1.0 + 0.5 * (pm[i, k] + pm[k, i]).real)
+                for i, k, j in zip(lat.bi, lat.bj, lat.jxy))
+        assert E == pytest.approx(e[0], abs=1e-10)
+
+
+def test_lanczos_c1_lowest_distinct_vs_dense():
+    """C1: chain 16, N_down = 3, 100 steps with full reorthogonalisation give the
+    4 lowest distinct levels of the dense matrix to 1e-10 relative."""
+    lat = wl.chain(16)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    H = gen_full_ham(16, 3, bonds)
+    ev = np.linalg.eigvalsh(H)
+    ref = lowest_distinct(ev, 4)
+    assert ref[0] == pytest.approx(-1.81500162, abs=1e-8)
+    v0 = start_vector(1, np.arange(560), complex_=False)
+    a, b, Psi = lanczos(lambda x: H @ x, v0, 100)
+    e, res, _ = ritz(a, b)
+    got = lowest_distinct(e, 4, residuals=res)
+    assert len(lowest_distinct(e, 6)) == 6 and lowest_distinct(e, 6)[2] != got[2]
+    assert np.allclose(got, ref, rtol=1e-10, atol=0)
+    # orthonormal Lanczos basis
+    G = Psi[:, :100].T @ Psi[:, :100]
+    assert np.abs(G - np.eye(100)).max() < 1e-12
+
+
+def test_trl_vs_dense_k_sector():
+    lat = wl.square(4)
+    geo = Geometry(*lat.dims)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    s, R = mk_list(geo, 4, (1, 0, 0))
+    Hk = gen_full_ham_sym_adapt(geo, 4, bonds, s, R, (1, 0, 0))
+    ev = np.linalg.eigvalsh(Hk)
+    v0 = start_vector(5, np.array(s, dtype=np.uint64) - 1, complex_=True)
+    e, X, nres, conv = trl(lambda x: Hk @ x, v0, NK=6, NM=14, IM=500, eps=1e-14)
+    assert conv
+    # distinct lowest levels present among Ritz values
+    for lv in lowest_distinct(ev, 3):
+        assert np.min(np.abs(e - lv)) < 1e-10 * max(1, abs(lv))
+    r = Hk @ X[:, 0] - e[0] * X[:, 0]
+    assert np.linalg.norm(r) < 1e-8
+
+
+def test_smq_alg11_equals_definition_with_stabilisers():
+    for lat, K in [(wl.chain(6), 2), (wl.square(4), 1), (wl.hypercubic(4, 2, 1), 2)]:
+        geo = Geometry(*lat.dims)
+        pos = positions(*lat.dims)
+        for Kv in wl.all_momenta(lat)[:3]:
+            s, R = mk_list(geo, K, Kv)
+            if not s:
+                continue
+            phi = np.random.default_rng(4).normal(size=len(s)) + 0.3j
+            u1 = expand_to_u1(geo, K, s, R, Kv, phi)
+            for Qv in wl.all_momenta(lat)[:4]:
+                kq = tuple((Kv[i] + Qv[i]) % lat.dims[i] for i in range(3))
+                s1, R1 = mk_list(geo, K + 1, kq)
+                q = 2 * np.pi * np.array(Qv) / np.array(lat.dims)
+                ref = smq_u1(geo.N, K, pos, q, u1)
+                got = expand_to_u1(geo, K + 1, s1, R1, kq, smq_to_vec(geo, K, s, R, Kv, phi, s1, R1, Qv)) \
+                    if s1 else np.zeros_like(ref)
+                assert np.abs(got - ref).max() < 1e-13
+
+
+def test_continued_fraction_vs_resolvent_and_sum_rules():
+    lat = wl.chain(10)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    N = 10
+    H2 = gen_full_ham(N, 2, bonds)
+    H3 = gen_full_ham(N, 3, bonds)
+    e, U = np.linalg.eigh(H2)
+    e0, phi = e[0], U[:, 0]
+    pos = positions(N, 1, 1)
+    q = np.array([2 * np.pi * 4 / N, 0, 0])
+    psi = smq_u1(N, 2, pos, q, phi.astype(complex))
+    w = np.vdot(psi, psi).real
+    a, b, _ = lanczos(lambda x: H3 @ x, psi, 60)
+    om = np.linspace(0, 8, 401)
+    for h, eta in [(0.0, 0.05), (2.0, 0.1)]:
+        S = continued_fraction(a, b, w, om, e0, eta, h)
+        z = om - h + e0 + 1j * eta
+        ref = np.array([-np.imag(np.vdot(psi, np.linalg.solve(zz * np.eye(H3.shape[0]) - H3, psi))) / np.pi
+                        for zz in z])
+        assert np.abs(S - ref).max() < 1e-10
+    # pole weights from eig(T) sum to the numerator
+    ee, C = diag_tri(a, b)
+    assert (w * C[0, :] ** 2).sum() == pytest.approx(w, rel=1e-12)
+
+
+def test_single_magnon_lorentzian():
+    """From the fully polarised state (K = 0 -> 1): S^-_q|FM> is the one-magnon
+    eigenstate, so S(q, w) is one Lorentzian of weight 1 at w = h + E_1(q) - E_FM."""
+    lat = wl.square(4)
+    N = 16
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    H1 = gen_full_ham(N, 1, bonds)
+    efm = lat.jz.sum() / 4
+    pos = positions(4, 4, 1)
+    for Q in [(1, 0), (2, 2), (0, 3)]:
+        q = 2 * np.pi * np.array([Q[0] / 4, Q[1] / 4, 0])
+        psi = smq_u1(N, 0, pos, q, np.array([1.0 + 0j]))
+        a, b, _ = lanczos(lambda x: H1 @ x, psi, 1)
+        e1 = efm - 2 + math.cos(q[0]) + math.cos(q[1])
+        assert a[0] == pytest.approx(e1, abs=1e-12)
+        om = np.linspace(0, 8, 101)
+        eta, h = 0.05, 4.0
+        S = continued_fraction(a[:1], b[:1], 1.0, om, efm, eta, h)
+        w0 = h + e1 - efm
+        assert np.abs(S - eta / np.pi / ((om - w0) ** 2 + eta ** 2)).max() < 1e-12

@@ -1,0 +1,169 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle runs.
+
+This module holds no arithmetic of the method: it only writes down lattices
+(site numbering, periodic nearest-neighbour bond lists, couplings) and seeded
+random draws.  Both the HIP library and the CPU oracle receive what it returns
+as plain arrays.
+
+Site numbering: site i <-> (x, y, z) with i = x + Lx*(y + Ly*z), all 0-based.
+A bond is (i, j, Jxy, Jz) with the XXZ convention of the paper's model
+(Sec. 2.2): J > 0 is antiferromagnetic.
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Lattice:
+    name: str
+    lx: int
+    ly: int
+    lz: int
+    bi: np.ndarray      # int32 [n_bonds]
+    bj: np.ndarray      # int32 [n_bonds]
+    jxy: np.ndarray     # float64 [n_bonds]
+    jz: np.ndarray      # float64 [n_bonds]
+    translation_invariant: bool = True
+
+    @property
+    def n_sites(self) -> int:
+        return self.lx * self.ly * self.lz
+
+    @property
+    def n_bonds(self) -> int:
+        return int(self.bi.shape[0])
+
+    @property
+    def dims(self) -> tuple:
+        return (self.lx, self.ly, self.lz)
+
+
+def site_index(x: int, y: int, z: int, lx: int, ly: int) -> int:
+    return x + lx * (y + ly * z)
+
+
+def hypercubic(lx: int, ly: int = 1, lz: int = 1, J: float = 1.0, Delta: float = 1.0,
+               name: str | None = None) -> Lattice:
+    """Periodic nearest-neighbour bonds on an lx x ly x lz lattice.
+
+    Each site gets one bond in each direction whose length is > 1 (a length-2
+    direction would otherwise give the same bond twice; length 2 keeps one).
+    """
+    bonds = []
+    for z in range(lz):
+        for y in range(ly):
+            for x in range(lx):
+                i = site_index(x, y, z, lx, ly)
+                for (L, nb) in ((lx, ((x + 1) % lx, y, z)), (ly, (x, (y + 1) % ly, z)),
+                                (lz, (x, y, (z + 1) % lz))):
+                    if L == 1:
+                        continue
+                    bonds.append((i, site_index(nb[0], nb[1], nb[2], lx, ly)))
+    # drop duplicate undirected bonds (length-2 directions)
+    seen = set()
+    uniq = []
+    for (i, j) in bonds:
+        key = (min(i, j), max(i, j))
+        if key in seen:
+            continue
+        seen.add(key)
+        uniq.append(key)
+    bi = np.array([b[0] for b in uniq], dtype=np.int32)
+    bj = np.array([b[1] for b in uniq], dtype=np.int32)
+    nb = len(uniq)
+    if name is None:
+        name = f"hypercubic{lx}x{ly}x{lz}"
+    return Lattice(name, lx, ly, lz, bi, bj,
+                   np.full(nb, float(J)), np.full(nb, float(J) * float(Delta)), True)
+
+
+def chain(L: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
+    return hypercubic(L, 1, 1, J, Delta, name=f"chain{L}")
+
+
+def square(L: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
+    return hypercubic(L, L, 1, J, Delta, name=f"square{L}x{L}")
+
+
+def cube(L: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
+    return hypercubic(L, L, L, J, Delta, name=f"cube{L}^3")
+
+
+def with_disorder(lat: Lattice, seed: int, jlo: float = 0.5, jhi: float = 1.5,
+                  dlo: float = 0.0, dhi: float = 2.0, per_bond: bool = True) -> Lattice:
+    """Bond disorder of the serving stream: J_ij ~ U[jlo, jhi] per bond (or one J
+    for all bonds when per_bond is False), Delta ~ U[dlo, dhi] once per request."""
+    rng = np.random.default_rng(seed)
+    if per_bond:
+        J = rng.uniform(jlo, jhi, size=lat.n_bonds)
+    else:
+        J = np.full(lat.n_bonds, rng.uniform(jlo, jhi))
+    Delta = rng.uniform(dlo, dhi)
+    return dataclasses.replace(lat, name=lat.name + f"+dis{seed}", jxy=J.astype(np.float64),
+                               jz=(J * Delta).astype(np.float64),
+                               translation_invariant=(not per_bond))
+
+
+def random_bonds(n_sites: int, n_bonds: int, seed: int) -> Lattice:
+    """A random bond graph (no translation symmetry) with random couplings."""
+    rng = np.random.default_rng(seed)
+    seen = set()
+    out = []
+    while len(out) < n_bonds:
+        i, j = rng.integers(0, n_sites, size=2)
+        if i == j:
+            continue
+        key = (int(min(i, j)), int(max(i, j)))
+        if key in seen:
+            continue
+        seen.add(key)
+        out.append(key)
+    bi = np.array([b[0] for b in out], dtype=np.int32)
+    bj = np.array([b[1] for b in out], dtype=np.int32)
+    return Lattice(f"random{n_sites}_{n_bonds}_{seed}", n_sites, 1, 1, bi, bj,
+                   rng.uniform(-1.0, 1.5, size=n_bonds), rng.uniform(-1.0, 2.0, size=n_bonds),
+                   False)
+
+
+def all_momenta(lat: Lattice) -> list:
+    """Every momentum index triple (Kx, Ky, Kz), Kx fastest."""
+    out = []
+    for kz in range(lat.lz):
+        for ky in range(lat.ly):
+            for kx in range(lat.lx):
+                out.append((kx, ky, kz))
+    return out
+
+
+def serving_stream(n_requests: int, seed: int, rate: float):
+    """Poisson arrivals of solve requests for the serving workload.
+
+    Lattice family uniform over {chain L in [16,64], square L in [6,12],
+    cube L in [6,10]}, all periodic; N_down uniform in {1..4}; with a momentum
+    sector with probability 1/2.  With a momentum sector the couplings are one
+    J ~ U[0.5,1.5] for all bonds (disorder would break translation symmetry);
+    without, J_ij ~ U[0.5,1.5] per bond; Delta ~ U[0,2] once per request.
+    Returns a list of dicts with arrival times in seconds.
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    for r in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        fam = int(rng.integers(0, 3))
+        if fam == 0:
+            L = int(rng.integers(16, 65)); lat = chain(L)
+        elif fam == 1:
+            L = int(rng.integers(6, 13)); lat = square(L)
+        else:
+            L = int(rng.integers(6, 11)); lat = cube(L)
+        n_down = int(rng.integers(1, 5))
+        use_k = bool(rng.integers(0, 2))
+        lat = with_disorder(lat, seed=int(rng.integers(0, 2**31)), per_bond=not use_k)
+        K = None
+        if use_k:
+            K = (int(rng.integers(0, lat.lx)), int(rng.integers(0, lat.ly)), int(rng.integers(0, lat.lz)))
+        reqs.append(dict(id=r, t_arrive=t, lattice=lat, n_down=n_down, K=K))
+    return reqs
