@@ -1,0 +1,277 @@
+/*
+ * qs3.h -- C ABI of the MI355X (gfx950) engine for the S=1/2 XXZ model near
+ * saturation, after "Quantum spin solver near saturation: QS^3"
+ * (Ueda, Yunoki, Shimokawa; arXiv 2107.00872).
+ *
+ * Model (Sec. 2.2, Eq. (xxz_hamiltonian)):
+ *   H = sum_b [ Jxy_b (s^x_i s^x_j + s^y_i s^y_j) + Jz_b s^z_i s^z_j ] - h sum_i s^z_i,
+ * J > 0 antiferromagnetic.  The Zeeman term is a constant in a fixed-N_down
+ * sector and is never part of H.v; it enters only the dynamical structure
+ * factor as a shift of the poles.
+ *
+ * States are ascending down-spin site tuples c_1 < ... < c_K (0-based sites,
+ * K = N_down) indexed by the combinatorial-number-system rank
+ *   rank = sum_m C(c_m, m)  in [0, C(N, K))                (Eq. (a_of_n), minus 1)
+ * so a vector of the fixed-N_down ("U(1)") sector is indexed by rank.
+ * Momentum sectors (Sec. 3.3) use the states
+ *   |a,k> = N_{a,k}^{-1/2} sum_t e^{-i k.t} T^t |a>        (Eq. (akstate))
+ * over the representatives a (the minimum rank of each translation orbit)
+ * compatible with k, in ascending rank order.  k = 2 pi (Kx/Lx, Ky/Ly, Kz/Lz).
+ * Site i has coordinates (x, y, z) with i = x + Lx*(y + Ly*z).
+ *
+ * Conventions of every entry point:
+ *  - return 0 (QS3_OK) or a negative QS3_E* code; nothing throws across the
+ *    ABI.  qs3_last_error() gives a message for the calling thread.
+ *  - "device" pointers are caller-owned HIP device allocations (for example
+ *    torch tensors); the library never frees them.  "host" pointers are read
+ *    or written during the call only; host inputs are copied.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls that
+ *    return host results synchronise with the stream before returning;
+ *    qs3_matvec and qs3_sector_start_vector only enqueue work.
+ *  - handles are opaque and owned by the library; destroy them in the reverse
+ *    order of creation (server, batch/sector, lattice, context).
+ *  - one context per host thread; a server is internally synchronised.
+ */
+#ifndef QS3_H
+#define QS3_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define QS3_OK        0
+#define QS3_EINVAL   -1   /* bad argument: site id, i == j, N_down out of range, k out
+                             of range, N != Lx*Ly*Lz, k requested on a lattice whose
+                             bond set is not translation invariant, dtype mismatch */
+#define QS3_ENOMEM   -2   /* footprint exceeds the context budget or hipMalloc failed */
+#define QS3_ENOCONV  -3   /* solver hit its iteration limit: outputs hold the best
+                             estimates and info->converged == 0 */
+#define QS3_ENUMERIC -4   /* NaN/Inf or a zero start vector */
+#define QS3_EDEVICE  -5   /* a HIP call failed */
+#define QS3_EBUSY    -6   /* a server ticket is not finished yet */
+#define QS3_ENOTFOUND -7  /* unknown server ticket */
+#define QS3_ECANCELED -8  /* the request was cancelled */
+
+/* ---- element types of device vectors ----------------------------------- */
+#define QS3_F64  0   /* real float64: fixed-N_down sectors (H is real symmetric) */
+#define QS3_F32  1   /* real float32 */
+#define QS3_C128 2   /* complex float64 (re, im interleaved): momentum sectors */
+#define QS3_C64  3   /* complex float32 */
+
+typedef struct qs3_ctx qs3_ctx;
+typedef struct qs3_lattice qs3_lattice;
+typedef struct qs3_sector qs3_sector;
+typedef struct qs3_batch qs3_batch;
+typedef struct qs3_server qs3_server;
+
+const char *qs3_version(void);
+const char *qs3_strerror(int code);
+const char *qs3_last_error(void);
+
+/* ---- context ----------------------------------------------------------- */
+/* Binds HIP device `device`.  hbm_budget_bytes bounds the device memory the
+ * library itself allocates (tables, Krylov workspace); 0 = 90% of the free
+ * memory at creation.  Allocations beyond it fail with QS3_ENOMEM. */
+int qs3_ctx_create(int device, uint64_t hbm_budget_bytes, qs3_ctx **out);
+int qs3_ctx_destroy(qs3_ctx *ctx);
+int qs3_ctx_memory(const qs3_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
+
+/* ---- lattice (Sec. 2.2 model; bond list as in the paper's FILExxz) ------ */
+/* n_sites = lx*ly*lz (<= 4096).  Bond b couples sites bi[b] != bj[b] (0-based)
+ * with exchange jxy[b] and Ising jz[b]; repeated bonds add.  Arrays are host,
+ * copied.  The lattice records whether the bond set (with couplings) is
+ * invariant under every translation of Z_lx x Z_ly x Z_lz; only then can
+ * momentum sectors be built on it. */
+int qs3_lattice_create(qs3_ctx *ctx, int lx, int ly, int lz, int n_bonds, const int32_t *bi,
+                       const int32_t *bj, const double *jxy, const double *jz,
+                       qs3_lattice **out);
+int qs3_lattice_destroy(qs3_lattice *lat);
+int qs3_lattice_info(const qs3_lattice *lat, int *n_sites, int *translation_invariant);
+
+/* ---- sectors (Sec. 3.1 fixed N_down; Sec. 3.3 momentum) ------------------ */
+/* kvec = NULL: the fixed-N_down sector, dimension C(N, K), real vectors
+ * (QS3_F64/QS3_F32).  kvec = {Kx, Ky, Kz} with 0 <= K_a < L_a: the momentum
+ * sector, complex vectors (QS3_C128/QS3_C64) over its representatives.
+ * 0 <= n_down <= min(N, 8); momentum sectors need n_down <= 6.  Building a
+ * momentum sector canonicalises every state of the fixed-N_down sector once
+ * on the device (the structure is shared by all sectors and batches of the
+ * same lattice and n_down). */
+int qs3_sector_create(qs3_lattice *lat, int n_down, const int32_t *kvec, qs3_sector **out);
+int qs3_sector_destroy(qs3_sector *sec);
+int qs3_sector_dim(const qs3_sector *sec, uint64_t *dim);
+/* Host copy of the basis: ranks[i] = 0-based rank of the i-th basis state
+ * (the representative for momentum sectors, ascending) and stab[i] = size of
+ * its stabiliser under translations (1 for fixed-N_down sectors), so that
+ * N_{a,k} = N * stab (Alg. 5).  Either pointer may be NULL. */
+int qs3_sector_basis(const qs3_sector *sec, uint64_t *ranks, uint32_t *stab);
+/* Start vector of the Lanczos iteration (Alg. 10's random_vec): element i is
+ * 2u - 1 with u the top 53 bits of SplitMix64(seed, counter) / 2^53, counter
+ * = ranks[i] (real) or 2*ranks[i] and 2*ranks[i]+1 (re, im).  v: device. */
+int qs3_sector_start_vector(qs3_sector *sec, uint64_t seed, void *v, int dtype, void *stream);
+
+/* w = H v (Alg. 9, matrix free, one output row per gather).  v, w: device,
+ * dim elements of `dtype`, not aliased.  QS3_F32/QS3_C64 accumulate each row
+ * in float32. */
+int qs3_matvec(qs3_sector *sec, const void *v, void *w, int dtype, void *stream);
+
+/* One row of H exactly as the device kernel forms it: the diagonal element
+ * and the off-diagonal (column, value) pairs in the order the kernel visits
+ * them (down spins ascending, then the site's bonds in bond order).  cols are
+ * basis indices; vals is re/im interleaved for momentum sectors.  *nnz may
+ * exceed cap (then only cap entries are written).  Host outputs. */
+int qs3_row(qs3_sector *sec, uint64_t row, int cap, int64_t *cols, double *vals, double *diag,
+            int *nnz);
+
+/* ---- eigensolver (Sec. 3.7, Alg. 10) ------------------------------------ */
+#define QS3_ALG_LANCZOS 0   /* conventional Lanczos, `steps` steps, no restart */
+#define QS3_ALG_TRL     1   /* thick-restart Lanczos */
+#define QS3_PREC_F64    0   /* float64 everywhere */
+#define QS3_PREC_F32MV  1   /* float32 matvec (float32 row accumulation), float64
+                               recurrence, reorthogonalisation and eigensolves */
+
+typedef struct {
+    int alg;            /* QS3_ALG_LANCZOS or QS3_ALG_TRL */
+    int nev;            /* wanted number of distinct lowest levels */
+    int nk;             /* TRL: kept Ritz vectors N_K (0 = nev + 5) */
+    int nm;             /* TRL: Krylov size N_M (0 = max(2 nk, 20)) */
+    int max_restarts;   /* TRL: I_M (0 = 2000) */
+    int steps;          /* LANCZOS: number of steps (0 = 100) */
+    double tol;         /* residual tolerance relative to max(1, |e|) (0 = 1e-9) */
+    uint64_t seed;      /* start vector seed */
+    int precision;      /* QS3_PREC_* */
+    int reorth;         /* 1 = full (classical Gram-Schmidt, twice), 0 = none */
+} qs3_eigs_opts;
+
+typedef struct {
+    int converged;      /* 1 if every wanted level met tol */
+    int n_restarts;
+    int n_matvec;
+    int n_found;        /* distinct levels returned (<= nev) */
+    double max_residual;
+    double seconds;     /* wall time of the call */
+} qs3_eigs_info;
+
+/* Lowest `nev` distinct levels: a Ritz value counts when its residual estimate
+ * |beta_m c_{m,i}| <= tol * max(1, |e_i|), and values closer than
+ * 1e-8 * max(1, |e|) are one level.  evals: host, nev doubles (unfound =
+ * NaN).  evecs: device, dim x nev (vector y at offset y*dim) of the sector's
+ * float64 type (QS3_F64 / QS3_C128), or NULL. */
+int qs3_eigs(qs3_sector *sec, const qs3_eigs_opts *opts, double *evals, void *evecs,
+             qs3_eigs_info *info, void *stream);
+
+/* Plain Lanczos coefficients from v0 (device, float64 type of the sector; or
+ * NULL for the seeded start vector): alpha[0..steps-1], beta[0..steps-1]
+ * (beta[x] = norm of the (x+2)-th vector before normalisation) and
+ * *norm0 = |v0|.  Host outputs.  Stops early at an invariant subspace: *done
+ * receives the number of steps taken. */
+int qs3_lanczos(qs3_sector *sec, const void *v0, int steps, int precision, int reorth,
+                uint64_t seed, double *alpha, double *beta, double *norm0, int *done,
+                void *stream);
+
+/* ---- observables (Sec. 3.6 and Sec. 4.2) -------------------------------- */
+/* <s^z_i> for i = 0..N-1 of the state vec (device, float64 type, any norm;
+ * the result is normalised).  In a momentum sector the translation-averaged
+ * operator gives M/N on every site. */
+int qs3_sz(qs3_sector *sec, const void *vec, double *out, void *stream);
+/* <s^z_i s^z_j> and <s^+_i s^-_j> for n_pairs host pairs (i[p], j[p]); in a
+ * momentum sector the translation average (1/N) sum_t of the pair moved by t
+ * (Sec. 3.6).  pm is complex (re, im interleaved, 2*n_pairs doubles).  i == j
+ * gives 1/4 and 1/2 + <s^z_i>. */
+int qs3_sisj(qs3_sector *sec, const void *vec, int n_pairs, const int32_t *i, const int32_t *j,
+             double *zz, double *pm, void *stream);
+/* Static structure factors at n_q momenta q (host, 3 doubles each):
+ * S^zz(q), S^{+-}(q) = <(S^-_q)^+ S^-_q> and S(q) = <S_{-q}.S_q> with
+ * S^a_q = N^{-1/2} sum_r e^{-i q.R_r} s^a_r, R_r the site coordinates. */
+int qs3_sq(qs3_sector *sec, const void *vec, int n_q, const double *q, double *szz,
+           double *spm, double *stot, void *stream);
+/* psi' = S^-_q phi (Sec. 3.8, Alg. 11) from `from` (N_down = K, momentum k)
+ * into `to` (K + 1, momentum k + q), computed as a gather over the rows of
+ * `to`.  qvec: host {Qx, Qy, Qz}.  Vectors: device complex float64. */
+int qs3_smq(qs3_sector *from, const void *vec_from, qs3_sector *to, const int32_t *qvec,
+            void *vec_to, void *stream);
+
+/* ---- dynamical structure factor (Sec. 3.9, Eq. (cfe)) -------------------- */
+typedef struct {
+    int steps;          /* Lanczos levels of the continued fraction (0 = 300) */
+    double eta;         /* Lorentzian broadening */
+    double field;       /* h of the Zeeman term: S^- poles move by +h */
+    int precision;      /* QS3_PREC_* */
+    int reorth;         /* 1 = full, 0 = none */
+} qs3_dsf_opts;
+
+/* S^{-}(q, omega) = -(1/pi) Im <psi'| (z - H)^-1 |psi'> with
+ * z = omega - h + E_0 + i eta and psi' = S^-_q |gs>, for n_q momenta qvecs
+ * (host, 3 ints each), by the continued fraction of the Lanczos coefficients
+ * started from psi'/|psi'|.  gs: momentum sector of the ground state, gs_vec:
+ * device complex float64.  Outputs (host): S[n_q*n_omega], alpha/beta
+ * [n_q*steps], weight[n_q] = |psi'|^2 = S^{+-}(q). */
+int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_t *qvecs,
+            const qs3_dsf_opts *opts, int n_omega, const double *omega, double *S,
+            double *alpha, double *beta, double *weight, void *stream);
+
+/* ---- batches of momentum sectors (one persistent launch per H.v) --------- */
+/* Every momentum kvecs[3*b..3*b+2] (b < n_sectors) of one lattice and n_down.
+ * Batch vectors use the layout [row][sector] over the union of all
+ * representatives (rows = union size), complex; entries of representatives
+ * incompatible with a sector are ignored on input and zero on output. */
+int qs3_batch_create(qs3_lattice *lat, int n_down, int n_sectors, const int32_t *kvecs,
+                     qs3_batch **out);
+int qs3_batch_destroy(qs3_batch *bat);
+/* rows: union size; dims[b]: dimension of sector b.  Host outputs. */
+int qs3_batch_dims(const qs3_batch *bat, uint64_t *rows, uint64_t *dims);
+int qs3_batch_matvec(qs3_batch *bat, const void *v, void *w, int dtype, void *stream);
+/* Per-sector lowest levels (evals[b*nev + y]) and info[b]; every sector runs
+ * its own Lanczos state inside the shared launches and stops updating when it
+ * converges. */
+int qs3_batch_eigs(qs3_batch *bat, const qs3_eigs_opts *opts, double *evals,
+                   qs3_eigs_info *info, void *stream);
+
+/* ---- serving: continuous batching of solve requests ---------------------- */
+typedef struct {
+    int max_active;          /* concurrent requests on the device (0 = 8) */
+    uint64_t budget_bytes;   /* device memory for admitted requests (0 = ctx budget) */
+} qs3_server_opts;
+
+typedef struct {
+    int lx, ly, lz, n_bonds;
+    const int32_t *bi, *bj;
+    const double *jxy, *jz;
+    int n_down;
+    int use_k;              /* 0: fixed-N_down sector; 1: momentum kvec */
+    int32_t kvec[3];
+    int nev;
+    int precision;          /* QS3_PREC_* */
+    uint64_t seed;
+} qs3_request;
+
+typedef struct {
+    int status;             /* QS3_OK, QS3_ENOCONV, QS3_ENOMEM (not admissible), ... */
+    int n_found;
+    double evals[16];
+    uint64_t dim;
+    uint64_t footprint_bytes;
+    double t_submit, t_start, t_done;   /* seconds on the server clock */
+    int n_matvec;
+} qs3_result;
+
+/* A server owns a worker thread that admits queued requests when their device
+ * footprint fits the budget and a slot is free, runs every admitted request's
+ * Lanczos state on its own stream (their kernels overlap on the device) and
+ * retires requests as they converge, so new requests join while others run.
+ * A request's result does not depend on what else is running. */
+int qs3_server_create(qs3_ctx *ctx, const qs3_server_opts *opts, qs3_server **out);
+int qs3_server_destroy(qs3_server *srv);
+int qs3_submit(qs3_server *srv, const qs3_request *req, uint64_t *ticket);
+/* QS3_OK with the result once done, QS3_EBUSY while queued or running. */
+int qs3_poll(qs3_server *srv, uint64_t ticket, qs3_result *out);
+int qs3_wait(qs3_server *srv, uint64_t ticket, qs3_result *out);
+int qs3_cancel(qs3_server *srv, uint64_t ticket);
+double qs3_server_clock(qs3_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QS3_H */

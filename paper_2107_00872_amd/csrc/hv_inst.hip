@@ -1,0 +1,276 @@
+// Launchers of the H.v, debug-row and structure-build kernels for one N_down
+// (QS3_INST_K, set by the build), so that the template instances of every
+// N_down compile in parallel translation units.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "hv_kernels.h"
+
+#ifndef QS3_INST_K
+#error "QS3_INST_K must be defined"
+#endif
+
+namespace qs3 {
+
+constexpr int KI = QS3_INST_K;
+// a rank type wider than 32 bits is only ever needed from N_down = 3 on
+constexpr bool WIDE_OK = KI >= 3;
+
+template <typename RT>
+static size_t lds_need(const qs3_lattice *lat, int K) {
+    size_t ntab = K >= 2 ? (size_t)(K - 1) * (lat->N + 1) : 0;
+    return ((ntab * sizeof(RT) + 15) & ~size_t(15)) + sizeof(int) * (lat->N + 1) +
+           sizeof(uint16_t) * lat->h_nbr.size() + 16;
+}
+
+// ------------------------------------------------------------------ U(1)
+template <typename RT, typename VT, typename OT>
+static int launch_u1(qs3_sector *sec, const void *v, void *w, hipStream_t s) {
+    qs3_lattice *lat = sec->lat;
+    LatArgs L = lat_args(lat);
+    size_t sh = lds_need<RT>(lat, KI);
+    QS3_REQUIRE(sh <= 160 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
+    uint64_t tiles = (sec->dim + 255) / 256;
+    int grid = grid_for(lat->ctx, tiles);
+    hipLaunchKernelGGL((k_hv_u1<KI, RT, VT, OT>), dim3(grid), dim3(256), sh, s, L,
+                       sec->bt->dev.as<RT>(), (RT)sec->dim, (const VT *)v, (OT *)w);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+template <typename RT>
+static int u1_types(qs3_sector *sec, const void *v, int vtype, void *w, int wtype, hipStream_t s) {
+    if (vtype == QS3_F64 && wtype == QS3_F64) return launch_u1<RT, double, double>(sec, v, w, s);
+    if (vtype == QS3_F32 && wtype == QS3_F32) return launch_u1<RT, float, float>(sec, v, w, s);
+    if (vtype == QS3_F32 && wtype == QS3_F64) return launch_u1<RT, float, double>(sec, v, w, s);
+    set_error("unsupported dtype pair for a fixed-N_down matvec");
+    return QS3_EINVAL;
+}
+
+template <>
+int hv_u1_K<KI>(qs3_sector *sec, const void *v, int vtype, void *w, int wtype, hipStream_t s) {
+    if constexpr (WIDE_OK) {
+        if (sec->bt->wide) return u1_types<uint64_t>(sec, v, vtype, w, wtype, s);
+    }
+    QS3_REQUIRE(!sec->bt->wide, QS3_EINVAL, "internal: wide ranks at small N_down");
+    return u1_types<uint32_t>(sec, v, vtype, w, wtype, s);
+}
+
+template <typename RT>
+static int row_u1_t(qs3_sector *sec, uint64_t row, int cap, int64_t *cols, double *vals,
+                    double *diag, int *nnz) {
+    qs3_ctx *ctx = sec->lat->ctx;
+    DevBuf buf;
+    size_t capb = std::max(cap, 1);
+    QS3_TRY(buf.alloc(ctx, capb * 16 + 64));
+    int64_t *dc = (int64_t *)buf.ptr;
+    double *dv = (double *)(dc + capb);
+    double *dd = dv + capb;
+    int *dn = (int *)(dd + 1);
+    hipLaunchKernelGGL((k_row_u1<KI, RT>), dim3(1), dim3(1), 0, 0, lat_args(sec->lat),
+                       sec->bt->dev.as<RT>(), (RT)row, cap, dc, dv, dd, dn);
+    QS3_HIP(hipGetLastError());
+    QS3_HIP(hipDeviceSynchronize());
+    int n = 0;
+    QS3_HIP(hipMemcpy(&n, dn, sizeof(int), hipMemcpyDeviceToHost));
+    QS3_HIP(hipMemcpy(diag, dd, sizeof(double), hipMemcpyDeviceToHost));
+    int m = std::min(n, cap);
+    if (m > 0) {
+        QS3_HIP(hipMemcpy(cols, dc, sizeof(int64_t) * m, hipMemcpyDeviceToHost));
+        QS3_HIP(hipMemcpy(vals, dv, sizeof(double) * m, hipMemcpyDeviceToHost));
+    }
+    *nnz = n;
+    return QS3_OK;
+}
+
+template <>
+int row_u1_K<KI>(qs3_sector *sec, uint64_t row, int cap, int64_t *cols, double *vals,
+                 double *diag, int *nnz) {
+    if constexpr (WIDE_OK) {
+        if (sec->bt->wide) return row_u1_t<uint64_t>(sec, row, cap, cols, vals, diag, nnz);
+    }
+    return row_u1_t<uint32_t>(sec, row, cap, cols, vals, diag, nnz);
+}
+
+#if QS3_INST_K <= 6
+// ------------------------------------------------------------------ momentum batches
+template <typename RT, typename CT, typename OT, bool TABLE>
+static int launch_batch(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
+    BatchArgs A = batch_args(bat);
+    size_t sh = lds_need<RT>(bat->lat, KI);
+    QS3_REQUIRE(sh <= 160 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
+    const int per = (A.B + A.G - 1) / A.G;
+    uint64_t rows_per_tile = 256 / A.G;
+    uint64_t tiles = (A.n_reps + rows_per_tile - 1) / rows_per_tile;
+    int grid = grid_for(bat->lat->ctx, tiles);
+    const RT *tab = bat->bt->dev.as<RT>();
+    using C2 = typename Cplx<CT>::type;
+    using O2 = typename Cplx<OT>::type;
+#define QS3_LB(BPL)                                                                             \
+    hipLaunchKernelGGL((k_hv_batch<KI, RT, CT, OT, TABLE, BPL>), dim3(grid), dim3(256), sh, s, A, \
+                       tab, (const C2 *)v, (O2 *)w)
+    if (per <= 1) QS3_LB(1);
+    else if (per <= 2) QS3_LB(2);
+    else if (per <= 4) QS3_LB(4);
+    else if (per <= 16) QS3_LB(16);
+    else if (per <= 32) QS3_LB(32);
+    else {
+        set_error("batch larger than 2048 sectors");
+        return QS3_EINVAL;
+    }
+#undef QS3_LB
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+template <typename RT, typename CT, typename OT>
+static int batch_mode(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
+    if (bat->ks->has_table) return launch_batch<RT, CT, OT, true>(bat, v, w, s);
+    return launch_batch<RT, CT, OT, false>(bat, v, w, s);
+}
+
+template <typename RT>
+static int batch_types(qs3_batch *bat, const void *v, int vtype, void *w, int wtype, hipStream_t s) {
+    if (vtype == QS3_C128 && wtype == QS3_C128) return batch_mode<RT, double, double>(bat, v, w, s);
+    if (vtype == QS3_C64 && wtype == QS3_C128) return batch_mode<RT, float, double>(bat, v, w, s);
+    set_error("unsupported dtype pair for a momentum matvec");
+    return QS3_EINVAL;
+}
+
+template <>
+int hv_batch_K<KI>(qs3_batch *bat, const void *v, int vtype, void *w, int wtype, hipStream_t s) {
+    if constexpr (WIDE_OK) {
+        if (bat->bt->wide) return batch_types<uint64_t>(bat, v, vtype, w, wtype, s);
+    }
+    return batch_types<uint32_t>(bat, v, vtype, w, wtype, s);
+}
+
+template <typename RT, bool TABLE>
+static int row_k_t(qs3_sector *sec, uint64_t u, int cap, int64_t *cols, double *vals,
+                   double *diag, int *nnz) {
+    qs3_ctx *ctx = sec->lat->ctx;
+    DevBuf buf;
+    size_t capb = std::max(cap, 1);
+    QS3_TRY(buf.alloc(ctx, capb * 24 + 64));
+    int64_t *dc = (int64_t *)buf.ptr;
+    double *dv = (double *)(dc + capb);
+    double *dd = dv + 2 * capb;
+    int *dn = (int *)(dd + 1);
+    BatchArgs A = batch_args(sec->bat);
+    hipLaunchKernelGGL((k_row_k<KI, RT, TABLE>), dim3(1), dim3(1), 0, 0, A,
+                       sec->bat->bt->dev.as<RT>(), u, cap, dc, dv, dd, dn);
+    QS3_HIP(hipGetLastError());
+    QS3_HIP(hipDeviceSynchronize());
+    int n = 0;
+    QS3_HIP(hipMemcpy(&n, dn, sizeof(int), hipMemcpyDeviceToHost));
+    QS3_HIP(hipMemcpy(diag, dd, sizeof(double), hipMemcpyDeviceToHost));
+    int m = std::min(n, cap);
+    if (m > 0) {
+        QS3_HIP(hipMemcpy(cols, dc, sizeof(int64_t) * m, hipMemcpyDeviceToHost));
+        QS3_HIP(hipMemcpy(vals, dv, sizeof(double) * 2 * m, hipMemcpyDeviceToHost));
+    }
+    *nnz = n;
+    return QS3_OK;
+}
+
+template <>
+int row_k_K<KI>(qs3_sector *sec, uint64_t u, int cap, int64_t *cols, double *vals, double *diag,
+                int *nnz) {
+    const bool tabm = sec->bat->ks->has_table;
+    if constexpr (WIDE_OK) {
+        if (sec->bat->bt->wide)
+            return tabm ? row_k_t<uint64_t, true>(sec, u, cap, cols, vals, diag, nnz)
+                        : row_k_t<uint64_t, false>(sec, u, cap, cols, vals, diag, nnz);
+    }
+    return tabm ? row_k_t<uint32_t, true>(sec, u, cap, cols, vals, diag, nnz)
+                : row_k_t<uint32_t, false>(sec, u, cap, cols, vals, diag, nnz);
+}
+
+// ------------------------------------------------------------------ structure build
+template <typename RT>
+static int build_t(qs3_lattice *lat, const BinomTable &bt, KStructure *ks, hipStream_t s) {
+    constexpr int K = KI;
+    qs3_ctx *ctx = lat->ctx;
+    LatArgs L = lat_args(lat);
+    const RT *tab = bt.dev.as<RT>();
+    BuildArgs A{L, bt.D, 0};
+    uint64_t nblk = std::min<uint64_t>((bt.D + 1023) / 1024, 65536);
+    nblk = std::max<uint64_t>(nblk, 1);
+    A.chunk = (bt.D + nblk - 1) / nblk;
+    nblk = (bt.D + A.chunk - 1) / A.chunk;
+    DevBuf cnt;
+    QS3_TRY(cnt.alloc(ctx, sizeof(unsigned long long) * (nblk + 1)));
+    hipLaunchKernelGGL((k_count_reps<K, RT>), dim3(nblk), dim3(256), 0, s, A, tab,
+                       cnt.as<unsigned long long>());
+    QS3_HIP(hipGetLastError());
+    std::vector<unsigned long long> h(nblk + 1, 0);
+    QS3_HIP(hipMemcpyAsync(h.data(), cnt.ptr, sizeof(unsigned long long) * nblk,
+                           hipMemcpyDeviceToHost, s));
+    QS3_HIP(hipStreamSynchronize(s));
+    unsigned long long tot = 0;
+    for (uint64_t b = 0; b < nblk; ++b) {
+        unsigned long long c = h[b];
+        h[b] = tot;
+        tot += c;
+    }
+    ks->n_reps = tot;
+    QS3_REQUIRE(tot < (1ull << 32), QS3_EINVAL, "more than 2^32 representatives");
+    QS3_HIP(hipMemcpyAsync(cnt.ptr, h.data(), sizeof(unsigned long long) * nblk,
+                           hipMemcpyHostToDevice, s));
+    QS3_TRY(ks->reps.alloc(ctx, sizeof(uint64_t) * std::max<uint64_t>(tot, 1)));
+    hipLaunchKernelGGL((k_write_reps<K, RT>), dim3(nblk), dim3(256), 0, s, A, tab,
+                       cnt.as<unsigned long long>(), ks->reps.as<uint64_t>());
+    QS3_HIP(hipGetLastError());
+    QS3_TRY(ks->stab.alloc(ctx, sizeof(uint16_t) * std::max<uint64_t>(tot, 1)));
+    if (tot)
+        hipLaunchKernelGGL((k_stab<K, RT>), dim3((tot + 255) / 256), dim3(256), 0, s, L, tab, tot,
+                           ks->reps.as<uint64_t>(), ks->stab.as<uint16_t>());
+    QS3_HIP(hipGetLastError());
+    // directory over the rank range
+    int Dbits = 1;
+    while (Dbits < 64 && (1ull << Dbits) < bt.D) ++Dbits;
+    int want = 1;
+    while (want < 24 && (1ull << want) < tot) ++want;
+    ks->dir_bits = std::min(want, Dbits);
+    ks->dir_shift = Dbits - ks->dir_bits;
+    uint64_t nb = (bt.D >> ks->dir_shift) + 1;
+    QS3_TRY(ks->dir.alloc(ctx, sizeof(uint32_t) * (nb + 2)));
+    hipLaunchKernelGGL(k_dir, dim3((nb + 256) / 256), dim3(256), 0, s, tot, ks->reps.as<uint64_t>(),
+                       ks->dir_shift, nb, ks->dir.as<uint32_t>());
+    QS3_HIP(hipGetLastError());
+    // rank -> (representative, translation) table when it fits comfortably
+    uint64_t tbytes = bt.D * sizeof(uint64_t);
+    uint64_t used = ctx->used.load();
+    uint64_t free_b = ctx->budget > used ? ctx->budget - used : 0;
+    ks->has_table = tbytes <= (16ull << 30) && tbytes <= free_b / 4;
+    if (ks->has_table) {
+        QS3_TRY(ks->table.alloc(ctx, tbytes));
+        hipLaunchKernelGGL((k_table<K, RT>), dim3((bt.D + 255) / 256), dim3(256), 0, s, A, tab,
+                           ks->reps.as<uint64_t>(), ks->dir.as<uint32_t>(), ks->dir_shift,
+                           ks->table.as<uint64_t>());
+        QS3_HIP(hipGetLastError());
+    }
+    ks->h_reps.resize(tot);
+    ks->h_stab.resize(tot);
+    if (tot) {
+        QS3_HIP(hipMemcpyAsync(ks->h_reps.data(), ks->reps.ptr, sizeof(uint64_t) * tot,
+                               hipMemcpyDeviceToHost, s));
+        QS3_HIP(hipMemcpyAsync(ks->h_stab.data(), ks->stab.ptr, sizeof(uint16_t) * tot,
+                               hipMemcpyDeviceToHost, s));
+    }
+    QS3_HIP(hipStreamSynchronize(s));
+    return QS3_OK;
+}
+
+template <>
+int build_kstruct_K<KI>(qs3_lattice *lat, const BinomTable &bt, KStructure *ks, hipStream_t s) {
+    if constexpr (WIDE_OK) {
+        if (bt.wide) return build_t<uint64_t>(lat, bt, ks, s);
+    }
+    return build_t<uint32_t>(lat, bt, ks, s);
+}
+#endif
+
+}  // namespace qs3

@@ -1,0 +1,529 @@
+// Matrix-free H.v of the XXZ model (Sec. 3.5, Alg. 9) for gfx950, pull form:
+// every output row is one gather, so no atomics are needed.
+//
+//  * k_hv_u1      fixed-N_down sector, one row per lane, consecutive ranks on
+//                 consecutive lanes (hops of the same down spin then land on
+//                 near-contiguous ranks), binomial columns and the adjacency in
+//                 LDS, XCD-contiguous row ranges.
+//  * k_hv_batch   any number B of momentum sectors of one (lattice, N_down) in
+//                 the [representative][sector] layout: a group of G lanes owns a
+//                 row, resolves every hop once (rank -> representative index and
+//                 translation, by table lookup or on-the-fly canonicalisation)
+//                 and each lane applies the hop to its own sectors with their
+//                 phases e^{ik.t}; one gather per hop reads G contiguous
+//                 complex elements.
+//  * structure build: representatives of every orbit, stabiliser sizes, the
+//    search directory and the rank -> (representative, translation) table.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "qs3_device.h"
+#include "qs3_impl.h"
+#include "qs3_hv.h"
+
+namespace qs3 {
+
+// ------------------------------------------------------------------ helpers
+template <typename T>
+struct Cplx;
+template <>
+struct Cplx<double> {
+    using type = double2;
+};
+template <>
+struct Cplx<float> {
+    using type = float2;
+};
+
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
+    // gfx950 dispatches workgroup b to XCD b % 8; give each XCD one contiguous
+    // slice of the logical block range so its L2 sees neighbouring rows.
+    return (n % 8u == 0u) ? (b % 8u) * (n / 8u) + b / 8u : b;
+}
+
+template <typename RT>
+__device__ __forceinline__ void load_lds_tables(unsigned char *smem, const LatArgs &L,
+                                                const RT *binom_g, int K, const RT **tab,
+                                                const int **ptr, const uint16_t **nbr) {
+    int ntab = K >= 2 ? (K - 1) * (L.N + 1) : 0;
+    RT *s_tab = (RT *)smem;
+    for (int i = threadIdx.x; i < ntab; i += blockDim.x) s_tab[i] = binom_g[i];
+    int *s_ptr = (int *)(smem + ((ntab * sizeof(RT) + 15) & ~size_t(15)));
+    for (int i = threadIdx.x; i <= L.N; i += blockDim.x) s_ptr[i] = L.ptr[i];
+    uint16_t *s_nbr = (uint16_t *)(s_ptr + L.N + 1);
+    for (int i = threadIdx.x; i < L.n_edges; i += blockDim.x) s_nbr[i] = L.nbr[i];
+    __syncthreads();
+    *tab = s_tab;
+    *ptr = s_ptr;
+    *nbr = s_nbr;
+}
+
+template <typename RT>
+static size_t lds_bytes(const qs3_lattice *lat, int K) {
+    size_t ntab = K >= 2 ? (size_t)(K - 1) * (lat->N + 1) : 0;
+    return ((ntab * sizeof(RT) + 15) & ~size_t(15)) + sizeof(int) * (lat->N + 1) +
+           sizeof(uint16_t) * lat->h_nbr.size() + 16;
+}
+
+// ------------------------------------------------------------------ U(1)
+template <int K, typename RT, typename VT, typename OT>
+__global__ __launch_bounds__(256) void k_hv_u1(LatArgs L, const RT *__restrict__ binom_g, RT D,
+                                               const VT *__restrict__ v, OT *__restrict__ w) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const RT *tab;
+    const int *ptr;
+    const uint16_t *nbr;
+    load_lds_tables<RT>(smem, L, binom_g, K, &tab, &ptr, &nbr);
+    Binom<RT> Bn{tab, L.N + 1};
+
+    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const uint64_t ntiles = ((uint64_t)D + 255) / 256;
+    const uint64_t t0 = ntiles * lb / gridDim.x, t1 = ntiles * (lb + 1) / gridDim.x;
+    const VT jxy_u = (VT)L.u_jxy_h, jz_u = (VT)L.u_jz_h, ez4 = (VT)L.ez4;
+    const bool UNIF = L.uniform != 0;
+    for (uint64_t tile = t0; tile < t1; ++tile) {
+        const uint64_t row64 = tile * 256 + threadIdx.x;
+        if (row64 >= (uint64_t)D) break;
+        const RT row = (RT)row64;
+        int c[K > 0 ? K : 1];
+        unrank<K, RT>(row, L.N, Bn, c);
+        HopRanker<K, RT> hr;
+        hr.init(c, Bn);
+        VT acc = 0, dz = 0;
+        StaticFor<0, K>::run([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int e0 = ptr[c[m]], e1 = ptr[c[m] + 1];
+            for (int e = e0; e < e1; ++e) {
+                const int j = nbr[e];
+                RT rp;
+                const bool up = hr.template hop<m>(c, row, j, Bn, &rp);
+                if (up) {
+                    const VT x = v[rp];
+                    if (UNIF) {
+                        acc += x;
+                        dz += (VT)1;
+                    } else if (sizeof(VT) == 8) {
+                        acc += (VT)L.jxy_h[e] * x;
+                        dz += (VT)L.jz_h[e];
+                    } else {
+                        acc += (VT)L.jxy_hf[e] * x;
+                        dz += (VT)L.jz_hf[e];
+                    }
+                }
+            }
+        });
+        VT diag, off;
+        if (UNIF) {
+            diag = ez4 - jz_u * dz;
+            off = jxy_u * acc;
+        } else {
+            diag = ez4 - dz;
+            off = acc;
+        }
+        w[row] = (OT)(diag * v[row] + off);
+    }
+}
+
+// ------------------------------------------------------------------ batch (momentum)
+
+template <int K, typename RT, bool TABLE>
+__device__ __forceinline__ void resolve_hop(const BatchArgs &A, const Binom<RT> &Bn, const Geom &g,
+                                            const int (&c)[K > 0 ? K : 1], int m, int j, RT rp,
+                                            uint32_t *u2, int *tx, int *ty, int *tz) {
+    if (TABLE) {
+        uint64_t ent = A.table[rp];
+        *u2 = (uint32_t)ent;
+        uint32_t t = (uint32_t)(ent >> 32);
+        *tx = t & 1023u;
+        *ty = (t >> 10) & 1023u;
+        *tz = (t >> 20) & 1023u;
+    } else {
+        int n2[K > 0 ? K : 1], best[K > 0 ? K : 1];
+#pragma unroll
+        for (int t = 0; t < K; ++t) n2[t] = (t == m) ? j : c[t];
+        sortK<K>(n2);
+        canonicalize<K>(n2, g, best, *tx, *ty, *tz);
+        uint64_t r = 0;
+#pragma unroll
+        for (int t = 0; t < K; ++t) r += (uint64_t)Bn.C(best[t], t + 1);
+        *u2 = (uint32_t)find_rep(A.reps, A.dir, A.dir_shift, r);
+    }
+}
+
+template <int K, typename RT, typename CT, typename OT, bool TABLE, int BPL>
+__global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restrict__ binom_g,
+                                                  const typename Cplx<CT>::type *__restrict__ v,
+                                                  typename Cplx<OT>::type *__restrict__ w) {
+    using C2 = typename Cplx<CT>::type;
+    using O2 = typename Cplx<OT>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const RT *tab;
+    const int *ptr;
+    const uint16_t *nbr;
+    load_lds_tables<RT>(smem, A.L, binom_g, K, &tab, &ptr, &nbr);
+    Binom<RT> Bn{tab, A.L.N + 1};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+
+    const int G = A.G, B = A.B;
+    const bool UNIF = A.L.uniform != 0;
+    const int lane = threadIdx.x % G;
+    const int slot = threadIdx.x / G;
+    const int rows_per_tile = blockDim.x / G;
+    int kx[BPL], ky[BPL], kz[BPL];
+    bool bval[BPL];
+#pragma unroll
+    for (int i = 0; i < BPL; ++i) {
+        int b = lane + i * G;
+        bval[i] = b < B;
+        int bb = bval[i] ? b : 0;
+        kx[i] = A.kmul[3 * bb];
+        ky[i] = A.kmul[3 * bb + 1];
+        kz[i] = A.kmul[3 * bb + 2];
+    }
+    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const uint64_t ntiles = (A.n_reps + rows_per_tile - 1) / rows_per_tile;
+    const uint64_t t0 = ntiles * lb / gridDim.x, t1 = ntiles * (lb + 1) / gridDim.x;
+    for (uint64_t tile = t0; tile < t1; ++tile) {
+        const uint64_t u = tile * rows_per_tile + slot;
+        if (u >= A.n_reps) break;
+        const uint64_t R64 = A.reps[u];
+        const RT R = (RT)R64;
+        const int su = A.stab[u];
+        const int ntu = su > 1 ? A.nt_of[u] : -1;
+        int c[K > 0 ? K : 1];
+        unrank<K, RT>(R, A.L.N, Bn, c);
+        HopRanker<K, RT> hr;
+        hr.init(c, Bn);
+        const CT isq = (CT)(1.0 / A.L.sqrt_tab[su]);
+        CT accr[BPL], acci[BPL];
+#pragma unroll
+        for (int i = 0; i < BPL; ++i) accr[i] = acci[i] = 0;
+        CT dz = 0;
+        StaticFor<0, K>::run([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int e0 = ptr[c[m]], e1 = ptr[c[m] + 1];
+            for (int e = e0; e < e1; ++e) {
+                const int j = nbr[e];
+                RT rp;
+                const bool up = hr.template hop<m>(c, R, j, Bn, &rp);
+                if (!up) continue;
+                uint32_t u2;
+                int tx, ty, tz;
+                resolve_hop<K, RT, TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
+                const int s2 = A.stab[u2];
+                const int nt2 = s2 > 1 ? A.nt_of[u2] : -1;
+                const CT jxy = UNIF ? (CT)A.L.u_jxy_h
+                                    : (sizeof(CT) == 8 ? (CT)A.L.jxy_h[e] : (CT)A.L.jxy_hf[e]);
+                dz += UNIF ? (CT)A.L.u_jz_h : (sizeof(CT) == 8 ? (CT)A.L.jz_h[e] : (CT)A.L.jz_hf[e]);
+                const CT coef = jxy * (CT)A.L.sqrt_tab[s2] * isq;
+                const C2 *vrow = v + (uint64_t)u2 * B;
+#pragma unroll
+                for (int i = 0; i < BPL; ++i) {
+                    if (!bval[i]) continue;
+                    const int b = lane + i * G;
+                    if (nt2 >= 0 && !A.compat_nt[(size_t)nt2 * B + b]) continue;
+                    int P = kx[i] * tx + ky[i] * ty + kz[i] * tz;
+                    int q = (int)((double)P * A.invM);
+                    P -= q * A.M;
+                    P += (P < 0) ? A.M : 0;
+                    P -= (P >= A.M) ? A.M : 0;
+                    const double2 ph = A.phase[P];
+                    const C2 x = vrow[b];
+                    const CT pr = coef * (CT)ph.x, pi = coef * (CT)ph.y;
+                    accr[i] += pr * x.x - pi * x.y;
+                    acci[i] += pr * x.y + pi * x.x;
+                }
+            }
+        });
+        const CT diag = (CT)A.L.ez4 - dz;
+        O2 *wrow = w + u * B;
+        const C2 *vself = v + u * B;
+#pragma unroll
+        for (int i = 0; i < BPL; ++i) {
+            if (!bval[i]) continue;
+            const int b = lane + i * G;
+            const bool ok = ntu < 0 || A.compat_nt[(size_t)ntu * B + b];
+            O2 o;
+            if (ok) {
+                C2 x = vself[b];
+                o.x = (OT)(diag * x.x + accr[i]);
+                o.y = (OT)(diag * x.y + acci[i]);
+            } else {
+                o.x = 0;
+                o.y = 0;
+            }
+            wrow[b] = o;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ structure build
+template <int K, typename RT>
+__device__ __forceinline__ bool is_orbit_min(const int (&c)[K > 0 ? K : 1], const Geom &g) {
+    // early-exit variant of canonicalize(): is c itself the minimum image?
+    int x[K > 0 ? K : 1], y[K > 0 ? K : 1], z[K > 0 ? K : 1];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        uint32_t p = g.coords[c[m]];
+        x[m] = p & 1023u;
+        y[m] = (p >> 10) & 1023u;
+        z[m] = (p >> 20) & 1023u;
+    }
+    // c must have coordinate 0 occupied on every axis
+    bool hx = g.lx == 1, hy = g.ly == 1, hz = g.lz == 1;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        hx |= x[m] == 0;
+        hy |= y[m] == 0;
+        hz |= z[m] == 0;
+    }
+    if (K == 0) return true;  // the empty set is its own orbit
+    if (!(hx && hy && hz)) return false;
+    const int nx = g.lx > 1 ? K : 1, ny = g.ly > 1 ? K : 1, nz = g.lz > 1 ? K : 1;
+    for (int iz = 0; iz < nz; ++iz) {
+        int tz = z[iz] == 0 ? 0 : g.lz - z[iz];
+        for (int iy = 0; iy < ny; ++iy) {
+            int ty = y[iy] == 0 ? 0 : g.ly - y[iy];
+            for (int ix = 0; ix < nx; ++ix) {
+                int tx = x[ix] == 0 ? 0 : g.lx - x[ix];
+                int img[K > 0 ? K : 1];
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    img[m] = wrap_add(x[m], tx, g.lx) + g.lx * wrap_add(y[m], ty, g.ly) +
+                             g.lxy * wrap_add(z[m], tz, g.lz);
+                sortK<K>(img);
+                int cmp = 0;
+#pragma unroll
+                for (int m = K - 1; m >= 0; --m)
+                    if (cmp == 0) cmp = (img[m] < c[m]) ? -1 : (img[m] > c[m] ? 1 : 0);
+                if (cmp < 0) return false;
+            }
+        }
+    }
+    return true;
+}
+
+
+template <int K, typename RT>
+__global__ __launch_bounds__(256) void k_count_reps(BuildArgs A, const RT *__restrict__ binom_g,
+                                                    unsigned long long *counts) {
+    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    const uint64_t lo = (uint64_t)blockIdx.x * A.chunk;
+    const uint64_t hi = min(A.D, lo + A.chunk);
+    unsigned long long cnt = 0;
+    for (uint64_t r = lo + threadIdx.x; r < hi; r += blockDim.x) {
+        int c[K > 0 ? K : 1];
+        unrank<K, RT>((RT)r, A.L.N, Bn, c);
+        cnt += is_orbit_min<K, RT>(c, g) ? 1 : 0;
+    }
+    __shared__ unsigned long long red[256];
+    red[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[blockIdx.x] = red[0];
+}
+
+template <int K, typename RT>
+__global__ __launch_bounds__(256) void k_write_reps(BuildArgs A, const RT *__restrict__ binom_g,
+                                                    const unsigned long long *offsets,
+                                                    uint64_t *reps) {
+    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    const uint64_t lo = (uint64_t)blockIdx.x * A.chunk;
+    const uint64_t hi = min(A.D, lo + A.chunk);
+    __shared__ unsigned int wave_cnt[4];
+    unsigned long long base = offsets[blockIdx.x];
+    const int wid = threadIdx.x / 64, ln = threadIdx.x % 64;
+    for (uint64_t r0 = lo; r0 < hi; r0 += blockDim.x) {
+        uint64_t r = r0 + threadIdx.x;
+        bool f = false;
+        if (r < hi) {
+            int c[K > 0 ? K : 1];
+            unrank<K, RT>((RT)r, A.L.N, Bn, c);
+            f = is_orbit_min<K, RT>(c, g);
+        }
+        unsigned long long bal = __ballot(f);
+        unsigned int before = __popcll(bal & ((1ull << ln) - 1ull));
+        if (ln == 0) wave_cnt[wid] = __popcll(bal);
+        __syncthreads();
+        unsigned int woff = 0, tot = 0;
+        for (int k = 0; k < (int)(blockDim.x / 64); ++k) {
+            if (k < wid) woff += wave_cnt[k];
+            tot += wave_cnt[k];
+        }
+        if (f) reps[base + woff + before] = r;
+        base += tot;
+        __syncthreads();
+    }
+}
+
+template <int K, typename RT>
+__global__ __launch_bounds__(256) void k_stab(LatArgs L, const RT *__restrict__ binom_g,
+                                              uint64_t n_reps, const uint64_t *__restrict__ reps,
+                                              uint16_t *stab) {
+    Binom<RT> Bn{binom_g, L.N + 1};
+    Geom g{L.lx, L.ly, L.lz, L.lx * L.ly, L.coords};
+    uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_reps) return;
+    int c[K > 0 ? K : 1];
+    unrank<K, RT>((RT)reps[u], L.N, Bn, c);
+    int x[K > 0 ? K : 1], y[K > 0 ? K : 1], z[K > 0 ? K : 1];
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        uint32_t p = g.coords[c[m]];
+        x[m] = p & 1023u;
+        y[m] = (p >> 10) & 1023u;
+        z[m] = (p >> 20) & 1023u;
+    }
+    // every stabiliser element maps the representative onto itself, so it is
+    // one of the candidate shifts; count each distinct shift once (first spin
+    // carrying a given coordinate value).
+    int count = 0;
+    const int nx = g.lx > 1 ? K : 1, ny = g.ly > 1 ? K : 1, nz = g.lz > 1 ? K : 1;
+    for (int iz = 0; iz < nz; ++iz) {
+        bool dz = false;
+        for (int q = 0; q < iz; ++q) dz |= z[q] == z[iz];
+        if (dz) continue;
+        int tz = z[iz] == 0 ? 0 : g.lz - z[iz];
+        for (int iy = 0; iy < ny; ++iy) {
+            bool dy = false;
+            for (int q = 0; q < iy; ++q) dy |= y[q] == y[iy];
+            if (dy) continue;
+            int ty = y[iy] == 0 ? 0 : g.ly - y[iy];
+            for (int ix = 0; ix < nx; ++ix) {
+                bool dx = false;
+                for (int q = 0; q < ix; ++q) dx |= x[q] == x[ix];
+                if (dx) continue;
+                int tx = x[ix] == 0 ? 0 : g.lx - x[ix];
+                int img[K > 0 ? K : 1];
+#pragma unroll
+                for (int m = 0; m < K; ++m)
+                    img[m] = wrap_add(x[m], tx, g.lx) + g.lx * wrap_add(y[m], ty, g.ly) +
+                             g.lxy * wrap_add(z[m], tz, g.lz);
+                sortK<K>(img);
+                bool eq = true;
+#pragma unroll
+                for (int m = 0; m < K; ++m) eq &= img[m] == c[m];
+                count += eq ? 1 : 0;
+            }
+        }
+    }
+    stab[u] = (uint16_t)(K == 0 ? L.N : count);
+}
+
+static __global__ void k_dir(uint64_t n_reps, const uint64_t *__restrict__ reps, int shift, uint64_t nb,
+                      uint32_t *dir) {
+    uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nb) return;
+    uint64_t key = b << shift;
+    uint64_t lo = 0, hi = n_reps;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (reps[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    dir[b] = (uint32_t)lo;
+}
+
+template <int K, typename RT>
+__global__ __launch_bounds__(256) void k_table(BuildArgs A, const RT *__restrict__ binom_g,
+                                               const uint64_t *__restrict__ reps,
+                                               const uint32_t *__restrict__ dir, int shift,
+                                               uint64_t *table) {
+    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= A.D) return;
+    int c[K > 0 ? K : 1], best[K > 0 ? K : 1];
+    unrank<K, RT>((RT)r, A.L.N, Bn, c);
+    int tx, ty, tz;
+    canonicalize<K>(c, g, best, tx, ty, tz);
+    uint64_t rr = 0;
+#pragma unroll
+    for (int t = 0; t < K; ++t) rr += (uint64_t)Bn.C(best[t], t + 1);
+    uint32_t u = (uint32_t)find_rep(reps, dir, shift, rr);
+    table[r] = pack_ent(u, tx, ty, tz);
+}
+
+// ------------------------------------------------------------------ debug rows
+template <int K, typename RT>
+__global__ void k_row_u1(LatArgs L, const RT *binom_g, RT row, int cap, int64_t *cols,
+                         double *vals, double *diag, int *nnz) {
+    Binom<RT> Bn{binom_g, L.N + 1};
+    int c[K > 0 ? K : 1];
+    unrank<K, RT>(row, L.N, Bn, c);
+    HopRanker<K, RT> hr;
+    hr.init(c, Bn);
+    int n = 0;
+    double dz = 0;
+    StaticFor<0, K>::run([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        for (int e = L.ptr[c[m]]; e < L.ptr[c[m] + 1]; ++e) {
+            int j = L.nbr[e];
+            RT rp;
+            const bool up = hr.template hop<m>(c, row, j, Bn, &rp);
+            if (!up) continue;
+            double jxy = L.uniform ? L.u_jxy_h : L.jxy_h[e];
+            dz += L.uniform ? L.u_jz_h : L.jz_h[e];
+            if (n < cap) {
+                cols[n] = (int64_t)rp;
+                vals[n] = jxy;
+            }
+            ++n;
+        }
+    });
+    *diag = L.ez4 - dz;
+    *nnz = n;
+}
+
+template <int K, typename RT, bool TABLE>
+__global__ void k_row_k(BatchArgs A, const RT *binom_g, uint64_t u, int cap, int64_t *cols,
+                        double *vals, double *diag, int *nnz) {
+    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    const RT R = (RT)A.reps[u];
+    const int su = A.stab[u];
+    int c[K > 0 ? K : 1];
+    unrank<K, RT>(R, A.L.N, Bn, c);
+    HopRanker<K, RT> hr;
+    hr.init(c, Bn);
+    int n = 0;
+    double dz = 0;
+    const double isq = 1.0 / A.L.sqrt_tab[su];
+    StaticFor<0, K>::run([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        for (int e = A.L.ptr[c[m]]; e < A.L.ptr[c[m] + 1]; ++e) {
+            int j = A.L.nbr[e];
+            RT rp;
+            const bool up = hr.template hop<m>(c, R, j, Bn, &rp);
+            if (!up) continue;
+            uint32_t u2;
+            int tx, ty, tz;
+            resolve_hop<K, RT, TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
+            const int s2 = A.stab[u2];
+            const int nt2 = s2 > 1 ? A.nt_of[u2] : -1;
+            dz += A.L.uniform ? A.L.u_jz_h : A.L.jz_h[e];
+            if (nt2 >= 0 && !A.compat_nt[nt2]) continue;  // B == 1
+            const double coef = (A.L.uniform ? A.L.u_jxy_h : A.L.jxy_h[e]) * A.L.sqrt_tab[s2] * isq;
+            int P = A.kmul[0] * tx + A.kmul[1] * ty + A.kmul[2] * tz;
+            P %= A.M;
+            if (n < cap) {
+                cols[n] = (int64_t)u2;
+                vals[2 * n] = coef * A.phase[P].x;
+                vals[2 * n + 1] = coef * A.phase[P].y;
+            }
+            ++n;
+        }
+    });
+    *diag = A.L.ez4 - dz;
+    *nnz = n;
+}
+
+}  // namespace qs3

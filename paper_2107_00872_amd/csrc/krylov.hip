@@ -1,0 +1,821 @@
+// Lanczos and thick-restart Lanczos (Sec. 3.7, Alg. 10) on the device.
+//
+// Vectors are "multi-vectors" of n rows x B columns in the layout [row][col]
+// (B = 1 for a single sector, B = number of momentum sectors for a batch),
+// real (fixed-N_down) or complex (momentum).  Every column is an independent
+// Lanczos run: its alpha, beta and reorthogonalisation coefficients are
+// per-column device scalars, so one launch of each kernel advances all
+// columns and the host only reads alpha/beta once per restart cycle.
+//
+// Column reductions are deterministic: fixed row chunks, a fixed in-block
+// tree, and a fixed-order sum over chunks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <limits>
+#include <vector>
+
+#include "qs3_device.h"
+#include "qs3_impl.h"
+#include "qs3_krylov.h"
+
+namespace qs3 {
+
+// ------------------------------------------------------------------ geometry of reductions
+static RedGeom red_geom(uint64_t n, int B) {
+    RedGeom g;
+    g.n = n;
+    g.B = B;
+    g.TC = 1;
+    while (g.TC < B && g.TC < 64) g.TC <<= 1;
+    g.TR = 256 / g.TC;
+    uint64_t rc = std::max<uint64_t>((uint64_t)g.TR * 8, (n + 1023) / 1024);
+    rc = (rc + g.TR - 1) / g.TR * g.TR;
+    g.RC = rc;
+    g.nchunk = (int)std::max<uint64_t>(1, (n + rc - 1) / rc);
+    g.ncoltile = (B + g.TC - 1) / g.TC;
+    return g;
+}
+
+template <bool CPLX>
+struct Elem;
+template <>
+struct Elem<false> {
+    using T = double;
+    __device__ static double re(T a) { return a; }
+};
+template <>
+struct Elem<true> {
+    using T = double2;
+};
+
+// conj(x) * y accumulated as (re, im)
+__device__ __forceinline__ void cdot_acc(double x, double y, double &sr, double &si) { sr += x * y; }
+__device__ __forceinline__ void cdot_acc(double2 x, double2 y, double &sr, double &si) {
+    sr += x.x * y.x + x.y * y.y;
+    si += x.x * y.y - x.y * y.x;
+}
+
+// ------------------------------------------------------------------ kernels
+// partial[(chunk * J + j) * B + b] (re, im) = sum over the chunk's rows of
+// conj(X_j[r, b]) * Y[r, b], for j < J (X_j = X + j * stride).
+template <bool CPLX, int JT>
+__global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__restrict__ X,
+                                                  uint64_t stride, int J, const double *__restrict__ Y,
+                                                  double2 *__restrict__ partial) {
+    using T = typename Elem<CPLX>::T;
+    const int tc = threadIdx.x % g.TC, tr = threadIdx.x / g.TC;
+    const int b = blockIdx.y * g.TC + tc;
+    const uint64_t r0 = (uint64_t)blockIdx.x * g.RC;
+    const uint64_t r1 = min(g.n, r0 + g.RC);
+    __shared__ double2 red[256][JT > 4 ? 4 : JT];
+    const T *Yt = (const T *)Y;
+    for (int j0 = 0; j0 < J; j0 += JT) {
+        double sr[JT], si[JT];
+#pragma unroll
+        for (int q = 0; q < JT; ++q) sr[q] = si[q] = 0.0;
+        if (b < g.B) {
+            for (uint64_t r = r0 + tr; r < r1; r += g.TR) {
+                const uint64_t e = r * g.B + b;
+                const T y = Yt[e];
+#pragma unroll
+                for (int q = 0; q < JT; ++q) {
+                    if (j0 + q < J) {
+                        const T x = ((const T *)(X + (size_t)(j0 + q) * stride))[e];
+                        cdot_acc(x, y, sr[q], si[q]);
+                    }
+                }
+            }
+        }
+        // tree over tr, four j at a time through LDS
+#pragma unroll
+        for (int q0 = 0; q0 < JT; q0 += 4) {
+            constexpr int W = JT > 4 ? 4 : JT;
+#pragma unroll
+            for (int q = 0; q < W; ++q) red[threadIdx.x][q] = make_double2(sr[q0 + q], si[q0 + q]);
+            __syncthreads();
+            for (int s = g.TR / 2; s > 0; s >>= 1) {
+                if (tr < s) {
+#pragma unroll
+                    for (int q = 0; q < W; ++q) {
+                        double2 a = red[threadIdx.x][q], c = red[threadIdx.x + s * g.TC][q];
+                        red[threadIdx.x][q] = make_double2(a.x + c.x, a.y + c.y);
+                    }
+                }
+                __syncthreads();
+            }
+            if (tr == 0 && b < g.B) {
+#pragma unroll
+                for (int q = 0; q < W; ++q)
+                    if (j0 + q0 + q < J)
+                        partial[((size_t)blockIdx.x * J + j0 + q0 + q) * g.B + b] = red[threadIdx.x][q];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// out[j * B + b] = sum_chunk partial[(chunk * J + j) * B + b], fixed order.
+__global__ void k_reduce_chunks(const double2 *__restrict__ partial, int nchunk, int JB,
+                                double2 *__restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= JB) return;
+    double sr = 0, si = 0;
+    for (int c = 0; c < nchunk; ++c) {
+        double2 p = partial[(size_t)c * JB + i];
+        sr += p.x;
+        si += p.y;
+    }
+    out[i] = make_double2(sr, si);
+}
+
+// W -= alpha[b] * P0 (+ beta[b] * P1 when P1 != null); alpha, beta real per column.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_lanczos_update(uint64_t ne, int B, double *__restrict__ W,
+                                                        const double *__restrict__ P0,
+                                                        const double *__restrict__ P1,
+                                                        const double2 *__restrict__ alpha,
+                                                        const double *__restrict__ beta) {
+    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const int b = (int)(e % (uint64_t)B);
+    const double a = alpha[b].x;
+    const double be = P1 ? beta[b] : 0.0;
+    if (CPLX) {
+        double2 w = ((double2 *)W)[e], p0 = ((const double2 *)P0)[e];
+        w.x -= a * p0.x;
+        w.y -= a * p0.y;
+        if (P1) {
+            double2 p1 = ((const double2 *)P1)[e];
+            w.x -= be * p1.x;
+            w.y -= be * p1.y;
+        }
+        ((double2 *)W)[e] = w;
+    } else {
+        double w = W[e] - a * P0[e];
+        if (P1) w -= be * P1[e];
+        W[e] = w;
+    }
+}
+
+// W -= sum_{j<J} X_j * h[j * B + b]
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_cgs_update(uint64_t ne, int B, double *__restrict__ W,
+                                                    const double *__restrict__ X, uint64_t stride,
+                                                    int J, const double2 *__restrict__ h) {
+    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const int b = (int)(e % (uint64_t)B);
+    if (CPLX) {
+        double2 w = ((double2 *)W)[e];
+        for (int j = 0; j < J; ++j) {
+            const double2 x = ((const double2 *)(X + (size_t)j * stride))[e];
+            const double2 c = h[(size_t)j * B + b];
+            w.x -= x.x * c.x - x.y * c.y;
+            w.y -= x.x * c.y + x.y * c.x;
+        }
+        ((double2 *)W)[e] = w;
+    } else {
+        double w = W[e];
+        for (int j = 0; j < J; ++j) w -= X[(size_t)j * stride + e] * h[(size_t)j * B + b].x;
+        W[e] = w;
+    }
+}
+
+// beta[b] = sqrt(nrm2[b].x); P = W / beta (0 if beta == 0)
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_scale_out(uint64_t ne, int B, const double *__restrict__ W,
+                                                   double *__restrict__ P,
+                                                   const double2 *__restrict__ nrm2) {
+    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const int b = (int)(e % (uint64_t)B);
+    const double nb = sqrt(fmax(nrm2[b].x, 0.0));
+    const double s = nb > 0.0 ? 1.0 / nb : 0.0;
+    if (CPLX) {
+        double2 w = ((const double2 *)W)[e];
+        ((double2 *)P)[e] = make_double2(w.x * s, w.y * s);
+    } else {
+        P[e] = W[e] * s;
+    }
+}
+
+__global__ void k_sqrt_to(int B, const double2 *__restrict__ nrm2, double *__restrict__ out) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) out[b] = sqrt(fmax(nrm2[b].x, 0.0));
+}
+
+__global__ void k_copy_re(int B, const double2 *__restrict__ in, double *__restrict__ out) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) out[b] = in[b].x;
+}
+
+// Out_y = sum_{x < NX} X_x * C[b][x][y] for y < NY (C real, per column), masked by active[b].
+template <bool CPLX, int NYT>
+__global__ __launch_bounds__(256) void k_rotate(uint64_t ne, int B, const double *__restrict__ X,
+                                                uint64_t stride, int NX, const double *__restrict__ Cm,
+                                                int NY, double *__restrict__ Out,
+                                                const uint8_t *__restrict__ active) {
+    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const int b = (int)(e % (uint64_t)B);
+    if (active && !active[b]) return;
+    const double *Cb = Cm + (size_t)b * NX * NY;
+    for (int y0 = 0; y0 < NY; y0 += NYT) {
+        double ar[NYT], ai[NYT];
+#pragma unroll
+        for (int q = 0; q < NYT; ++q) ar[q] = ai[q] = 0.0;
+        for (int x = 0; x < NX; ++x) {
+            if (CPLX) {
+                const double2 v = ((const double2 *)(X + (size_t)x * stride))[e];
+#pragma unroll
+                for (int q = 0; q < NYT; ++q) {
+                    if (y0 + q < NY) {
+                        const double c = Cb[(size_t)x * NY + y0 + q];
+                        ar[q] += v.x * c;
+                        ai[q] += v.y * c;
+                    }
+                }
+            } else {
+                const double v = X[(size_t)x * stride + e];
+#pragma unroll
+                for (int q = 0; q < NYT; ++q)
+                    if (y0 + q < NY) ar[q] += v * Cb[(size_t)x * NY + y0 + q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NYT; ++q) {
+            if (y0 + q >= NY) break;
+            if (CPLX)
+                ((double2 *)(Out + (size_t)(y0 + q) * stride))[e] = make_double2(ar[q], ai[q]);
+            else
+                Out[(size_t)(y0 + q) * stride + e] = ar[q];
+        }
+    }
+}
+
+// Dst = Src for active columns (doubles per element = dpe)
+__global__ void k_masked_copy(uint64_t ne, int B, int dpe, const double *__restrict__ Src,
+                              double *__restrict__ Dst, const uint8_t *__restrict__ active) {
+    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ne) return;
+    const int b = (int)(e % (uint64_t)B);
+    if (active && !active[b]) return;
+    for (int q = 0; q < dpe; ++q) Dst[e * dpe + q] = Src[e * dpe + q];
+}
+
+__global__ void k_to_f32(uint64_t nd, const double *__restrict__ in, float *__restrict__ out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nd) out[i] = (float)in[i];
+}
+
+__global__ void k_fill0(uint64_t nd, double *__restrict__ p) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nd) p[i] = 0.0;
+}
+
+// ------------------------------------------------------------------ start vectors
+__global__ void k_start_u1(uint64_t D, uint64_t seed, double *__restrict__ v) {
+    uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < D) v[r] = u01_pm1(splitmix64(seed, r));
+}
+__global__ void k_start_u1_f32(uint64_t D, uint64_t seed, float *__restrict__ v) {
+    uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < D) v[r] = (float)u01_pm1(splitmix64(seed, r));
+}
+
+// union layout [u][b]; zero where the representative is incompatible with b
+__global__ void k_start_batch(uint64_t n, int B, const uint64_t *__restrict__ reps,
+                              const uint16_t *__restrict__ stab, const int32_t *__restrict__ nt_of,
+                              const uint8_t *__restrict__ compat_nt,
+                              const uint64_t *__restrict__ seeds, double2 *__restrict__ v) {
+    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * (uint64_t)B) return;
+    const uint64_t u = e / B;
+    const int b = (int)(e % B);
+    bool ok = true;
+    if (stab[u] > 1) ok = compat_nt[(size_t)nt_of[u] * B + b] != 0;
+    double2 o = make_double2(0.0, 0.0);
+    if (ok) {
+        const uint64_t r = reps[u];
+        o.x = u01_pm1(splitmix64(seeds[b], 2 * r));
+        o.y = u01_pm1(splitmix64(seeds[b], 2 * r + 1));
+    }
+    v[e] = o;
+}
+
+__global__ void k_scatter(uint64_t d, const int64_t *__restrict__ c2u, const double2 *__restrict__ src,
+                          double2 *__restrict__ dst) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d) dst[c2u[i]] = src[i];
+}
+__global__ void k_gather(uint64_t d, const int64_t *__restrict__ c2u, const double2 *__restrict__ src,
+                         double2 *__restrict__ dst) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d) dst[i] = src[c2u[i]];
+}
+__global__ void k_scatter_f(uint64_t d, const int64_t *__restrict__ c2u, const float2 *__restrict__ src,
+                            float2 *__restrict__ dst) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d) dst[c2u[i]] = src[i];
+}
+__global__ void k_gather_f(uint64_t d, const int64_t *__restrict__ c2u, const float2 *__restrict__ src,
+                           float2 *__restrict__ dst) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < d) dst[i] = src[c2u[i]];
+}
+
+static inline dim3 grid1(uint64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+int start_vector_u1(qs3_sector *sec, uint64_t seed, void *v, int dtype, hipStream_t s) {
+    if (sec->dim == 0) return QS3_OK;
+    if (dtype == QS3_F64)
+        hipLaunchKernelGGL(k_start_u1, grid1(sec->dim), dim3(256), 0, s, sec->dim, seed, (double *)v);
+    else if (dtype == QS3_F32)
+        hipLaunchKernelGGL(k_start_u1_f32, grid1(sec->dim), dim3(256), 0, s, sec->dim, seed, (float *)v);
+    else {
+        set_error("dtype of a fixed-N_down sector is QS3_F64 or QS3_F32");
+        return QS3_EINVAL;
+    }
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+int start_vector_batch(qs3_batch *bat, const uint64_t *seeds_dev, double *v, hipStream_t s) {
+    uint64_t n = bat->ks->n_reps;
+    if (n == 0) return QS3_OK;
+    hipLaunchKernelGGL(k_start_batch, grid1(n * bat->B), dim3(256), 0, s, n, bat->B,
+                       bat->ks->reps.as<uint64_t>(), bat->ks->stab.as<uint16_t>(),
+                       bat->ks->nt_of.as<int32_t>(), bat->compat_nt.as<uint8_t>(), seeds_dev,
+                       (double2 *)v);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+int scatter_compact(qs3_sector *sec, const double *src, double *dst_union, hipStream_t s) {
+    uint64_t n = sec->bat->ks->n_reps;
+    hipLaunchKernelGGL(k_fill0, grid1(2 * n), dim3(256), 0, s, 2 * n, dst_union);
+    if (sec->dim)
+        hipLaunchKernelGGL(k_scatter, grid1(sec->dim), dim3(256), 0, s, sec->dim,
+                           sec->comp2u.as<int64_t>(), (const double2 *)src, (double2 *)dst_union);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+int gather_compact(qs3_sector *sec, const double *src_union, double *dst, hipStream_t s) {
+    if (sec->dim)
+        hipLaunchKernelGGL(k_gather, grid1(sec->dim), dim3(256), 0, s, sec->dim,
+                           sec->comp2u.as<int64_t>(), (const double2 *)src_union, (double2 *)dst);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+int scatter_compact_f32(qs3_sector *sec, const float *src, float *dst_union, hipStream_t s) {
+    uint64_t n = sec->bat->ks->n_reps;
+    hipLaunchKernelGGL(k_fill0, grid1(n), dim3(256), 0, s, n, (double *)dst_union);  // 2n floats
+    if (sec->dim)
+        hipLaunchKernelGGL(k_scatter_f, grid1(sec->dim), dim3(256), 0, s, sec->dim,
+                           sec->comp2u.as<int64_t>(), (const float2 *)src, (float2 *)dst_union);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+int gather_compact_f32(qs3_sector *sec, const float *src_union, float *dst, hipStream_t s) {
+    if (sec->dim)
+        hipLaunchKernelGGL(k_gather_f, grid1(sec->dim), dim3(256), 0, s, sec->dim,
+                           sec->comp2u.as<int64_t>(), (const float2 *)src_union, (float2 *)dst);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+// ------------------------------------------------------------------ host eigensolver
+// Cyclic Jacobi for a real symmetric n x n matrix A (row-major, destroyed):
+// eigenvalues ascending in e, eigenvectors as columns of V (row-major n x n).
+void jacobi_eig(int n, std::vector<double> &A, std::vector<double> &e, std::vector<double> &V) {
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    auto a = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
+    double fro = 0;
+    for (double x : A) fro += x * x;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = i + 1; j < n; ++j) off += a(i, j) * a(i, j);
+        if (off <= 1e-34 * fro || off == 0.0) break;
+        for (int p = 0; p < n; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = a(p, q);
+                if (apq == 0.0) continue;
+                const double app = a(p, p), aqq = a(q, q);
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {  // columns p, q
+                    const double akp = a(k, p), akq = a(k, q);
+                    a(k, p) = c * akp - s * akq;
+                    a(k, q) = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // rows p, q
+                    const double apk = a(p, k), aqk = a(q, k);
+                    a(p, k) = c * apk - s * aqk;
+                    a(q, k) = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - s * vkq;
+                    V[(size_t)k * n + q] = s * vkp + c * vkq;
+                }
+            }
+        }
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return a(x, x) < a(y, y); });
+    e.resize(n);
+    std::vector<double> V2((size_t)n * n);
+    for (int k = 0; k < n; ++k) {
+        e[k] = a(idx[k], idx[k]);
+        for (int i = 0; i < n; ++i) V2[(size_t)i * n + k] = V[(size_t)i * n + idx[k]];
+    }
+    V.swap(V2);
+}
+
+// ------------------------------------------------------------------ engine
+Engine::~Engine() = default;
+
+int Engine::init(qs3_ctx *c, Operator *o, int slots_, int precision_, int reorth_, hipStream_t s) {
+    ctx = c;
+    op = o;
+    st = s;
+    n = op->rows();
+    B = op->cols();
+    cplx = op->is_complex();
+    dpe = cplx ? 2 : 1;
+    ne = n * (uint64_t)B;
+    stride = ne * dpe;
+    slots = slots_;
+    precision = precision_;
+    reorth = reorth_;
+    rg = red_geom(n, B);
+    QS3_TRY(Psi.alloc(ctx, sizeof(double) * stride * slots));
+    QS3_TRY(W.alloc(ctx, sizeof(double) * stride));
+    if (precision == QS3_PREC_F32MV) QS3_TRY(X32.alloc(ctx, sizeof(float) * stride));
+    const int maxJ = slots;
+    QS3_TRY(partial.alloc(ctx, sizeof(double2) * (size_t)rg.nchunk * maxJ * B));
+    QS3_TRY(hvec.alloc(ctx, sizeof(double2) * (size_t)maxJ * B));
+    QS3_TRY(alpha.alloc(ctx, sizeof(double2) * (size_t)B));
+    QS3_TRY(nrm2.alloc(ctx, sizeof(double2) * (size_t)B));
+    QS3_TRY(ab_hist.alloc(ctx, sizeof(double) * 2 * (size_t)slots * B));
+    QS3_TRY(act.alloc(ctx, (size_t)B + 8));
+    return QS3_OK;
+}
+
+double *Engine::slot(int j) { return Psi.as<double>() + (size_t)j * stride; }
+
+int Engine::apply(const double *x, double *y) {
+    if (precision == QS3_PREC_F32MV) {
+        hipLaunchKernelGGL(k_to_f32, grid1(stride), dim3(256), 0, st, stride, x, X32.as<float>());
+        QS3_HIP(hipGetLastError());
+        return op->apply_f32in(X32.as<float>(), y, st);
+    }
+    return op->apply(x, y, st);
+}
+
+int Engine::multidot(const double *X, int J, const double *Y, double2 *out) {
+    dim3 grid(rg.nchunk, rg.ncoltile);
+#define QS3_MD(CP)                                                                             \
+    hipLaunchKernelGGL((k_multidot<CP, 4>), grid, dim3(256), 0, st, rg, X, stride, J, Y,        \
+                       partial.as<double2>())
+    if (cplx) QS3_MD(true); else QS3_MD(false);
+#undef QS3_MD
+    QS3_HIP(hipGetLastError());
+    int JB = J * B;
+    hipLaunchKernelGGL(k_reduce_chunks, grid1(JB), dim3(256), 0, st, partial.as<double2>(),
+                       rg.nchunk, JB, out);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+// One Lanczos step: slot x holds psi_x (normalised); writes alpha_x, beta_x and
+// psi_{x+1} into slot x+1.  prev: slot of psi_{x-1} or -1.  Reorthogonalises
+// against slots 0..x.
+int Engine::step(int x, int prev) {
+    QS3_TRY(apply(slot(x), W.as<double>()));
+    QS3_TRY(multidot(slot(x), 1, W.as<double>(), alpha.as<double2>()));
+    double *betap = ab_hist.as<double>() + (size_t)slots * B + (size_t)(prev < 0 ? 0 : prev) * B;
+    if (cplx)
+        hipLaunchKernelGGL(k_lanczos_update<true>, grid1(ne), dim3(256), 0, st, ne, B,
+                           W.as<double>(), slot(x), prev >= 0 ? slot(prev) : nullptr,
+                           alpha.as<double2>(), betap);
+    else
+        hipLaunchKernelGGL(k_lanczos_update<false>, grid1(ne), dim3(256), 0, st, ne, B,
+                           W.as<double>(), slot(x), prev >= 0 ? slot(prev) : nullptr,
+                           alpha.as<double2>(), betap);
+    QS3_HIP(hipGetLastError());
+    // store alpha_x
+    hipLaunchKernelGGL(k_copy_re, grid1(B), dim3(256), 0, st, B, alpha.as<double2>(),
+                       ab_hist.as<double>() + (size_t)x * B);
+    for (int pass = 0; pass < reorth; ++pass) {
+        QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), hvec.as<double2>()));
+        if (cplx)
+            hipLaunchKernelGGL(k_cgs_update<true>, grid1(ne), dim3(256), 0, st, ne, B,
+                               W.as<double>(), slot(0), stride, x + 1, hvec.as<double2>());
+        else
+            hipLaunchKernelGGL(k_cgs_update<false>, grid1(ne), dim3(256), 0, st, ne, B,
+                               W.as<double>(), slot(0), stride, x + 1, hvec.as<double2>());
+        QS3_HIP(hipGetLastError());
+    }
+    QS3_TRY(multidot(W.as<double>(), 1, W.as<double>(), nrm2.as<double2>()));
+    hipLaunchKernelGGL(k_sqrt_to, grid1(B), dim3(256), 0, st, B, nrm2.as<double2>(),
+                       ab_hist.as<double>() + (size_t)slots * B + (size_t)x * B);
+    if (cplx)
+        hipLaunchKernelGGL(k_scale_out<true>, grid1(ne), dim3(256), 0, st, ne, B, W.as<double>(),
+                           slot(x + 1), nrm2.as<double2>());
+    else
+        hipLaunchKernelGGL(k_scale_out<false>, grid1(ne), dim3(256), 0, st, ne, B, W.as<double>(),
+                           slot(x + 1), nrm2.as<double2>());
+    QS3_HIP(hipGetLastError());
+    ++n_matvec;
+    return QS3_OK;
+}
+
+// slot 0 := v0 / |v0|; norms0[b] = |v0|
+int Engine::normalize_into_slot0(const double *v0, std::vector<double> *norms0) {
+    QS3_TRY(multidot(v0, 1, v0, nrm2.as<double2>()));
+    if (cplx)
+        hipLaunchKernelGGL(k_scale_out<true>, grid1(ne), dim3(256), 0, st, ne, B, v0, slot(0),
+                           nrm2.as<double2>());
+    else
+        hipLaunchKernelGGL(k_scale_out<false>, grid1(ne), dim3(256), 0, st, ne, B, v0, slot(0),
+                           nrm2.as<double2>());
+    QS3_HIP(hipGetLastError());
+    if (norms0) {
+        std::vector<double2> h(B);
+        QS3_HIP(hipMemcpyAsync(h.data(), nrm2.ptr, sizeof(double2) * B, hipMemcpyDeviceToHost, st));
+        QS3_HIP(hipStreamSynchronize(st));
+        norms0->resize(B);
+        for (int b = 0; b < B; ++b) (*norms0)[b] = std::sqrt(std::max(h[b].x, 0.0));
+    }
+    return QS3_OK;
+}
+
+int Engine::read_ab(int x0, int x1, std::vector<double> &a, std::vector<double> &bb) {
+    // a[x * B + b], bb[x * B + b] for x in [x0, x1)
+    int cnt = x1 - x0;
+    a.resize((size_t)slots * B);
+    bb.resize((size_t)slots * B);
+    if (cnt <= 0) return QS3_OK;
+    QS3_HIP(hipMemcpyAsync(a.data() + (size_t)x0 * B, ab_hist.as<double>() + (size_t)x0 * B,
+                           sizeof(double) * cnt * B, hipMemcpyDeviceToHost, st));
+    QS3_HIP(hipMemcpyAsync(bb.data() + (size_t)x0 * B,
+                           ab_hist.as<double>() + (size_t)slots * B + (size_t)x0 * B,
+                           sizeof(double) * cnt * B, hipMemcpyDeviceToHost, st));
+    QS3_HIP(hipStreamSynchronize(st));
+    return QS3_OK;
+}
+
+int Engine::rotate(int from_slot, int NX, const std::vector<double> &Cm, int NY, int to_slot,
+                   const uint8_t *active_host) {
+    DevBuf dC;
+    QS3_TRY(dC.alloc(ctx, sizeof(double) * Cm.size()));
+    QS3_HIP(hipMemcpyAsync(dC.ptr, Cm.data(), sizeof(double) * Cm.size(), hipMemcpyHostToDevice, st));
+    const uint8_t *actd = nullptr;
+    if (active_host) {
+        QS3_HIP(hipMemcpyAsync(act.ptr, active_host, B, hipMemcpyHostToDevice, st));
+        actd = act.as<uint8_t>();
+    }
+    if (cplx)
+        hipLaunchKernelGGL((k_rotate<true, 8>), grid1(ne), dim3(256), 0, st, ne, B, slot(from_slot),
+                           stride, NX, dC.as<double>(), NY, slot(to_slot), actd);
+    else
+        hipLaunchKernelGGL((k_rotate<false, 8>), grid1(ne), dim3(256), 0, st, ne, B, slot(from_slot),
+                           stride, NX, dC.as<double>(), NY, slot(to_slot), actd);
+    QS3_HIP(hipGetLastError());
+    QS3_HIP(hipStreamSynchronize(st));  // dC is released at return
+    return QS3_OK;
+}
+
+int Engine::copy_slot(int from, int to, const uint8_t *active_host) {
+    const uint8_t *actd = nullptr;
+    if (active_host) {
+        QS3_HIP(hipMemcpyAsync(act.ptr, active_host, B, hipMemcpyHostToDevice, st));
+        actd = act.as<uint8_t>();
+    }
+    hipLaunchKernelGGL(k_masked_copy, grid1(ne), dim3(256), 0, st, ne, B, dpe, slot(from), slot(to),
+                       actd);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+// ------------------------------------------------------------------ host-side solver logic
+static void build_tri(int m, const double *a, const double *b, std::vector<double> &T) {
+    T.assign((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) {
+        T[(size_t)i * m + i] = a[i];
+        if (i + 1 < m) T[(size_t)i * m + i + 1] = T[(size_t)(i + 1) * m + i] = b[i];
+    }
+}
+
+// lowest `nev` distinct converged levels (indices into e)
+static std::vector<int> pick_levels(const std::vector<double> &e, const std::vector<double> &res,
+                                    int nev, double tol, bool require_conv, bool *all_conv) {
+    std::vector<int> out;
+    *all_conv = true;
+    double last = std::numeric_limits<double>::quiet_NaN();
+    for (size_t i = 0; i < e.size() && (int)out.size() < nev; ++i) {
+        const double sc = std::max(1.0, std::fabs(e[i]));
+        const bool conv = res[i] <= tol * sc;
+        if (!conv) {
+            *all_conv = false;
+            if (require_conv) continue;
+        }
+        if (!out.empty() && std::fabs(e[i] - last) <= 1e-8 * sc) continue;
+        out.push_back((int)i);
+        last = e[i];
+    }
+    if ((int)out.size() < nev) *all_conv = false;
+    return out;
+}
+
+int run_lanczos(Engine &E, const double *v0, int steps, std::vector<double> &a_out,
+                std::vector<double> &b_out, std::vector<double> &norm0, std::vector<int> &done) {
+    const int B = E.B;
+    QS3_TRY(E.normalize_into_slot0(v0, &norm0));
+    for (int x = 0; x < steps; ++x) QS3_TRY(E.step(x, x - 1));
+    std::vector<double> a, b;
+    QS3_TRY(E.read_ab(0, steps, a, b));
+    a_out.assign((size_t)B * steps, 0.0);
+    b_out.assign((size_t)B * steps, 0.0);
+    done.assign(B, steps);
+    for (int c = 0; c < B; ++c) {
+        for (int x = 0; x < steps; ++x) {
+            a_out[(size_t)c * steps + x] = a[(size_t)x * B + c];
+            b_out[(size_t)c * steps + x] = b[(size_t)x * B + c];
+        }
+        for (int x = 0; x < steps; ++x) {
+            const double sc = std::max(1.0, std::fabs(a_out[(size_t)c * steps + x]));
+            if (b_out[(size_t)c * steps + x] <= 1e-14 * sc) {
+                done[c] = x + 1;
+                break;
+            }
+        }
+    }
+    return QS3_OK;
+}
+
+// Plain Lanczos eigensolve (QS3_ALG_LANCZOS): `steps` steps, Ritz values of T.
+int solve_lanczos(Engine &E, const double *v0, const qs3_eigs_opts &o, std::vector<double> &evals,
+                  std::vector<qs3_eigs_info> &info, int want_vecs, double *vec_out) {
+    const int B = E.B, steps = o.steps;
+    std::vector<double> a, b, n0;
+    std::vector<int> done;
+    QS3_TRY(run_lanczos(E, v0, steps, a, b, n0, done));
+    evals.assign((size_t)B * o.nev, std::numeric_limits<double>::quiet_NaN());
+    info.assign(B, qs3_eigs_info{});
+    std::vector<double> Cfull((size_t)B * steps * std::max(o.nev, 1), 0.0);
+    for (int c = 0; c < B; ++c) {
+        const int m = done[c];
+        std::vector<double> T, e, V;
+        build_tri(m, &a[(size_t)c * steps], &b[(size_t)c * steps], T);
+        jacobi_eig(m, T, e, V);
+        std::vector<double> res(m);
+        const double bm = b[(size_t)c * steps + m - 1];
+        for (int i = 0; i < m; ++i) res[i] = std::fabs(bm * V[(size_t)(m - 1) * m + i]);
+        bool allc;
+        auto lv = pick_levels(e, res, o.nev, o.tol, true, &allc);
+        double mr = 0;
+        for (size_t y = 0; y < lv.size(); ++y) {
+            evals[(size_t)c * o.nev + y] = e[lv[y]];
+            mr = std::max(mr, res[lv[y]]);
+            for (int x = 0; x < m; ++x) Cfull[((size_t)c * steps + x) * o.nev + y] = V[(size_t)x * m + lv[y]];
+        }
+        info[c].converged = allc ? 1 : 0;
+        info[c].n_found = (int)lv.size();
+        info[c].max_residual = mr;
+        info[c].n_matvec = steps;
+    }
+    if (want_vecs) {
+        // Ritz vectors: slots [steps+1 ..) hold the result temporarily
+        QS3_TRY(E.rotate(0, steps, Cfull, o.nev, steps + 1, nullptr));
+        for (int y = 0; y < o.nev; ++y)
+            QS3_HIP(hipMemcpyAsync(vec_out + (size_t)y * E.stride, E.slot(steps + 1 + y),
+                                   sizeof(double) * E.stride, hipMemcpyDeviceToDevice, E.st));
+    }
+    return QS3_OK;
+}
+
+// Thick-restart Lanczos (Alg. 10) for every column; columns freeze when
+// converged.  Slots: 0..NM (Krylov basis + residual), NM+1..NM+NK (rotation).
+int solve_trl(Engine &E, const double *v0, const qs3_eigs_opts &o, std::vector<double> &evals,
+              std::vector<qs3_eigs_info> &info, int want_vecs, double *vec_out) {
+    const int B = E.B, NK = o.nk, NM = o.nm, nev = o.nev;
+    evals.assign((size_t)B * nev, std::numeric_limits<double>::quiet_NaN());
+    info.assign(B, qs3_eigs_info{});
+    std::vector<uint8_t> active(B, 1);
+    std::vector<std::vector<int>> final_lv(B);
+    std::vector<double> n0;
+    QS3_TRY(E.normalize_into_slot0(v0, &n0));
+    for (int c = 0; c < B; ++c)
+        if (!(n0[c] > 0) || !std::isfinite(n0[c])) {
+            set_error("zero or non-finite start vector");
+            return QS3_ENUMERIC;
+        }
+    // first cycle: steps 0..NM-1
+    for (int x = 0; x < NM; ++x) QS3_TRY(E.step(x, x - 1));
+    std::vector<double> a, bb;
+    QS3_TRY(E.read_ab(0, NM, a, bb));
+    // per-column tridiagonal/arrowhead state
+    std::vector<std::vector<double>> al(B, std::vector<double>(NM)), be(B, std::vector<double>(NM));
+    std::vector<std::vector<double>> coup(B, std::vector<double>(NK, 0.0));
+    for (int c = 0; c < B; ++c)
+        for (int x = 0; x < NM; ++x) {
+            al[c][x] = a[(size_t)x * B + c];
+            be[c][x] = bb[(size_t)x * B + c];
+        }
+    bool first = true;
+    int restarts = 0;
+    std::vector<double> Crot((size_t)B * NM * NK, 0.0);
+    while (true) {
+        bool any_active = false;
+        for (int c = 0; c < B; ++c) {
+            if (!active[c]) continue;
+            std::vector<double> T((size_t)NM * NM, 0.0), e, V;
+            for (int x = 0; x < NM; ++x) T[(size_t)x * NM + x] = al[c][x];
+            if (first) {
+                for (int x = 0; x + 1 < NM; ++x) T[(size_t)x * NM + x + 1] = T[(size_t)(x + 1) * NM + x] = be[c][x];
+            } else {
+                for (int y = 0; y < NK; ++y) T[(size_t)y * NM + NK] = T[(size_t)NK * NM + y] = coup[c][y];
+                for (int z = NK; z + 1 < NM; ++z) T[(size_t)z * NM + z + 1] = T[(size_t)(z + 1) * NM + z] = be[c][z];
+            }
+            jacobi_eig(NM, T, e, V);
+            const double bm = be[c][NM - 1];
+            std::vector<double> res(NM);
+            for (int i = 0; i < NM; ++i) res[i] = std::fabs(bm * V[(size_t)(NM - 1) * NM + i]);
+            bool allc;
+            auto lv = pick_levels(std::vector<double>(e.begin(), e.begin() + NK),
+                                  std::vector<double>(res.begin(), res.begin() + NK), nev, o.tol,
+                                  false, &allc);
+            // every Ritz value below the highest wanted level must have converged
+            if (allc && !lv.empty()) {
+                const double top = e[lv.back()];
+                for (int i = 0; i < NK; ++i)
+                    if (e[i] <= top + 1e-8 * std::max(1.0, std::fabs(top)) &&
+                        res[i] > o.tol * std::max(1.0, std::fabs(e[i])))
+                        allc = false;
+            }
+            // rotation coefficients (Ritz vectors y < NK) and arrowhead couplings
+            for (int x = 0; x < NM; ++x)
+                for (int y = 0; y < NK; ++y) Crot[((size_t)c * NM + x) * NK + y] = V[(size_t)x * NM + y];
+            for (int y = 0; y < NK; ++y) {
+                coup[c][y] = bm * V[(size_t)(NM - 1) * NM + y];
+                al[c][y] = e[y];
+            }
+            double mr = 0;
+            for (size_t y = 0; y < lv.size(); ++y) {
+                evals[(size_t)c * nev + y] = e[lv[y]];
+                mr = std::max(mr, res[lv[y]]);
+            }
+            info[c].n_found = (int)lv.size();
+            info[c].max_residual = mr;
+            info[c].n_restarts = restarts;
+            final_lv[c] = lv;
+            if (allc) {
+                info[c].converged = 1;
+            } else {
+                any_active = true;
+            }
+        }
+        // Ritz vectors into slots NM+1.., then back into 0..NK-1; residual to NK
+        QS3_TRY(E.rotate(0, NM, Crot, NK, NM + 1, active.data()));
+        for (int y = 0; y < NK; ++y) QS3_TRY(E.copy_slot(NM + 1 + y, y, active.data()));
+        for (int c = 0; c < B; ++c)
+            if (info[c].converged) active[c] = 0;
+        if (!any_active || restarts >= o.max_restarts) break;
+        QS3_TRY(E.copy_slot(NM, NK, active.data()));
+        // restart cycle: x = NK (no three-term partner: the couplings to the
+        // kept Ritz vectors are removed by the full reorthogonalisation), then
+        // x = NK+1..NM-1
+        QS3_TRY(E.step(NK, -1));
+        for (int x = NK + 1; x < NM; ++x) QS3_TRY(E.step(x, x - 1));
+        QS3_TRY(E.read_ab(NK, NM, a, bb));
+        for (int c = 0; c < B; ++c)
+            for (int x = NK; x < NM; ++x) {
+                al[c][x] = a[(size_t)x * B + c];
+                be[c][x] = bb[(size_t)x * B + c];
+            }
+        first = false;
+        ++restarts;
+    }
+    for (int c = 0; c < B; ++c) info[c].n_matvec = E.n_matvec;
+    if (want_vecs) {
+        // the wanted levels' Ritz vectors are slots final_lv (single column use)
+        for (int y = 0; y < nev && y < (int)final_lv[0].size(); ++y)
+            QS3_HIP(hipMemcpyAsync(vec_out + (size_t)y * E.stride, E.slot(final_lv[0][y]),
+                                   sizeof(double) * E.stride, hipMemcpyDeviceToDevice, E.st));
+    }
+    return QS3_OK;
+}
+
+}  // namespace qs3

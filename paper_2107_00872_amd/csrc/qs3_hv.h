@@ -1,0 +1,49 @@
+// Kernel argument blocks and the per-N_down entry points of the H.v kernels
+// (each N_down is instantiated in its own translation unit, hv_inst.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "qs3_impl.h"
+
+namespace qs3 {
+
+struct BatchArgs {
+    LatArgs L;
+    uint64_t n_reps;
+    const uint64_t *reps;
+    const uint16_t *stab;
+    const int32_t *nt_of;
+    const uint8_t *compat_nt;
+    const uint64_t *table;
+    const uint32_t *dir;
+    int dir_shift;
+    int B, G;
+    const int32_t *kmul;  // 3*B: K_a * (M / L_a) mod M
+    int M;
+    double invM;
+    const double2 *phase;  // e^{2 pi i P / M}
+};
+
+struct BuildArgs {
+    LatArgs L;
+    uint64_t D;
+    uint64_t chunk;  // ranks per block
+};
+
+BatchArgs batch_args(qs3_batch *bat);
+int grid_for(qs3_ctx *ctx, uint64_t tiles);
+
+template <int K>
+int hv_u1_K(qs3_sector *sec, const void *v, int vtype, void *w, int wtype, hipStream_t s);
+template <int K>
+int row_u1_K(qs3_sector *sec, uint64_t row, int cap, int64_t *cols, double *vals, double *diag,
+             int *nnz);
+template <int K>
+int hv_batch_K(qs3_batch *bat, const void *v, int vtype, void *w, int wtype, hipStream_t s);
+template <int K>
+int row_k_K(qs3_sector *sec, uint64_t u, int cap, int64_t *cols, double *vals, double *diag,
+            int *nnz);
+template <int K>
+int build_kstruct_K(qs3_lattice *lat, const BinomTable &bt, KStructure *ks, hipStream_t s);
+
+}  // namespace qs3

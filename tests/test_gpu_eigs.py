@@ -1,0 +1,116 @@
+"""GPU eigensolvers (Alg. 10) against dense diagonalisation by the oracle.
+
+Eigenvalue tolerance: 1e-10 relative for float64, 1e-5 relative for the
+float32-matvec variant (float64 recurrence).
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import native as orc
+from oracle.hamiltonian import bonds_1based, gen_full_ham
+from oracle.lanczos import lowest_distinct, lanczos as orc_lanczos
+from oracle.rng import start_vector as orc_start
+from oracle.translation import Geometry, mk_list, gen_full_ham_sym_adapt
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qs3():
+    from paper_2107_00872_amd import qs3 as q
+    orc.build(force=False)
+    return q
+
+
+@pytest.fixture(scope="module")
+def ctx(qs3):
+    return qs3.Context(0)
+
+
+def dense_u1(lat, K):
+    return gen_full_ham(lat.n_sites, K, bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz))
+
+
+def test_c1_lanczos_100_steps(qs3, ctx):
+    """C1: chain 16, N_down = 3, 100 Lanczos steps from the seeded start vector:
+    the 4 lowest distinct levels match dense diagonalisation to 1e-10, and the
+    alpha/beta sequence matches the oracle's Lanczos from the same vector."""
+    lat = wl.chain(16)
+    L = qs3.Lattice.of(ctx, lat)
+    sec = qs3.Sector(L, 3)
+    H = dense_u1(lat, 3)
+    ref = lowest_distinct(np.linalg.eigvalsh(H), 4)
+    res = sec.eigs(nev=4, alg=qs3.ALG_LANCZOS, steps=100, seed=1)
+    assert res.status == qs3.QS3_OK
+    assert np.allclose(res.evals, ref, rtol=1e-10, atol=0)
+    a, b, n0, done = sec.lanczos(100, seed=1)
+    v0 = orc_start(1, np.arange(560), complex_=False)
+    oa, ob, _ = orc_lanczos(lambda x: H @ x, v0, 100)
+    assert n0 == pytest.approx(np.linalg.norm(v0), rel=1e-14)
+    # early coefficients agree tightly; later ones drift only at rounding level
+    assert np.abs(a[:30] - oa[:30]).max() < 1e-10
+    assert np.abs(b[:30] - ob[:30]).max() < 1e-10
+    # float32 matvec variant
+    r32 = sec.eigs(nev=4, alg=qs3.ALG_LANCZOS, steps=100, seed=1, precision=qs3.PREC_F32MV, tol=1e-5)
+    assert np.allclose(r32.evals, ref, rtol=1e-5, atol=0)
+
+
+@pytest.mark.parametrize("lat,K,nev", [(wl.chain(16), 3, 4), (wl.square(4), 4, 3),
+                                       (wl.with_disorder(wl.chain(14), 2), 4, 3), (wl.square(6), 2, 5)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_trl_u1_vs_dense(qs3, ctx, lat, K, nev):
+    L = qs3.Lattice.of(ctx, lat)
+    sec = qs3.Sector(L, K)
+    H = dense_u1(lat, K)
+    ref = lowest_distinct(np.linalg.eigvalsh(H), nev)
+    X = torch.empty(nev * sec.dim, dtype=torch.float64, device="cuda")
+    res = sec.eigs(nev=nev, alg=qs3.ALG_TRL, seed=2, evecs=X)
+    assert res.status == qs3.QS3_OK, res.info.max_residual
+    assert np.allclose(res.evals, ref, rtol=1e-10, atol=1e-12)
+    Xh = X.cpu().numpy().reshape(nev, sec.dim)
+    for y in range(nev):
+        r = H @ Xh[y] - res.evals[y] * Xh[y]
+        assert np.linalg.norm(r) < 1e-7 and abs(np.linalg.norm(Xh[y]) - 1) < 1e-10
+
+
+@pytest.mark.parametrize("lat,K", [(wl.square(4), 3), (wl.chain(12), 4), (wl.hypercubic(4, 2, 1), 3)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_trl_k_vs_dense(qs3, ctx, lat, K):
+    L = qs3.Lattice.of(ctx, lat)
+    geo = Geometry(*lat.dims)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    for Kv in wl.all_momenta(lat)[:4]:
+        s, R = mk_list(geo, K, Kv)
+        if len(s) < 4:
+            continue
+        Hk = gen_full_ham_sym_adapt(geo, K, bonds, s, R, Kv)
+        nev = 2
+        ref = lowest_distinct(np.linalg.eigvalsh(Hk), nev)
+        sec = qs3.Sector(L, K, Kv)
+        X = torch.empty(nev * sec.dim, dtype=torch.complex128, device="cuda")
+        res = sec.eigs(nev=nev, alg=qs3.ALG_TRL, seed=3, evecs=X)
+        assert np.allclose(res.evals[:len(ref)], ref, rtol=1e-10, atol=1e-12)
+        Xh = X.cpu().numpy().reshape(nev, sec.dim)
+        r = Hk @ Xh[0] - res.evals[0] * Xh[0]
+        assert np.linalg.norm(r) < 1e-7
+        sec.close()
+
+
+def test_batch_eigs_all_k(qs3, ctx):
+    """Every momentum sector of the 6x6 square at N_down = 3 in one batch: the
+    lowest two distinct levels per sector match dense diagonalisation."""
+    lat = wl.square(6)
+    L = qs3.Lattice.of(ctx, lat)
+    ks = wl.all_momenta(lat)
+    bat = qs3.Batch(L, 3, ks)
+    ev, infos, rc = bat.eigs(nev=2, alg=qs3.ALG_TRL, seed=5)
+    assert rc == qs3.QS3_OK
+    geo = Geometry(*lat.dims)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    for b, Kv in enumerate(ks[::5]):
+        s, R = orc.mk_list(lat.dims, 3, Kv)
+        Hk = gen_full_ham_sym_adapt(geo, 3, bonds, list(map(int, s)), list(R), Kv)
+        ref = lowest_distinct(np.linalg.eigvalsh(Hk), 2)
+        assert np.allclose(ev[ks.index(Kv)], ref, rtol=1e-10, atol=1e-12)
