@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "hv_kernels.h"
+#include "obs_kernels.h"
 
 #ifndef QS3_INST_K
 #error "QS3_INST_K must be defined"
@@ -92,6 +93,68 @@ int row_u1_K<KI>(qs3_sector *sec, uint64_t row, int cap, int64_t *cols, double *
         if (sec->bt->wide) return row_u1_t<uint64_t>(sec, row, cap, cols, vals, diag, nnz);
     }
     return row_u1_t<uint32_t>(sec, row, cap, cols, vals, diag, nnz);
+}
+
+
+// ------------------------------------------------------------------ observables (fixed N_down)
+template <typename RT>
+static int obs_u1_t(qs3_sector *sec, const double *phi, int npairs, const int32_t *pi,
+                    const int32_t *pj, std::vector<double> &p_site, std::vector<double> &q,
+                    std::vector<double> &pm, hipStream_t s) {
+    constexpr int K = KI;
+    qs3_lattice *lat = sec->lat;
+    const int N = lat->N;
+    LatArgs L = lat_args(lat);
+    const RT *tab = sec->bt->dev.as<RT>();
+    const BinomTable &bt = *sec->bt;
+    p_site.assign(N, 0.0);
+    q.assign(npairs, 0.0);
+    pm.assign(npairs, 0.0);
+    if (K == 0) return QS3_OK;
+    {
+        const uint64_t cnt = bt.C(N - 1, K - 1);
+        const int nchunk = (int)std::max<uint64_t>(1, std::min<uint64_t>((cnt + 4095) / 4096, (2048 + N - 1) / N));
+        DevBuf part;
+        QS3_TRY(part.alloc(lat->ctx, sizeof(double2) * (size_t)N * nchunk));
+        hipLaunchKernelGGL((k_site_prob<K, RT>), dim3(N, nchunk), dim3(256), 0, s, L, tab, cnt, nchunk,
+                           phi, part.as<double2>());
+        QS3_HIP(hipGetLastError());
+        std::vector<double2> h((size_t)N * nchunk);
+        QS3_HIP(hipMemcpyAsync(h.data(), part.ptr, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, s));
+        QS3_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < N; ++i)
+            for (int c = 0; c < nchunk; ++c) p_site[i] += h[(size_t)i * nchunk + c].x;
+    }
+    if (npairs > 0) {
+        const uint64_t cq = K >= 2 ? bt.C(N - 2, K - 2) : 0, cpm = bt.C(N - 2, K - 1);
+        const uint64_t cmax = std::max(cq, cpm);
+        const int nchunk = (int)std::max<uint64_t>(1, std::min<uint64_t>((cmax + 4095) / 4096,
+                                                                          (4096 + npairs - 1) / npairs));
+        DevBuf part;
+        QS3_TRY(part.alloc(lat->ctx, sizeof(double2) * (size_t)npairs * nchunk));
+        hipLaunchKernelGGL((k_pair_u1<K, RT>), dim3(npairs, nchunk), dim3(256), 0, s, L, tab, pi, pj, cq,
+                           cpm, nchunk, phi, part.as<double2>());
+        QS3_HIP(hipGetLastError());
+        std::vector<double2> h((size_t)npairs * nchunk);
+        QS3_HIP(hipMemcpyAsync(h.data(), part.ptr, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, s));
+        QS3_HIP(hipStreamSynchronize(s));
+        for (int p = 0; p < npairs; ++p)
+            for (int c = 0; c < nchunk; ++c) {
+                q[p] += h[(size_t)p * nchunk + c].x;
+                pm[p] += h[(size_t)p * nchunk + c].y;
+            }
+    }
+    return QS3_OK;
+}
+
+template <>
+int obs_u1_K<KI>(qs3_sector *sec, const double *phi, int npairs, const int32_t *pi,
+                 const int32_t *pj, std::vector<double> &p_site, std::vector<double> &q,
+                 std::vector<double> &pm, hipStream_t s) {
+    if constexpr (WIDE_OK) {
+        if (sec->bt->wide) return obs_u1_t<uint64_t>(sec, phi, npairs, pi, pj, p_site, q, pm, s);
+    }
+    return obs_u1_t<uint32_t>(sec, phi, npairs, pi, pj, p_site, q, pm, s);
 }
 
 #if QS3_INST_K <= 6
@@ -187,6 +250,103 @@ int row_k_K<KI>(qs3_sector *sec, uint64_t u, int cap, int64_t *cols, double *val
     return tabm ? row_k_t<uint32_t, true>(sec, u, cap, cols, vals, diag, nnz)
                 : row_k_t<uint32_t, false>(sec, u, cap, cols, vals, diag, nnz);
 }
+
+
+// ------------------------------------------------------------------ momentum observables
+template <typename RT, bool TABLE>
+static int corr_k_t(qs3_sector *sec, const double *phi_union, int ndisp, const int32_t *disp,
+                    std::vector<double> &zz, std::vector<double> &nrm, std::vector<double> &pr,
+                    std::vector<double> &pim, hipStream_t s) {
+    qs3_batch *bat = sec->bat;
+    BatchArgs A = batch_args(bat);
+    const int nchunk = (int)std::max<uint64_t>(1, std::min<uint64_t>((A.n_reps + 1023) / 1024,
+                                                                      (2048 + ndisp - 1) / ndisp));
+    DevBuf part;
+    QS3_TRY(part.alloc(sec->lat->ctx, sizeof(double2) * 2 * (size_t)ndisp * nchunk));
+    hipLaunchKernelGGL((k_corr_k<KI, RT, TABLE>), dim3(ndisp, nchunk), dim3(256), 0, s, A,
+                       bat->bt->dev.as<RT>(), disp, nchunk, (const double2 *)phi_union,
+                       part.as<double2>());
+    QS3_HIP(hipGetLastError());
+    std::vector<double2> h(2 * (size_t)ndisp * nchunk);
+    QS3_HIP(hipMemcpyAsync(h.data(), part.ptr, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, s));
+    QS3_HIP(hipStreamSynchronize(s));
+    zz.assign(ndisp, 0.0);
+    nrm.assign(ndisp, 0.0);
+    pr.assign(ndisp, 0.0);
+    pim.assign(ndisp, 0.0);
+    for (int d = 0; d < ndisp; ++d)
+        for (int c = 0; c < nchunk; ++c) {
+            const double2 a = h[((size_t)d * nchunk + c) * 2], b = h[((size_t)d * nchunk + c) * 2 + 1];
+            zz[d] += a.x;
+            nrm[d] += a.y;
+            pr[d] += b.x;
+            pim[d] += b.y;
+        }
+    return QS3_OK;
+}
+
+template <>
+int corr_k_K<KI>(qs3_sector *sec, const double *phi_union, int ndisp, const int32_t *disp,
+                 std::vector<double> &zz, std::vector<double> &nrm, std::vector<double> &pr,
+                 std::vector<double> &pim, hipStream_t s) {
+    const bool tabm = sec->bat->ks->has_table;
+    if constexpr (WIDE_OK) {
+        if (sec->bat->bt->wide)
+            return tabm ? corr_k_t<uint64_t, true>(sec, phi_union, ndisp, disp, zz, nrm, pr, pim, s)
+                        : corr_k_t<uint64_t, false>(sec, phi_union, ndisp, disp, zz, nrm, pr, pim, s);
+    }
+    return tabm ? corr_k_t<uint32_t, true>(sec, phi_union, ndisp, disp, zz, nrm, pr, pim, s)
+                : corr_k_t<uint32_t, false>(sec, phi_union, ndisp, disp, zz, nrm, pr, pim, s);
+}
+
+#if QS3_INST_K <= 5
+template <typename RTa, typename RTb, bool TABLE>
+static int smq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+                 double *out, hipStream_t s) {
+    SmqArgs S{batch_args(src), batch_args(dst), qmul};
+    const int G = S.dst.G, B = S.dst.B;
+    const int per = (B + G - 1) / G;
+    const uint64_t rows_per = 256 / G;
+    const unsigned grid = (unsigned)((S.dst.n_reps + rows_per - 1) / rows_per);
+    const RTa *ta = src->bt->dev.as<RTa>();
+    const RTb *tb = dst->bt->dev.as<RTb>();
+#define QS3_SMQ(BPL)                                                                                  \
+    hipLaunchKernelGGL((k_smq<KI, RTa, RTb, TABLE, BPL>), dim3(grid), dim3(256), 0, s, S, ta, tb,      \
+                       (const double2 *)phi, (double2 *)out)
+    if (per <= 1) QS3_SMQ(1);
+    else if (per <= 2) QS3_SMQ(2);
+    else if (per <= 4) QS3_SMQ(4);
+    else if (per <= 16) QS3_SMQ(16);
+    else {
+        set_error("at most 1024 momenta per S^-_q batch");
+        return QS3_EINVAL;
+    }
+#undef QS3_SMQ
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+template <typename RTa, typename RTb>
+static int smq_mode(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+                    double *out, hipStream_t s) {
+    if (src->ks->has_table) return smq_t<RTa, RTb, true>(src, dst, qmul, phi, out, s);
+    return smq_t<RTa, RTb, false>(src, dst, qmul, phi, out, s);
+}
+
+template <>
+int smq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+              double *out, hipStream_t s) {
+    const bool wa = src->bt->wide, wb = dst->bt->wide;
+    if constexpr (KI >= 3) {
+        if (wa && wb) return smq_mode<uint64_t, uint64_t>(src, dst, qmul, phi, out, s);
+    }
+    if constexpr (KI >= 2) {
+        if (!wa && wb) return smq_mode<uint32_t, uint64_t>(src, dst, qmul, phi, out, s);
+    }
+    QS3_REQUIRE(!wa && !wb, QS3_EINVAL, "internal: rank width");
+    return smq_mode<uint32_t, uint32_t>(src, dst, qmul, phi, out, s);
+}
+#endif
 
 // ------------------------------------------------------------------ structure build
 template <typename RT>

@@ -25,17 +25,20 @@ namespace qs3 {
 
 // ------------------------------------------------------------------ geometry of reductions
 static RedGeom red_geom(uint64_t n, int B) {
+    // about 1024 blocks per reduction launch (4 per CU); chunk rows are a
+    // multiple of the block's row count
     RedGeom g;
     g.n = n;
     g.B = B;
     g.TC = 1;
     while (g.TC < B && g.TC < 64) g.TC <<= 1;
     g.TR = 256 / g.TC;
-    uint64_t rc = std::max<uint64_t>((uint64_t)g.TR * 8, (n + 1023) / 1024);
+    g.ncoltile = (B + g.TC - 1) / g.TC;
+    const uint64_t want = std::max<uint64_t>(1, 1024 / g.ncoltile);
+    uint64_t rc = std::max<uint64_t>((uint64_t)g.TR, (n + want - 1) / want);
     rc = (rc + g.TR - 1) / g.TR * g.TR;
     g.RC = rc;
     g.nchunk = (int)std::max<uint64_t>(1, (n + rc - 1) / rc);
-    g.ncoltile = (B + g.TC - 1) / g.TC;
     return g;
 }
 
@@ -59,47 +62,54 @@ __device__ __forceinline__ void cdot_acc(double2 x, double2 y, double &sr, doubl
 }
 
 // ------------------------------------------------------------------ kernels
-// partial[(chunk * J + j) * B + b] (re, im) = sum over the chunk's rows of
-// conj(X_j[r, b]) * Y[r, b], for j < J (X_j = X + j * stride).
+// partial[(chunk * JO + j) * B + b] (re, im) = sum over the chunk's rows of
+// conj(X_j[r, b]) * Y[r, b] for j < J (X_j = X + j * stride) and, when
+// selfdot, |Y[r, b]|^2 at j = J (JO = J + selfdot outputs).  Columns with
+// mask[b] == 0 are skipped (their partials are written as zero).
 template <bool CPLX, int JT>
 __global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__restrict__ X,
-                                                  uint64_t stride, int J, const double *__restrict__ Y,
+                                                  uint64_t stride, int J, int selfdot,
+                                                  const double *__restrict__ Y,
+                                                  const uint8_t *__restrict__ mask,
                                                   double2 *__restrict__ partial) {
     using T = typename Elem<CPLX>::T;
     const int tc = threadIdx.x % g.TC, tr = threadIdx.x / g.TC;
     const int b = blockIdx.y * g.TC + tc;
     const uint64_t r0 = (uint64_t)blockIdx.x * g.RC;
     const uint64_t r1 = min(g.n, r0 + g.RC);
-    __shared__ double2 red[256][JT > 4 ? 4 : JT];
+    const int JO = J + selfdot;
+    const bool on = b < g.B && (!mask || mask[b]);
+    __shared__ double2 red[256][4];
     const T *Yt = (const T *)Y;
-    for (int j0 = 0; j0 < J; j0 += JT) {
+    for (int j0 = 0; j0 < JO; j0 += JT) {
         double sr[JT], si[JT];
 #pragma unroll
         for (int q = 0; q < JT; ++q) sr[q] = si[q] = 0.0;
-        if (b < g.B) {
+        if (on) {
             for (uint64_t r = r0 + tr; r < r1; r += g.TR) {
                 const uint64_t e = r * g.B + b;
                 const T y = Yt[e];
 #pragma unroll
                 for (int q = 0; q < JT; ++q) {
-                    if (j0 + q < J) {
-                        const T x = ((const T *)(X + (size_t)(j0 + q) * stride))[e];
+                    const int jj = j0 + q;
+                    if (jj < J) {
+                        const T x = ((const T *)(X + (size_t)jj * stride))[e];
                         cdot_acc(x, y, sr[q], si[q]);
+                    } else if (jj == J && selfdot) {
+                        cdot_acc(y, y, sr[q], si[q]);
                     }
                 }
             }
         }
-        // tree over tr, four j at a time through LDS
 #pragma unroll
         for (int q0 = 0; q0 < JT; q0 += 4) {
-            constexpr int W = JT > 4 ? 4 : JT;
 #pragma unroll
-            for (int q = 0; q < W; ++q) red[threadIdx.x][q] = make_double2(sr[q0 + q], si[q0 + q]);
+            for (int q = 0; q < 4; ++q) red[threadIdx.x][q] = make_double2(sr[q0 + q], si[q0 + q]);
             __syncthreads();
             for (int s = g.TR / 2; s > 0; s >>= 1) {
                 if (tr < s) {
 #pragma unroll
-                    for (int q = 0; q < W; ++q) {
+                    for (int q = 0; q < 4; ++q) {
                         double2 a = red[threadIdx.x][q], c = red[threadIdx.x + s * g.TC][q];
                         red[threadIdx.x][q] = make_double2(a.x + c.x, a.y + c.y);
                     }
@@ -108,27 +118,96 @@ __global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__res
             }
             if (tr == 0 && b < g.B) {
 #pragma unroll
-                for (int q = 0; q < W; ++q)
-                    if (j0 + q0 + q < J)
-                        partial[((size_t)blockIdx.x * J + j0 + q0 + q) * g.B + b] = red[threadIdx.x][q];
+                for (int q = 0; q < 4; ++q)
+                    if (j0 + q0 + q < JO)
+                        partial[((size_t)blockIdx.x * JO + j0 + q0 + q) * g.B + b] = red[threadIdx.x][q];
             }
             __syncthreads();
         }
     }
 }
 
-// out[j * B + b] = sum_chunk partial[(chunk * J + j) * B + b], fixed order.
-__global__ void k_reduce_chunks(const double2 *__restrict__ partial, int nchunk, int JB,
-                                double2 *__restrict__ out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// W -= sum_{j<J} X_j h[j * B + b] on the columns with mask[b] != 0 (all when
+// mask is null), and partial[chunk * B + b] = sum over the chunk's rows of
+// |W|^2 after the update (the norm for beta, fused into the same pass).
+template <bool CPLX>
+__global__ __launch_bounds__(256) void k_cgs_update_norm(RedGeom g, double *__restrict__ W,
+                                                         const double *__restrict__ X, uint64_t stride,
+                                                         int J, const double2 *__restrict__ h,
+                                                         const uint8_t *__restrict__ mask,
+                                                         double2 *__restrict__ partial) {
+    using T = typename Elem<CPLX>::T;
+    const int tc = threadIdx.x % g.TC, tr = threadIdx.x / g.TC;
+    const int b = blockIdx.y * g.TC + tc;
+    const uint64_t r0 = (uint64_t)blockIdx.x * g.RC;
+    const uint64_t r1 = min(g.n, r0 + g.RC);
+    const bool on = b < g.B && (!mask || mask[b]);
+    double acc = 0.0;
+    if (on) {
+        for (uint64_t r = r0 + tr; r < r1; r += g.TR) {
+            const uint64_t e = r * g.B + b;
+            if (CPLX) {
+                double2 w = ((double2 *)W)[e];
+                for (int jj = 0; jj < J; ++jj) {
+                    const double2 x = ((const double2 *)(X + (size_t)jj * stride))[e];
+                    const double2 c = h[(size_t)jj * g.B + b];
+                    w.x -= x.x * c.x - x.y * c.y;
+                    w.y -= x.x * c.y + x.y * c.x;
+                }
+                ((double2 *)W)[e] = w;
+                acc += w.x * w.x + w.y * w.y;
+            } else {
+                double w = W[e];
+                for (int jj = 0; jj < J; ++jj) w -= X[(size_t)jj * stride + e] * h[(size_t)jj * g.B + b].x;
+                W[e] = w;
+                acc += w * w;
+            }
+        }
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = g.TR / 2; s > 0; s >>= 1) {
+        if (tr < s) red[threadIdx.x] += red[threadIdx.x + s * g.TC];
+        __syncthreads();
+    }
+    if (tr == 0 && b < g.B) partial[(size_t)blockIdx.x * g.B + b] = make_double2(red[threadIdx.x], 0.0);
+}
+
+// second Gram-Schmidt pass where the first one cancelled more than half of
+// |W|^2 (Daniel-Gragg-Kaufman-Stewart criterion, eta^2 = 1/2)
+__global__ void k_dgks_flag(int B, const double2 *__restrict__ before, const double2 *__restrict__ after,
+                            uint8_t *__restrict__ flag) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) flag[b] = after[b].x < 0.5 * before[b].x ? 1 : 0;
+}
+
+__global__ void k_merge_norm(int B, const uint8_t *__restrict__ flag, const double2 *__restrict__ n2,
+                             double2 *__restrict__ n1) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B && flag[b]) n1[b] = n2[b];
+}
+
+// out[j * B + b] = sum_chunk partial[(chunk * J + j) * B + b]: one wavefront
+// per output, lanes take chunks lane, lane+64, ... in order, then a fixed
+// shuffle tree -- deterministic for a given chunking.
+__global__ __launch_bounds__(256) void k_reduce_chunks(const double2 *__restrict__ partial, int nchunk,
+                                                       int JB, double2 *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= JB) return;
     double sr = 0, si = 0;
-    for (int c = 0; c < nchunk; ++c) {
+    for (int c = lane; c < nchunk; c += 64) {
         double2 p = partial[(size_t)c * JB + i];
         sr += p.x;
         si += p.y;
     }
-    out[i] = make_double2(sr, si);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sr += __shfl_down(sr, off, 64);
+        si += __shfl_down(si, off, 64);
+    }
+    if (lane == 0) out[i] = make_double2(sr, si);
 }
 
 // W -= alpha[b] * P0 (+ beta[b] * P1 when P1 != null); alpha, beta real per column.
@@ -463,12 +542,12 @@ int Engine::init(qs3_ctx *c, Operator *o, int slots_, int precision_, int reorth
     QS3_TRY(W.alloc(ctx, sizeof(double) * stride));
     if (precision == QS3_PREC_F32MV) QS3_TRY(X32.alloc(ctx, sizeof(float) * stride));
     const int maxJ = slots;
-    QS3_TRY(partial.alloc(ctx, sizeof(double2) * (size_t)rg.nchunk * maxJ * B));
-    QS3_TRY(hvec.alloc(ctx, sizeof(double2) * (size_t)maxJ * B));
+    QS3_TRY(partial.alloc(ctx, sizeof(double2) * (size_t)rg.nchunk * (maxJ + 1) * B));
+    QS3_TRY(hvec.alloc(ctx, sizeof(double2) * (size_t)(maxJ + 1) * B));
     QS3_TRY(alpha.alloc(ctx, sizeof(double2) * (size_t)B));
     QS3_TRY(nrm2.alloc(ctx, sizeof(double2) * (size_t)B));
     QS3_TRY(ab_hist.alloc(ctx, sizeof(double) * 2 * (size_t)slots * B));
-    QS3_TRY(act.alloc(ctx, (size_t)B + 8));
+    QS3_TRY(act.alloc(ctx, 2 * (size_t)B + 16));
     return QS3_OK;
 }
 
@@ -483,27 +562,47 @@ int Engine::apply(const double *x, double *y) {
     return op->apply(x, y, st);
 }
 
-int Engine::multidot(const double *X, int J, const double *Y, double2 *out) {
+int Engine::multidot(const double *X, int J, const double *Y, double2 *out, int selfdot,
+                     const uint8_t *mask) {
     dim3 grid(rg.nchunk, rg.ncoltile);
-#define QS3_MD(CP)                                                                             \
-    hipLaunchKernelGGL((k_multidot<CP, 4>), grid, dim3(256), 0, st, rg, X, stride, J, Y,        \
-                       partial.as<double2>())
-    if (cplx) QS3_MD(true); else QS3_MD(false);
-#undef QS3_MD
+    const int JO = J + selfdot;
+    if (cplx)
+        hipLaunchKernelGGL((k_multidot<true, 8>), grid, dim3(256), 0, st, rg, X, stride, J, selfdot, Y,
+                           mask, partial.as<double2>());
+    else
+        hipLaunchKernelGGL((k_multidot<false, 8>), grid, dim3(256), 0, st, rg, X, stride, J, selfdot, Y,
+                           mask, partial.as<double2>());
     QS3_HIP(hipGetLastError());
-    int JB = J * B;
-    hipLaunchKernelGGL(k_reduce_chunks, grid1(JB), dim3(256), 0, st, partial.as<double2>(),
+    const int JB = JO * B;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((JB + 3) / 4), dim3(256), 0, st, partial.as<double2>(),
                        rg.nchunk, JB, out);
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }
 
+int Engine::cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double2 *nrm_out) {
+    dim3 grid(rg.nchunk, rg.ncoltile);
+    if (cplx)
+        hipLaunchKernelGGL((k_cgs_update_norm<true>), grid, dim3(256), 0, st, rg, W.as<double>(), slot(0),
+                           stride, J, h, mask, partial.as<double2>());
+    else
+        hipLaunchKernelGGL((k_cgs_update_norm<false>), grid, dim3(256), 0, st, rg, W.as<double>(), slot(0),
+                           stride, J, h, mask, partial.as<double2>());
+    QS3_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((B + 3) / 4), dim3(256), 0, st, partial.as<double2>(), rg.nchunk,
+                       B, nrm_out);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
 // One Lanczos step: slot x holds psi_x (normalised); writes alpha_x, beta_x and
-// psi_{x+1} into slot x+1.  prev: slot of psi_{x-1} or -1.  Reorthogonalises
-// against slots 0..x.
+// psi_{x+1} into slot x+1.  prev: slot of psi_{x-1} or -1.  Full
+// reorthogonalisation against slots 0..x by classical Gram-Schmidt, with a
+// second pass only for the columns whose first pass cancelled more than half
+// of |W|^2; the norm is fused into the update.
 int Engine::step(int x, int prev) {
     QS3_TRY(apply(slot(x), W.as<double>()));
-    QS3_TRY(multidot(slot(x), 1, W.as<double>(), alpha.as<double2>()));
+    QS3_TRY(multidot(slot(x), 1, W.as<double>(), alpha.as<double2>(), 0, nullptr));
     double *betap = ab_hist.as<double>() + (size_t)slots * B + (size_t)(prev < 0 ? 0 : prev) * B;
     if (cplx)
         hipLaunchKernelGGL(k_lanczos_update<true>, grid1(ne), dim3(256), 0, st, ne, B,
@@ -514,20 +613,26 @@ int Engine::step(int x, int prev) {
                            W.as<double>(), slot(x), prev >= 0 ? slot(prev) : nullptr,
                            alpha.as<double2>(), betap);
     QS3_HIP(hipGetLastError());
-    // store alpha_x
     hipLaunchKernelGGL(k_copy_re, grid1(B), dim3(256), 0, st, B, alpha.as<double2>(),
                        ab_hist.as<double>() + (size_t)x * B);
-    for (int pass = 0; pass < reorth; ++pass) {
-        QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), hvec.as<double2>()));
-        if (cplx)
-            hipLaunchKernelGGL(k_cgs_update<true>, grid1(ne), dim3(256), 0, st, ne, B,
-                               W.as<double>(), slot(0), stride, x + 1, hvec.as<double2>());
-        else
-            hipLaunchKernelGGL(k_cgs_update<false>, grid1(ne), dim3(256), 0, st, ne, B,
-                               W.as<double>(), slot(0), stride, x + 1, hvec.as<double2>());
-        QS3_HIP(hipGetLastError());
+    double2 *h = hvec.as<double2>();
+    double2 *n_before = h + (size_t)(x + 1) * B;  // the self-dot output of the first pass
+    if (reorth > 0) {
+        QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 1, nullptr));
+        QS3_TRY(cgs_update_norm(x + 1, h, nullptr, nrm2.as<double2>()));
+        if (reorth > 1) {
+            uint8_t *flag = act.as<uint8_t>() + 8 + B;
+            hipLaunchKernelGGL(k_dgks_flag, grid1(B), dim3(256), 0, st, B, n_before, nrm2.as<double2>(), flag);
+            QS3_HIP(hipGetLastError());
+            QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 0, flag));
+            double2 *n2 = h + (size_t)(x + 1) * B;
+            QS3_TRY(cgs_update_norm(x + 1, h, flag, n2));
+            hipLaunchKernelGGL(k_merge_norm, grid1(B), dim3(256), 0, st, B, flag, n2, nrm2.as<double2>());
+            QS3_HIP(hipGetLastError());
+        }
+    } else {
+        QS3_TRY(multidot(W.as<double>(), 1, W.as<double>(), nrm2.as<double2>(), 0, nullptr));
     }
-    QS3_TRY(multidot(W.as<double>(), 1, W.as<double>(), nrm2.as<double2>()));
     hipLaunchKernelGGL(k_sqrt_to, grid1(B), dim3(256), 0, st, B, nrm2.as<double2>(),
                        ab_hist.as<double>() + (size_t)slots * B + (size_t)x * B);
     if (cplx)
@@ -543,7 +648,7 @@ int Engine::step(int x, int prev) {
 
 // slot 0 := v0 / |v0|; norms0[b] = |v0|
 int Engine::normalize_into_slot0(const double *v0, std::vector<double> *norms0) {
-    QS3_TRY(multidot(v0, 1, v0, nrm2.as<double2>()));
+    QS3_TRY(multidot(v0, 1, v0, nrm2.as<double2>(), 0, nullptr));
     if (cplx)
         hipLaunchKernelGGL(k_scale_out<true>, grid1(ne), dim3(256), 0, st, ne, B, v0, slot(0),
                            nrm2.as<double2>());
@@ -587,10 +692,10 @@ int Engine::rotate(int from_slot, int NX, const std::vector<double> &Cm, int NY,
         actd = act.as<uint8_t>();
     }
     if (cplx)
-        hipLaunchKernelGGL((k_rotate<true, 8>), grid1(ne), dim3(256), 0, st, ne, B, slot(from_slot),
+        hipLaunchKernelGGL((k_rotate<true, 16>), grid1(ne), dim3(256), 0, st, ne, B, slot(from_slot),
                            stride, NX, dC.as<double>(), NY, slot(to_slot), actd);
     else
-        hipLaunchKernelGGL((k_rotate<false, 8>), grid1(ne), dim3(256), 0, st, ne, B, slot(from_slot),
+        hipLaunchKernelGGL((k_rotate<false, 16>), grid1(ne), dim3(256), 0, st, ne, B, slot(from_slot),
                            stride, NX, dC.as<double>(), NY, slot(to_slot), actd);
     QS3_HIP(hipGetLastError());
     QS3_HIP(hipStreamSynchronize(st));  // dC is released at return
@@ -628,8 +733,11 @@ static std::vector<int> pick_levels(const std::vector<double> &e, const std::vec
         const double sc = std::max(1.0, std::fabs(e[i]));
         const bool conv = res[i] <= tol * sc;
         if (!conv) {
-            *all_conv = false;
+            // fixed-step Lanczos: skip Ritz values that have not converged
+            // (e.g. partner copies of degenerate levels emerging from
+            // rounding); the restarted solver instead waits for them
             if (require_conv) continue;
+            *all_conv = false;
         }
         if (!out.empty() && std::fabs(e[i] - last) <= 1e-8 * sc) continue;
         out.push_back((int)i);

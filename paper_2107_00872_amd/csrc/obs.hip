@@ -1,15 +1,393 @@
-// Observables (Sec. 3.6, 4.2), S^-_q (Alg. 11) and the dynamical structure
-// factor (Sec. 3.9).
+// Observables (Sec. 3.6, Sec. 4.2), S^-_q (Sec. 3.8, Alg. 11) and the
+// continued-fraction dynamical structure factor (Sec. 3.9, Eq. (cfe)).
+// Device work runs in the gather kernels of obs_kernels.h; the host only sums
+// the per-block partials in a fixed order and evaluates Fourier sums and the
+// continued fraction (O(N^2 n_q) and O(steps n_omega) scalars).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <complex>
+#include <map>
+#include <numeric>
+#include <vector>
+
+#include "qs3_hv.h"
 #include "qs3_impl.h"
+#include "qs3_krylov.h"
+
+namespace qs3 {
+
+#define QS3_SW7(K, CALL)          \
+    switch (K) {                  \
+        case 0: return CALL(0);   \
+        case 1: return CALL(1);   \
+        case 2: return CALL(2);   \
+        case 3: return CALL(3);   \
+        case 4: return CALL(4);   \
+        case 5: return CALL(5);   \
+        case 6: return CALL(6);   \
+        case 7: return CALL(7);   \
+        case 8: return CALL(8);   \
+        default: break;           \
+    }                             \
+    set_error("N_down out of range"); \
+    return QS3_EINVAL;
+
+static int obs_u1(qs3_sector *sec, const double *phi, int npairs, const int32_t *pi, const int32_t *pj,
+                  std::vector<double> &p, std::vector<double> &q, std::vector<double> &pm, hipStream_t s) {
+#define QS3_OU1(k) obs_u1_K<k>(sec, phi, npairs, pi, pj, p, q, pm, s)
+    QS3_SW7(sec->K, QS3_OU1)
+#undef QS3_OU1
+}
+
+static int corr_k(qs3_sector *sec, const double *phi, int nd, const int32_t *disp, std::vector<double> &zz,
+                  std::vector<double> &nr, std::vector<double> &pr, std::vector<double> &pim, hipStream_t s) {
+#define QS3_CK(k) corr_k_K<(k > 6 ? 6 : k)>(sec, phi, nd, disp, zz, nr, pr, pim, s)
+    QS3_SW7(sec->K, QS3_CK)
+#undef QS3_CK
+}
+
+static int smq_any(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi, double *out,
+                   hipStream_t s) {
+#define QS3_SQ(k) smq_K<(k > 5 ? 5 : k)>(src, dst, qmul, phi, out, s)
+    QS3_REQUIRE(src->K <= 5, QS3_EINVAL, "S^-_q needs N_down + 1 <= 6");
+    QS3_SW7(src->K, QS3_SQ)
+#undef QS3_SQ
+}
+
+// ---- shared helpers
+static int vec_norm2(qs3_sector *sec, const void *vec, double *out, hipStream_t s) {
+    // |vec|^2 through the engine's deterministic reduction
+    struct NoOp : Operator {
+        uint64_t n;
+        bool c;
+        uint64_t rows() const override { return n; }
+        int cols() const override { return 1; }
+        bool is_complex() const override { return c; }
+        int apply(const double *, double *, hipStream_t) override { return QS3_EINVAL; }
+        int apply_f32in(const float *, double *, hipStream_t) override { return QS3_EINVAL; }
+    } op;
+    op.n = sec->dim;
+    op.c = sec->has_k;
+    Engine E;
+    QS3_TRY(E.init(sec->lat->ctx, &op, 1, QS3_PREC_F64, 0, s));
+    std::vector<double> nr;
+    QS3_TRY(E.normalize_into_slot0((const double *)vec, &nr));
+    *out = nr[0] * nr[0];
+    return QS3_OK;
+}
+
+// Translation-averaged correlations of a momentum-sector state for every
+// displacement d: Czz[d] = (1/N) <sum_r s^z_r s^z_{r+d}>,
+// Cpm[d] = (1/N) <sum_r s^+_r s^-_{r+d}> (Sec. 3.6).
+static int k_correlations(qs3_sector *sec, const void *vec, std::vector<double> &Czz,
+                          std::vector<std::complex<double>> &Cpm, hipStream_t s) {
+    qs3_lattice *lat = sec->lat;
+    const int N = lat->N;
+    DevBuf un, dd;
+    QS3_TRY(un.alloc(lat->ctx, sizeof(double) * 2 * std::max<uint64_t>(sec->bat->ks->n_reps, 1)));
+    QS3_TRY(scatter_compact(sec, (const double *)vec, un.as<double>(), s));
+    std::vector<int32_t> disp(N);
+    for (int d = 0; d < N; ++d) {
+        int x = d % lat->lx, y = (d / lat->lx) % lat->ly, z = d / (lat->lx * lat->ly);
+        disp[d] = x | (y << 10) | (z << 20);
+    }
+    QS3_TRY(dd.alloc(lat->ctx, sizeof(int32_t) * N));
+    QS3_HIP(hipMemcpyAsync(dd.ptr, disp.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
+    std::vector<double> zz, nr, pr, pim;
+    QS3_TRY(corr_k(sec, un.as<double>(), N, dd.as<int32_t>(), zz, nr, pr, pim, s));
+    const double n2 = nr[0];
+    QS3_REQUIRE(n2 > 0 && std::isfinite(n2), QS3_ENUMERIC, "zero or non-finite state");
+    const int K = sec->K;
+    Czz.assign(N, 0.0);
+    Cpm.assign(N, 0.0);
+    for (int d = 0; d < N; ++d) {
+        if (d == 0) {
+            Czz[d] = 0.25;
+            Cpm[d] = 0.5 + (0.5 * N - K) / N;  // s^+_r s^-_r = 1/2 + s^z_r
+        } else {
+            Czz[d] = (0.25 * N - K + zz[d] / n2) / N;
+            Cpm[d] = std::complex<double>(pr[d], pim[d]) / (n2 * N);
+        }
+    }
+    return QS3_OK;
+}
+
+static void coords_of(const qs3_lattice *lat, int s, int &x, int &y, int &z) {
+    x = s % lat->lx;
+    y = (s / lat->lx) % lat->ly;
+    z = s / (lat->lx * lat->ly);
+}
+
+static int disp_index(const qs3_lattice *lat, int i, int j) {
+    int xi, yi, zi, xj, yj, zj;
+    coords_of(lat, i, xi, yi, zi);
+    coords_of(lat, j, xj, yj, zj);
+    int dx = (xj - xi + lat->lx) % lat->lx, dy = (yj - yi + lat->ly) % lat->ly,
+        dz = (zj - zi + lat->lz) % lat->lz;
+    return dx + lat->lx * (dy + lat->ly * dz);
+}
+
+}  // namespace qs3
 
 using namespace qs3;
 
 extern "C" {
-int qs3_sz(qs3_sector *, const void *, double *, void *) { set_error("not built yet"); return QS3_EINVAL; }
-int qs3_sisj(qs3_sector *, const void *, int, const int32_t *, const int32_t *, double *, double *, void *) { set_error("not built yet"); return QS3_EINVAL; }
-int qs3_sq(qs3_sector *, const void *, int, const double *, double *, double *, double *, void *) { set_error("not built yet"); return QS3_EINVAL; }
-int qs3_smq(qs3_sector *, const void *, qs3_sector *, const int32_t *, void *, void *) { set_error("not built yet"); return QS3_EINVAL; }
-int qs3_dsf(qs3_sector *, const void *, double, int, const int32_t *, const qs3_dsf_opts *, int, const double *, double *, double *, double *, double *, void *) { set_error("not built yet"); return QS3_EINVAL; }
+
+int qs3_sz(qs3_sector *sec, const void *vec, double *out, void *stream) {
+    QS3_REQUIRE(sec && vec && out, QS3_EINVAL, "NULL argument");
+    hipSetDevice(sec->lat->ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int N = sec->lat->N;
+    double n2 = 0;
+    QS3_TRY(vec_norm2(sec, vec, &n2, s));
+    QS3_REQUIRE(n2 > 0 && std::isfinite(n2), QS3_ENUMERIC, "zero or non-finite state");
+    if (sec->has_k) {
+        // the translation-averaged s^z_r is (1/N) sum_r s^z_r = M / N in the sector
+        for (int i = 0; i < N; ++i) out[i] = (0.5 * N - sec->K) / N;
+        return QS3_OK;
+    }
+    std::vector<double> p, q, pm;
+    QS3_TRY(obs_u1(sec, (const double *)vec, 0, nullptr, nullptr, p, q, pm, s));
+    for (int i = 0; i < N; ++i) out[i] = 0.5 - p[i] / n2;
+    return QS3_OK;
 }
+
+int qs3_sisj(qs3_sector *sec, const void *vec, int n_pairs, const int32_t *pi, const int32_t *pj,
+             double *zz, double *pm, void *stream) {
+    QS3_REQUIRE(sec && vec && (n_pairs == 0 || (pi && pj && zz && pm)), QS3_EINVAL, "NULL argument");
+    hipSetDevice(sec->lat->ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int N = sec->lat->N;
+    for (int p = 0; p < n_pairs; ++p)
+        QS3_REQUIRE(pi[p] >= 0 && pi[p] < N && pj[p] >= 0 && pj[p] < N, QS3_EINVAL, "site out of range");
+    if (sec->has_k) {
+        std::vector<double> Czz;
+        std::vector<std::complex<double>> Cpm;
+        QS3_TRY(k_correlations(sec, vec, Czz, Cpm, s));
+        for (int p = 0; p < n_pairs; ++p) {
+            int d = disp_index(sec->lat, pi[p], pj[p]);
+            zz[p] = Czz[d];
+            pm[2 * p] = Cpm[d].real();
+            pm[2 * p + 1] = Cpm[d].imag();
+        }
+        return QS3_OK;
+    }
+    double n2 = 0;
+    QS3_TRY(vec_norm2(sec, vec, &n2, s));
+    QS3_REQUIRE(n2 > 0 && std::isfinite(n2), QS3_ENUMERIC, "zero or non-finite state");
+    std::vector<int32_t> hi_, hj_;
+    std::vector<int> idx;
+    for (int p = 0; p < n_pairs; ++p)
+        if (pi[p] != pj[p]) {
+            hi_.push_back(pi[p]);
+            hj_.push_back(pj[p]);
+            idx.push_back(p);
+        }
+    DevBuf dpi, dpj;
+    const int np = (int)idx.size();
+    QS3_TRY(dpi.alloc(sec->lat->ctx, sizeof(int32_t) * std::max(np, 1)));
+    QS3_TRY(dpj.alloc(sec->lat->ctx, sizeof(int32_t) * std::max(np, 1)));
+    if (np) {
+        QS3_HIP(hipMemcpyAsync(dpi.ptr, hi_.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, s));
+        QS3_HIP(hipMemcpyAsync(dpj.ptr, hj_.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, s));
+    }
+    std::vector<double> p, q, pmv;
+    QS3_TRY(obs_u1(sec, (const double *)vec, np, dpi.as<int32_t>(), dpj.as<int32_t>(), p, q, pmv, s));
+    for (int t = 0; t < n_pairs; ++t) {
+        if (pi[t] == pj[t]) {
+            zz[t] = 0.25;
+            pm[2 * t] = 1.0 - p[pi[t]] / n2;  // 1/2 + <s^z_i>
+            pm[2 * t + 1] = 0.0;
+        }
+    }
+    for (int k = 0; k < np; ++k) {
+        const int t = idx[k];
+        const double xi = p[pi[t]] / n2, xj = p[pj[t]] / n2;
+        zz[t] = 0.25 - 0.5 * (xi + xj) + q[k] / n2;
+        pm[2 * t] = pmv[k] / n2;
+        pm[2 * t + 1] = 0.0;
+    }
+    return QS3_OK;
+}
+
+int qs3_sq(qs3_sector *sec, const void *vec, int n_q, const double *qv, double *szz, double *spm,
+           double *stot, void *stream) {
+    QS3_REQUIRE(sec && vec && qv && szz && spm && stot && n_q >= 0, QS3_EINVAL, "NULL argument");
+    hipSetDevice(sec->lat->ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    qs3_lattice *lat = sec->lat;
+    const int N = lat->N;
+    std::vector<double> R(3 * N);
+    for (int r = 0; r < N; ++r) {
+        int x, y, z;
+        coords_of(lat, r, x, y, z);
+        R[3 * r] = x;
+        R[3 * r + 1] = y;
+        R[3 * r + 2] = z;
+    }
+    if (sec->has_k) {
+        // S(q) = sum_d e^{-i q.d} C(d) with the translation-averaged C
+        std::vector<double> Czz;
+        std::vector<std::complex<double>> Cpm;
+        QS3_TRY(k_correlations(sec, vec, Czz, Cpm, s));
+        const double szv = (0.5 * N - sec->K) / N;
+        for (int k = 0; k < n_q; ++k) {
+            std::complex<double> a = 0, b = 0, c = 0;
+            for (int d = 0; d < N; ++d) {
+                const double ph = qv[3 * k] * R[3 * d] + qv[3 * k + 1] * R[3 * d + 1] + qv[3 * k + 2] * R[3 * d + 2];
+                const std::complex<double> e(std::cos(ph), -std::sin(ph));
+                a += e * Czz[d];
+                b += e * Cpm[d];
+                // <s^-_r s^+_{r+d}> = <s^+_{r+d} s^-_r> = conj? -> C^{-+}(d) = Cpm(-d) for d != 0
+                const int md = (d == 0) ? 0 : disp_index(lat, d, 0);
+                const std::complex<double> cmp = (d == 0) ? std::complex<double>(0.5 - szv) : Cpm[md];
+                c += e * cmp;
+            }
+            szz[k] = a.real();
+            spm[k] = b.real();
+            stot[k] = a.real() + 0.5 * (b.real() + c.real());
+        }
+        return QS3_OK;
+    }
+    // fixed-N_down: all pairs, then the Fourier sums
+    std::vector<int32_t> pi, pj;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            pi.push_back(i);
+            pj.push_back(j);
+        }
+    std::vector<double> zz(N * N), pm(2 * N * N);
+    QS3_TRY(qs3_sisj(sec, vec, N * N, pi.data(), pj.data(), zz.data(), pm.data(), stream));
+    for (int k = 0; k < n_q; ++k) {
+        std::vector<std::complex<double>> e(N);
+        for (int r = 0; r < N; ++r) {
+            const double ph = qv[3 * k] * R[3 * r] + qv[3 * k + 1] * R[3 * r + 1] + qv[3 * k + 2] * R[3 * r + 2];
+            e[r] = std::complex<double>(std::cos(ph), std::sin(ph));
+        }
+        double a = 0, b = 0, c = 0;
+        for (int r = 0; r < N; ++r)
+            for (int rp = 0; rp < N; ++rp) {
+                const std::complex<double> w = e[r] * std::conj(e[rp]);
+                a += (w * zz[r * N + rp]).real();
+                b += (w * std::complex<double>(pm[2 * (r * N + rp)], pm[2 * (r * N + rp) + 1])).real();
+                const double mp = (r == rp) ? (1.0 - pm[2 * (r * N + r)]) : pm[2 * (rp * N + r)];
+                c += (w * mp).real();
+            }
+        szz[k] = a / N;
+        spm[k] = b / N;
+        stot[k] = (a + 0.5 * (b + c)) / N;
+    }
+    return QS3_OK;
+}
+
+int qs3_smq(qs3_sector *from, const void *vec_from, qs3_sector *to, const int32_t *qvec, void *vec_to,
+            void *stream) {
+    QS3_REQUIRE(from && to && vec_from && vec_to && qvec, QS3_EINVAL, "NULL argument");
+    QS3_REQUIRE(from->has_k && to->has_k, QS3_EINVAL, "S^-_q acts between momentum sectors");
+    QS3_REQUIRE(from->lat == to->lat && to->K == from->K + 1, QS3_EINVAL,
+                "target sector must be the same lattice with N_down + 1");
+    qs3_lattice *lat = from->lat;
+    const int L[3] = {lat->lx, lat->ly, lat->lz};
+    for (int a = 0; a < 3; ++a)
+        QS3_REQUIRE(((from->kv[a] + qvec[a]) % L[a] + L[a]) % L[a] == to->kv[a], QS3_EINVAL,
+                    "target momentum must be k + q");
+    hipSetDevice(lat->ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int M = from->bat->M;
+    int32_t qm[3] = {(int)(((long)((qvec[0] % L[0]) + L[0]) % L[0]) * (M / L[0]) % M),
+                     (int)(((long)((qvec[1] % L[1]) + L[1]) % L[1]) * (M / L[1]) % M),
+                     (int)(((long)((qvec[2] % L[2]) + L[2]) % L[2]) * (M / L[2]) % M)};
+    DevBuf ua, ub, dq;
+    QS3_TRY(ua.alloc(lat->ctx, sizeof(double) * 2 * std::max<uint64_t>(from->bat->ks->n_reps, 1)));
+    QS3_TRY(ub.alloc(lat->ctx, sizeof(double) * 2 * std::max<uint64_t>(to->bat->ks->n_reps, 1)));
+    QS3_TRY(dq.alloc(lat->ctx, sizeof(qm)));
+    QS3_HIP(hipMemcpyAsync(dq.ptr, qm, sizeof(qm), hipMemcpyHostToDevice, s));
+    QS3_TRY(scatter_compact(from, (const double *)vec_from, ua.as<double>(), s));
+    QS3_TRY(smq_any(from->bat, to->bat, dq.as<int32_t>(), ua.as<double>(), ub.as<double>(), s));
+    QS3_TRY(gather_compact(to, ub.as<double>(), (double *)vec_to, s));
+    QS3_HIP(hipStreamSynchronize(s));
+    return QS3_OK;
+}
+
+int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_t *qvecs,
+            const qs3_dsf_opts *opts, int n_omega, const double *omega, double *S, double *alpha,
+            double *beta, double *weight, void *stream) {
+    QS3_REQUIRE(gs && gs_vec && qvecs && opts && n_q > 0 && n_omega >= 0, QS3_EINVAL, "bad argument");
+    QS3_REQUIRE(gs->has_k, QS3_EINVAL, "the ground state must be a momentum-sector vector");
+    QS3_REQUIRE(gs->K <= 5, QS3_EINVAL, "S^- needs N_down + 1 <= 6");
+    qs3_lattice *lat = gs->lat;
+    hipSetDevice(lat->ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int steps = opts->steps > 0 ? opts->steps : 300;
+    const int L[3] = {lat->lx, lat->ly, lat->lz};
+    const int M = gs->bat->M;
+    // target sectors k0 + q, one batch column each
+    std::vector<int32_t> kt(3 * n_q), qm(3 * n_q);
+    for (int b = 0; b < n_q; ++b)
+        for (int a = 0; a < 3; ++a) {
+            const int qa = ((qvecs[3 * b + a] % L[a]) + L[a]) % L[a];
+            kt[3 * b + a] = (gs->kv[a] + qa) % L[a];
+            qm[3 * b + a] = (int)((long)qa * (M / L[a]) % M);
+        }
+    qs3_batch *tb = nullptr;
+    QS3_TRY(qs3_batch_create(lat, gs->K + 1, n_q, kt.data(), &tb));
+    std::unique_ptr<qs3_batch, int (*)(qs3_batch *)> tb_guard(tb, qs3_batch_destroy);
+    DevBuf ua, psi, dq;
+    QS3_TRY(ua.alloc(lat->ctx, sizeof(double) * 2 * std::max<uint64_t>(gs->bat->ks->n_reps, 1)));
+    QS3_TRY(psi.alloc(lat->ctx, sizeof(double) * 2 * std::max<uint64_t>(tb->ks->n_reps, 1) * n_q));
+    QS3_TRY(dq.alloc(lat->ctx, sizeof(int32_t) * 3 * n_q));
+    QS3_HIP(hipMemcpyAsync(dq.ptr, qm.data(), sizeof(int32_t) * 3 * n_q, hipMemcpyHostToDevice, s));
+    QS3_TRY(scatter_compact(gs, (const double *)gs_vec, ua.as<double>(), s));
+    // normalise the ground state on the fly: weights use |gs|^2 = 1
+    double g2 = 0;
+    QS3_TRY(vec_norm2(gs, gs_vec, &g2, s));
+    QS3_REQUIRE(g2 > 0 && std::isfinite(g2), QS3_ENUMERIC, "zero or non-finite ground state");
+    QS3_TRY(smq_any(gs->bat, tb, dq.as<int32_t>(), ua.as<double>(), psi.as<double>(), s));
+    // Lanczos from psi'/|psi'| in every target sector (Alg. 10, lines 3-11)
+    struct TOp : Operator {
+        qs3_batch *b;
+        uint64_t rows() const override { return b->ks->n_reps; }
+        int cols() const override { return b->B; }
+        bool is_complex() const override { return true; }
+        int apply(const double *x, double *y, hipStream_t st) override {
+            return hv_batch(b, x, QS3_C128, y, QS3_C128, st);
+        }
+        int apply_f32in(const float *x, double *y, hipStream_t st) override {
+            return hv_batch(b, x, QS3_C64, y, QS3_C128, st);
+        }
+    } op;
+    op.b = tb;
+    Engine E;
+    QS3_TRY(E.init(lat->ctx, &op, steps + 1, opts->precision, opts->reorth ? 2 : 0, s));
+    std::vector<double> a, bb, n0;
+    std::vector<int> done;
+    QS3_TRY(run_lanczos(E, psi.as<double>(), steps, a, bb, n0, done));
+    const double pi = std::acos(-1.0);
+    for (int q = 0; q < n_q; ++q) {
+        const double w = n0[q] * n0[q] / g2;
+        if (weight) weight[q] = w;
+        if (alpha)
+            for (int x = 0; x < steps; ++x) alpha[(size_t)q * steps + x] = a[(size_t)q * steps + x];
+        if (beta)
+            for (int x = 0; x < steps; ++x) beta[(size_t)q * steps + x] = bb[(size_t)q * steps + x];
+        const int m = (w > 0) ? done[q] : 0;
+        for (int k = 0; k < n_omega; ++k) {
+            if (m == 0) {
+                S[(size_t)q * n_omega + k] = 0.0;
+                continue;
+            }
+            const std::complex<double> z(omega[k] - opts->field + e0, opts->eta);
+            std::complex<double> g = 0.0;
+            for (int i = m - 1; i >= 0; --i) {
+                const std::complex<double> tail =
+                    (i < m - 1) ? bb[(size_t)q * steps + i] * bb[(size_t)q * steps + i] * g : 0.0;
+                g = 1.0 / (z - a[(size_t)q * steps + i] - tail);
+            }
+            S[(size_t)q * n_omega + k] = -(w * g).imag() / pi;
+        }
+    }
+    return QS3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,295 @@
+// Device kernels of the observables (Sec. 3.6, Sec. 4.2) and of S^-_q
+// (Sec. 3.8), all as gathers with per-block partial sums (deterministic).
+#pragma once
+#include "hv_kernels.h"
+
+namespace qs3 {
+
+// Reduced-space site map: the e-th site (0-based) of {0..N-1} minus {lo, hi}
+// (lo < hi; hi = -1 removes only lo).
+__device__ __forceinline__ int skip_sites(int e, int lo, int hi) {
+    int s = e + (e >= lo ? 1 : 0);
+    if (hi >= 0) s += (s >= hi ? 1 : 0);
+    return s;
+}
+
+template <int K, typename RT>
+__device__ __forceinline__ RT rank_sorted(int (&t)[K > 0 ? K : 1], const Binom<RT> &Bn) {
+    sortK<K>(t);
+    RT r = 0;
+#pragma unroll
+    for (int m = 0; m < K; ++m) r += Bn.C(t[m], m + 1);
+    return r;
+}
+
+__device__ __forceinline__ void block_sum2(double2 v, double2 *out) {
+    __shared__ double2 red[256];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            red[threadIdx.x] = make_double2(red[threadIdx.x].x + red[threadIdx.x + s].x,
+                                            red[threadIdx.x].y + red[threadIdx.x + s].y);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// <x_i> numerator: sum over states containing site i of |phi|^2 (fixed-N_down,
+// real).  grid = (N, nchunk); subsets of K-1 sites of the other N-1.
+template <int K, typename RT>
+__global__ __launch_bounds__(256) void k_site_prob(LatArgs L, const RT *__restrict__ binom_g, uint64_t cnt,
+                                                   int nchunk, const double *__restrict__ phi,
+                                                   double2 *__restrict__ partial) {
+    Binom<RT> Bn{binom_g, L.N + 1};
+    const int i = blockIdx.x;
+    const uint64_t per = (cnt + nchunk - 1) / nchunk;
+    const uint64_t s0 = per * blockIdx.y, s1 = min(cnt, s0 + per);
+    double acc = 0;
+    for (uint64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+        int t[K > 0 ? K : 1];
+        if (K >= 2) {
+            int e[(K - 1) > 0 ? (K - 1) : 1];
+            unrank<(K - 1 > 0 ? K - 1 : 0), RT>((RT)s, L.N - 1, Bn, e);
+#pragma unroll
+            for (int m = 0; m + 1 < K; ++m) t[m] = skip_sites(e[m], i, -1);
+        }
+        if (K >= 1) t[K - 1] = i;
+        const double p = phi[rank_sorted<K, RT>(t, Bn)];
+        acc += p * p;
+    }
+    block_sum2(make_double2(acc, 0.0), &partial[(size_t)blockIdx.x * nchunk + blockIdx.y]);
+}
+
+// Pair sums (fixed-N_down, real): q_ij = sum over states containing i and j of
+// |phi|^2 (subsets of K-2 of the other N-2 sites) and
+// pm_ij = sum_S phi(S + j) phi(S + i) (subsets S of K-1 of the other N-2).
+// grid = (n_pairs, nchunk).
+template <int K, typename RT>
+__global__ __launch_bounds__(256) void k_pair_u1(LatArgs L, const RT *__restrict__ binom_g,
+                                                 const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
+                                                 uint64_t cnt_q, uint64_t cnt_pm, int nchunk,
+                                                 const double *__restrict__ phi,
+                                                 double2 *__restrict__ partial) {
+    Binom<RT> Bn{binom_g, L.N + 1};
+    const int p = blockIdx.x;
+    const int i = pi[p], j = pj[p];
+    const int lo = min(i, j), hi = max(i, j);
+    double aq = 0, apm = 0;
+    if (K >= 2) {
+        const uint64_t per = (cnt_q + nchunk - 1) / nchunk;
+        const uint64_t s0 = per * blockIdx.y, s1 = min(cnt_q, s0 + per);
+        for (uint64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+            int t[K > 0 ? K : 1];
+            if (K >= 3) {
+                int e[(K - 2) > 0 ? (K - 2) : 1];
+                unrank<(K - 2 > 0 ? K - 2 : 0), RT>((RT)s, L.N - 2, Bn, e);
+#pragma unroll
+                for (int m = 0; m + 2 < K; ++m) t[m] = skip_sites(e[m], lo, hi);
+            }
+            t[K - 2] = i;
+            t[K - 1] = j;
+            const double v = phi[rank_sorted<K, RT>(t, Bn)];
+            aq += v * v;
+        }
+    }
+    if (K >= 1) {
+        const uint64_t per = (cnt_pm + nchunk - 1) / nchunk;
+        const uint64_t s0 = per * blockIdx.y, s1 = min(cnt_pm, s0 + per);
+        for (uint64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+            int ti[K > 0 ? K : 1], tj[K > 0 ? K : 1];
+            if (K >= 2) {
+                int e[(K - 1) > 0 ? (K - 1) : 1];
+                unrank<(K - 1 > 0 ? K - 1 : 0), RT>((RT)s, L.N - 2, Bn, e);
+#pragma unroll
+                for (int m = 0; m + 1 < K; ++m) ti[m] = tj[m] = skip_sites(e[m], lo, hi);
+            }
+            ti[K - 1] = i;
+            tj[K - 1] = j;
+            apm += phi[rank_sorted<K, RT>(tj, Bn)] * phi[rank_sorted<K, RT>(ti, Bn)];
+        }
+    }
+    block_sum2(make_double2(aq, apm), &partial[(size_t)blockIdx.x * nchunk + blockIdx.y]);
+}
+
+// Momentum sector (union layout, one column): for displacement d = disp[dd]
+// (packed dx | dy<<10 | dz<<20) accumulate over the rows of the chunk
+//   zz: |phi_u|^2 * #{pairs of down spins at displacement d}
+//   pm: conj(phi_u) * (O_d phi)_u with O_d = sum_r s^+_r s^-_{r+d}; the pull
+//       form applies O_d^+ (a down spin at c moves to c - d) with the
+//       momentum-basis element e^{ik.t} sqrt(s'/s_u)
+//   nrm: |phi_u|^2
+// grid = (n_disp, nchunk); partial[(dd * nchunk + chunk) * 2 + {0,1}].
+template <int K, typename RT, bool TABLE>
+__global__ __launch_bounds__(256) void k_corr_k(BatchArgs A, const RT *__restrict__ binom_g,
+                                                const int32_t *__restrict__ disp, int nchunk,
+                                                const double2 *__restrict__ phi,
+                                                double2 *__restrict__ partial) {
+    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    const int dd = blockIdx.x;
+    const int dp = disp[dd];
+    const int dx = dp & 1023, dy = (dp >> 10) & 1023, dz = (dp >> 20) & 1023;
+    const uint64_t per = (A.n_reps + nchunk - 1) / nchunk;
+    const uint64_t u0 = per * blockIdx.y, u1 = min(A.n_reps, u0 + per);
+    double azz = 0, anr = 0, apr = 0, api = 0;
+    for (uint64_t u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
+        const int su = A.stab[u];
+        if (su > 1 && !A.compat_nt[A.nt_of[u]]) continue;
+        const double2 f = phi[u];
+        const double f2 = f.x * f.x + f.y * f.y;
+        const RT R = (RT)A.reps[u];
+        int c[K > 0 ? K : 1];
+        unrank<K, RT>(R, A.L.N, Bn, c);
+        int tr[K > 0 ? K : 1], back[K > 0 ? K : 1];
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            const uint32_t pc = g.coords[c[m]];
+            const int x = pc & 1023u, y = (pc >> 10) & 1023u, z = (pc >> 20) & 1023u;
+            tr[m] = wrap_add(x, dx, g.lx) + g.lx * wrap_add(y, dy, g.ly) + g.lxy * wrap_add(z, dz, g.lz);
+            back[m] = wrap_add(x, dx ? g.lx - dx : 0, g.lx) + g.lx * wrap_add(y, dy ? g.ly - dy : 0, g.ly) +
+                      g.lxy * wrap_add(z, dz ? g.lz - dz : 0, g.lz);
+        }
+        int npair = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+#pragma unroll
+            for (int q = 0; q < K; ++q) npair += (tr[m] == c[q]) ? 1 : 0;
+        azz += f2 * (double)npair;
+        anr += f2;
+        HopRanker<K, RT> hr;
+        hr.init(c, Bn);
+        double sr = 0, si = 0;
+        const double isq = 1.0 / A.L.sqrt_tab[su];
+        StaticFor<0, K>::run([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            RT rp;
+            const int j = back[m];
+            if (!hr.template hop<m>(c, R, j, Bn, &rp)) return;
+            uint32_t u2;
+            int tx, ty, tz;
+            resolve_hop<K, RT, TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
+            const int s2 = A.stab[u2];
+            if (s2 > 1 && !A.compat_nt[A.nt_of[u2]]) return;
+            int P = A.kmul[0] * tx + A.kmul[1] * ty + A.kmul[2] * tz;
+            P %= A.M;
+            const double2 ph = A.phase[P];
+            const double coef = A.L.sqrt_tab[s2] * isq;
+            const double2 x = phi[u2];
+            sr += coef * (ph.x * x.x - ph.y * x.y);
+            si += coef * (ph.x * x.y + ph.y * x.x);
+        });
+        // conj(f) * (sr + i si)
+        apr += f.x * sr + f.y * si;
+        api += f.x * si - f.y * sr;
+    }
+    __shared__ double2 red[256][2];
+    red[threadIdx.x][0] = make_double2(azz, anr);
+    red[threadIdx.x][1] = make_double2(apr, api);
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                red[threadIdx.x][q] = make_double2(red[threadIdx.x][q].x + red[threadIdx.x + s][q].x,
+                                                   red[threadIdx.x][q].y + red[threadIdx.x + s][q].y);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[((size_t)dd * nchunk + blockIdx.y) * 2] = red[0][0];
+        partial[((size_t)dd * nchunk + blockIdx.y) * 2 + 1] = red[0][1];
+    }
+}
+
+// S^-_q as a gather (Sec. 3.8, Alg. 11 read row by row).  Target rows are the
+// representatives beta of the (K+1)-down structure, columns b the sectors
+// k + q_b.  For every down spin r0 of beta, a' = beta minus r0 has the
+// representative alpha = T^t a' in the K-down structure and contributes
+//   e^{-i q_b.R_r0 + i k.t} sqrt(s_alpha / (N s_beta)) phi_alpha,
+// the matrix element <beta, k+q | S^-_q | alpha, k> from the definition of the
+// momentum states (Eq. (akstate)).
+struct SmqArgs {
+    BatchArgs src;    // K-down structure, source sector (B = 1)
+    BatchArgs dst;    // (K+1)-down structure, target sectors (B = n_q)
+    const int32_t *qmul;  // 3 * B: Q_a (M / L_a) mod M
+};
+
+template <int K, typename RTa, typename RTb, bool TABLE, int BPL>
+__global__ __launch_bounds__(256) void k_smq(SmqArgs S, const RTa *__restrict__ binom_a,
+                                             const RTb *__restrict__ binom_b,
+                                             const double2 *__restrict__ phi,
+                                             double2 *__restrict__ out) {
+    constexpr int K1 = K + 1;
+    const BatchArgs &A = S.src;
+    const BatchArgs &D = S.dst;
+    Binom<RTa> Ba{binom_a, A.L.N + 1};
+    Binom<RTb> Bb{binom_b, A.L.N + 1};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    const int G = D.G, B = D.B;
+    const int lane = threadIdx.x % G, slot = threadIdx.x / G;
+    const int rows_per = blockDim.x / G;
+    const uint64_t u = (uint64_t)blockIdx.x * rows_per + slot;
+    if (u >= D.n_reps) return;
+    const int sb = D.stab[u];
+    const int ntb = sb > 1 ? D.nt_of[u] : -1;
+    int c[K1];
+    unrank<K1, RTb>((RTb)D.reps[u], A.L.N, Bb, c);
+    double accr[BPL], acci[BPL];
+#pragma unroll
+    for (int i = 0; i < BPL; ++i) accr[i] = acci[i] = 0.0;
+    const double isb = 1.0 / (A.L.sqrt_tab[sb] * sqrt((double)A.L.N));
+#pragma unroll
+    for (int m = 0; m < K1; ++m) {
+        int a[K > 0 ? K : 1];
+#pragma unroll
+        for (int t = 0; t < K; ++t) a[t] = c[t < m ? t : t + 1];
+        uint32_t ua;
+        int tx, ty, tz;
+        if (TABLE) {
+            RTa r = 0;
+#pragma unroll
+            for (int t = 0; t < K; ++t) r += Ba.C(a[t], t + 1);
+            const uint64_t ent = A.table[r];
+            ua = (uint32_t)ent;
+            const uint32_t tt = (uint32_t)(ent >> 32);
+            tx = tt & 1023u;
+            ty = (tt >> 10) & 1023u;
+            tz = (tt >> 20) & 1023u;
+        } else {
+            int best[K > 0 ? K : 1];
+            canonicalize<K>(a, g, best, tx, ty, tz);
+            uint64_t r = 0;
+#pragma unroll
+            for (int t = 0; t < K; ++t) r += (uint64_t)Ba.C(best[t], t + 1);
+            ua = (uint32_t)find_rep(A.reps, A.dir, A.dir_shift, r);
+        }
+        const int sa = A.stab[ua];
+        if (sa > 1 && !A.compat_nt[A.nt_of[ua]]) continue;
+        const double2 f = phi[ua];
+        const double coef = A.L.sqrt_tab[sa] * isb;
+        const uint32_t pr0 = g.coords[c[m]];
+        const int x0 = pr0 & 1023u, y0 = (pr0 >> 10) & 1023u, z0 = (pr0 >> 20) & 1023u;
+        const int Pk = A.kmul[0] * tx + A.kmul[1] * ty + A.kmul[2] * tz;
+#pragma unroll
+        for (int i = 0; i < BPL; ++i) {
+            const int b = lane + i * G;
+            if (b >= B) continue;
+            int P = Pk - (S.qmul[3 * b] * x0 + S.qmul[3 * b + 1] * y0 + S.qmul[3 * b + 2] * z0);
+            P %= A.M;
+            if (P < 0) P += A.M;
+            const double2 ph = A.phase[P];
+            accr[i] += coef * (ph.x * f.x - ph.y * f.y);
+            acci[i] += coef * (ph.x * f.y + ph.y * f.x);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < BPL; ++i) {
+        const int b = lane + i * G;
+        if (b >= B) continue;
+        const bool ok = ntb < 0 || D.compat_nt[(size_t)ntb * B + b];
+        out[u * B + b] = ok ? make_double2(accr[i], acci[i]) : make_double2(0.0, 0.0);
+    }
+}
+
+}  // namespace qs3

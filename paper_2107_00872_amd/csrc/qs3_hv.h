@@ -47,3 +47,27 @@ template <int K>
 int build_kstruct_K(qs3_lattice *lat, const BinomTable &bt, KStructure *ks, hipStream_t s);
 
 }  // namespace qs3
+
+namespace qs3 {
+
+// Observables (obs_kernels.h), instantiated per N_down in hv_inst.hip.
+// Fixed-N_down sector, real vector phi (device): p_site[i] = sum_{a ∋ i}
+// |phi_a|^2; for pairs (pi, pj device, i != j): q[p] = sum_{a ∋ i, j} |phi_a|^2,
+// pm[p] = sum_S phi(S+j) phi(S+i).  Host outputs.
+template <int K>
+int obs_u1_K(qs3_sector *sec, const double *phi, int npairs, const int32_t *pi,
+             const int32_t *pj, std::vector<double> &p_site, std::vector<double> &q,
+             std::vector<double> &pm, hipStream_t s);
+// Momentum sector in union layout: per displacement (packed, device) the sums
+// zz (pair counts weighted by |phi|^2), nrm = |phi|^2 and pm (complex).
+template <int K>
+int corr_k_K(qs3_sector *sec, const double *phi_union, int ndisp, const int32_t *disp,
+             std::vector<double> &zz, std::vector<double> &nrm, std::vector<double> &pm_re,
+             std::vector<double> &pm_im, hipStream_t s);
+// S^-_q gather from the source sector (batch of one, union layout) into the
+// target batch (union layout [row][sector]); qmul: device, 3 ints per target.
+template <int K>
+int smq_K(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi_union,
+          double *out_union, hipStream_t s);
+
+}  // namespace qs3

@@ -41,7 +41,9 @@ struct Engine {
     int init(qs3_ctx *c, Operator *o, int slots, int precision, int reorth, hipStream_t s);
     double *slot(int j);
     int apply(const double *x, double *y);
-    int multidot(const double *X, int J, const double *Y, double2 *out);
+    int multidot(const double *X, int J, const double *Y, double2 *out, int selfdot,
+                 const uint8_t *mask);
+    int cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double2 *nrm_out);
     int step(int x, int prev);
     int normalize_into_slot0(const double *v0, std::vector<double> *norms0);
     int read_ab(int x0, int x1, std::vector<double> &a, std::vector<double> &b);

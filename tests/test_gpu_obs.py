@@ -1,0 +1,181 @@
+"""GPU observables (Sec. 3.6, 4.2), S^-_q (Alg. 11) and the continued-fraction
+S(q, omega) (Eq. (cfe)) against the oracle on the same input vectors.
+
+Tolerances: correlations and structure factors are sums of |phi|^2-weighted
+terms of size <= 1 over at most C(N, K) states; 1e-12 absolute covers their
+float64 rounding.  The continued fraction is compared through its Lanczos
+coefficients (1e-10) and on the omega grid (1e-8 relative to max S).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import native as orc
+from oracle.dynamics import continued_fraction, smq_to_vec
+from oracle.lanczos import lanczos as orc_lanczos
+from oracle.observables import corr_pm, corr_zz, positions, structure_factors, sz
+from oracle.translation import Geometry, expand_to_u1, gen_full_ham_sym_adapt, mk_list
+from oracle.hamiltonian import bonds_1based
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qs3():
+    from paper_2107_00872_amd import qs3 as q
+    orc.build(force=False)
+    return q
+
+
+@pytest.fixture(scope="module")
+def ctx(qs3):
+    return qs3.Context(0)
+
+
+def all_pairs(N):
+    return [i for i in range(N) for j in range(N)], [j for i in range(N) for j in range(N)]
+
+
+def qgrid(lat):
+    return np.array([[2 * np.pi * kx / lat.lx, 2 * np.pi * ky / lat.ly, 2 * np.pi * kz / lat.lz]
+                     for (kx, ky, kz) in wl.all_momenta(lat)])
+
+
+@pytest.mark.parametrize("lat,K", [(wl.with_disorder(wl.chain(10), 4), 3), (wl.square(4), 3),
+                                   (wl.random_bonds(9, 16, 1), 4), (wl.chain(8), 1)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_u1_observables(qs3, ctx, lat, K):
+    L = qs3.Lattice.of(ctx, lat)
+    sec = qs3.Sector(L, K)
+    N = lat.n_sites
+    X = torch.empty(sec.dim, dtype=torch.float64, device="cuda")
+    sec.eigs(nev=1, evecs=X, seed=4)
+    phi = X.cpu().numpy()
+    ref_sz = sz(phi, N, K)
+    assert np.abs(sec.sz(X) - ref_sz).max() < 1e-12
+    pi, pj = all_pairs(N)
+    zz, pm = sec.sisj(X, pi, pj)
+    rzz, rpm = corr_zz(phi, N, K), corr_pm(phi, N, K)
+    assert np.abs(zz - rzz.reshape(-1)).max() < 1e-12
+    assert np.abs(pm - rpm.reshape(-1)).max() < 1e-12
+    qs = qgrid(lat)
+    szz, spm, stot = sec.sq(X, qs)
+    ref = structure_factors(rzz, rpm, ref_sz, positions(*lat.dims), qs)
+    assert np.abs(szz - ref[:, 0]).max() < 1e-11
+    assert np.abs(spm - ref[:, 1]).max() < 1e-11
+    assert np.abs(stot - ref[:, 2]).max() < 1e-11
+    # sum rules (pins independent of the oracle)
+    M = N / 2 - K
+    assert sec.sz(X).sum() == pytest.approx(M, abs=1e-12)
+    if lat.translation_invariant:
+        assert spm.sum() == pytest.approx(N - K, abs=1e-10)
+        assert szz.sum() == pytest.approx(N / 4, abs=1e-10)
+
+
+@pytest.mark.parametrize("lat,K", [(wl.square(4), 3), (wl.chain(8), 3), (wl.hypercubic(4, 2, 1), 2)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_k_observables_translation_averaged(qs3, ctx, lat, K):
+    """Any vector of a momentum sector is an eigenvector of T, so its
+    correlations are translation invariant: the translation-averaged values of
+    the device equal the oracle's direct values on the expanded state."""
+    L = qs3.Lattice.of(ctx, lat)
+    geo = Geometry(*lat.dims)
+    N = lat.n_sites
+    pi, pj = all_pairs(N)
+    for Kv in wl.all_momenta(lat)[:5]:
+        s, R = mk_list(geo, K, Kv)
+        if not s:
+            continue
+        sec = qs3.Sector(L, K, Kv)
+        rng = np.random.default_rng(2)
+        phi = rng.normal(size=len(s)) + 1j * rng.normal(size=len(s))
+        X = torch.from_numpy(phi).cuda()
+        u1 = expand_to_u1(geo, K, s, R, Kv, phi)
+        rzz, rpm = corr_zz(u1, N, K), corr_pm(u1, N, K)
+        zz, pm = sec.sisj(X, pi, pj)
+        assert np.abs(zz - rzz.reshape(-1)).max() < 1e-12
+        assert np.abs(pm - rpm.reshape(-1)).max() < 1e-12
+        qs = qgrid(lat)
+        szz, spm, stot = sec.sq(X, qs)
+        ref = structure_factors(rzz, rpm, sz(u1, N, K), positions(*lat.dims), qs)
+        assert np.abs(np.stack([szz, spm, stot], 1) - ref).max() < 1e-11
+        assert np.abs(sec.sz(X) - sz(u1, N, K)).max() < 1e-12
+        sec.close()
+
+
+@pytest.mark.parametrize("lat,K", [(wl.chain(6), 2), (wl.square(4), 1), (wl.square(4), 2),
+                                   (wl.hypercubic(4, 2, 1), 2), (wl.cube(3), 2)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_smq_gather_vs_alg11(qs3, ctx, lat, K):
+    L = qs3.Lattice.of(ctx, lat)
+    for Kv in wl.all_momenta(lat)[:3]:
+        sigma, R = orc.mk_list(lat.dims, K, Kv)
+        if len(sigma) == 0:
+            continue
+        src = qs3.Sector(L, K, Kv)
+        rng = np.random.default_rng(7)
+        phi = rng.normal(size=len(sigma)) + 1j * rng.normal(size=len(sigma))
+        X = torch.from_numpy(phi).cuda()
+        for Qv in wl.all_momenta(lat)[:6]:
+            kq = tuple((Kv[a] + Qv[a]) % lat.dims[a] for a in range(3))
+            s1, R1 = orc.mk_list(lat.dims, K + 1, kq)
+            if len(s1) == 0:
+                continue
+            dst = qs3.Sector(L, K + 1, kq)
+            out = torch.empty(dst.dim, dtype=torch.complex128, device="cuda")
+            src.smq(X, dst, Qv, out)
+            ref = orc.smq(lat.dims, K, Kv, sigma, R, phi, s1, R1, Qv)
+            assert np.abs(out.cpu().numpy() - ref).max() < 1e-12 * max(1, np.abs(phi).max()) * (K + 1)
+            dst.close()
+        src.close()
+
+
+def test_dsf_small_vs_oracle(qs3, ctx):
+    """4x4 square, N_down = 2 ground state at its lowest k, S^-(q, omega) for all
+    q at h = 2: Lanczos coefficients, weights and the continued fraction against
+    the oracle (dense k+q blocks, oracle Lanczos from the oracle's S^-_q)."""
+    lat = wl.square(4)
+    L = qs3.Lattice.of(ctx, lat)
+    geo = Geometry(*lat.dims)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    ks = wl.all_momenta(lat)
+    K = 2
+    best = None
+    for Kv in ks:
+        s, R = mk_list(geo, K, Kv)
+        e = np.linalg.eigvalsh(gen_full_ham_sym_adapt(geo, K, bonds, s, R, Kv))[0]
+        if best is None or e < best[0] - 1e-10:
+            best = (e, Kv)
+    e0, k0 = best
+    gs = qs3.Sector(L, K, k0)
+    X = torch.empty(gs.dim, dtype=torch.complex128, device="cuda")
+    res = gs.eigs(nev=1, evecs=X, seed=9)
+    assert res.evals[0] == pytest.approx(e0, abs=1e-10)
+    omega = np.linspace(0, 8, 401)
+    steps = 40
+    S, a, b, w = gs.dsf(X, res.evals[0], ks, omega, steps=steps, eta=0.1, field=2.0)
+    phi = X.cpu().numpy()
+    sigma, R = orc.mk_list(lat.dims, K, k0)
+    tot = 0.0
+    for qi, Qv in enumerate(ks):
+        kq = tuple((k0[a_] + Qv[a_]) % lat.dims[a_] for a_ in range(3))
+        s1, R1 = orc.mk_list(lat.dims, K + 1, kq)
+        psi = orc.smq(lat.dims, K, k0, sigma, R, phi, s1, R1, Qv)
+        wq = float(np.vdot(psi, psi).real)
+        assert w[qi] == pytest.approx(wq, abs=1e-12)
+        tot += wq
+        Hk = gen_full_ham_sym_adapt(geo, K + 1, bonds, list(map(int, s1)), list(R1), kq)
+        m = min(steps, len(s1))
+        oa, ob, _ = orc_lanczos(lambda x: Hk @ x, psi, m)
+        # coefficients are defined up to the (numerical) end of the Krylov
+        # space of psi': stop where beta falls below 1e-8 |H|
+        eff = next((i + 1 for i in range(len(ob)) if ob[i] < 1e-8 * 8), len(ob))
+        assert np.abs(a[qi, :eff] - oa[:eff]).max() < 1e-10
+        if eff > 1:
+            assert np.abs(b[qi, :eff - 1] - ob[:eff - 1]).max() < 1e-10
+        Sref = continued_fraction(oa, ob, wq, omega, res.evals[0], 0.1, 2.0)
+        assert np.abs(S[qi] - Sref).max() < 1e-8 * max(1.0, np.abs(Sref).max())
+    assert tot == pytest.approx(lat.n_sites - K, abs=1e-10)   # sum_q S^{+-}(q) = N - K
