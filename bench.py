@@ -80,11 +80,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=50)
+    ap.add_argument("--requests", type=int, default=0, help="c5: number of requests (default 40)")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c2 (default) is the headline configuration; the others print their own line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(sharding is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "c2":
+        import bench_extra
+        print(json.dumps(getattr(bench_extra, args.workload)(args)))
+        return
 
     import numpy as np
     import torch

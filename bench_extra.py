@@ -1,0 +1,213 @@
+"""The other workloads of bench.py (python bench.py --workload c1|c3|c4|c5).
+
+c1  periodic chain N=16, N_down=3 (dim 560): 100-step float64 Lanczos, lowest 4
+    distinct levels; solve latency p50/p99 over repeated solves.
+c3  periodic 10x10x10 cube, N_down=3: all 1000 momentum sectors (166,167 each) in
+    one batch, ground energy per sector (the dispersion E(k)); float64 and the
+    float32-matvec variant with its eigenvalue error against float64.
+c4  periodic 10x10 square, N_down=3 ground state (lowest over the 100 sectors),
+    S^-(q, omega) for all 100 q into N_down=4: 300 continued-fraction Lanczos
+    levels, eta=0.05, 2000 omega points in [0, 8], field h = 4 (the saturation
+    field of the square lattice); float64 and float32-matvec.
+c5  serving: Poisson arrivals of random solve requests (workloads.serving_stream),
+    rate 0.8 / (mean one-at-a-time service time); p50/p99 latency and solves/s
+    against the same requests run one at a time.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+import workloads as wl
+from paper_2107_00872_amd import qs3
+
+
+def _ctx():
+    torch.cuda.set_device(0)
+    return qs3.Context(0)
+
+
+def _pct(x, p):
+    return float(np.percentile(np.asarray(x), p))
+
+
+def c1(args):
+    ctx = _ctx()
+    lat = wl.chain(16)
+    sec = qs3.Sector(qs3.Lattice.of(ctx, lat), 3)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        sec.eigs(nev=4, alg=qs3.ALG_LANCZOS, steps=100, seed=1, stream=stream)
+    lat_s = []
+    reps = max(20, args.steps * 20)
+    for r in range(reps):
+        t0 = time.perf_counter()
+        res = sec.eigs(nev=4, alg=qs3.ALG_LANCZOS, steps=100, seed=1 + r, stream=stream)
+        lat_s.append(time.perf_counter() - t0)
+    out = {"metric": "Lanczos solve latency (100 steps, lowest 4 distinct levels)", "workload": "c1",
+           "value": _pct(lat_s, 50) * 1e3, "unit": "ms p50", "p99_ms": _pct(lat_s, 99) * 1e3,
+           "rows_per_s": 100 * sec.dim / _pct(lat_s, 50), "evals": [float(x) for x in res.evals],
+           "dim": sec.dim, "note": "latency bound (d = 560)"}
+    try:
+        from oracle import native as orc
+        from oracle.lanczos import lanczos, ritz, lowest_distinct
+        from oracle.rng import start_vector
+        orc.build(force=False)
+        B = orc.Bonds.of(lat)
+        v0 = start_vector(1, np.arange(sec.dim), complex_=False)
+        t0 = time.perf_counter()
+        a, b, _ = lanczos(lambda x: orc.hv_u1(16, 3, B, x, nthreads=1), v0, 100)
+        e, res_, _ = ritz(a, b)
+        out["cpu_baseline"] = {"value": (time.perf_counter() - t0) * 1e3, "unit": "ms per solve",
+                               "cores": 1, "kind": "oracle", "sample": "one 100-step solve"}
+    except Exception as exc:  # the CPU leg is informative only
+        out["cpu_baseline_error"] = str(exc)
+    return out
+
+
+def c3(args):
+    ctx = _ctx()
+    lat = wl.cube(10)
+    L = qs3.Lattice.of(ctx, lat)
+    ks = wl.all_momenta(lat)
+    t0 = time.perf_counter()
+    bat = qs3.Batch(L, 3, ks)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    # batched H.v rate (all 1000 sectors in one launch)
+    v = torch.zeros(bat.rows, bat.B, dtype=torch.complex128, device="cuda")
+    v.real.uniform_(-1, 1)
+    w = torch.empty_like(v)
+    bat.matvec(v, w, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        bat.matvec(v, w, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    t_mv = e0.elapsed_time(e1) / 5e3
+    nhops = lat.n_bonds * 2 * math.comb(lat.n_sites - 2, 2)
+    alg_bytes = 16.0 * (2 * bat.rows * bat.B) + 16.0 * nhops / lat.n_sites * bat.B
+    del v, w
+    torch.cuda.empty_cache()
+    out = {"metric": "batched E(k) over 1000 momentum sectors", "workload": "c3", "rows": bat.rows,
+           "sectors": bat.B, "setup_s": t_setup, "matvec_ms": t_mv * 1e3,
+           "matvec_sector_rows_per_s": bat.rows * bat.B / t_mv,
+           "matvec_alg_GBs": alg_bytes / t_mv / 1e9}
+    res = {}
+    for prec, name in [(qs3.PREC_F64, "f64"), (qs3.PREC_F32MV, "f32mv")]:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, infos, rc = bat.eigs(nev=1, seed=1, precision=prec, tol=1e-9 if prec == 0 else 1e-6,
+                                 stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = ev[:, 0].copy()
+        out[name] = {"seconds": dt, "solves_per_s": bat.B / dt, "matvecs": infos[0].n_matvec,
+                     "converged": int(sum(i.converged for i in infos)), "rc": rc,
+                     "sector_rows_per_s": infos[0].n_matvec * bat.rows * bat.B / dt,
+                     "E_min": float(ev[:, 0].min()), "E_max": float(ev[:, 0].max())}
+    out["f32mv"]["max_rel_err_vs_f64"] = float(np.max(np.abs(res["f32mv"] - res["f64"]) / np.abs(res["f64"])))
+    out["value"] = out["f64"]["solves_per_s"]
+    out["unit"] = "sector solves/s (float64)"
+    g = ks.index((0, 0, 0))
+    out["E_gamma"] = float(res["f64"][g])
+    return out
+
+
+def c4(args):
+    ctx = _ctx()
+    lat = wl.square(10)
+    L = qs3.Lattice.of(ctx, lat)
+    ks = wl.all_momenta(lat)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    bat = qs3.Batch(L, 3, ks)
+    ev, infos, rc = bat.eigs(nev=1, seed=1, stream=stream)
+    order = sorted(range(len(ks)), key=lambda b: (round(ev[b, 0], 9), ks[b][0], ks[b][1]))
+    k0 = ks[order[0]]
+    gs = qs3.Sector(L, 3, k0)
+    X = torch.empty(gs.dim, dtype=torch.complex128, device="cuda")
+    r = gs.eigs(nev=1, evecs=X, seed=1, stream=stream)
+    torch.cuda.synchronize()
+    t_gs = time.perf_counter() - t0
+    omega = np.linspace(0.0, 8.0, 2000)
+    out = {"metric": "S^-(q, omega) for all 100 q", "workload": "c4", "k0": list(k0), "E0": float(r.evals[0]),
+           "degenerate_k": int(sum(abs(ev[b, 0] - r.evals[0]) < 1e-10 for b in range(len(ks)))),
+           "gs_seconds": t_gs}
+    S = {}
+    for prec, name in [(qs3.PREC_F64, "f64"), (qs3.PREC_F32MV, "f32mv")]:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Sq, a, b, w = gs.dsf(X, r.evals[0], ks, omega, steps=300, eta=0.05, field=4.0, precision=prec,
+                             stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        S[name] = Sq
+        out[name] = {"seconds": dt, "q_per_s": len(ks) / dt, "sum_weights": float(w.sum()),
+                     "integral_check": float(np.trapezoid(Sq, omega, axis=1).sum())}
+    out["f32mv"]["max_abs_dS_vs_f64"] = float(np.abs(S["f32mv"] - S["f64"]).max())
+    out["f32mv"]["max_S"] = float(np.abs(S["f64"]).max())
+    out["value"] = out["f64"]["q_per_s"]
+    out["unit"] = "q/s (300-level continued fraction, float64)"
+    return out
+
+
+def c5(args):
+    import sys
+    ctx = _ctx()
+    n = int(getattr(args, "requests", 0) or 40)
+    probe = wl.serving_stream(n, seed=7, rate=1.0)
+    # one-at-a-time service times (FP64, same requests)
+    srv = qs3.Server(ctx, max_active=1)
+    service, results_alone = [], {}
+    for q in probe:
+        t0 = time.perf_counter()
+        r = srv.wait(srv.submit(q["lattice"], q["n_down"], q["K"], nev=3, seed=1 + q["id"]))
+        service.append(time.perf_counter() - t0)
+        results_alone[q["id"]] = (r.status, list(r.evals[:r.n_found]))
+        print(f"alone {q['id']} {q['lattice'].name} K={q['n_down']} k={q['K']} dim={r.dim} "
+              f"status={r.status} {service[-1]:.3f}s", file=sys.stderr, flush=True)
+    srv.close()
+    ok_service = [s for s, q in zip(service, probe) if results_alone[q["id"]][0] == 0]
+    mean_s = float(np.mean(ok_service))
+    rate = 0.8 / mean_s
+    stream = wl.serving_stream(n, seed=7, rate=rate)
+    # serial FIFO queue with the measured service times = one-at-a-time latencies
+    t_free, lat_serial = 0.0, []
+    for q, s in zip(stream, service):
+        start = max(t_free, q["t_arrive"])
+        t_free = start + s
+        lat_serial.append(t_free - q["t_arrive"])
+    serial_makespan = t_free
+    # served with continuous batching
+    srv = qs3.Server(ctx, max_active=8)
+    t_base = time.perf_counter()
+    tickets = []
+    for q in stream:
+        while time.perf_counter() - t_base < q["t_arrive"]:
+            time.sleep(0.0005)
+        tickets.append(srv.submit(q["lattice"], q["n_down"], q["K"], nev=3, seed=1 + q["id"]))
+    res = []
+    for t in tickets:
+        res.append(srv.wait(t))
+        print(f"served {len(res)}/{n} status={res[-1].status}", file=sys.stderr, flush=True)
+    makespan = time.perf_counter() - t_base
+    srv.close()
+    lat_served = [r.t_done - r.t_submit for r in res]
+    same = sum(1 for q, r in zip(stream, res)
+               if r.status == results_alone[q["id"]][0] and list(r.evals[:r.n_found]) == results_alone[q["id"]][1])
+    statuses = {}
+    for r in res:
+        statuses[str(r.status)] = statuses.get(str(r.status), 0) + 1
+    return {"metric": "served solves/s and latency vs one-at-a-time FP64", "workload": "c5",
+            "value": n / makespan, "unit": "solves/s",
+            "requests": n, "rate_per_s": rate, "mean_service_s": mean_s,
+            "p50_ms": _pct(lat_served, 50) * 1e3, "p99_ms": _pct(lat_served, 99) * 1e3,
+            "serial_p50_ms": _pct(lat_serial, 50) * 1e3, "serial_p99_ms": _pct(lat_serial, 99) * 1e3,
+            "serial_solves_per_s": n / serial_makespan, "status_counts": statuses,
+            "identical_to_alone": same}

@@ -168,60 +168,6 @@ int get_kstruct(qs3_lattice *lat, int K, std::shared_ptr<KStructure> *out, hipSt
     return QS3_OK;
 }
 
-// ---- operators for the Krylov engine
-struct U1Op : Operator {
-    qs3_sector *sec;
-    explicit U1Op(qs3_sector *s) : sec(s) {}
-    uint64_t rows() const override { return sec->dim; }
-    int cols() const override { return 1; }
-    bool is_complex() const override { return false; }
-    int apply(const double *x, double *y, hipStream_t s) override {
-        return hv_u1(sec, x, QS3_F64, y, QS3_F64, s);
-    }
-    int apply_f32in(const float *x, double *y, hipStream_t s) override {
-        return hv_u1(sec, x, QS3_F32, y, QS3_F64, s);
-    }
-};
-
-struct BatchOp : Operator {
-    qs3_batch *bat;
-    explicit BatchOp(qs3_batch *b) : bat(b) {}
-    uint64_t rows() const override { return bat->ks->n_reps; }
-    int cols() const override { return bat->B; }
-    bool is_complex() const override { return true; }
-    int apply(const double *x, double *y, hipStream_t s) override {
-        return hv_batch(bat, x, QS3_C128, y, QS3_C128, s);
-    }
-    int apply_f32in(const float *x, double *y, hipStream_t s) override {
-        return hv_batch(bat, x, QS3_C64, y, QS3_C128, s);
-    }
-};
-
-static int fill_opts(qs3_eigs_opts &o, uint64_t min_dim) {
-    if (o.nev <= 0) o.nev = 1;
-    if (o.nk <= 0) o.nk = o.nev + 5;
-    if (o.nm <= 0) o.nm = std::max(2 * o.nk, 20);
-    if (o.max_restarts <= 0) o.max_restarts = 2000;
-    if (o.steps <= 0) o.steps = 100;
-    if (!(o.tol > 0)) o.tol = 1e-9;
-    QS3_REQUIRE(o.nev <= 16, QS3_EINVAL, "nev must be <= 16");
-    QS3_REQUIRE(o.precision == QS3_PREC_F64 || o.precision == QS3_PREC_F32MV, QS3_EINVAL,
-                "unknown precision");
-    if (o.alg == QS3_ALG_TRL) {
-        QS3_REQUIRE(o.reorth != 0, QS3_EINVAL, "thick restart needs reorthogonalisation");
-        QS3_REQUIRE(o.nk > o.nev - 1 && o.nm > o.nk, QS3_EINVAL, "need nev <= nk < nm");
-        if ((uint64_t)o.nm > min_dim) {
-            // the Krylov space would exhaust the sector: plain Lanczos over it
-            o.alg = QS3_ALG_LANCZOS;
-            o.steps = (int)std::max<uint64_t>(min_dim, 1);
-        }
-    } else {
-        QS3_REQUIRE(o.alg == QS3_ALG_LANCZOS, QS3_EINVAL, "unknown algorithm");
-        if ((uint64_t)o.steps > min_dim) o.steps = (int)std::max<uint64_t>(min_dim, 1);
-    }
-    return QS3_OK;
-}
-
 }  // namespace qs3
 
 using namespace qs3;
@@ -509,11 +455,8 @@ int qs3_batch_eigs(qs3_batch *bat, const qs3_eigs_opts *opts, double *evals, qs3
     QS3_TRY(fill_opts(o, mind));
     hipStream_t s = (hipStream_t)stream;
     BatchOp op(bat);
-    Engine E;
-    int slots = o.alg == QS3_ALG_TRL ? o.nm + 1 + o.nk : o.steps + 1 + o.nev;
-    QS3_TRY(E.init(bat->lat->ctx, &op, slots, o.precision, o.reorth ? 2 : 0, s));
     DevBuf v0, seeds;
-    QS3_TRY(v0.alloc(bat->lat->ctx, sizeof(double) * E.stride));
+    QS3_TRY(v0.alloc(bat->lat->ctx, sizeof(double) * 2 * bat->ks->n_reps * (uint64_t)bat->B));
     std::vector<uint64_t> hs(bat->B);
     for (int b = 0; b < bat->B; ++b) hs[b] = o.seed + (uint64_t)b;
     QS3_TRY(seeds.alloc(bat->lat->ctx, sizeof(uint64_t) * bat->B));
@@ -521,10 +464,7 @@ int qs3_batch_eigs(qs3_batch *bat, const qs3_eigs_opts *opts, double *evals, qs3
     QS3_TRY(start_vector_batch(bat, seeds.as<uint64_t>(), v0.as<double>(), s));
     std::vector<double> ev;
     std::vector<qs3_eigs_info> inf;
-    int rc = o.alg == QS3_ALG_TRL ? solve_trl(E, v0.as<double>(), o, ev, inf, 0, nullptr)
-                                  : solve_lanczos(E, v0.as<double>(), o, ev, inf, 0, nullptr);
-    if (rc < 0) return rc;
-    QS3_HIP(hipStreamSynchronize(s));
+    QS3_TRY(solve_blocking(bat->lat->ctx, &op, o, v0.as<double>(), s, ev, inf, nullptr));
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     bool allc = true;
     for (int b = 0; b < bat->B; ++b) {
@@ -667,11 +607,9 @@ static int sector_eigs(qs3_sector *sec, qs3_eigs_opts o, std::vector<double> &ev
     std::unique_ptr<Operator> op;
     if (sec->has_k) op.reset(new BatchOp(sec->bat));
     else op.reset(new U1Op(sec));
-    Engine E;
-    int slots = o.alg == QS3_ALG_TRL ? o.nm + 1 + o.nk : o.steps + 1 + o.nev;
-    QS3_TRY(E.init(ctx, op.get(), slots, o.precision, o.reorth ? 2 : 0, s));
+    const uint64_t stride = sec->has_k ? 2 * sec->bat->ks->n_reps : sec->dim;
     DevBuf v0, vo;
-    QS3_TRY(v0.alloc(ctx, sizeof(double) * E.stride));
+    QS3_TRY(v0.alloc(ctx, sizeof(double) * stride));
     if (!sec->has_k) {
         QS3_TRY(start_vector_u1(sec, o.seed, v0.ptr, QS3_F64, s));
     } else {
@@ -681,15 +619,13 @@ static int sector_eigs(qs3_sector *sec, qs3_eigs_opts o, std::vector<double> &ev
         QS3_TRY(start_vector_batch(sec->bat, sd.as<uint64_t>(), v0.as<double>(), s));
         QS3_HIP(hipStreamSynchronize(s));
     }
-    if (evecs) QS3_TRY(vo.alloc(ctx, sizeof(double) * E.stride * o.nev));
+    if (evecs) QS3_TRY(vo.alloc(ctx, sizeof(double) * stride * o.nev));
     std::vector<qs3_eigs_info> infs;
-    int rc = o.alg == QS3_ALG_TRL ? solve_trl(E, v0.as<double>(), o, ev, infs, evecs != nullptr, vo.as<double>())
-                                  : solve_lanczos(E, v0.as<double>(), o, ev, infs, evecs != nullptr, vo.as<double>());
-    if (rc < 0) return rc;
+    QS3_TRY(solve_blocking(ctx, op.get(), o, v0.as<double>(), s, ev, infs, evecs ? vo.as<double>() : nullptr));
     inf = infs[0];
     if (evecs) {
         for (int y = 0; y < o.nev; ++y) {
-            double *src = vo.as<double>() + (size_t)y * E.stride;
+            double *src = vo.as<double>() + (size_t)y * stride;
             if (!sec->has_k)
                 QS3_HIP(hipMemcpyAsync((double *)evecs + (size_t)y * sec->dim, src,
                                        sizeof(double) * sec->dim, hipMemcpyDeviceToDevice, s));

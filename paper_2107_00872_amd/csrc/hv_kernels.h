@@ -154,6 +154,31 @@ __device__ __forceinline__ void resolve_hop(const BatchArgs &A, const Binom<RT> 
     }
 }
 
+// Hop number h of a row (down spins ascending, each site's bonds in order):
+// the spin index m and the edge e.
+template <int K>
+__device__ __forceinline__ void hop_of(int h, const int (&off)[K + 1], const int (&c)[K > 0 ? K : 1],
+                                       const int *ptr, int *m, int *e) {
+    int mm = 0;
+#pragma unroll
+    for (int t = 1; t < K; ++t) mm += (off[t] <= h) ? 1 : 0;
+    int o = 0, cm = 0;
+#pragma unroll
+    for (int t = 0; t < K; ++t) {
+        o = (t == mm) ? off[t] : o;
+        cm = (t == mm) ? c[t] : cm;
+    }
+    *m = mm;
+    *e = ptr[cm] + (h - o);
+}
+
+// The momentum kernel.  A group of G lanes owns a row; in rounds of G, lane l
+// resolves hop (round * G + l) -- its target rank, representative index and
+// translation (table lookup or canonicalisation), stabiliser ratio -- so the
+// group pays each hop's resolution once and in parallel.  The resolved hops
+// are then broadcast lane by lane with wavefront shuffles and every lane
+// applies them to its own sectors b = lane, lane + G, ... with the phase
+// e^{ik_b.t}; the gather of one hop reads G contiguous complex elements.
 template <int K, typename RT, typename CT, typename OT, bool TABLE, int BPL>
 __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restrict__ binom_g,
                                                   const typename Cplx<CT>::type *__restrict__ v,
@@ -198,47 +223,70 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
         unrank<K, RT>(R, A.L.N, Bn, c);
         HopRanker<K, RT> hr;
         hr.init(c, Bn);
+        int off[K + 1];
+        off[0] = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) off[m + 1] = off[m] + (ptr[c[m] + 1] - ptr[c[m]]);
+        const int nh = off[K];
         const CT isq = (CT)(1.0 / A.L.sqrt_tab[su]);
         CT accr[BPL], acci[BPL];
 #pragma unroll
         for (int i = 0; i < BPL; ++i) accr[i] = acci[i] = 0;
         CT dz = 0;
-        StaticFor<0, K>::run([&](auto mc) {
-            constexpr int m = decltype(mc)::value;
-            const int e0 = ptr[c[m]], e1 = ptr[c[m] + 1];
-            for (int e = e0; e < e1; ++e) {
+        for (int base = 0; base < nh; base += G) {
+            // ---- resolve hop base + lane
+            const int h = base + lane;
+            uint32_t u2 = 0, tp = 0;
+            int nt2 = -1;
+            double coef = 0.0, jzv = 0.0;
+            bool ok = false;
+            if (h < nh) {
+                int m, e;
+                hop_of<K>(h, off, c, ptr, &m, &e);
                 const int j = nbr[e];
                 RT rp;
-                const bool up = hr.template hop<m>(c, R, j, Bn, &rp);
-                if (!up) continue;
-                uint32_t u2;
-                int tx, ty, tz;
-                resolve_hop<K, RT, TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
-                const int s2 = A.stab[u2];
-                const int nt2 = s2 > 1 ? A.nt_of[u2] : -1;
-                const CT jxy = UNIF ? (CT)A.L.u_jxy_h
-                                    : (sizeof(CT) == 8 ? (CT)A.L.jxy_h[e] : (CT)A.L.jxy_hf[e]);
-                dz += UNIF ? (CT)A.L.u_jz_h : (sizeof(CT) == 8 ? (CT)A.L.jz_h[e] : (CT)A.L.jz_hf[e]);
-                const CT coef = jxy * (CT)A.L.sqrt_tab[s2] * isq;
-                const C2 *vrow = v + (uint64_t)u2 * B;
+                if (hr.hop_rt(m, c, R, j, Bn, &rp)) {
+                    int tx, ty, tz;
+                    resolve_hop<K, RT, TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
+                    const int s2 = A.stab[u2];
+                    nt2 = s2 > 1 ? A.nt_of[u2] : -1;
+                    tp = (uint32_t)(tx | (ty << 10) | (tz << 20));
+                    const double jxy = UNIF ? A.L.u_jxy_h : A.L.jxy_h[e];
+                    coef = jxy * A.L.sqrt_tab[s2] * (double)isq;
+                    jzv = UNIF ? A.L.u_jz_h : A.L.jz_h[e];
+                    ok = true;
+                }
+            }
+            // ---- apply the round's hops to this lane's sectors
+            const int cnt = min(G, nh - base);
+            for (int q = 0; q < cnt; ++q) {
+                const int bok = __shfl((int)ok, q, G);
+                if (!bok) continue;
+                const uint32_t bu = (uint32_t)__shfl((int)u2, q, G);
+                const uint32_t bt = (uint32_t)__shfl((int)tp, q, G);
+                const int bnt = __shfl(nt2, q, G);
+                const CT bc = (CT)__shfl(coef, q, G);
+                dz += (CT)__shfl(jzv, q, G);
+                const int tx = bt & 1023u, ty = (bt >> 10) & 1023u, tz = (bt >> 20) & 1023u;
+                const C2 *vrow = v + (uint64_t)bu * B;
 #pragma unroll
                 for (int i = 0; i < BPL; ++i) {
                     if (!bval[i]) continue;
                     const int b = lane + i * G;
-                    if (nt2 >= 0 && !A.compat_nt[(size_t)nt2 * B + b]) continue;
+                    if (bnt >= 0 && !A.compat_nt[(size_t)bnt * B + b]) continue;
                     int P = kx[i] * tx + ky[i] * ty + kz[i] * tz;
-                    int q = (int)((double)P * A.invM);
-                    P -= q * A.M;
+                    const int qq = (int)((double)P * A.invM);
+                    P -= qq * A.M;
                     P += (P < 0) ? A.M : 0;
                     P -= (P >= A.M) ? A.M : 0;
                     const double2 ph = A.phase[P];
                     const C2 x = vrow[b];
-                    const CT pr = coef * (CT)ph.x, pi = coef * (CT)ph.y;
+                    const CT pr = bc * (CT)ph.x, pi = bc * (CT)ph.y;
                     accr[i] += pr * x.x - pi * x.y;
                     acci[i] += pr * x.y + pi * x.x;
                 }
             }
-        });
+        }
         const CT diag = (CT)A.L.ez4 - dz;
         O2 *wrow = w + u * B;
         const C2 *vself = v + u * B;
@@ -246,9 +294,9 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
         for (int i = 0; i < BPL; ++i) {
             if (!bval[i]) continue;
             const int b = lane + i * G;
-            const bool ok = ntu < 0 || A.compat_nt[(size_t)ntu * B + b];
+            const bool okr = ntu < 0 || A.compat_nt[(size_t)ntu * B + b];
             O2 o;
-            if (ok) {
+            if (okr) {
                 C2 x = vself[b];
                 o.x = (OT)(diag * x.x + accr[i]);
                 o.y = (OT)(diag * x.y + acci[i]);

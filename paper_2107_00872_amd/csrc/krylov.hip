@@ -681,35 +681,19 @@ int Engine::read_ab(int x0, int x1, std::vector<double> &a, std::vector<double> 
     return QS3_OK;
 }
 
-int Engine::rotate(int from_slot, int NX, const std::vector<double> &Cm, int NY, int to_slot,
-                   const uint8_t *active_host) {
-    DevBuf dC;
-    QS3_TRY(dC.alloc(ctx, sizeof(double) * Cm.size()));
-    QS3_HIP(hipMemcpyAsync(dC.ptr, Cm.data(), sizeof(double) * Cm.size(), hipMemcpyHostToDevice, st));
-    const uint8_t *actd = nullptr;
-    if (active_host) {
-        QS3_HIP(hipMemcpyAsync(act.ptr, active_host, B, hipMemcpyHostToDevice, st));
-        actd = act.as<uint8_t>();
-    }
+int Engine::rotate_dev(int from_slot, int NX, const double *dC, int NY, int to_slot, const uint8_t *act_dev) {
     if (cplx)
         hipLaunchKernelGGL((k_rotate<true, 16>), grid1(ne), dim3(256), 0, st, ne, B, slot(from_slot),
-                           stride, NX, dC.as<double>(), NY, slot(to_slot), actd);
+                           stride, NX, dC, NY, slot(to_slot), act_dev);
     else
         hipLaunchKernelGGL((k_rotate<false, 16>), grid1(ne), dim3(256), 0, st, ne, B, slot(from_slot),
-                           stride, NX, dC.as<double>(), NY, slot(to_slot), actd);
+                           stride, NX, dC, NY, slot(to_slot), act_dev);
     QS3_HIP(hipGetLastError());
-    QS3_HIP(hipStreamSynchronize(st));  // dC is released at return
     return QS3_OK;
 }
 
-int Engine::copy_slot(int from, int to, const uint8_t *active_host) {
-    const uint8_t *actd = nullptr;
-    if (active_host) {
-        QS3_HIP(hipMemcpyAsync(act.ptr, active_host, B, hipMemcpyHostToDevice, st));
-        actd = act.as<uint8_t>();
-    }
-    hipLaunchKernelGGL(k_masked_copy, grid1(ne), dim3(256), 0, st, ne, B, dpe, slot(from), slot(to),
-                       actd);
+int Engine::copy_slot_dev(int from, int to, const uint8_t *act_dev) {
+    hipLaunchKernelGGL(k_masked_copy, grid1(ne), dim3(256), 0, st, ne, B, dpe, slot(from), slot(to), act_dev);
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }
@@ -723,7 +707,10 @@ static void build_tri(int m, const double *a, const double *b, std::vector<doubl
     }
 }
 
-// lowest `nev` distinct converged levels (indices into e)
+// lowest `nev` distinct levels (indices into e, ascending).  require_conv:
+// skip Ritz values that have not converged (fixed-step Lanczos, where partner
+// copies of degenerate levels emerge from rounding and never finish); else an
+// unconverged value among the wanted ones clears *all_conv.
 static std::vector<int> pick_levels(const std::vector<double> &e, const std::vector<double> &res,
                                     int nev, double tol, bool require_conv, bool *all_conv) {
     std::vector<int> out;
@@ -733,9 +720,6 @@ static std::vector<int> pick_levels(const std::vector<double> &e, const std::vec
         const double sc = std::max(1.0, std::fabs(e[i]));
         const bool conv = res[i] <= tol * sc;
         if (!conv) {
-            // fixed-step Lanczos: skip Ritz values that have not converged
-            // (e.g. partner copies of degenerate levels emerging from
-            // rounding); the restarted solver instead waits for them
             if (require_conv) continue;
             *all_conv = false;
         }
@@ -773,155 +757,254 @@ int run_lanczos(Engine &E, const double *v0, int steps, std::vector<double> &a_o
     return QS3_OK;
 }
 
-// Plain Lanczos eigensolve (QS3_ALG_LANCZOS): `steps` steps, Ritz values of T.
-int solve_lanczos(Engine &E, const double *v0, const qs3_eigs_opts &o, std::vector<double> &evals,
-                  std::vector<qs3_eigs_info> &info, int want_vecs, double *vec_out) {
-    const int B = E.B, steps = o.steps;
-    std::vector<double> a, b, n0;
-    std::vector<int> done;
-    QS3_TRY(run_lanczos(E, v0, steps, a, b, n0, done));
+// ------------------------------------------------------------------ resumable solver
+template <typename T>
+static int pinned(T **p, size_t n) {
+    void *q = nullptr;
+    QS3_HIP(hipHostMalloc(&q, sizeof(T) * std::max<size_t>(n, 1), hipHostMallocDefault));
+    *p = (T *)q;
+    return QS3_OK;
+}
+
+SolveRun::~SolveRun() {
+    if (ev) (void)hipEventDestroy(ev);
+    if (hab) (void)hipHostFree(hab);
+    if (hC) (void)hipHostFree(hC);
+    if (hact) (void)hipHostFree(hact);
+}
+
+int SolveRun::slots_for(const qs3_eigs_opts &o) {
+    return o.alg == QS3_ALG_TRL ? o.nm + 1 + o.nk : o.steps + 1 + o.nev;
+}
+
+int SolveRun::init(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &opts, hipStream_t s) {
+    o = opts;
+    QS3_TRY(E.init(ctx, op, slots_for(o), o.precision, o.reorth ? 2 : 0, s));
+    B = E.B;
+    const int NX = o.alg == QS3_ALG_TRL ? o.nm : o.steps;
+    const int NY = o.alg == QS3_ALG_TRL ? o.nk : o.nev;
+    QS3_TRY(pinned(&hab, 2 * (size_t)E.slots * B));
+    QS3_TRY(pinned(&hC, (size_t)B * NX * NY));
+    QS3_TRY(pinned(&hact, 2 * (size_t)B));
+    QS3_TRY(dC.alloc(ctx, sizeof(double) * (size_t)B * NX * NY));
+    QS3_TRY(dact.alloc(ctx, 2 * (size_t)B));
+    QS3_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     evals.assign((size_t)B * o.nev, std::numeric_limits<double>::quiet_NaN());
     info.assign(B, qs3_eigs_info{});
-    std::vector<double> Cfull((size_t)B * steps * std::max(o.nev, 1), 0.0);
-    for (int c = 0; c < B; ++c) {
-        const int m = done[c];
-        std::vector<double> T, e, V;
-        build_tri(m, &a[(size_t)c * steps], &b[(size_t)c * steps], T);
-        jacobi_eig(m, T, e, V);
-        std::vector<double> res(m);
-        const double bm = b[(size_t)c * steps + m - 1];
-        for (int i = 0; i < m; ++i) res[i] = std::fabs(bm * V[(size_t)(m - 1) * m + i]);
-        bool allc;
-        auto lv = pick_levels(e, res, o.nev, o.tol, true, &allc);
-        double mr = 0;
-        for (size_t y = 0; y < lv.size(); ++y) {
-            evals[(size_t)c * o.nev + y] = e[lv[y]];
-            mr = std::max(mr, res[lv[y]]);
-            for (int x = 0; x < m; ++x) Cfull[((size_t)c * steps + x) * o.nev + y] = V[(size_t)x * m + lv[y]];
-        }
-        info[c].converged = allc ? 1 : 0;
-        info[c].n_found = (int)lv.size();
-        info[c].max_residual = mr;
-        info[c].n_matvec = steps;
+    active.assign(B, 1);
+    final_lv.assign(B, {});
+    return QS3_OK;
+}
+
+int SolveRun::enqueue_ab_copy(int x0, int x1) {
+    const int cnt = x1 - x0;
+    if (cnt > 0) {
+        QS3_HIP(hipMemcpyAsync(hab + (size_t)x0 * B, E.ab_hist.as<double>() + (size_t)x0 * B,
+                               sizeof(double) * cnt * B, hipMemcpyDeviceToHost, E.st));
+        QS3_HIP(hipMemcpyAsync(hab + (size_t)E.slots * B + (size_t)x0 * B,
+                               E.ab_hist.as<double>() + (size_t)E.slots * B + (size_t)x0 * B,
+                               sizeof(double) * cnt * B, hipMemcpyDeviceToHost, E.st));
     }
-    if (want_vecs) {
-        // Ritz vectors: slots [steps+1 ..) hold the result temporarily
-        QS3_TRY(E.rotate(0, steps, Cfull, o.nev, steps + 1, nullptr));
-        for (int y = 0; y < o.nev; ++y)
-            QS3_HIP(hipMemcpyAsync(vec_out + (size_t)y * E.stride, E.slot(steps + 1 + y),
-                                   sizeof(double) * E.stride, hipMemcpyDeviceToDevice, E.st));
+    QS3_HIP(hipEventRecord(ev, E.st));
+    return QS3_OK;
+}
+
+bool SolveRun::ready() const { return hipEventQuery(ev) == hipSuccess; }
+
+int SolveRun::wait() {
+    QS3_HIP(hipEventSynchronize(ev));
+    return QS3_OK;
+}
+
+int SolveRun::begin(const double *v0) {
+    QS3_TRY(E.normalize_into_slot0(v0, nullptr));
+    const int steps = o.alg == QS3_ALG_TRL ? o.nm : o.steps;
+    for (int x = 0; x < steps; ++x) QS3_TRY(E.step(x, x - 1));
+    QS3_TRY(enqueue_ab_copy(0, steps));
+    phase = 1;
+    if (o.alg == QS3_ALG_TRL) {
+        al.assign(B, std::vector<double>(o.nm));
+        be.assign(B, std::vector<double>(o.nm));
+        coup.assign(B, std::vector<double>(o.nk, 0.0));
     }
     return QS3_OK;
 }
 
-// Thick-restart Lanczos (Alg. 10) for every column; columns freeze when
-// converged.  Slots: 0..NM (Krylov basis + residual), NM+1..NM+NK (rotation).
-int solve_trl(Engine &E, const double *v0, const qs3_eigs_opts &o, std::vector<double> &evals,
-              std::vector<qs3_eigs_info> &info, int want_vecs, double *vec_out) {
-    const int B = E.B, NK = o.nk, NM = o.nm, nev = o.nev;
-    evals.assign((size_t)B * nev, std::numeric_limits<double>::quiet_NaN());
-    info.assign(B, qs3_eigs_info{});
-    std::vector<uint8_t> active(B, 1);
-    std::vector<std::vector<int>> final_lv(B);
-    std::vector<double> n0;
-    QS3_TRY(E.normalize_into_slot0(v0, &n0));
-    for (int c = 0; c < B; ++c)
-        if (!(n0[c] > 0) || !std::isfinite(n0[c])) {
-            set_error("zero or non-finite start vector");
-            return QS3_ENUMERIC;
+int SolveRun::advance(bool *done) {
+    *done = false;
+    if (phase == 4) {
+        *done = true;
+        return QS3_OK;
+    }
+    const double *ha = hab, *hb = hab + (size_t)E.slots * B;
+    if (o.alg == QS3_ALG_LANCZOS) {
+        if (phase == 3) {
+            phase = 4;
+            *done = true;
+            return QS3_OK;
         }
-    // first cycle: steps 0..NM-1
-    for (int x = 0; x < NM; ++x) QS3_TRY(E.step(x, x - 1));
-    std::vector<double> a, bb;
-    QS3_TRY(E.read_ab(0, NM, a, bb));
-    // per-column tridiagonal/arrowhead state
-    std::vector<std::vector<double>> al(B, std::vector<double>(NM)), be(B, std::vector<double>(NM));
-    std::vector<std::vector<double>> coup(B, std::vector<double>(NK, 0.0));
-    for (int c = 0; c < B; ++c)
-        for (int x = 0; x < NM; ++x) {
-            al[c][x] = a[(size_t)x * B + c];
-            be[c][x] = bb[(size_t)x * B + c];
-        }
-    bool first = true;
-    int restarts = 0;
-    std::vector<double> Crot((size_t)B * NM * NK, 0.0);
-    while (true) {
-        bool any_active = false;
+        const int S = o.steps, nev = o.nev;
+        std::fill(hC, hC + (size_t)B * S * nev, 0.0);
         for (int c = 0; c < B; ++c) {
-            if (!active[c]) continue;
-            std::vector<double> T((size_t)NM * NM, 0.0), e, V;
-            for (int x = 0; x < NM; ++x) T[(size_t)x * NM + x] = al[c][x];
-            if (first) {
-                for (int x = 0; x + 1 < NM; ++x) T[(size_t)x * NM + x + 1] = T[(size_t)(x + 1) * NM + x] = be[c][x];
-            } else {
-                for (int y = 0; y < NK; ++y) T[(size_t)y * NM + NK] = T[(size_t)NK * NM + y] = coup[c][y];
-                for (int z = NK; z + 1 < NM; ++z) T[(size_t)z * NM + z + 1] = T[(size_t)(z + 1) * NM + z] = be[c][z];
+            int m = S;
+            for (int x = 0; x < S; ++x)
+                if (hb[(size_t)x * B + c] <= 1e-14 * std::max(1.0, std::fabs(ha[(size_t)x * B + c]))) {
+                    m = x + 1;
+                    break;
+                }
+            std::vector<double> a(m), b(m), T, e, V;
+            for (int x = 0; x < m; ++x) {
+                a[x] = ha[(size_t)x * B + c];
+                b[x] = hb[(size_t)x * B + c];
             }
-            jacobi_eig(NM, T, e, V);
-            const double bm = be[c][NM - 1];
-            std::vector<double> res(NM);
-            for (int i = 0; i < NM; ++i) res[i] = std::fabs(bm * V[(size_t)(NM - 1) * NM + i]);
+            build_tri(m, a.data(), b.data(), T);
+            jacobi_eig(m, T, e, V);
+            std::vector<double> res(m);
+            for (int i = 0; i < m; ++i) res[i] = std::fabs(b[m - 1] * V[(size_t)(m - 1) * m + i]);
             bool allc;
-            auto lv = pick_levels(std::vector<double>(e.begin(), e.begin() + NK),
-                                  std::vector<double>(res.begin(), res.begin() + NK), nev, o.tol,
-                                  false, &allc);
-            // every Ritz value below the highest wanted level must have converged
-            if (allc && !lv.empty()) {
-                const double top = e[lv.back()];
-                for (int i = 0; i < NK; ++i)
-                    if (e[i] <= top + 1e-8 * std::max(1.0, std::fabs(top)) &&
-                        res[i] > o.tol * std::max(1.0, std::fabs(e[i])))
-                        allc = false;
-            }
-            // rotation coefficients (Ritz vectors y < NK) and arrowhead couplings
-            for (int x = 0; x < NM; ++x)
-                for (int y = 0; y < NK; ++y) Crot[((size_t)c * NM + x) * NK + y] = V[(size_t)x * NM + y];
-            for (int y = 0; y < NK; ++y) {
-                coup[c][y] = bm * V[(size_t)(NM - 1) * NM + y];
-                al[c][y] = e[y];
-            }
+            auto lv = pick_levels(e, res, nev, o.tol, true, &allc);
+            // a Krylov space that closed (breakdown) or spans every row holds
+            // all the levels the start vector reaches: fewer than nev is final
+            const bool exhausted = m < S || (uint64_t)S >= E.n;
+            if (exhausted && !lv.empty()) allc = true;
             double mr = 0;
             for (size_t y = 0; y < lv.size(); ++y) {
                 evals[(size_t)c * nev + y] = e[lv[y]];
                 mr = std::max(mr, res[lv[y]]);
+                for (int x = 0; x < m; ++x) hC[((size_t)c * S + x) * nev + y] = V[(size_t)x * m + lv[y]];
             }
+            info[c].converged = allc ? 1 : 0;
             info[c].n_found = (int)lv.size();
             info[c].max_residual = mr;
-            info[c].n_restarts = restarts;
-            final_lv[c] = lv;
-            if (allc) {
-                info[c].converged = 1;
-            } else {
-                any_active = true;
-            }
+            info[c].n_matvec = E.n_matvec;
         }
-        // Ritz vectors into slots NM+1.., then back into 0..NK-1; residual to NK
-        QS3_TRY(E.rotate(0, NM, Crot, NK, NM + 1, active.data()));
-        for (int y = 0; y < NK; ++y) QS3_TRY(E.copy_slot(NM + 1 + y, y, active.data()));
-        for (int c = 0; c < B; ++c)
-            if (info[c].converged) active[c] = 0;
-        if (!any_active || restarts >= o.max_restarts) break;
-        QS3_TRY(E.copy_slot(NM, NK, active.data()));
-        // restart cycle: x = NK (no three-term partner: the couplings to the
-        // kept Ritz vectors are removed by the full reorthogonalisation), then
-        // x = NK+1..NM-1
-        QS3_TRY(E.step(NK, -1));
-        for (int x = NK + 1; x < NM; ++x) QS3_TRY(E.step(x, x - 1));
-        QS3_TRY(E.read_ab(NK, NM, a, bb));
-        for (int c = 0; c < B; ++c)
-            for (int x = NK; x < NM; ++x) {
-                al[c][x] = a[(size_t)x * B + c];
-                be[c][x] = bb[(size_t)x * B + c];
-            }
-        first = false;
-        ++restarts;
+        if (want_vecs) {
+            QS3_HIP(hipMemcpyAsync(dC.ptr, hC, sizeof(double) * (size_t)B * S * nev, hipMemcpyHostToDevice, E.st));
+            QS3_TRY(E.rotate_dev(0, S, dC.as<double>(), nev, S + 1, nullptr));
+            QS3_HIP(hipEventRecord(ev, E.st));
+            phase = 3;
+            return QS3_OK;
+        }
+        phase = 4;
+        *done = true;
+        return QS3_OK;
     }
-    for (int c = 0; c < B; ++c) info[c].n_matvec = E.n_matvec;
-    if (want_vecs) {
-        // the wanted levels' Ritz vectors are slots final_lv (single column use)
-        for (int y = 0; y < nev && y < (int)final_lv[0].size(); ++y)
-            QS3_HIP(hipMemcpyAsync(vec_out + (size_t)y * E.stride, E.slot(final_lv[0][y]),
-                                   sizeof(double) * E.stride, hipMemcpyDeviceToDevice, E.st));
+    // ---- thick restart (Alg. 10)
+    const int NK = o.nk, NM = o.nm, nev = o.nev;
+    const int x0 = first ? 0 : NK;
+    for (int c = 0; c < B; ++c)
+        for (int x = x0; x < NM; ++x) {
+            al[c][x] = ha[(size_t)x * B + c];
+            be[c][x] = hb[(size_t)x * B + c];
+        }
+    bool any_active = false;
+    uint8_t *act_rot = hact, *act_next = hact + B;
+    for (int c = 0; c < B; ++c) {
+        act_rot[c] = active[c];
+        if (!active[c]) continue;
+        std::vector<double> T((size_t)NM * NM, 0.0), e, V;
+        for (int x = 0; x < NM; ++x) T[(size_t)x * NM + x] = al[c][x];
+        if (first) {
+            for (int x = 0; x + 1 < NM; ++x) T[(size_t)x * NM + x + 1] = T[(size_t)(x + 1) * NM + x] = be[c][x];
+        } else {
+            for (int y = 0; y < NK; ++y) T[(size_t)y * NM + NK] = T[(size_t)NK * NM + y] = coup[c][y];
+            for (int z = NK; z + 1 < NM; ++z) T[(size_t)z * NM + z + 1] = T[(size_t)(z + 1) * NM + z] = be[c][z];
+        }
+        jacobi_eig(NM, T, e, V);
+        const double bm = be[c][NM - 1];
+        std::vector<double> res(NM);
+        for (int i = 0; i < NM; ++i) res[i] = std::fabs(bm * V[(size_t)(NM - 1) * NM + i]);
+        bool allc;
+        auto lv = pick_levels(std::vector<double>(e.begin(), e.begin() + NK),
+                              std::vector<double>(res.begin(), res.begin() + NK), nev, o.tol, false, &allc);
+        // every Ritz value below the highest wanted level must have converged
+        if (allc && !lv.empty()) {
+            const double top = e[lv.back()];
+            for (int i = 0; i < NK; ++i)
+                if (e[i] <= top + 1e-8 * std::max(1.0, std::fabs(top)) &&
+                    res[i] > o.tol * std::max(1.0, std::fabs(e[i])))
+                    allc = false;
+        }
+        for (int x = 0; x < NM; ++x)
+            for (int y = 0; y < NK; ++y) hC[((size_t)c * NM + x) * NK + y] = V[(size_t)x * NM + y];
+        for (int y = 0; y < NK; ++y) {
+            coup[c][y] = bm * V[(size_t)(NM - 1) * NM + y];
+            al[c][y] = e[y];
+        }
+        double mr = 0;
+        for (size_t y = 0; y < lv.size(); ++y) {
+            evals[(size_t)c * nev + y] = e[lv[y]];
+            mr = std::max(mr, res[lv[y]]);
+        }
+        info[c].n_found = (int)lv.size();
+        info[c].max_residual = mr;
+        info[c].n_restarts = restarts;
+        info[c].n_matvec = E.n_matvec;
+        final_lv[c] = lv;
+        if (allc) info[c].converged = 1;
+        else any_active = true;
+    }
+    for (int c = 0; c < B; ++c) {
+        if (info[c].converged) active[c] = 0;
+        act_next[c] = active[c];
+    }
+    // Ritz vectors into slots NM+1.., then back into 0..NK-1 (rotated columns)
+    QS3_HIP(hipMemcpyAsync(dC.ptr, hC, sizeof(double) * (size_t)B * NM * NK, hipMemcpyHostToDevice, E.st));
+    QS3_HIP(hipMemcpyAsync(dact.ptr, hact, 2 * (size_t)B, hipMemcpyHostToDevice, E.st));
+    const uint8_t *d_rot = dact.as<uint8_t>(), *d_next = dact.as<uint8_t>() + B;
+    QS3_TRY(E.rotate_dev(0, NM, dC.as<double>(), NK, NM + 1, d_rot));
+    for (int y = 0; y < NK; ++y) QS3_TRY(E.copy_slot_dev(NM + 1 + y, y, d_rot));
+    if (!any_active || restarts >= o.max_restarts) {
+        QS3_HIP(hipEventRecord(ev, E.st));
+        phase = 4;
+        *done = true;
+        return QS3_OK;
+    }
+    // restart cycle: the residual becomes psi_{NK+1}; the first step has no
+    // three-term partner (the couplings to the kept Ritz vectors are removed by
+    // the full reorthogonalisation), then x = NK+1..NM-1
+    QS3_TRY(E.copy_slot_dev(NM, NK, d_next));
+    QS3_TRY(E.step(NK, -1));
+    for (int x = NK + 1; x < NM; ++x) QS3_TRY(E.step(x, x - 1));
+    QS3_TRY(enqueue_ab_copy(NK, NM));
+    first = false;
+    ++restarts;
+    phase = 2;
+    return QS3_OK;
+}
+
+int SolveRun::vec_slot(int col, int y) const {
+    if (o.alg == QS3_ALG_TRL) return y < (int)final_lv[col].size() ? final_lv[col][y] : -1;
+    return o.steps + 1 + y;
+}
+
+static int run_blocking(SolveRun &R, const double *v0) {
+    QS3_TRY(R.begin(v0));
+    bool done = false;
+    while (!done) {
+        QS3_TRY(R.wait());
+        QS3_TRY(R.advance(&done));
+    }
+    QS3_TRY(R.wait());
+    return QS3_OK;
+}
+
+int solve_blocking(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &o, const double *v0, hipStream_t s,
+                   std::vector<double> &evals, std::vector<qs3_eigs_info> &info, double *vec_out) {
+    SolveRun R;
+    R.want_vecs = vec_out != nullptr;
+    QS3_TRY(R.init(ctx, op, o, s));
+    QS3_TRY(run_blocking(R, v0));
+    evals = R.evals;
+    info = R.info;
+    if (vec_out) {
+        for (int y = 0; y < o.nev; ++y) {
+            const int sl = R.vec_slot(0, y);
+            if (sl < 0) continue;
+            QS3_HIP(hipMemcpyAsync(vec_out + (size_t)y * R.E.stride, R.E.slot(sl), sizeof(double) * R.E.stride,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+        QS3_HIP(hipStreamSynchronize(s));
     }
     return QS3_OK;
 }

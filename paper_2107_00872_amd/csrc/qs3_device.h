@@ -103,6 +103,24 @@ struct HopRanker {
         *out = R - Bt[M] + corr + B.C(j, p + 1);
         return !down;
     }
+    // the same with a run-time spin index m (branch-free selects)
+    __host__ __device__ __forceinline__ bool hop_rt(int m, const int (&c)[K > 0 ? K : 1], RT R, int j,
+                                                    const Binom<RT> &B, RT *out) const {
+        bool down = false;
+        int p = 0;
+        RT corr = 0, bm = 0;
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            const bool self = t == m;
+            const bool lt = c[t] < j;
+            down |= !self && (c[t] == j);
+            p += (!self && lt) ? 1 : 0;
+            corr += self ? (RT)0 : (t < m ? (lt ? (RT)0 : dU[t]) : (lt ? dD[t] : (RT)0));
+            bm = self ? Bt[t] : bm;
+        }
+        *out = R - bm + corr + B.C(j, p + 1);
+        return !down;
+    }
 };
 
 // ---------------------------------------------------------------------------

@@ -1,5 +1,6 @@
 // Krylov engine interface (internal).
 #pragma once
+#include <algorithm>
 #include <vector>
 
 #include "qs3_impl.h"
@@ -47,18 +48,106 @@ struct Engine {
     int step(int x, int prev);
     int normalize_into_slot0(const double *v0, std::vector<double> *norms0);
     int read_ab(int x0, int x1, std::vector<double> &a, std::vector<double> &b);
-    int rotate(int from_slot, int NX, const std::vector<double> &Cm, int NY, int to_slot,
-               const uint8_t *active_host);
-    int copy_slot(int from, int to, const uint8_t *active_host);
+    int rotate_dev(int from_slot, int NX, const double *dC, int NY, int to_slot, const uint8_t *act_dev);
+    int copy_slot_dev(int from, int to, const uint8_t *act_dev);
 };
+
+// A Lanczos / thick-restart Lanczos solve that advances without blocking:
+// begin() enqueues the first cycle, ready() polls its event, advance() does
+// the host part (tridiagonal / arrowhead eigensolves, convergence) and
+// enqueues the next cycle.  Every column is a separate sector and stops
+// changing once it has converged.
+struct SolveRun {
+    Engine E;
+    qs3_eigs_opts o{};
+    int B = 1;
+    bool want_vecs = false;
+    int phase = 0;  // 1 first cycle, 2 restart cycle, 3 final rotation, 4 done
+    bool first = true;
+    int restarts = 0;
+    double *hab = nullptr, *hC = nullptr;
+    uint8_t *hact = nullptr;
+    DevBuf dC, dact;
+    hipEvent_t ev = nullptr;
+    std::vector<std::vector<double>> al, be, coup;
+    std::vector<uint8_t> active;
+    std::vector<std::vector<int>> final_lv;
+    std::vector<double> evals;
+    std::vector<qs3_eigs_info> info;
+    ~SolveRun();
+    static int slots_for(const qs3_eigs_opts &o);
+    int init(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &opts, hipStream_t s);
+    int begin(const double *v0);
+    bool ready() const;
+    int wait();
+    int advance(bool *done);
+    int vec_slot(int col, int y) const;
+
+   private:
+    int enqueue_ab_copy(int x0, int x1);
+};
+
+int solve_blocking(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &o, const double *v0, hipStream_t s,
+                   std::vector<double> &evals, std::vector<qs3_eigs_info> &info, double *vec_out);
 
 void jacobi_eig(int n, std::vector<double> &A, std::vector<double> &e, std::vector<double> &V);
 int run_lanczos(Engine &E, const double *v0, int steps, std::vector<double> &a_out,
                 std::vector<double> &b_out, std::vector<double> &norm0, std::vector<int> &done);
-int solve_lanczos(Engine &E, const double *v0, const qs3_eigs_opts &o, std::vector<double> &evals,
-                  std::vector<qs3_eigs_info> &info, int want_vecs, double *vec_out);
-int solve_trl(Engine &E, const double *v0, const qs3_eigs_opts &o, std::vector<double> &evals,
-              std::vector<qs3_eigs_info> &info, int want_vecs, double *vec_out);
+
+// ---- operators for the Krylov engine
+struct U1Op : Operator {
+    qs3_sector *sec;
+    explicit U1Op(qs3_sector *s) : sec(s) {}
+    uint64_t rows() const override { return sec->dim; }
+    int cols() const override { return 1; }
+    bool is_complex() const override { return false; }
+    int apply(const double *x, double *y, hipStream_t s) override {
+        return hv_u1(sec, x, QS3_F64, y, QS3_F64, s);
+    }
+    int apply_f32in(const float *x, double *y, hipStream_t s) override {
+        return hv_u1(sec, x, QS3_F32, y, QS3_F64, s);
+    }
+};
+
+struct BatchOp : Operator {
+    qs3_batch *bat;
+    explicit BatchOp(qs3_batch *b) : bat(b) {}
+    uint64_t rows() const override { return bat->ks->n_reps; }
+    int cols() const override { return bat->B; }
+    bool is_complex() const override { return true; }
+    int apply(const double *x, double *y, hipStream_t s) override {
+        return hv_batch(bat, x, QS3_C128, y, QS3_C128, s);
+    }
+    int apply_f32in(const float *x, double *y, hipStream_t s) override {
+        return hv_batch(bat, x, QS3_C64, y, QS3_C128, s);
+    }
+};
+
+inline int fill_opts(qs3_eigs_opts &o, uint64_t min_dim) {
+    if (o.nev <= 0) o.nev = 1;
+    if (o.nk <= 0) o.nk = o.nev + 5;
+    if (o.nm <= 0) o.nm = std::max(2 * o.nk, 20);
+    if (o.max_restarts <= 0) o.max_restarts = 2000;
+    if (o.steps <= 0) o.steps = 100;
+    if (!(o.tol > 0)) o.tol = 1e-9;
+    QS3_REQUIRE(o.nev <= 16, QS3_EINVAL, "nev must be <= 16");
+    QS3_REQUIRE(o.precision == QS3_PREC_F64 || o.precision == QS3_PREC_F32MV, QS3_EINVAL,
+                "unknown precision");
+    if (o.alg == QS3_ALG_TRL) {
+        QS3_REQUIRE(o.reorth != 0, QS3_EINVAL, "thick restart needs reorthogonalisation");
+        QS3_REQUIRE(o.nk > o.nev - 1 && o.nm > o.nk, QS3_EINVAL, "need nev <= nk < nm");
+        if ((uint64_t)o.nm > min_dim) {
+            // the Krylov space would exhaust the sector: plain Lanczos over it
+            o.alg = QS3_ALG_LANCZOS;
+            o.steps = (int)std::max<uint64_t>(min_dim, 1);
+        }
+    } else {
+        QS3_REQUIRE(o.alg == QS3_ALG_LANCZOS, QS3_EINVAL, "unknown algorithm");
+        if ((uint64_t)o.steps > min_dim) o.steps = (int)std::max<uint64_t>(min_dim, 1);
+    }
+    return QS3_OK;
+}
+
 
 int scatter_compact_f32(qs3_sector *sec, const float *src, float *dst_union, hipStream_t s);
 int gather_compact_f32(qs3_sector *sec, const float *src_union, float *dst, hipStream_t s);
