@@ -51,6 +51,7 @@ BatchArgs batch_args(qs3_batch *bat) {
     A.M = bat->M;
     A.invM = 1.0 / bat->M;
     A.phase = bat->phase.as<double2>();
+    A.active = bat->active_dev;
     return A;
 }
 
@@ -144,6 +145,14 @@ int row_k(qs3_sector *sec, uint64_t row, int cap, int64_t *cols, double *vals, d
         cols[i] = (it != c2u.end() && *it == cols[i]) ? (int64_t)(it - c2u.begin()) : -1;
     }
     return QS3_OK;
+}
+
+#define QS3_SMALL(k) lanczos_small_K<k>(lat, bt, bat, S, s)
+#define QS3_SMALL_HI QS3_SMALL
+int lanczos_small(qs3_lattice *lat, int K, const BinomTable *bt, qs3_batch *bat, const SmallArgs &S,
+                  hipStream_t s) {
+    if (S.slots + 2 > 520 || S.n > 65536) return 1;
+    QS3_SWITCH_K(K, 8, QS3_SMALL)
 }
 
 #define QS3_BUILD(k) build_kstruct_K<k>(lat, *bt, ks, s)

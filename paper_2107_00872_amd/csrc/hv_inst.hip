@@ -157,6 +157,31 @@ int obs_u1_K<KI>(qs3_sector *sec, const double *phi, int npairs, const int32_t *
     return obs_u1_t<uint32_t>(sec, phi, npairs, pi, pj, p_site, q, pm, s);
 }
 
+// ------------------------------------------------------------------ small sectors
+template <typename RT, bool CPLX, bool TABLE>
+static int small_t(qs3_lattice *lat, const BinomTable *bt, qs3_batch *bat, const SmallArgs &S, hipStream_t s) {
+    BatchArgs A{};
+    if (bat) A = batch_args(bat);
+    else A.L = lat_args(lat);
+    const size_t sh = lds_need<RT>(lat, KI);
+    QS3_REQUIRE(sh <= 64 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
+    hipLaunchKernelGGL((k_lanczos_small<KI, RT, CPLX, TABLE>), dim3(1), dim3(1024), sh, s, S, A, bt->dev.as<RT>());
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+template <>
+int lanczos_small_K<KI>(qs3_lattice *lat, const BinomTable *bt, qs3_batch *bat, const SmallArgs &S, hipStream_t s) {
+    if (bt->wide) return 1;  // small sectors never need 64-bit ranks
+    if (!bat) return small_t<uint32_t, false, false>(lat, bt, bat, S, s);
+#if QS3_INST_K <= 6
+    if (bat->ks->has_table) return small_t<uint32_t, true, true>(lat, bt, bat, S, s);
+    return small_t<uint32_t, true, false>(lat, bt, bat, S, s);
+#else
+    return 1;
+#endif
+}
+
 #if QS3_INST_K <= 6
 // ------------------------------------------------------------------ momentum batches
 template <typename RT, typename CT, typename OT, bool TABLE>

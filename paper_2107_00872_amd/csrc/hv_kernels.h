@@ -70,6 +70,51 @@ static size_t lds_bytes(const qs3_lattice *lat, int K) {
 }
 
 // ------------------------------------------------------------------ U(1)
+// One output row of the fixed-N_down H.v (Alg. 9 with sigma = all ranks):
+// the Ising diagonal E_FM - sum over (down site, up neighbour) of Jz/2, and
+// Jxy/2 v[rank'] for every hop of a down spin to an up neighbour.
+template <int K, typename RT, typename VT>
+__device__ __forceinline__ VT hv_row_u1(const LatArgs &L, const Binom<RT> &Bn, const int *ptr,
+                                        const uint16_t *nbr, RT row, const VT *__restrict__ v) {
+    const bool UNIF = L.uniform != 0;
+    int c[K > 0 ? K : 1];
+    unrank<K, RT>(row, L.N, Bn, c);
+    HopRanker<K, RT> hr;
+    hr.init(c, Bn);
+    VT acc = 0, dz = 0;
+    StaticFor<0, K>::run([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        const int e0 = ptr[c[m]], e1 = ptr[c[m] + 1];
+        for (int e = e0; e < e1; ++e) {
+            const int j = nbr[e];
+            RT rp;
+            const bool up = hr.template hop<m>(c, row, j, Bn, &rp);
+            if (up) {
+                const VT x = v[rp];
+                if (UNIF) {
+                    acc += x;
+                    dz += (VT)1;
+                } else if (sizeof(VT) == 8) {
+                    acc += (VT)L.jxy_h[e] * x;
+                    dz += (VT)L.jz_h[e];
+                } else {
+                    acc += (VT)L.jxy_hf[e] * x;
+                    dz += (VT)L.jz_hf[e];
+                }
+            }
+        }
+    });
+    VT diag, off;
+    if (UNIF) {
+        diag = (VT)L.ez4 - (VT)L.u_jz_h * dz;
+        off = (VT)L.u_jxy_h * acc;
+    } else {
+        diag = (VT)L.ez4 - dz;
+        off = acc;
+    }
+    return diag * v[row] + off;
+}
+
 template <int K, typename RT, typename VT, typename OT>
 __global__ __launch_bounds__(256) void k_hv_u1(LatArgs L, const RT *__restrict__ binom_g, RT D,
                                                const VT *__restrict__ v, OT *__restrict__ w) {
@@ -83,48 +128,10 @@ __global__ __launch_bounds__(256) void k_hv_u1(LatArgs L, const RT *__restrict__
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const uint64_t ntiles = ((uint64_t)D + 255) / 256;
     const uint64_t t0 = ntiles * lb / gridDim.x, t1 = ntiles * (lb + 1) / gridDim.x;
-    const VT jxy_u = (VT)L.u_jxy_h, jz_u = (VT)L.u_jz_h, ez4 = (VT)L.ez4;
-    const bool UNIF = L.uniform != 0;
     for (uint64_t tile = t0; tile < t1; ++tile) {
         const uint64_t row64 = tile * 256 + threadIdx.x;
         if (row64 >= (uint64_t)D) break;
-        const RT row = (RT)row64;
-        int c[K > 0 ? K : 1];
-        unrank<K, RT>(row, L.N, Bn, c);
-        HopRanker<K, RT> hr;
-        hr.init(c, Bn);
-        VT acc = 0, dz = 0;
-        StaticFor<0, K>::run([&](auto mc) {
-            constexpr int m = decltype(mc)::value;
-            const int e0 = ptr[c[m]], e1 = ptr[c[m] + 1];
-            for (int e = e0; e < e1; ++e) {
-                const int j = nbr[e];
-                RT rp;
-                const bool up = hr.template hop<m>(c, row, j, Bn, &rp);
-                if (up) {
-                    const VT x = v[rp];
-                    if (UNIF) {
-                        acc += x;
-                        dz += (VT)1;
-                    } else if (sizeof(VT) == 8) {
-                        acc += (VT)L.jxy_h[e] * x;
-                        dz += (VT)L.jz_h[e];
-                    } else {
-                        acc += (VT)L.jxy_hf[e] * x;
-                        dz += (VT)L.jz_hf[e];
-                    }
-                }
-            }
-        });
-        VT diag, off;
-        if (UNIF) {
-            diag = ez4 - jz_u * dz;
-            off = jxy_u * acc;
-        } else {
-            diag = ez4 - dz;
-            off = acc;
-        }
-        w[row] = (OT)(diag * v[row] + off);
+        w[row64] = (OT)hv_row_u1<K, RT, VT>(L, Bn, ptr, nbr, (RT)row64, v);
     }
 }
 
@@ -203,7 +210,7 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
 #pragma unroll
     for (int i = 0; i < BPL; ++i) {
         int b = lane + i * G;
-        bval[i] = b < B;
+        bval[i] = b < B && (!A.active || A.active[b < B ? b : 0]);
         int bb = bval[i] ? b : 0;
         kx[i] = A.kmul[3 * bb];
         ky[i] = A.kmul[3 * bb + 1];
@@ -572,6 +579,215 @@ __global__ void k_row_k(BatchArgs A, const RT *binom_g, uint64_t u, int cap, int
     });
     *diag = A.L.ez4 - dz;
     *nnz = n;
+}
+
+
+// ------------------------------------------------------------------ small sectors
+// One row of a single momentum sector (a batch of one, union layout), hops
+// resolved one after the other.
+template <int K, typename RT, bool TABLE>
+__device__ __forceinline__ double2 hv_row_k1(const BatchArgs &A, const Binom<RT> &Bn, const Geom &g,
+                                             const int *ptr, const uint16_t *nbr, uint64_t u,
+                                             const double2 *__restrict__ v) {
+    const int su = A.stab[u];
+    if (su > 1 && !A.compat_nt[A.nt_of[u]]) return make_double2(0.0, 0.0);
+    const bool UNIF = A.L.uniform != 0;
+    const RT R = (RT)A.reps[u];
+    int c[K > 0 ? K : 1];
+    unrank<K, RT>(R, A.L.N, Bn, c);
+    HopRanker<K, RT> hr;
+    hr.init(c, Bn);
+    const double isq = 1.0 / A.L.sqrt_tab[su];
+    double ar = 0, ai = 0, dz = 0;
+    StaticFor<0, K>::run([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        for (int e = ptr[c[m]]; e < ptr[c[m] + 1]; ++e) {
+            const int j = nbr[e];
+            RT rp;
+            if (!hr.template hop<m>(c, R, j, Bn, &rp)) continue;
+            uint32_t u2;
+            int tx, ty, tz;
+            resolve_hop<K, RT, TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
+            dz += UNIF ? A.L.u_jz_h : A.L.jz_h[e];
+            const int s2 = A.stab[u2];
+            if (s2 > 1 && !A.compat_nt[A.nt_of[u2]]) continue;
+            const double coef = (UNIF ? A.L.u_jxy_h : A.L.jxy_h[e]) * A.L.sqrt_tab[s2] * isq;
+            int P = A.kmul[0] * tx + A.kmul[1] * ty + A.kmul[2] * tz;
+            P %= A.M;
+            const double2 ph = A.phase[P], x = v[u2];
+            const double pr = coef * ph.x, pi = coef * ph.y;
+            ar += pr * x.x - pi * x.y;
+            ai += pr * x.y + pi * x.x;
+        }
+    });
+    const double diag = A.L.ez4 - dz;
+    const double2 x = v[u];
+    return make_double2(diag * x.x + ar, diag * x.y + ai);
+}
+
+
+
+__device__ __forceinline__ void dot_acc(double x, double y, double2 &s) { s.x += x * y; }
+__device__ __forceinline__ void dot_acc(double2 x, double2 y, double2 &s) {
+    s.x += x.x * y.x + x.y * y.y;
+    s.y += x.x * y.y - x.y * y.x;
+}
+__device__ __forceinline__ double2 wave_sum2(double2 v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        v.x += __shfl_down(v.x, off, 64);
+        v.y += __shfl_down(v.y, off, 64);
+    }
+    return v;
+}
+
+// Sum over the workgroup, fixed order (waves in order), result in every thread.
+__device__ __forceinline__ double2 block_sum_all(double2 v, double2 *red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum2(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double2 s = make_double2(0.0, 0.0);
+    for (int q = 0; q < nw; ++q) {
+        s.x += red[q].x;
+        s.y += red[q].y;
+    }
+    return s;
+}
+
+// A whole Lanczos cycle of one small sector in one workgroup: H.v rows, alpha,
+// the three-term update, classical Gram-Schmidt against every earlier vector
+// (the second pass where the first cancelled more than half of |w|^2) and the
+// normalisation, with the Krylov basis in global memory (it stays in L2 for
+// the sizes this kernel is used for).  CPLX: momentum sector (union layout),
+// else fixed-N_down.
+template <int K, typename RT, bool CPLX, bool TABLE>
+__global__ __launch_bounds__(1024) void k_lanczos_small(SmallArgs S, BatchArgs A, const RT *__restrict__ binom_g) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double2 red[16];
+    __shared__ double2 hsh[520];
+    const RT *tab;
+    const int *ptr;
+    const uint16_t *nbr;
+    load_lds_tables<RT>(smem, A.L, binom_g, K, &tab, &ptr, &nbr);
+    Binom<RT> Bn{tab, A.L.N + 1};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    const uint64_t n = S.n;
+    auto P = [&](int j) { return S.Psi + (size_t)j * S.stride; };
+    for (int x = S.x0; x < S.x1; ++x) {
+        const int prev = (x == S.x0) ? S.prev_first : x - 1;
+        // ---- W = H psi_x
+        if (CPLX) {
+            const double2 *px = (const double2 *)P(x);
+            for (uint64_t r = tid; r < n; r += nt)
+                ((double2 *)S.W)[r] = hv_row_k1<K, RT, TABLE>(A, Bn, g, ptr, nbr, r, px);
+        } else {
+            const double *px = P(x);
+            for (uint64_t r = tid; r < n; r += nt) S.W[r] = hv_row_u1<K, RT, double>(A.L, Bn, ptr, nbr, (RT)r, px);
+        }
+        __syncthreads();
+        // ---- alpha = Re <psi_x, W>; W -= alpha psi_x + beta_prev psi_prev
+        double2 s = make_double2(0.0, 0.0);
+        for (uint64_t r = tid; r < n; r += nt) {
+            if (CPLX) dot_acc(((const double2 *)P(x))[r], ((const double2 *)S.W)[r], s);
+            else dot_acc(P(x)[r], S.W[r], s);
+        }
+        const double a = block_sum_all(s, red).x;
+        const double bp = prev >= 0 ? S.ab[S.slots + prev] : 0.0;
+        for (uint64_t r = tid; r < n; r += nt) {
+            if (CPLX) {
+                double2 w = ((double2 *)S.W)[r];
+                const double2 p0 = ((const double2 *)P(x))[r];
+                w.x -= a * p0.x;
+                w.y -= a * p0.y;
+                if (prev >= 0) {
+                    const double2 p1 = ((const double2 *)P(prev))[r];
+                    w.x -= bp * p1.x;
+                    w.y -= bp * p1.y;
+                }
+                ((double2 *)S.W)[r] = w;
+            } else {
+                double w = S.W[r] - a * P(x)[r];
+                if (prev >= 0) w -= bp * P(prev)[r];
+                S.W[r] = w;
+            }
+        }
+        if (tid == 0) S.ab[x] = a;
+        __syncthreads();
+        // ---- classical Gram-Schmidt against slots 0..x: one pass, and a
+        // second where the first cancelled more than half of |W|^2
+        auto cgs_dots = [&](bool self) {
+            for (int j = wave; j <= x + (self ? 1 : 0); j += nw) {
+                double2 h = make_double2(0.0, 0.0);
+                for (uint64_t r = lane; r < n; r += 64) {
+                    if (CPLX) {
+                        const double2 w = ((const double2 *)S.W)[r];
+                        dot_acc(j <= x ? ((const double2 *)P(j))[r] : w, w, h);
+                    } else {
+                        const double w = S.W[r];
+                        dot_acc(j <= x ? P(j)[r] : w, w, h);
+                    }
+                }
+                h = wave_sum2(h);
+                if (lane == 0) hsh[j] = h;
+            }
+            __syncthreads();
+        };
+        auto cgs_update = [&]() -> double {
+            double2 acc = make_double2(0.0, 0.0);
+            for (uint64_t r = tid; r < n; r += nt) {
+                if (CPLX) {
+                    double2 w = ((double2 *)S.W)[r];
+                    for (int j = 0; j <= x; ++j) {
+                        const double2 xj = ((const double2 *)P(j))[r], c = hsh[j];
+                        w.x -= xj.x * c.x - xj.y * c.y;
+                        w.y -= xj.x * c.y + xj.y * c.x;
+                    }
+                    ((double2 *)S.W)[r] = w;
+                    acc.x += w.x * w.x + w.y * w.y;
+                } else {
+                    double w = S.W[r];
+                    for (int j = 0; j <= x; ++j) w -= P(j)[r] * hsh[j].x;
+                    S.W[r] = w;
+                    acc.x += w * w;
+                }
+            }
+            return block_sum_all(acc, red).x;
+        };
+        double nrm2;
+        if (S.reorth > 0) {
+            cgs_dots(true);
+            const double before = hsh[x + 1].x;
+            nrm2 = cgs_update();
+            if (S.reorth > 1 && nrm2 < 0.5 * before) {
+                __syncthreads();
+                cgs_dots(false);
+                nrm2 = cgs_update();
+            }
+        } else {
+            double2 acc = make_double2(0.0, 0.0);
+            for (uint64_t r = tid; r < n; r += nt) {
+                if (CPLX) dot_acc(((const double2 *)S.W)[r], ((const double2 *)S.W)[r], acc);
+                else dot_acc(S.W[r], S.W[r], acc);
+            }
+            nrm2 = block_sum_all(acc, red).x;
+        }
+        const double beta = sqrt(fmax(nrm2, 0.0));
+        const double sc = beta > 0.0 ? 1.0 / beta : 0.0;
+        for (uint64_t r = tid; r < n; r += nt) {
+            if (CPLX) {
+                const double2 w = ((const double2 *)S.W)[r];
+                ((double2 *)P(x + 1))[r] = make_double2(w.x * sc, w.y * sc);
+            } else {
+                P(x + 1)[r] = S.W[r] * sc;
+            }
+        }
+        if (tid == 0) S.ab[S.slots + x] = beta;
+        __syncthreads();
+    }
 }
 
 }  // namespace qs3

@@ -15,10 +15,12 @@
 #include <chrono>
 #include <cmath>
 #include <limits>
+#include <thread>
 #include <vector>
 
 #include "qs3_device.h"
 #include "qs3_impl.h"
+#include "qs3_hv.h"
 #include "qs3_krylov.h"
 
 namespace qs3 {
@@ -177,9 +179,9 @@ __global__ __launch_bounds__(256) void k_cgs_update_norm(RedGeom g, double *__re
 // second Gram-Schmidt pass where the first one cancelled more than half of
 // |W|^2 (Daniel-Gragg-Kaufman-Stewart criterion, eta^2 = 1/2)
 __global__ void k_dgks_flag(int B, const double2 *__restrict__ before, const double2 *__restrict__ after,
-                            uint8_t *__restrict__ flag) {
+                            const uint8_t *__restrict__ mask, uint8_t *__restrict__ flag) {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) flag[b] = after[b].x < 0.5 * before[b].x ? 1 : 0;
+    if (b < B) flag[b] = (after[b].x < 0.5 * before[b].x && (!mask || mask[b])) ? 1 : 0;
 }
 
 __global__ void k_merge_norm(int B, const uint8_t *__restrict__ flag, const double2 *__restrict__ n2,
@@ -216,10 +218,12 @@ __global__ __launch_bounds__(256) void k_lanczos_update(uint64_t ne, int B, doub
                                                         const double *__restrict__ P0,
                                                         const double *__restrict__ P1,
                                                         const double2 *__restrict__ alpha,
-                                                        const double *__restrict__ beta) {
+                                                        const double *__restrict__ beta,
+                                                        const uint8_t *__restrict__ mask) {
     uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     const int b = (int)(e % (uint64_t)B);
+    if (mask && !mask[b]) return;
     const double a = alpha[b].x;
     const double be = P1 ? beta[b] : 0.0;
     if (CPLX) {
@@ -267,10 +271,12 @@ __global__ __launch_bounds__(256) void k_cgs_update(uint64_t ne, int B, double *
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_scale_out(uint64_t ne, int B, const double *__restrict__ W,
                                                    double *__restrict__ P,
-                                                   const double2 *__restrict__ nrm2) {
+                                                   const double2 *__restrict__ nrm2,
+                                                   const uint8_t *__restrict__ mask) {
     uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     const int b = (int)(e % (uint64_t)B);
+    if (mask && !mask[b]) return;
     const double nb = sqrt(fmax(nrm2[b].x, 0.0));
     const double s = nb > 0.0 ? 1.0 / nb : 0.0;
     if (CPLX) {
@@ -557,8 +563,10 @@ int Engine::apply(const double *x, double *y) {
     if (precision == QS3_PREC_F32MV) {
         hipLaunchKernelGGL(k_to_f32, grid1(stride), dim3(256), 0, st, stride, x, X32.as<float>());
         QS3_HIP(hipGetLastError());
+        op->set_mask(colmask);
         return op->apply_f32in(X32.as<float>(), y, st);
     }
+    op->set_mask(colmask);
     return op->apply(x, y, st);
 }
 
@@ -602,27 +610,28 @@ int Engine::cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double
 // of |W|^2; the norm is fused into the update.
 int Engine::step(int x, int prev) {
     QS3_TRY(apply(slot(x), W.as<double>()));
-    QS3_TRY(multidot(slot(x), 1, W.as<double>(), alpha.as<double2>(), 0, nullptr));
+    QS3_TRY(multidot(slot(x), 1, W.as<double>(), alpha.as<double2>(), 0, colmask));
     double *betap = ab_hist.as<double>() + (size_t)slots * B + (size_t)(prev < 0 ? 0 : prev) * B;
     if (cplx)
         hipLaunchKernelGGL(k_lanczos_update<true>, grid1(ne), dim3(256), 0, st, ne, B,
                            W.as<double>(), slot(x), prev >= 0 ? slot(prev) : nullptr,
-                           alpha.as<double2>(), betap);
+                           alpha.as<double2>(), betap, colmask);
     else
         hipLaunchKernelGGL(k_lanczos_update<false>, grid1(ne), dim3(256), 0, st, ne, B,
                            W.as<double>(), slot(x), prev >= 0 ? slot(prev) : nullptr,
-                           alpha.as<double2>(), betap);
+                           alpha.as<double2>(), betap, colmask);
     QS3_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_copy_re, grid1(B), dim3(256), 0, st, B, alpha.as<double2>(),
                        ab_hist.as<double>() + (size_t)x * B);
     double2 *h = hvec.as<double2>();
     double2 *n_before = h + (size_t)(x + 1) * B;  // the self-dot output of the first pass
     if (reorth > 0) {
-        QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 1, nullptr));
-        QS3_TRY(cgs_update_norm(x + 1, h, nullptr, nrm2.as<double2>()));
+        QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 1, colmask));
+        QS3_TRY(cgs_update_norm(x + 1, h, colmask, nrm2.as<double2>()));
         if (reorth > 1) {
             uint8_t *flag = act.as<uint8_t>() + 8 + B;
-            hipLaunchKernelGGL(k_dgks_flag, grid1(B), dim3(256), 0, st, B, n_before, nrm2.as<double2>(), flag);
+            hipLaunchKernelGGL(k_dgks_flag, grid1(B), dim3(256), 0, st, B, n_before, nrm2.as<double2>(), colmask,
+                               flag);
             QS3_HIP(hipGetLastError());
             QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 0, flag));
             double2 *n2 = h + (size_t)(x + 1) * B;
@@ -631,19 +640,57 @@ int Engine::step(int x, int prev) {
             QS3_HIP(hipGetLastError());
         }
     } else {
-        QS3_TRY(multidot(W.as<double>(), 1, W.as<double>(), nrm2.as<double2>(), 0, nullptr));
+        QS3_TRY(multidot(W.as<double>(), 1, W.as<double>(), nrm2.as<double2>(), 0, colmask));
     }
     hipLaunchKernelGGL(k_sqrt_to, grid1(B), dim3(256), 0, st, B, nrm2.as<double2>(),
                        ab_hist.as<double>() + (size_t)slots * B + (size_t)x * B);
     if (cplx)
         hipLaunchKernelGGL(k_scale_out<true>, grid1(ne), dim3(256), 0, st, ne, B, W.as<double>(),
-                           slot(x + 1), nrm2.as<double2>());
+                           slot(x + 1), nrm2.as<double2>(), colmask);
     else
         hipLaunchKernelGGL(k_scale_out<false>, grid1(ne), dim3(256), 0, st, ne, B, W.as<double>(),
-                           slot(x + 1), nrm2.as<double2>());
+                           slot(x + 1), nrm2.as<double2>(), colmask);
     QS3_HIP(hipGetLastError());
     ++n_matvec;
     return QS3_OK;
+}
+
+// Small single-column sectors run a whole cycle in one workgroup (one launch
+// instead of ~15 per step) while their Krylov basis fits comfortably in L2.
+int Engine::cycle(int x0, int x1, int prev_first) {
+    const size_t basis_bytes = sizeof(double) * stride * (size_t)slots;
+    if (B == 1 && precision == QS3_PREC_F64 && basis_bytes <= (2u << 20)) {
+        const int rc = op->small_cycle(*this, x0, x1, prev_first);
+        if (rc != 1) {
+            if (rc == QS3_OK) n_matvec += x1 - x0;
+            return rc;
+        }
+    }
+    for (int x = x0; x < x1; ++x) QS3_TRY(step(x, x == x0 ? prev_first : x - 1));
+    return QS3_OK;
+}
+
+static SmallArgs small_args(Engine &E, int x0, int x1, int prev_first) {
+    SmallArgs S;
+    S.n = E.n;
+    S.x0 = x0;
+    S.x1 = x1;
+    S.prev_first = prev_first;
+    S.Psi = E.Psi.as<double>();
+    S.stride = E.stride;
+    S.W = E.W.as<double>();
+    S.ab = E.ab_hist.as<double>();
+    S.slots = E.slots;
+    S.reorth = E.reorth;
+    return S;
+}
+
+int small_cycle_u1(qs3_sector *sec, Engine &E, int x0, int x1, int prev_first) {
+    return lanczos_small(sec->lat, sec->K, sec->bt.get(), nullptr, small_args(E, x0, x1, prev_first), E.st);
+}
+
+int small_cycle_batch(qs3_batch *bat, Engine &E, int x0, int x1, int prev_first) {
+    return lanczos_small(bat->lat, bat->K, bat->bt.get(), bat, small_args(E, x0, x1, prev_first), E.st);
 }
 
 // slot 0 := v0 / |v0|; norms0[b] = |v0|
@@ -651,10 +698,10 @@ int Engine::normalize_into_slot0(const double *v0, std::vector<double> *norms0) 
     QS3_TRY(multidot(v0, 1, v0, nrm2.as<double2>(), 0, nullptr));
     if (cplx)
         hipLaunchKernelGGL(k_scale_out<true>, grid1(ne), dim3(256), 0, st, ne, B, v0, slot(0),
-                           nrm2.as<double2>());
+                           nrm2.as<double2>(), nullptr);
     else
         hipLaunchKernelGGL(k_scale_out<false>, grid1(ne), dim3(256), 0, st, ne, B, v0, slot(0),
-                           nrm2.as<double2>());
+                           nrm2.as<double2>(), nullptr);
     QS3_HIP(hipGetLastError());
     if (norms0) {
         std::vector<double2> h(B);
@@ -707,35 +754,184 @@ static void build_tri(int m, const double *a, const double *b, std::vector<doubl
     }
 }
 
-// lowest `nev` distinct levels (indices into e, ascending).  require_conv:
-// skip Ritz values that have not converged (fixed-step Lanczos, where partner
-// copies of degenerate levels emerge from rounding and never finish); else an
-// unconverged value among the wanted ones clears *all_conv.
+// The lowest `nev` distinct levels (indices into the ascending e).  Ritz
+// values within 1e-8 max(1, |e|) of the previous level belong to it (partner
+// copies of a degenerate level, which rounding lets emerge, are ignored
+// whether or not they have converged); a level is converged when its lowest
+// Ritz value's residual is <= tol max(1, |e|).  require_conv (fixed-step
+// Lanczos, which cannot iterate further): unconverged values are skipped.
 static std::vector<int> pick_levels(const std::vector<double> &e, const std::vector<double> &res,
                                     int nev, double tol, bool require_conv, bool *all_conv) {
     std::vector<int> out;
     *all_conv = true;
-    double last = std::numeric_limits<double>::quiet_NaN();
+    double last = 0.0;
     for (size_t i = 0; i < e.size() && (int)out.size() < nev; ++i) {
         const double sc = std::max(1.0, std::fabs(e[i]));
         const bool conv = res[i] <= tol * sc;
-        if (!conv) {
-            if (require_conv) continue;
-            *all_conv = false;
-        }
+        if (require_conv && !conv) continue;
         if (!out.empty() && std::fabs(e[i] - last) <= 1e-8 * sc) continue;
         out.push_back((int)i);
         last = e[i];
+        if (!conv) *all_conv = false;
     }
     if ((int)out.size() < nev) *all_conv = false;
     return out;
+}
+
+// Eigenvalues of the symmetric tridiagonal matrix (diagonal d, off-diagonal
+// e[i] coupling i and i+1) by the implicit QL algorithm with Wilkinson-type
+// shifts (Bowdler, Martin, Reinsch and Wilkinson 1968), tracking rows
+// `first` and `last` of the eigenvector matrix through the plane rotations.
+// Outputs ascending eigenvalues w and the matching components z0 (row 0) and
+// zl (row n-1).
+static void tridiag_ql(int n, const double *d_in, const double *e_in, std::vector<double> &w,
+                       std::vector<double> &z0, std::vector<double> &zl) {
+    std::vector<double> d(d_in, d_in + n), e(n, 0.0), a(n, 0.0), b(n, 0.0);
+    for (int i = 0; i + 1 < n; ++i) e[i] = e_in[i];
+    a[0] = 1.0;
+    b[n - 1] = 1.0;
+    const double eps = std::numeric_limits<double>::epsilon();
+    for (int l = 0; l < n; ++l) {
+        int iter = 0;
+        for (;;) {
+            int m = l;
+            for (; m + 1 < n; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= eps * dd) break;
+            }
+            if (m == l || iter++ > 90) break;
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
+            double sn = 1.0, cs = 1.0, p = 0.0;
+            int i = m - 1;
+            bool underflow = false;
+            for (; i >= l; --i) {
+                const double f = sn * e[i], bb = cs * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    d[i + 1] -= p;
+                    e[m] = 0.0;
+                    underflow = true;
+                    break;
+                }
+                sn = f / r;
+                cs = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * sn + 2.0 * cs * bb;
+                p = sn * r;
+                d[i + 1] = g + p;
+                g = cs * r - bb;
+                // the same rotation on the tracked rows of the eigenvector matrix
+                double t = a[i + 1];
+                a[i + 1] = sn * a[i] + cs * t;
+                a[i] = cs * a[i] - sn * t;
+                t = b[i + 1];
+                b[i + 1] = sn * b[i] + cs * t;
+                b[i] = cs * b[i] - sn * t;
+            }
+            if (underflow) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
+    w.resize(n);
+    z0.resize(n);
+    zl.resize(n);
+    for (int k = 0; k < n; ++k) {
+        w[k] = d[idx[k]];
+        z0[k] = a[idx[k]];
+        zl[k] = b[idx[k]];
+    }
+}
+
+// Eigenvector of the tridiagonal matrix for the eigenvalue lam by two steps
+// of inverse iteration (LU with partial pivoting of T - (lam + delta) I).
+static void tridiag_vector(int n, const double *d, const double *e, double lam, double *x) {
+    double nrm = 0;
+    for (int i = 0; i < n; ++i) nrm = std::max(nrm, std::fabs(d[i]) + (i + 1 < n ? std::fabs(e[i]) : 0.0) +
+                                                   (i > 0 ? std::fabs(e[i - 1]) : 0.0));
+    const double shift = lam + 1e-13 * std::max(nrm, 1.0);
+    std::vector<double> a(n), bu(n), c2(n), l(n);  // U: diag a, super bu, super-super c2
+    std::vector<int> piv(n, 0);
+    std::vector<double> sub(n), dia(n), sup(n);
+    for (int i = 0; i < n; ++i) {
+        dia[i] = d[i] - shift;
+        sup[i] = i + 1 < n ? e[i] : 0.0;
+        sub[i] = i + 1 < n ? e[i] : 0.0;  // sub[i] = T[i+1][i]
+    }
+    // Gaussian elimination with row interchanges on the band
+    for (int i = 0; i < n; ++i) {
+        a[i] = dia[i];
+        bu[i] = sup[i];
+        c2[i] = 0.0;
+    }
+    for (int i = 0; i + 1 < n; ++i) {
+        // rows i and i+1: row i = (a[i], bu[i], c2[i]) at cols (i, i+1, i+2); row i+1 = (sub[i], dia, sup)
+        double r0 = a[i], r1 = bu[i], r2 = c2[i];
+        double s0 = sub[i], s1 = a[i + 1], s2 = bu[i + 1];
+        if (std::fabs(s0) > std::fabs(r0)) {
+            std::swap(r0, s0);
+            std::swap(r1, s1);
+            std::swap(r2, s2);
+            piv[i] = 1;
+        }
+        const double m = r0 != 0.0 ? s0 / r0 : 0.0;
+        l[i] = m;
+        a[i] = r0;
+        bu[i] = r1;
+        c2[i] = r2;
+        a[i + 1] = s1 - m * r1;
+        bu[i + 1] = s2 - m * r2;
+    }
+    for (int i = 0; i < n; ++i)
+        if (a[i] == 0.0) a[i] = 1e-300;
+    for (int i = 0; i < n; ++i) x[i] = 1.0;
+    for (int it = 0; it < 3; ++it) {
+        for (int i = 0; i + 1 < n; ++i) {  // forward: apply the row interchanges and multipliers
+            if (piv[i]) std::swap(x[i], x[i + 1]);
+            x[i + 1] -= l[i] * x[i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = x[i];
+            if (i + 1 < n) s -= bu[i] * x[i + 1];
+            if (i + 2 < n) s -= c2[i] * x[i + 2];
+            x[i] = s / a[i];
+        }
+        double nn = 0;
+        for (int i = 0; i < n; ++i) nn += x[i] * x[i];
+        nn = std::sqrt(nn);
+        for (int i = 0; i < n; ++i) x[i] /= nn;
+    }
+}
+
+// Run f(c) for c in [0, n) on a few host threads (the per-column host work of
+// a batch: eigensolves of small tridiagonal / arrowhead matrices).
+template <typename F>
+static void parallel_columns(int n, F &&f) {
+    const int nt = std::min(16, std::max(1, n / 8));
+    if (nt <= 1) {
+        for (int c = 0; c < n; ++c) f(c);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+            for (int c = t; c < n; c += nt) f(c);
+        });
+    for (auto &x : th) x.join();
 }
 
 int run_lanczos(Engine &E, const double *v0, int steps, std::vector<double> &a_out,
                 std::vector<double> &b_out, std::vector<double> &norm0, std::vector<int> &done) {
     const int B = E.B;
     QS3_TRY(E.normalize_into_slot0(v0, &norm0));
-    for (int x = 0; x < steps; ++x) QS3_TRY(E.step(x, x - 1));
+    QS3_TRY(E.cycle(0, steps, -1));
     std::vector<double> a, b;
     QS3_TRY(E.read_ab(0, steps, a, b));
     a_out.assign((size_t)B * steps, 0.0);
@@ -819,7 +1015,7 @@ int SolveRun::wait() {
 int SolveRun::begin(const double *v0) {
     QS3_TRY(E.normalize_into_slot0(v0, nullptr));
     const int steps = o.alg == QS3_ALG_TRL ? o.nm : o.steps;
-    for (int x = 0; x < steps; ++x) QS3_TRY(E.step(x, x - 1));
+    QS3_TRY(E.cycle(0, steps, -1));
     QS3_TRY(enqueue_ab_copy(0, steps));
     phase = 1;
     if (o.alg == QS3_ALG_TRL) {
@@ -845,22 +1041,21 @@ int SolveRun::advance(bool *done) {
         }
         const int S = o.steps, nev = o.nev;
         std::fill(hC, hC + (size_t)B * S * nev, 0.0);
-        for (int c = 0; c < B; ++c) {
+        parallel_columns(B, [&](int c) {
             int m = S;
             for (int x = 0; x < S; ++x)
                 if (hb[(size_t)x * B + c] <= 1e-14 * std::max(1.0, std::fabs(ha[(size_t)x * B + c]))) {
                     m = x + 1;
                     break;
                 }
-            std::vector<double> a(m), b(m), T, e, V;
+            std::vector<double> a(m), b(m), e, z0, zl;
             for (int x = 0; x < m; ++x) {
                 a[x] = ha[(size_t)x * B + c];
                 b[x] = hb[(size_t)x * B + c];
             }
-            build_tri(m, a.data(), b.data(), T);
-            jacobi_eig(m, T, e, V);
+            tridiag_ql(m, a.data(), b.data(), e, z0, zl);
             std::vector<double> res(m);
-            for (int i = 0; i < m; ++i) res[i] = std::fabs(b[m - 1] * V[(size_t)(m - 1) * m + i]);
+            for (int i = 0; i < m; ++i) res[i] = std::fabs(b[m - 1] * zl[i]);
             bool allc;
             auto lv = pick_levels(e, res, nev, o.tol, true, &allc);
             // a Krylov space that closed (breakdown) or spans every row holds
@@ -868,16 +1063,20 @@ int SolveRun::advance(bool *done) {
             const bool exhausted = m < S || (uint64_t)S >= E.n;
             if (exhausted && !lv.empty()) allc = true;
             double mr = 0;
+            std::vector<double> vec(m);
             for (size_t y = 0; y < lv.size(); ++y) {
                 evals[(size_t)c * nev + y] = e[lv[y]];
                 mr = std::max(mr, res[lv[y]]);
-                for (int x = 0; x < m; ++x) hC[((size_t)c * S + x) * nev + y] = V[(size_t)x * m + lv[y]];
+                if (want_vecs) {
+                    tridiag_vector(m, a.data(), b.data(), e[lv[y]], vec.data());
+                    for (int x = 0; x < m; ++x) hC[((size_t)c * S + x) * nev + y] = vec[x];
+                }
             }
             info[c].converged = allc ? 1 : 0;
             info[c].n_found = (int)lv.size();
             info[c].max_residual = mr;
             info[c].n_matvec = E.n_matvec;
-        }
+        });
         if (want_vecs) {
             QS3_HIP(hipMemcpyAsync(dC.ptr, hC, sizeof(double) * (size_t)B * S * nev, hipMemcpyHostToDevice, E.st));
             QS3_TRY(E.rotate_dev(0, S, dC.as<double>(), nev, S + 1, nullptr));
@@ -897,11 +1096,10 @@ int SolveRun::advance(bool *done) {
             al[c][x] = ha[(size_t)x * B + c];
             be[c][x] = hb[(size_t)x * B + c];
         }
-    bool any_active = false;
     uint8_t *act_rot = hact, *act_next = hact + B;
-    for (int c = 0; c < B; ++c) {
-        act_rot[c] = active[c];
-        if (!active[c]) continue;
+    for (int c = 0; c < B; ++c) act_rot[c] = active[c];
+    parallel_columns(B, [&](int c) {
+        if (!active[c]) return;
         std::vector<double> T((size_t)NM * NM, 0.0), e, V;
         for (int x = 0; x < NM; ++x) T[(size_t)x * NM + x] = al[c][x];
         if (first) {
@@ -917,14 +1115,6 @@ int SolveRun::advance(bool *done) {
         bool allc;
         auto lv = pick_levels(std::vector<double>(e.begin(), e.begin() + NK),
                               std::vector<double>(res.begin(), res.begin() + NK), nev, o.tol, false, &allc);
-        // every Ritz value below the highest wanted level must have converged
-        if (allc && !lv.empty()) {
-            const double top = e[lv.back()];
-            for (int i = 0; i < NK; ++i)
-                if (e[i] <= top + 1e-8 * std::max(1.0, std::fabs(top)) &&
-                    res[i] > o.tol * std::max(1.0, std::fabs(e[i])))
-                    allc = false;
-        }
         for (int x = 0; x < NM; ++x)
             for (int y = 0; y < NK; ++y) hC[((size_t)c * NM + x) * NK + y] = V[(size_t)x * NM + y];
         for (int y = 0; y < NK; ++y) {
@@ -942,12 +1132,15 @@ int SolveRun::advance(bool *done) {
         info[c].n_matvec = E.n_matvec;
         final_lv[c] = lv;
         if (allc) info[c].converged = 1;
-        else any_active = true;
-    }
+    });
+    bool any_active = false;
+    for (int c = 0; c < B; ++c)
+        if (active[c] && !info[c].converged) any_active = true;
     for (int c = 0; c < B; ++c) {
         if (info[c].converged) active[c] = 0;
         act_next[c] = active[c];
     }
+    // from here on the kernels skip the columns that have converged
     // Ritz vectors into slots NM+1.., then back into 0..NK-1 (rotated columns)
     QS3_HIP(hipMemcpyAsync(dC.ptr, hC, sizeof(double) * (size_t)B * NM * NK, hipMemcpyHostToDevice, E.st));
     QS3_HIP(hipMemcpyAsync(dact.ptr, hact, 2 * (size_t)B, hipMemcpyHostToDevice, E.st));
@@ -963,9 +1156,9 @@ int SolveRun::advance(bool *done) {
     // restart cycle: the residual becomes psi_{NK+1}; the first step has no
     // three-term partner (the couplings to the kept Ritz vectors are removed by
     // the full reorthogonalisation), then x = NK+1..NM-1
+    E.colmask = B > 1 ? d_next : nullptr;
     QS3_TRY(E.copy_slot_dev(NM, NK, d_next));
-    QS3_TRY(E.step(NK, -1));
-    for (int x = NK + 1; x < NM; ++x) QS3_TRY(E.step(x, x - 1));
+    QS3_TRY(E.cycle(NK, NM, -1));
     QS3_TRY(enqueue_ab_copy(NK, NM));
     first = false;
     ++restarts;

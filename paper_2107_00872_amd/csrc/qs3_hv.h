@@ -22,6 +22,7 @@ struct BatchArgs {
     int M;
     double invM;
     const double2 *phase;  // e^{2 pi i P / M}
+    const uint8_t *active;  // per sector, or null: rows of inactive sectors are left untouched
 };
 
 struct BuildArgs {
@@ -30,7 +31,25 @@ struct BuildArgs {
     uint64_t chunk;  // ranks per block
 };
 
+struct SmallArgs {
+    uint64_t n;         // rows (single column)
+    int x0, x1;         // steps x0..x1-1
+    int prev_first;     // slot of the three-term partner of step x0, or -1
+    double *Psi;        // slots of `stride` doubles
+    uint64_t stride;
+    double *W;
+    double *ab;         // alpha at [x], beta at [slots + x]
+    int slots;
+    int reorth;         // 0 none, 1 one pass, 2 second pass where needed
+};
+
 BatchArgs batch_args(qs3_batch *bat);
+// One Lanczos cycle of a small single-column sector in one workgroup (bat =
+// null: fixed-N_down sector).  Returns 1 when the size is not supported.
+int lanczos_small(qs3_lattice *lat, int K, const BinomTable *bt, qs3_batch *bat, const SmallArgs &S,
+                  hipStream_t s);
+template <int K>
+int lanczos_small_K(qs3_lattice *lat, const BinomTable *bt, qs3_batch *bat, const SmallArgs &S, hipStream_t s);
 int grid_for(qs3_ctx *ctx, uint64_t tiles);
 
 template <int K>

@@ -168,7 +168,7 @@ struct qs3_batch {
     qs3::DevBuf compat_nt;        // uint8 [n_nt * B]
     std::vector<uint8_t> h_compat_nt;
     std::vector<uint64_t> dims;   // per sector
-    std::vector<uint8_t> active;  // per sector (solver use)
+    const uint8_t *active_dev = nullptr;  // device mask set by the solver while it applies H
 };
 
 struct qs3_sector {

@@ -7,6 +7,8 @@
 
 namespace qs3 {
 
+struct Engine;
+
 // The operator a Lanczos run applies: n rows x B columns, [row][col] layout.
 struct Operator {
     virtual ~Operator() = default;
@@ -15,6 +17,10 @@ struct Operator {
     virtual bool is_complex() const = 0;
     virtual int apply(const double *x, double *y, hipStream_t s) = 0;        // float64 in/out
     virtual int apply_f32in(const float *x, double *y, hipStream_t s) = 0;  // float32 in, row sums float32
+    // columns with mask[b] == 0 need not be computed (device mask or null)
+    virtual void set_mask(const uint8_t *) {}
+    // a whole cycle of steps x0..x1-1 in one workgroup; 1 = not supported
+    virtual int small_cycle(Engine &, int, int, int) { return 1; }
 };
 
 // Geometry of the deterministic column reductions: a block covers TC columns
@@ -36,6 +42,7 @@ struct Engine {
     int B = 1, dpe = 1, slots = 0, precision = 0, reorth = 2;
     bool cplx = false;
     int n_matvec = 0;
+    const uint8_t *colmask = nullptr;  // device: columns still iterating (null = all)
     RedGeom rg{};
     DevBuf Psi, W, X32, partial, hvec, alpha, nrm2, ab_hist, act;
     ~Engine();
@@ -46,6 +53,8 @@ struct Engine {
                  const uint8_t *mask);
     int cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double2 *nrm_out);
     int step(int x, int prev);
+    // steps x0..x1-1 (step x0's three-term partner is slot prev_first or none)
+    int cycle(int x0, int x1, int prev_first);
     int normalize_into_slot0(const double *v0, std::vector<double> *norms0);
     int read_ab(int x0, int x1, std::vector<double> &a, std::vector<double> &b);
     int rotate_dev(int from_slot, int NX, const double *dC, int NY, int to_slot, const uint8_t *act_dev);
@@ -95,9 +104,13 @@ int run_lanczos(Engine &E, const double *v0, int steps, std::vector<double> &a_o
                 std::vector<double> &b_out, std::vector<double> &norm0, std::vector<int> &done);
 
 // ---- operators for the Krylov engine
+int small_cycle_u1(qs3_sector *sec, Engine &E, int x0, int x1, int prev_first);
+int small_cycle_batch(qs3_batch *bat, Engine &E, int x0, int x1, int prev_first);
+
 struct U1Op : Operator {
     qs3_sector *sec;
     explicit U1Op(qs3_sector *s) : sec(s) {}
+    int small_cycle(Engine &E, int x0, int x1, int pf) override { return small_cycle_u1(sec, E, x0, x1, pf); }
     uint64_t rows() const override { return sec->dim; }
     int cols() const override { return 1; }
     bool is_complex() const override { return false; }
@@ -115,11 +128,22 @@ struct BatchOp : Operator {
     uint64_t rows() const override { return bat->ks->n_reps; }
     int cols() const override { return bat->B; }
     bool is_complex() const override { return true; }
+    const uint8_t *mask = nullptr;
+    void set_mask(const uint8_t *m) override { mask = m; }
+    int small_cycle(Engine &E, int x0, int x1, int pf) override {
+        return bat->B == 1 ? small_cycle_batch(bat, E, x0, x1, pf) : 1;
+    }
     int apply(const double *x, double *y, hipStream_t s) override {
-        return hv_batch(bat, x, QS3_C128, y, QS3_C128, s);
+        bat->active_dev = mask;
+        int rc = hv_batch(bat, x, QS3_C128, y, QS3_C128, s);
+        bat->active_dev = nullptr;
+        return rc;
     }
     int apply_f32in(const float *x, double *y, hipStream_t s) override {
-        return hv_batch(bat, x, QS3_C64, y, QS3_C128, s);
+        bat->active_dev = mask;
+        int rc = hv_batch(bat, x, QS3_C64, y, QS3_C128, s);
+        bat->active_dev = nullptr;
+        return rc;
     }
 };
 
