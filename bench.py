@@ -120,12 +120,18 @@ def main():
     qs = np.array([[2 * np.pi * kx / lat.lx, 2 * np.pi * ky / lat.ly, 0.0] for (kx, ky, kz) in ks])
     gs_vec = torch.empty(d, dtype=torch.float64, device="cuda")
 
+    t_batch = []
+
     def one_step(seed):
         rows = 0
         r1 = full.eigs(nev=1, alg=qs3.ALG_TRL, seed=seed, evecs=gs_vec, stream=stream)
         rows += r1.info.n_matvec * d
+        tb = time.perf_counter()
         ev, infos, rc = bat.eigs(nev=5, alg=qs3.ALG_TRL, seed=seed, stream=stream)
-        rows += infos[0].n_matvec * bat.rows * bat.B
+        t_batch.append(time.perf_counter() - tb)
+        # each sector's rows count for the steps it took (converged sectors
+        # are masked out of the later launches)
+        rows += sum(int(i.n_matvec) * int(dm) for i, dm in zip(infos, bat.dims))
         obs = None
         try:
             zz, pm = full.sisj(gs_vec, [p[0] for p in pairs], [p[1] for p in pairs], stream=stream)
@@ -193,7 +199,23 @@ def main():
     e1.synchronize()
     t_bat = e0.elapsed_time(e1) / 1e3 / args.matvec_reps
 
+    # ---- the same 100 momentum solves one at a time (plain float64 path, the
+    # sectors created beforehand), seeds as in the batch of the last step
+    secs = [qs3.Sector(L, K, k) for k in ks]
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    ev_serial = [secs[b].eigs(nev=5, alg=qs3.ALG_TRL, seed=args.steps + b, stream=stream).evals
+                 for b in range(len(ks))]
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - ts
+    for sc in secs:
+        sc.close()
     r1, ev, infos, obs = last
+    ev_serial = np.array(ev_serial)
+    both = np.isfinite(ev_serial) & np.isfinite(ev)
+    serial = {"solves_per_s": len(ks) / t_serial, "seconds": t_serial,
+              "batched_solves_per_s": bat.B / t_batch[-1], "batched_seconds": t_batch[-1],
+              "max_rel_diff": float(np.max(np.abs(ev_serial[both] - ev[both]) / np.abs(ev[both])))}
     out = {
         "metric": "H.v rows/s (whole solve step) + %HBM roofline of the H.v kernel",
         "value": rows_tot / t_all,
@@ -219,6 +241,7 @@ def main():
                    "u1_f32_ms": t_mv32 * 1e3, "u1_f64_ms": t_mv * 1e3,
                    "batch100_rows_per_s": bat.rows * bat.B / t_bat, "batch100_ms": t_bat * 1e3},
         "solves_per_s": (1 + bat.B) / (t_all / args.steps),
+        "k_sectors_one_at_a_time": serial,
         "step_ms_p50": 1e3 * float(np.percentile(times, 50)),
         "step_ms_max": 1e3 * float(np.max(times)),
         "setup_s": t_setup,

@@ -107,11 +107,30 @@ def c3(args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res[name] = ev[:, 0].copy()
-        out[name] = {"seconds": dt, "solves_per_s": bat.B / dt, "matvecs": infos[0].n_matvec,
+        mv = np.array([i.n_matvec for i in infos])
+        out[name] = {"seconds": dt, "solves_per_s": bat.B / dt, "matvecs_max": int(mv.max()),
+                     "matvecs_p50": float(np.median(mv)), "width_min": int(min(i.width for i in infos)),
                      "converged": int(sum(i.converged for i in infos)), "rc": rc,
-                     "sector_rows_per_s": infos[0].n_matvec * bat.rows * bat.B / dt,
+                     "sector_rows_per_s": float(np.sum(mv * bat.dims.astype(np.float64))) / dt,
                      "E_min": float(ev[:, 0].min()), "E_max": float(ev[:, 0].max())}
     out["f32mv"]["max_rel_err_vs_f64"] = float(np.max(np.abs(res["f32mv"] - res["f64"]) / np.abs(res["f64"])))
+    # plain float64 path one sector at a time on a seeded random sample of 20
+    # momenta, the batch's seeds
+    sample = sorted(np.random.default_rng(2021).choice(len(ks), 20, replace=False).tolist())
+    secs = [qs3.Sector(L, 3, ks[b]) for b in sample]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev_s = [secs[i].eigs(nev=1, seed=1 + b, stream=stream) for i, b in enumerate(sample)]
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    for sc in secs:
+        sc.close()
+    e_s = np.array([r.evals[0] for r in ev_s])
+    out["f64_one_at_a_time"] = {
+        "sample": [list(ks[b]) for b in sample], "seconds": t_s, "solves_per_s": len(sample) / t_s,
+        "matvecs": [int(r.info.n_matvec) for r in ev_s],
+        "max_rel_diff_vs_batched": float(np.max(np.abs(e_s - res["f64"][sample]) / np.abs(e_s)))}
+    out["batched_speedup_f64"] = out["f64"]["solves_per_s"] / out["f64_one_at_a_time"]["solves_per_s"]
     out["value"] = out["f64"]["solves_per_s"]
     out["unit"] = "sector solves/s (float64)"
     g = ks.index((0, 0, 0))

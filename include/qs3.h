@@ -152,6 +152,10 @@ typedef struct {
     int n_found;        /* distinct levels returned (<= nev) */
     double max_residual;
     double seconds;     /* wall time of the call */
+    int width;          /* columns of the launches that ran the last restart
+                           (1 for a sector; in a batch the batch size, or fewer
+                           once the solver narrowed to the sectors still
+                           iterating) */
 } qs3_eigs_info;
 
 /* Lowest `nev` distinct levels: a Ritz value counts when its residual estimate

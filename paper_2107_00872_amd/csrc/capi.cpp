@@ -429,6 +429,30 @@ int qs3_batch_destroy(qs3_batch *bat) {
     return QS3_OK;
 }
 
+namespace qs3 {
+
+// A batch operator that owns its batch (the restriction of another one).
+struct OwnedBatchOp : BatchOp {
+    explicit OwnedBatchOp(qs3_batch *b) : BatchOp(b) {}
+    ~OwnedBatchOp() override { qs3_batch_destroy(bat); }
+};
+
+int BatchOp::subset(const std::vector<int> &cols, std::unique_ptr<Operator> *out) {
+    QS3_REQUIRE(!cols.empty(), QS3_EINVAL, "empty column subset");
+    std::vector<int32_t> kv;
+    kv.reserve(3 * cols.size());
+    for (int c : cols) {
+        QS3_REQUIRE(c >= 0 && c < bat->B, QS3_EINVAL, "column out of range");
+        kv.insert(kv.end(), bat->kv.begin() + 3 * c, bat->kv.begin() + 3 * c + 3);
+    }
+    qs3_batch *nb = nullptr;
+    QS3_TRY(qs3_batch_create(bat->lat, bat->K, (int)cols.size(), kv.data(), &nb));
+    out->reset(new OwnedBatchOp(nb));
+    return QS3_OK;
+}
+
+}  // namespace qs3
+
 int qs3_batch_dims(const qs3_batch *bat, uint64_t *rows, uint64_t *dims) {
     QS3_REQUIRE(bat, QS3_EINVAL, "batch is NULL");
     if (rows) *rows = bat->ks->n_reps;

@@ -351,6 +351,18 @@ __global__ void k_masked_copy(uint64_t ne, int B, int dpe, const double *__restr
     for (int q = 0; q < dpe; ++q) Dst[e * dpe + q] = Src[e * dpe + q];
 }
 
+// Dst[r, j] = Src[r, idx[j]] (rows n, Bs source and Bd destination columns,
+// dpe doubles per element)
+__global__ void k_gather_cols(uint64_t n, int Bs, int Bd, int dpe, const double *__restrict__ Src,
+                              double *__restrict__ Dst, const int32_t *__restrict__ idx) {
+    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * (uint64_t)Bd) return;
+    const uint64_t r = e / (uint64_t)Bd;
+    const int j = (int)(e - r * (uint64_t)Bd);
+    const uint64_t se = r * (uint64_t)Bs + (uint64_t)idx[j];
+    for (int q = 0; q < dpe; ++q) Dst[e * dpe + q] = Src[se * dpe + q];
+}
+
 __global__ void k_to_f32(uint64_t nd, const double *__restrict__ in, float *__restrict__ out) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nd) out[i] = (float)in[i];
@@ -745,6 +757,18 @@ int Engine::copy_slot_dev(int from, int to, const uint8_t *act_dev) {
     return QS3_OK;
 }
 
+int Engine::gather_columns_into(Engine &dst, int from_slot, int to_slot, const int32_t *idx_dev) {
+    const uint64_t cnt = n * (uint64_t)dst.B;
+    hipLaunchKernelGGL(k_gather_cols, grid1(cnt), dim3(256), 0, st, n, B, dst.B, dpe, slot(from_slot),
+                       dst.slot(to_slot), idx_dev);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+void Engine::release() {
+    for (DevBuf *b : {&Psi, &W, &X32, &partial, &hvec, &alpha, &nrm2, &ab_hist, &act}) b->release();
+}
+
 // ------------------------------------------------------------------ host-side solver logic
 static void build_tri(int m, const double *a, const double *b, std::vector<double> &T) {
     T.assign((size_t)m * m, 0.0);
@@ -967,6 +991,7 @@ SolveRun::~SolveRun() {
     if (hab) (void)hipHostFree(hab);
     if (hC) (void)hipHostFree(hC);
     if (hact) (void)hipHostFree(hact);
+    if (hidx) (void)hipHostFree(hidx);
 }
 
 int SolveRun::slots_for(const qs3_eigs_opts &o) {
@@ -975,15 +1000,17 @@ int SolveRun::slots_for(const qs3_eigs_opts &o) {
 
 int SolveRun::init(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &opts, hipStream_t s) {
     o = opts;
-    QS3_TRY(E.init(ctx, op, slots_for(o), o.precision, o.reorth ? 2 : 0, s));
-    B = E.B;
+    QS3_TRY(root.init(ctx, op, slots_for(o), o.precision, o.reorth ? 2 : 0, s));
+    B = root.B;
     const int NX = o.alg == QS3_ALG_TRL ? o.nm : o.steps;
     const int NY = o.alg == QS3_ALG_TRL ? o.nk : o.nev;
-    QS3_TRY(pinned(&hab, 2 * (size_t)E.slots * B));
+    QS3_TRY(pinned(&hab, 2 * (size_t)root.slots * B));
     QS3_TRY(pinned(&hC, (size_t)B * NX * NY));
     QS3_TRY(pinned(&hact, 2 * (size_t)B));
+    QS3_TRY(pinned(&hidx, (size_t)B));
     QS3_TRY(dC.alloc(ctx, sizeof(double) * (size_t)B * NX * NY));
     QS3_TRY(dact.alloc(ctx, 2 * (size_t)B));
+    QS3_TRY(didx.alloc(ctx, sizeof(int32_t) * (size_t)B));
     QS3_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     evals.assign((size_t)B * o.nev, std::numeric_limits<double>::quiet_NaN());
     info.assign(B, qs3_eigs_info{});
@@ -992,14 +1019,18 @@ int SolveRun::init(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &opts, hipStr
     return QS3_OK;
 }
 
+// alpha/beta of steps x0..x1-1 of the current engine into hab ([x][column],
+// the current engine's column count), then the event
 int SolveRun::enqueue_ab_copy(int x0, int x1) {
+    Engine &E = eng();
+    const int Bc = E.B;
     const int cnt = x1 - x0;
     if (cnt > 0) {
-        QS3_HIP(hipMemcpyAsync(hab + (size_t)x0 * B, E.ab_hist.as<double>() + (size_t)x0 * B,
-                               sizeof(double) * cnt * B, hipMemcpyDeviceToHost, E.st));
-        QS3_HIP(hipMemcpyAsync(hab + (size_t)E.slots * B + (size_t)x0 * B,
-                               E.ab_hist.as<double>() + (size_t)E.slots * B + (size_t)x0 * B,
-                               sizeof(double) * cnt * B, hipMemcpyDeviceToHost, E.st));
+        QS3_HIP(hipMemcpyAsync(hab + (size_t)x0 * Bc, E.ab_hist.as<double>() + (size_t)x0 * Bc,
+                               sizeof(double) * cnt * Bc, hipMemcpyDeviceToHost, E.st));
+        QS3_HIP(hipMemcpyAsync(hab + (size_t)E.slots * Bc + (size_t)x0 * Bc,
+                               E.ab_hist.as<double>() + (size_t)E.slots * Bc + (size_t)x0 * Bc,
+                               sizeof(double) * cnt * Bc, hipMemcpyDeviceToHost, E.st));
     }
     QS3_HIP(hipEventRecord(ev, E.st));
     return QS3_OK;
@@ -1013,9 +1044,9 @@ int SolveRun::wait() {
 }
 
 int SolveRun::begin(const double *v0) {
-    QS3_TRY(E.normalize_into_slot0(v0, nullptr));
+    QS3_TRY(root.normalize_into_slot0(v0, nullptr));
     const int steps = o.alg == QS3_ALG_TRL ? o.nm : o.steps;
-    QS3_TRY(E.cycle(0, steps, -1));
+    QS3_TRY(root.cycle(0, steps, -1));
     QS3_TRY(enqueue_ab_copy(0, steps));
     phase = 1;
     if (o.alg == QS3_ALG_TRL) {
@@ -1026,13 +1057,51 @@ int SolveRun::begin(const double *v0) {
     return QS3_OK;
 }
 
+// Moves the columns with keep[j] != 0 into a new engine over the operator
+// restricted to them: the kept Ritz vectors (slots 0..NK-1) and the residual
+// (slot NM) become slots 0..NK of the new engine.  *compacted = false when
+// the operator has no restriction (the run then goes on with masks).
+int SolveRun::compact(const uint8_t *keep, bool *compacted) {
+    *compacted = false;
+    Engine &E = eng();
+    std::vector<int> sel;
+    for (int j = 0; j < E.B; ++j)
+        if (keep[j]) sel.push_back(j);
+    if (sel.empty()) return QS3_OK;
+    std::unique_ptr<Operator> nop;
+    const int rc = E.op->subset(sel, &nop);
+    if (rc == 1 || !nop) return QS3_OK;
+    QS3_TRY(rc);
+    auto ne = std::make_unique<Engine>();
+    QS3_TRY(ne->init(E.ctx, nop.get(), E.slots, E.precision, E.reorth, E.st));
+    ne->n_matvec = E.n_matvec;
+    const int nb = (int)sel.size();
+    for (int j = 0; j < nb; ++j) hidx[j] = sel[j];
+    QS3_HIP(hipMemcpyAsync(didx.ptr, hidx, sizeof(int32_t) * nb, hipMemcpyHostToDevice, E.st));
+    const int NK = o.nk, NM = o.nm;
+    for (int y = 0; y < NK; ++y) QS3_TRY(E.gather_columns_into(*ne, y, y, didx.as<int32_t>()));
+    QS3_TRY(E.gather_columns_into(*ne, NM, NK, didx.as<int32_t>()));
+    std::vector<int> nmap(nb);
+    for (int j = 0; j < nb; ++j) nmap[j] = col(sel[j]);
+    // the previous engine's memory is released below: let the copies finish
+    QS3_HIP(hipStreamSynchronize(E.st));
+    if (!narrow) root.release();
+    narrow = std::move(ne);
+    narrow_op = std::move(nop);
+    cmap = std::move(nmap);
+    *compacted = true;
+    return QS3_OK;
+}
+
 int SolveRun::advance(bool *done) {
     *done = false;
     if (phase == 4) {
         *done = true;
         return QS3_OK;
     }
-    const double *ha = hab, *hb = hab + (size_t)E.slots * B;
+    Engine &E = eng();
+    const int Bc = E.B;
+    const double *ha = hab, *hb = hab + (size_t)E.slots * Bc;
     if (o.alg == QS3_ALG_LANCZOS) {
         if (phase == 3) {
             phase = 4;
@@ -1076,6 +1145,7 @@ int SolveRun::advance(bool *done) {
             info[c].n_found = (int)lv.size();
             info[c].max_residual = mr;
             info[c].n_matvec = E.n_matvec;
+            info[c].width = B;
         });
         if (want_vecs) {
             QS3_HIP(hipMemcpyAsync(dC.ptr, hC, sizeof(double) * (size_t)B * S * nev, hipMemcpyHostToDevice, E.st));
@@ -1088,17 +1158,21 @@ int SolveRun::advance(bool *done) {
         *done = true;
         return QS3_OK;
     }
-    // ---- thick restart (Alg. 10)
+    // ---- thick restart (Alg. 10); j indexes the current engine's columns,
+    // c = col(j) the sector
     const int NK = o.nk, NM = o.nm, nev = o.nev;
     const int x0 = first ? 0 : NK;
-    for (int c = 0; c < B; ++c)
+    for (int j = 0; j < Bc; ++j) {
+        const int c = col(j);
         for (int x = x0; x < NM; ++x) {
-            al[c][x] = ha[(size_t)x * B + c];
-            be[c][x] = hb[(size_t)x * B + c];
+            al[c][x] = ha[(size_t)x * Bc + j];
+            be[c][x] = hb[(size_t)x * Bc + j];
         }
-    uint8_t *act_rot = hact, *act_next = hact + B;
-    for (int c = 0; c < B; ++c) act_rot[c] = active[c];
-    parallel_columns(B, [&](int c) {
+    }
+    uint8_t *act_rot = hact, *act_next = hact + Bc;
+    for (int j = 0; j < Bc; ++j) act_rot[j] = active[col(j)];
+    parallel_columns(Bc, [&](int j) {
+        const int c = col(j);
         if (!active[c]) return;
         std::vector<double> T((size_t)NM * NM, 0.0), e, V;
         for (int x = 0; x < NM; ++x) T[(size_t)x * NM + x] = al[c][x];
@@ -1116,7 +1190,7 @@ int SolveRun::advance(bool *done) {
         auto lv = pick_levels(std::vector<double>(e.begin(), e.begin() + NK),
                               std::vector<double>(res.begin(), res.begin() + NK), nev, o.tol, false, &allc);
         for (int x = 0; x < NM; ++x)
-            for (int y = 0; y < NK; ++y) hC[((size_t)c * NM + x) * NK + y] = V[(size_t)x * NM + y];
+            for (int y = 0; y < NK; ++y) hC[((size_t)j * NM + x) * NK + y] = V[(size_t)x * NM + y];
         for (int y = 0; y < NK; ++y) {
             coup[c][y] = bm * V[(size_t)(NM - 1) * NM + y];
             al[c][y] = e[y];
@@ -1130,21 +1204,25 @@ int SolveRun::advance(bool *done) {
         info[c].max_residual = mr;
         info[c].n_restarts = restarts;
         info[c].n_matvec = E.n_matvec;
+        info[c].width = Bc;
         final_lv[c] = lv;
         if (allc) info[c].converged = 1;
     });
     bool any_active = false;
-    for (int c = 0; c < B; ++c)
-        if (active[c] && !info[c].converged) any_active = true;
-    for (int c = 0; c < B; ++c) {
+    int n_next = 0;
+    for (int j = 0; j < Bc; ++j) {
+        const int c = col(j);
         if (info[c].converged) active[c] = 0;
-        act_next[c] = active[c];
+        act_next[j] = active[c];
+        if (active[c]) {
+            any_active = true;
+            ++n_next;
+        }
     }
-    // from here on the kernels skip the columns that have converged
     // Ritz vectors into slots NM+1.., then back into 0..NK-1 (rotated columns)
-    QS3_HIP(hipMemcpyAsync(dC.ptr, hC, sizeof(double) * (size_t)B * NM * NK, hipMemcpyHostToDevice, E.st));
-    QS3_HIP(hipMemcpyAsync(dact.ptr, hact, 2 * (size_t)B, hipMemcpyHostToDevice, E.st));
-    const uint8_t *d_rot = dact.as<uint8_t>(), *d_next = dact.as<uint8_t>() + B;
+    QS3_HIP(hipMemcpyAsync(dC.ptr, hC, sizeof(double) * (size_t)Bc * NM * NK, hipMemcpyHostToDevice, E.st));
+    QS3_HIP(hipMemcpyAsync(dact.ptr, hact, 2 * (size_t)Bc, hipMemcpyHostToDevice, E.st));
+    const uint8_t *d_rot = dact.as<uint8_t>(), *d_next = dact.as<uint8_t>() + Bc;
     QS3_TRY(E.rotate_dev(0, NM, dC.as<double>(), NK, NM + 1, d_rot));
     for (int y = 0; y < NK; ++y) QS3_TRY(E.copy_slot_dev(NM + 1 + y, y, d_rot));
     if (!any_active || restarts >= o.max_restarts) {
@@ -1153,12 +1231,22 @@ int SolveRun::advance(bool *done) {
         *done = true;
         return QS3_OK;
     }
-    // restart cycle: the residual becomes psi_{NK+1}; the first step has no
-    // three-term partner (the couplings to the kept Ritz vectors are removed by
-    // the full reorthogonalisation), then x = NK+1..NM-1
-    E.colmask = B > 1 ? d_next : nullptr;
-    QS3_TRY(E.copy_slot_dev(NM, NK, d_next));
-    QS3_TRY(E.cycle(NK, NM, -1));
+    // from here on the kernels skip the columns that have converged, or the
+    // columns still iterating move into a narrower engine
+    bool compacted = false;
+    if (Bc > 1 && !want_vecs && 4 * n_next <= Bc) QS3_TRY(compact(act_next, &compacted));
+    Engine &En = eng();
+    if (compacted) {
+        En.colmask = nullptr;
+    } else {
+        // restart cycle: the residual becomes psi_{NK+1}
+        En.colmask = Bc > 1 ? d_next : nullptr;
+        QS3_TRY(En.copy_slot_dev(NM, NK, d_next));
+    }
+    // the first step has no three-term partner (the couplings to the kept
+    // Ritz vectors are removed by the full reorthogonalisation), then
+    // x = NK+1..NM-1
+    QS3_TRY(En.cycle(NK, NM, -1));
     QS3_TRY(enqueue_ab_copy(NK, NM));
     first = false;
     ++restarts;
@@ -1194,7 +1282,7 @@ int solve_blocking(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &o, const dou
         for (int y = 0; y < o.nev; ++y) {
             const int sl = R.vec_slot(0, y);
             if (sl < 0) continue;
-            QS3_HIP(hipMemcpyAsync(vec_out + (size_t)y * R.E.stride, R.E.slot(sl), sizeof(double) * R.E.stride,
+            QS3_HIP(hipMemcpyAsync(vec_out + (size_t)y * R.eng().stride, R.eng().slot(sl), sizeof(double) * R.eng().stride,
                                    hipMemcpyDeviceToDevice, s));
         }
         QS3_HIP(hipStreamSynchronize(s));

@@ -1,6 +1,7 @@
 // Krylov engine interface (internal).
 #pragma once
 #include <algorithm>
+#include <memory>
 #include <vector>
 
 #include "qs3_impl.h"
@@ -21,6 +22,8 @@ struct Operator {
     virtual void set_mask(const uint8_t *) {}
     // a whole cycle of steps x0..x1-1 in one workgroup; 1 = not supported
     virtual int small_cycle(Engine &, int, int, int) { return 1; }
+    // the operator restricted to the listed columns (ascending); 1 = not supported
+    virtual int subset(const std::vector<int> &, std::unique_ptr<Operator> *) { return 1; }
 };
 
 // Geometry of the deterministic column reductions: a block covers TC columns
@@ -59,15 +62,26 @@ struct Engine {
     int read_ab(int x0, int x1, std::vector<double> &a, std::vector<double> &b);
     int rotate_dev(int from_slot, int NX, const double *dC, int NY, int to_slot, const uint8_t *act_dev);
     int copy_slot_dev(int from, int to, const uint8_t *act_dev);
+    // dst slot to_slot, column j := this engine's slot from_slot, column idx[j]
+    int gather_columns_into(Engine &dst, int from_slot, int to_slot, const int32_t *idx_dev);
+    void release();
 };
 
 // A Lanczos / thick-restart Lanczos solve that advances without blocking:
 // begin() enqueues the first cycle, ready() polls its event, advance() does
 // the host part (tridiagonal / arrowhead eigensolves, convergence) and
 // enqueues the next cycle.  Every column is a separate sector and stops
-// changing once it has converged.
+// changing once it has converged.  When no eigenvectors are wanted and at
+// most a quarter of the columns still iterate, a thick restart moves them
+// into a narrower engine (the operator restricted to those columns), so the
+// slowest sectors no longer pay for the converged ones.
 struct SolveRun {
-    Engine E;
+    Engine root;                       // over all the operator's columns
+    std::unique_ptr<Engine> narrow;    // after compaction: the columns still iterating
+    std::unique_ptr<Operator> narrow_op;
+    std::vector<int> cmap;             // column j of the narrow engine is column cmap[j]
+    Engine &eng() { return narrow ? *narrow : root; }
+    int col(int j) const { return cmap.empty() ? j : cmap[j]; }
     qs3_eigs_opts o{};
     int B = 1;
     bool want_vecs = false;
@@ -76,7 +90,8 @@ struct SolveRun {
     int restarts = 0;
     double *hab = nullptr, *hC = nullptr;
     uint8_t *hact = nullptr;
-    DevBuf dC, dact;
+    int32_t *hidx = nullptr;
+    DevBuf dC, dact, didx;
     hipEvent_t ev = nullptr;
     std::vector<std::vector<double>> al, be, coup;
     std::vector<uint8_t> active;
@@ -94,6 +109,7 @@ struct SolveRun {
 
    private:
     int enqueue_ab_copy(int x0, int x1);
+    int compact(const uint8_t *keep, bool *compacted);
 };
 
 int solve_blocking(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &o, const double *v0, hipStream_t s,
@@ -145,6 +161,7 @@ struct BatchOp : Operator {
         bat->active_dev = nullptr;
         return rc;
     }
+    int subset(const std::vector<int> &cols, std::unique_ptr<Operator> *out) override;
 };
 
 inline int fill_opts(qs3_eigs_opts &o, uint64_t min_dim) {

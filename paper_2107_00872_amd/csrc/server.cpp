@@ -210,7 +210,7 @@ static void worker_main(qs3_server *S) {
                     (void)r->run->wait();
                     const auto &inf = r->run->info[0];
                     r->res.n_found = inf.n_found;
-                    r->res.n_matvec = r->run->E.n_matvec;
+                    r->res.n_matvec = r->run->eng().n_matvec;
                     for (int y = 0; y < r->opts.nev && y < 16; ++y) r->res.evals[y] = r->run->evals[y];
                     status = inf.converged ? QS3_OK : QS3_ENOCONV;
                 }

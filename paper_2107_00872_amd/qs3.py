@@ -32,7 +32,8 @@ class EigsOpts(ctypes.Structure):
 
 class EigsInfo(ctypes.Structure):
     _fields_ = [("converged", ctypes.c_int), ("n_restarts", ctypes.c_int), ("n_matvec", ctypes.c_int),
-                ("n_found", ctypes.c_int), ("max_residual", dbl), ("seconds", dbl)]
+                ("n_found", ctypes.c_int), ("max_residual", dbl), ("seconds", dbl),
+                ("width", ctypes.c_int)]
 
 
 class DsfOpts(ctypes.Structure):
