@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=50)
+    ap.add_argument("--no-one-at-a-time", action="store_true",
+                    help="skip the one-sector-at-a-time comparison (shorter profiles)")
     ap.add_argument("--requests", type=int, default=0, help="c5: number of requests (default 40)")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
                     help="c2 (default) is the headline configuration; the others print their own line")
@@ -173,6 +175,10 @@ def main():
     e1.record(stream)
     e1.synchronize()
     t_mv = e0.elapsed_time(e1) / 1e3 / args.matvec_reps
+    # a plain device copy of the same d float64 (d*8 bytes read, d*8 written):
+    # the reference dispatch that scales the FETCH_SIZE / WRITE_SIZE counters
+    # of a profiled run to bytes
+    w.copy_(v)
     alg_bytes = 8.0 * (2 * d + n_hops)
     achieved = alg_bytes / t_mv / 1e9
     # float32-row variant of the same kernel
@@ -201,21 +207,23 @@ def main():
 
     # ---- the same 100 momentum solves one at a time (plain float64 path, the
     # sectors created beforehand), seeds as in the batch of the last step
-    secs = [qs3.Sector(L, K, k) for k in ks]
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    ev_serial = [secs[b].eigs(nev=5, alg=qs3.ALG_TRL, seed=args.steps + b, stream=stream).evals
-                 for b in range(len(ks))]
-    torch.cuda.synchronize()
-    t_serial = time.perf_counter() - ts
-    for sc in secs:
-        sc.close()
     r1, ev, infos, obs = last
-    ev_serial = np.array(ev_serial)
-    both = np.isfinite(ev_serial) & np.isfinite(ev)
-    serial = {"solves_per_s": len(ks) / t_serial, "seconds": t_serial,
-              "batched_solves_per_s": bat.B / t_batch[-1], "batched_seconds": t_batch[-1],
-              "max_rel_diff": float(np.max(np.abs(ev_serial[both] - ev[both]) / np.abs(ev[both])))}
+    serial = None
+    if not args.no_one_at_a_time:
+        secs = [qs3.Sector(L, K, k) for k in ks]
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ev_serial = [secs[b].eigs(nev=5, alg=qs3.ALG_TRL, seed=args.steps + b, stream=stream).evals
+                     for b in range(len(ks))]
+        torch.cuda.synchronize()
+        t_serial = time.perf_counter() - ts
+        for sc in secs:
+            sc.close()
+        ev_serial = np.array(ev_serial)
+        both = np.isfinite(ev_serial) & np.isfinite(ev)
+        serial = {"solves_per_s": len(ks) / t_serial, "seconds": t_serial,
+                  "batched_solves_per_s": bat.B / t_batch[-1], "batched_seconds": t_batch[-1],
+                  "max_rel_diff": float(np.max(np.abs(ev_serial[both] - ev[both]) / np.abs(ev[both])))}
     out = {
         "metric": "H.v rows/s (whole solve step) + %HBM roofline of the H.v kernel",
         "value": rows_tot / t_all,

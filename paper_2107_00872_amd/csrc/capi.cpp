@@ -262,12 +262,16 @@ int qs3_lattice_create(qs3_ctx *ctx, int lx, int ly, int lz, int n_bonds, const 
     lat->h_ptr.assign(N + 1, 0);
     for (long s = 0; s < N; ++s) {
         lat->h_ptr[s + 1] = lat->h_ptr[s] + (int)nb[s].size();
+        lat->max_degree = std::max(lat->max_degree, (int)nb[s].size());
         for (auto &pr : nb[s]) {
             lat->h_nbr.push_back((uint16_t)pr.first);
             lat->h_jxy_h.push_back(lat->jxy[pr.second] / 2.0);
             lat->h_jz_h.push_back(lat->jz[pr.second] / 2.0);
         }
     }
+    lat->regular = N > 0;
+    for (long s = 0; s < N; ++s)
+        if ((int)nb[s].size() != lat->max_degree) lat->regular = false;
     lat->uniform = n_bonds > 0;
     for (int b = 1; b < n_bonds; ++b)
         if (lat->jxy[b] != lat->jxy[0] || lat->jz[b] != lat->jz[0]) lat->uniform = false;

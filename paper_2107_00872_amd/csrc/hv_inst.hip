@@ -27,18 +27,31 @@ static size_t lds_need(const qs3_lattice *lat, int K) {
 }
 
 // ------------------------------------------------------------------ U(1)
-template <typename RT, typename VT, typename OT>
-static int launch_u1(qs3_sector *sec, const void *v, void *w, hipStream_t s) {
+template <typename RT, typename VT, typename OT, int ZM>
+static int launch_u1_z(qs3_sector *sec, const void *v, void *w, hipStream_t s) {
     qs3_lattice *lat = sec->lat;
     LatArgs L = lat_args(lat);
     size_t sh = lds_need<RT>(lat, KI);
     QS3_REQUIRE(sh <= 160 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
     uint64_t tiles = (sec->dim + 255) / 256;
     int grid = grid_for(lat->ctx, tiles);
-    hipLaunchKernelGGL((k_hv_u1<KI, RT, VT, OT>), dim3(grid), dim3(256), sh, s, L,
+    hipLaunchKernelGGL((k_hv_u1<KI, RT, VT, OT, ZM>), dim3(grid), dim3(256), sh, s, L,
                        sec->bt->dev.as<RT>(), (RT)sec->dim, (const VT *)v, (OT *)w);
     QS3_HIP(hipGetLastError());
     return QS3_OK;
+}
+
+// the unrolled all-hops-in-flight row for uniform couplings on lattices where
+// every site has 2, 4 or 6 neighbours (chains, square and cubic lattices)
+// while K * degree stays within the registers; the plain loop otherwise
+template <typename RT, typename VT, typename OT>
+static int launch_u1(qs3_sector *sec, const void *v, void *w, hipStream_t s) {
+    const qs3_lattice *lat = sec->lat;
+    const int z = (lat->uniform && lat->regular) ? lat->max_degree : 0;
+    if (z == 2 && KI * 2 <= 24) return launch_u1_z<RT, VT, OT, 2>(sec, v, w, s);
+    if (z == 4 && KI * 4 <= 24) return launch_u1_z<RT, VT, OT, 4>(sec, v, w, s);
+    if (z == 6 && KI * 6 <= 24) return launch_u1_z<RT, VT, OT, 6>(sec, v, w, s);
+    return launch_u1_z<RT, VT, OT, 0>(sec, v, w, s);
 }
 
 template <typename RT>

@@ -73,14 +73,42 @@ static size_t lds_bytes(const qs3_lattice *lat, int K) {
 // One output row of the fixed-N_down H.v (Alg. 9 with sigma = all ranks):
 // the Ising diagonal E_FM - sum over (down site, up neighbour) of Jz/2, and
 // Jxy/2 v[rank'] for every hop of a down spin to an up neighbour.
-template <int K, typename RT, typename VT>
+//
+// ZM > 0 (uniform couplings, every site has exactly ZM neighbours, stored
+// contiguously from ZM * site): all K*ZM candidate hops are ranked first and
+// their gathers issued together (a slot that is no hop reads the row's own
+// element and is dropped by a select), so a row waits for one memory latency
+// instead of one per hop and carries no divergent branches.  ZM = 0: a plain
+// loop over each down spin's neighbours (any degree, any couplings).
+template <int K, typename RT, typename VT, int ZM>
 __device__ __forceinline__ VT hv_row_u1(const LatArgs &L, const Binom<RT> &Bn, const int *ptr,
                                         const uint16_t *nbr, RT row, const VT *__restrict__ v) {
-    const bool UNIF = L.uniform != 0;
     int c[K > 0 ? K : 1];
     unrank<K, RT>(row, L.N, Bn, c);
     HopRanker<K, RT> hr;
     hr.init(c, Bn);
+    if constexpr (ZM > 0) {
+        constexpr int NH = (K > 0 ? K : 1) * ZM;
+        VT x[NH];
+        uint64_t okm = 0;  // bit h: slot h is a hop
+        StaticFor<0, K>::run([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int e0 = c[m] * ZM;
+#pragma unroll
+            for (int q = 0; q < ZM; ++q) {
+                RT rp;
+                const bool up = hr.template hop<m>(c, row, (int)nbr[e0 + q], Bn, &rp);
+                okm |= up ? (uint64_t(1) << (m * ZM + q)) : uint64_t(0);
+                x[m * ZM + q] = v[up ? rp : row];
+            }
+        });
+        VT acc = 0;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) acc += ((okm >> h) & 1u) ? x[h] : (VT)0;
+        const VT diag = (VT)L.ez4 - (VT)L.u_jz_h * (VT)__popcll(okm);
+        return diag * v[row] + (VT)L.u_jxy_h * acc;
+    }
+    const bool UNIF = L.uniform != 0;
     VT acc = 0, dz = 0;
     StaticFor<0, K>::run([&](auto mc) {
         constexpr int m = decltype(mc)::value;
@@ -115,7 +143,7 @@ __device__ __forceinline__ VT hv_row_u1(const LatArgs &L, const Binom<RT> &Bn, c
     return diag * v[row] + off;
 }
 
-template <int K, typename RT, typename VT, typename OT>
+template <int K, typename RT, typename VT, typename OT, int ZM>
 __global__ __launch_bounds__(256) void k_hv_u1(LatArgs L, const RT *__restrict__ binom_g, RT D,
                                                const VT *__restrict__ v, OT *__restrict__ w) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -131,7 +159,7 @@ __global__ __launch_bounds__(256) void k_hv_u1(LatArgs L, const RT *__restrict__
     for (uint64_t tile = t0; tile < t1; ++tile) {
         const uint64_t row64 = tile * 256 + threadIdx.x;
         if (row64 >= (uint64_t)D) break;
-        w[row64] = (OT)hv_row_u1<K, RT, VT>(L, Bn, ptr, nbr, (RT)row64, v);
+        w[row64] = (OT)hv_row_u1<K, RT, VT, ZM>(L, Bn, ptr, nbr, (RT)row64, v);
     }
 }
 
@@ -686,7 +714,7 @@ __global__ __launch_bounds__(1024) void k_lanczos_small(SmallArgs S, BatchArgs A
                 ((double2 *)S.W)[r] = hv_row_k1<K, RT, TABLE>(A, Bn, g, ptr, nbr, r, px);
         } else {
             const double *px = P(x);
-            for (uint64_t r = tid; r < n; r += nt) S.W[r] = hv_row_u1<K, RT, double>(A.L, Bn, ptr, nbr, (RT)r, px);
+            for (uint64_t r = tid; r < n; r += nt) S.W[r] = hv_row_u1<K, RT, double, 0>(A.L, Bn, ptr, nbr, (RT)r, px);
         }
         __syncthreads();
         // ---- alpha = Re <psi_x, W>; W -= alpha psi_x + beta_prev psi_prev

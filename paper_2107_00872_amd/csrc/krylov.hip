@@ -297,7 +297,9 @@ __global__ void k_copy_re(int B, const double2 *__restrict__ in, double *__restr
     if (b < B) out[b] = in[b].x;
 }
 
-// Out_y = sum_{x < NX} X_x * C[b][x][y] for y < NY (C real, per column), masked by active[b].
+// Out_y = sum_{x < NX} X_x * C[x][y][b] for y < NY (C real, per column, the
+// column index fastest so a wavefront's coefficient loads are contiguous),
+// masked by active[b].
 template <bool CPLX, int NYT>
 __global__ __launch_bounds__(256) void k_rotate(uint64_t ne, int B, const double *__restrict__ X,
                                                 uint64_t stride, int NX, const double *__restrict__ Cm,
@@ -307,7 +309,8 @@ __global__ __launch_bounds__(256) void k_rotate(uint64_t ne, int B, const double
     if (e >= ne) return;
     const int b = (int)(e % (uint64_t)B);
     if (active && !active[b]) return;
-    const double *Cb = Cm + (size_t)b * NX * NY;
+    const double *Cb = Cm + b;
+    const size_t cs = (size_t)B;  // stride between consecutive (x, y) coefficients
     for (int y0 = 0; y0 < NY; y0 += NYT) {
         double ar[NYT], ai[NYT];
 #pragma unroll
@@ -318,7 +321,7 @@ __global__ __launch_bounds__(256) void k_rotate(uint64_t ne, int B, const double
 #pragma unroll
                 for (int q = 0; q < NYT; ++q) {
                     if (y0 + q < NY) {
-                        const double c = Cb[(size_t)x * NY + y0 + q];
+                        const double c = Cb[((size_t)x * NY + y0 + q) * cs];
                         ar[q] += v.x * c;
                         ai[q] += v.y * c;
                     }
@@ -327,7 +330,7 @@ __global__ __launch_bounds__(256) void k_rotate(uint64_t ne, int B, const double
                 const double v = X[(size_t)x * stride + e];
 #pragma unroll
                 for (int q = 0; q < NYT; ++q)
-                    if (y0 + q < NY) ar[q] += v * Cb[(size_t)x * NY + y0 + q];
+                    if (y0 + q < NY) ar[q] += v * Cb[((size_t)x * NY + y0 + q) * cs];
             }
         }
 #pragma unroll
@@ -1138,7 +1141,7 @@ int SolveRun::advance(bool *done) {
                 mr = std::max(mr, res[lv[y]]);
                 if (want_vecs) {
                     tridiag_vector(m, a.data(), b.data(), e[lv[y]], vec.data());
-                    for (int x = 0; x < m; ++x) hC[((size_t)c * S + x) * nev + y] = vec[x];
+                    for (int x = 0; x < m; ++x) hC[((size_t)x * nev + y) * B + c] = vec[x];
                 }
             }
             info[c].converged = allc ? 1 : 0;
@@ -1190,7 +1193,7 @@ int SolveRun::advance(bool *done) {
         auto lv = pick_levels(std::vector<double>(e.begin(), e.begin() + NK),
                               std::vector<double>(res.begin(), res.begin() + NK), nev, o.tol, false, &allc);
         for (int x = 0; x < NM; ++x)
-            for (int y = 0; y < NK; ++y) hC[((size_t)j * NM + x) * NK + y] = V[(size_t)x * NM + y];
+            for (int y = 0; y < NK; ++y) hC[((size_t)x * NK + y) * Bc + j] = V[(size_t)x * NM + y];
         for (int y = 0; y < NK; ++y) {
             coup[c][y] = bm * V[(size_t)(NM - 1) * NM + y];
             al[c][y] = e[y];

@@ -9,6 +9,7 @@
 #include <complex>
 #include <map>
 #include <numeric>
+#include <unordered_map>
 #include <vector>
 
 #include "qs3_hv.h"
@@ -176,16 +177,24 @@ int qs3_sisj(qs3_sector *sec, const void *vec, int n_pairs, const int32_t *pi, c
     double n2 = 0;
     QS3_TRY(vec_norm2(sec, vec, &n2, s));
     QS3_REQUIRE(n2 > 0 && std::isfinite(n2), QS3_ENUMERIC, "zero or non-finite state");
+    // the pair sums are symmetric in (i, j) and the kernel forms the same
+    // products in the same order for both orders: one launch row per
+    // unordered pair
     std::vector<int32_t> hi_, hj_;
-    std::vector<int> idx;
+    std::vector<int> which(n_pairs, -1);
+    std::unordered_map<int64_t, int> uniq;
     for (int p = 0; p < n_pairs; ++p)
         if (pi[p] != pj[p]) {
-            hi_.push_back(pi[p]);
-            hj_.push_back(pj[p]);
-            idx.push_back(p);
+            const int lo = std::min(pi[p], pj[p]), hi = std::max(pi[p], pj[p]);
+            auto ins = uniq.emplace((int64_t)lo * N + hi, (int)hi_.size());
+            if (ins.second) {
+                hi_.push_back(lo);
+                hj_.push_back(hi);
+            }
+            which[p] = ins.first->second;
         }
     DevBuf dpi, dpj;
-    const int np = (int)idx.size();
+    const int np = (int)hi_.size();
     QS3_TRY(dpi.alloc(sec->lat->ctx, sizeof(int32_t) * std::max(np, 1)));
     QS3_TRY(dpj.alloc(sec->lat->ctx, sizeof(int32_t) * std::max(np, 1)));
     if (np) {
@@ -201,8 +210,9 @@ int qs3_sisj(qs3_sector *sec, const void *vec, int n_pairs, const int32_t *pi, c
             pm[2 * t + 1] = 0.0;
         }
     }
-    for (int k = 0; k < np; ++k) {
-        const int t = idx[k];
+    for (int t = 0; t < n_pairs; ++t) {
+        const int k = which[t];
+        if (k < 0) continue;
         const double xi = p[pi[t]] / n2, xj = p[pj[t]] / n2;
         zz[t] = 0.25 - 0.5 * (xi + xj) + q[k] / n2;
         pm[2 * t] = pmv[k] / n2;

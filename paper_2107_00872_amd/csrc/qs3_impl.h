@@ -121,6 +121,8 @@ struct qs3_lattice {
     // adjacency (both directions), CSR over sites
     std::vector<int> h_ptr;
     std::vector<uint16_t> h_nbr;
+    int max_degree = 0;    // most neighbours of a site
+    bool regular = false;  // every site has max_degree neighbours
     std::vector<double> h_jxy_h, h_jz_h;  // Jxy/2, Jz/2 per directed edge
     bool uniform = false;
     double u_jxy_h = 0, u_jz_h = 0;
