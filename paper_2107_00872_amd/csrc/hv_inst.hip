@@ -215,6 +215,7 @@ static int launch_batch(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
     if (per <= 1) QS3_LB(1);
     else if (per <= 2) QS3_LB(2);
     else if (per <= 4) QS3_LB(4);
+    else if (per <= 8) QS3_LB(8);
     else if (per <= 16) QS3_LB(16);
     else if (per <= 32) QS3_LB(32);
     else {

@@ -220,6 +220,7 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                                                   typename Cplx<OT>::type *__restrict__ w) {
     using C2 = typename Cplx<CT>::type;
     using O2 = typename Cplx<OT>::type;
+    constexpr int QC = BPL >= 8 ? 1 : 8 / BPL;  // hops whose gathers are in flight together
     extern __shared__ __align__(16) unsigned char smem[];
     const RT *tab;
     const int *ptr;
@@ -292,33 +293,94 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                     ok = true;
                 }
             }
-            // ---- apply the round's hops to this lane's sectors
+            // ---- apply the round's hops to this lane's sectors, QC hops at a
+            // time (QC * BPL gathers): their gathers and phase loads are all
+            // issued before any is consumed; a slot that applies nothing reads
+            // element 0 and is dropped by a select.  Groups narrower than QC
+            // and 32 sectors per lane (too many registers) go one hop at a time.
             const int cnt = min(G, nh - base);
-            for (int q = 0; q < cnt; ++q) {
-                const int bok = __shfl((int)ok, q, G);
-                if (!bok) continue;
-                const uint32_t bu = (uint32_t)__shfl((int)u2, q, G);
-                const uint32_t bt = (uint32_t)__shfl((int)tp, q, G);
-                const int bnt = __shfl(nt2, q, G);
-                const CT bc = (CT)__shfl(coef, q, G);
-                dz += (CT)__shfl(jzv, q, G);
-                const int tx = bt & 1023u, ty = (bt >> 10) & 1023u, tz = (bt >> 20) & 1023u;
-                const C2 *vrow = v + (uint64_t)bu * B;
+            if (BPL >= 32 || G < QC) {
+                for (int q = 0; q < cnt; ++q) {
+                    const int bok = __shfl((int)ok, q, G);
+                    if (!bok) continue;
+                    const uint32_t bu = (uint32_t)__shfl((int)u2, q, G);
+                    const uint32_t bt = (uint32_t)__shfl((int)tp, q, G);
+                    const int bnt = __shfl(nt2, q, G);
+                    const CT bc = (CT)__shfl(coef, q, G);
+                    dz += (CT)__shfl(jzv, q, G);
+                    const int tx = bt & 1023u, ty = (bt >> 10) & 1023u, tz = (bt >> 20) & 1023u;
+                    const C2 *vrow = v + (uint64_t)bu * B;
 #pragma unroll
-                for (int i = 0; i < BPL; ++i) {
-                    if (!bval[i]) continue;
-                    const int b = lane + i * G;
-                    if (bnt >= 0 && !A.compat_nt[(size_t)bnt * B + b]) continue;
-                    int P = kx[i] * tx + ky[i] * ty + kz[i] * tz;
-                    const int qq = (int)((double)P * A.invM);
-                    P -= qq * A.M;
-                    P += (P < 0) ? A.M : 0;
-                    P -= (P >= A.M) ? A.M : 0;
-                    const double2 ph = A.phase[P];
-                    const C2 x = vrow[b];
-                    const CT pr = bc * (CT)ph.x, pi = bc * (CT)ph.y;
-                    accr[i] += pr * x.x - pi * x.y;
-                    acci[i] += pr * x.y + pi * x.x;
+                    for (int i = 0; i < BPL; ++i) {
+                        if (!bval[i]) continue;
+                        const int b = lane + i * G;
+                        if (bnt >= 0 && !A.compat_nt[(size_t)bnt * B + b]) continue;
+                        int P = kx[i] * tx + ky[i] * ty + kz[i] * tz;
+                        const int qq = (int)((double)P * A.invM);
+                        P -= qq * A.M;
+                        P += (P < 0) ? A.M : 0;
+                        P -= (P >= A.M) ? A.M : 0;
+                        const double2 ph = A.phase[P];
+                        const C2 x = vrow[b];
+                        const CT pr = bc * (CT)ph.x, pi = bc * (CT)ph.y;
+                        accr[i] += pr * x.x - pi * x.y;
+                        acci[i] += pr * x.y + pi * x.x;
+                    }
+                }
+                continue;
+            }
+            for (int q0 = 0; q0 < cnt; q0 += QC) {
+                bool hok[QC];
+                uint32_t hu[QC];
+                int htx[QC], hty[QC], htz[QC], hnt[QC];
+                CT hc[QC];
+#pragma unroll
+                for (int r = 0; r < QC; ++r) {
+                    const int q = q0 + r;
+                    const int qs = q < cnt ? q : 0;
+                    const int okq = __shfl((int)ok, qs, G);
+                    hok[r] = q < cnt && okq != 0;
+                    hu[r] = (uint32_t)__shfl((int)u2, qs, G);
+                    const uint32_t bt = (uint32_t)__shfl((int)tp, qs, G);
+                    htx[r] = bt & 1023u;
+                    hty[r] = (bt >> 10) & 1023u;
+                    htz[r] = (bt >> 20) & 1023u;
+                    hnt[r] = __shfl(nt2, qs, G);
+                    hc[r] = (CT)__shfl(coef, qs, G);
+                    const CT jz = (CT)__shfl(jzv, qs, G);
+                    if (hok[r]) dz += jz;
+                }
+                C2 x[QC][BPL];
+                double2 ph[QC][BPL];
+#pragma unroll
+                for (int r = 0; r < QC; ++r) {
+#pragma unroll
+                    for (int i = 0; i < BPL; ++i) {
+                        const int b = lane + i * G;
+                        bool use = hok[r] && bval[i];
+                        if (use && hnt[r] >= 0) use = A.compat_nt[(size_t)hnt[r] * B + b] != 0;
+                        int P = kx[i] * htx[r] + ky[i] * hty[r] + kz[i] * htz[r];
+                        const int qq = (int)((double)P * A.invM);
+                        P -= qq * A.M;
+                        P += (P < 0) ? A.M : 0;
+                        P -= (P >= A.M) ? A.M : 0;
+                        const uint64_t idx = use ? (uint64_t)hu[r] * B + b : 0;
+                        x[r][i] = v[idx];
+                        ph[r][i] = A.phase[use ? P : 0];
+                        if (!use) {
+                            x[r][i].x = 0;
+                            x[r][i].y = 0;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < QC; ++r) {
+#pragma unroll
+                    for (int i = 0; i < BPL; ++i) {
+                        const CT pr = hc[r] * (CT)ph[r][i].x, pi = hc[r] * (CT)ph[r][i].y;
+                        accr[i] += pr * x[r][i].x - pi * x[r][i].y;
+                        acci[i] += pr * x[r][i].y + pi * x[r][i].x;
+                    }
                 }
             }
         }

@@ -64,14 +64,42 @@ __device__ __forceinline__ void cdot_acc(double2 x, double2 y, double &sr, doubl
 }
 
 // ------------------------------------------------------------------ kernels
+// The three-term part of a Lanczos step, applied on the fly (never stored):
+// Y - alpha_b P0 - beta_b P1 per column, in the order a separate update pass
+// would use.  P0 == null: Y unchanged; P1 == null: no beta term.
+struct ThreeTerm {
+    const double *P0 = nullptr, *P1 = nullptr;
+    const double2 *alpha = nullptr;
+    const double *beta = nullptr;
+};
+
+__device__ __forceinline__ double three_term(double w, uint64_t e, const ThreeTerm &f, double a, double be) {
+    w -= a * f.P0[e];
+    if (f.P1) w -= be * f.P1[e];
+    return w;
+}
+__device__ __forceinline__ double2 three_term(double2 w, uint64_t e, const ThreeTerm &f, double a, double be) {
+    const double2 p0 = ((const double2 *)f.P0)[e];
+    w.x -= a * p0.x;
+    w.y -= a * p0.y;
+    if (f.P1) {
+        const double2 p1 = ((const double2 *)f.P1)[e];
+        w.x -= be * p1.x;
+        w.y -= be * p1.y;
+    }
+    return w;
+}
+
 // partial[(chunk * JO + j) * B + b] (re, im) = sum over the chunk's rows of
-// conj(X_j[r, b]) * Y[r, b] for j < J (X_j = X + j * stride) and, when
-// selfdot, |Y[r, b]|^2 at j = J (JO = J + selfdot outputs).  Columns with
-// mask[b] == 0 are skipped (their partials are written as zero).
-template <bool CPLX, int JT>
+// conj(X_j[r, b]) * Y'[r, b] for j < J (X_j = X + j * stride) and, when
+// selfdot, |Y'[r, b]|^2 at j = J (JO = J + selfdot outputs), with Y' = Y
+// after the three-term part f.  Up to JM outputs accumulate in registers in
+// one pass over the rows (Y read once); more take ceil(JO / JM) passes.
+// Columns with mask[b] == 0 are skipped (their partials are written as zero).
+template <bool CPLX, int JM>
 __global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__restrict__ X,
                                                   uint64_t stride, int J, int selfdot,
-                                                  const double *__restrict__ Y,
+                                                  const double *__restrict__ Y, ThreeTerm f,
                                                   const uint8_t *__restrict__ mask,
                                                   double2 *__restrict__ partial) {
     using T = typename Elem<CPLX>::T;
@@ -81,18 +109,21 @@ __global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__res
     const uint64_t r1 = min(g.n, r0 + g.RC);
     const int JO = J + selfdot;
     const bool on = b < g.B && (!mask || mask[b]);
+    const double fa = (on && f.P0) ? f.alpha[b].x : 0.0;
+    const double fb = (on && f.P0 && f.P1) ? f.beta[b] : 0.0;
     __shared__ double2 red[256][4];
     const T *Yt = (const T *)Y;
-    for (int j0 = 0; j0 < JO; j0 += JT) {
-        double sr[JT], si[JT];
+    for (int j0 = 0; j0 < JO; j0 += JM) {
+        double sr[JM], si[JM];
 #pragma unroll
-        for (int q = 0; q < JT; ++q) sr[q] = si[q] = 0.0;
+        for (int q = 0; q < JM; ++q) sr[q] = si[q] = 0.0;
         if (on) {
             for (uint64_t r = r0 + tr; r < r1; r += g.TR) {
                 const uint64_t e = r * g.B + b;
-                const T y = Yt[e];
+                T y = Yt[e];
+                if (f.P0) y = three_term(y, e, f, fa, fb);
 #pragma unroll
-                for (int q = 0; q < JT; ++q) {
+                for (int q = 0; q < JM; ++q) {
                     const int jj = j0 + q;
                     if (jj < J) {
                         const T x = ((const T *)(X + (size_t)jj * stride))[e];
@@ -104,7 +135,8 @@ __global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__res
             }
         }
 #pragma unroll
-        for (int q0 = 0; q0 < JT; q0 += 4) {
+        for (int q0 = 0; q0 < JM; q0 += 4) {
+            if (j0 + q0 >= JO) break;
 #pragma unroll
             for (int q = 0; q < 4; ++q) red[threadIdx.x][q] = make_double2(sr[q0 + q], si[q0 + q]);
             __syncthreads();
@@ -129,27 +161,30 @@ __global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__res
     }
 }
 
-// W -= sum_{j<J} X_j h[j * B + b] on the columns with mask[b] != 0 (all when
-// mask is null), and partial[chunk * B + b] = sum over the chunk's rows of
-// |W|^2 after the update (the norm for beta, fused into the same pass).
+// W := W' - sum_{j<J} X_j h[j * B + b] on the columns with mask[b] != 0 (all
+// when mask is null), W' = W after the three-term part f, and
+// partial[chunk * B + b] = sum over the chunk's rows of |W|^2 after the
+// update (the norm for beta, fused into the same pass).
 template <bool CPLX>
 __global__ __launch_bounds__(256) void k_cgs_update_norm(RedGeom g, double *__restrict__ W,
                                                          const double *__restrict__ X, uint64_t stride,
-                                                         int J, const double2 *__restrict__ h,
+                                                         int J, const double2 *__restrict__ h, ThreeTerm f,
                                                          const uint8_t *__restrict__ mask,
                                                          double2 *__restrict__ partial) {
-    using T = typename Elem<CPLX>::T;
     const int tc = threadIdx.x % g.TC, tr = threadIdx.x / g.TC;
     const int b = blockIdx.y * g.TC + tc;
     const uint64_t r0 = (uint64_t)blockIdx.x * g.RC;
     const uint64_t r1 = min(g.n, r0 + g.RC);
     const bool on = b < g.B && (!mask || mask[b]);
+    const double fa = (on && f.P0) ? f.alpha[b].x : 0.0;
+    const double fb = (on && f.P0 && f.P1) ? f.beta[b] : 0.0;
     double acc = 0.0;
     if (on) {
         for (uint64_t r = r0 + tr; r < r1; r += g.TR) {
             const uint64_t e = r * g.B + b;
             if (CPLX) {
                 double2 w = ((double2 *)W)[e];
+                if (f.P0) w = three_term(w, e, f, fa, fb);
                 for (int jj = 0; jj < J; ++jj) {
                     const double2 x = ((const double2 *)(X + (size_t)jj * stride))[e];
                     const double2 c = h[(size_t)jj * g.B + b];
@@ -160,6 +195,7 @@ __global__ __launch_bounds__(256) void k_cgs_update_norm(RedGeom g, double *__re
                 acc += w.x * w.x + w.y * w.y;
             } else {
                 double w = W[e];
+                if (f.P0) w = three_term(w, e, f, fa, fb);
                 for (int jj = 0; jj < J; ++jj) w -= X[(size_t)jj * stride + e] * h[(size_t)jj * g.B + b].x;
                 W[e] = w;
                 acc += w * w;
@@ -585,32 +621,45 @@ int Engine::apply(const double *x, double *y) {
     return op->apply(x, y, st);
 }
 
-int Engine::multidot(const double *X, int J, const double *Y, double2 *out, int selfdot,
-                     const uint8_t *mask) {
+template <bool CPLX>
+static void launch_multidot(const RedGeom &rg, hipStream_t st, const double *X, uint64_t stride, int J,
+                            int selfdot, const double *Y, const ThreeTerm &f, const uint8_t *mask,
+                            double2 *partial) {
     dim3 grid(rg.nchunk, rg.ncoltile);
     const int JO = J + selfdot;
-    if (cplx)
-        hipLaunchKernelGGL((k_multidot<true, 8>), grid, dim3(256), 0, st, rg, X, stride, J, selfdot, Y,
-                           mask, partial.as<double2>());
+    if (JO <= 4)
+        hipLaunchKernelGGL((k_multidot<CPLX, 4>), grid, dim3(256), 0, st, rg, X, stride, J, selfdot, Y, f, mask,
+                           partial);
     else
-        hipLaunchKernelGGL((k_multidot<false, 8>), grid, dim3(256), 0, st, rg, X, stride, J, selfdot, Y,
-                           mask, partial.as<double2>());
+        hipLaunchKernelGGL((k_multidot<CPLX, 8>), grid, dim3(256), 0, st, rg, X, stride, J, selfdot, Y, f, mask,
+                           partial);
+}
+
+int Engine::multidot(const double *X, int J, const double *Y, double2 *out, int selfdot,
+                     const uint8_t *mask, const ThreeTerm *f) {
+    const ThreeTerm none{};
+    if (cplx)
+        launch_multidot<true>(rg, st, X, stride, J, selfdot, Y, f ? *f : none, mask, partial.as<double2>());
+    else
+        launch_multidot<false>(rg, st, X, stride, J, selfdot, Y, f ? *f : none, mask, partial.as<double2>());
     QS3_HIP(hipGetLastError());
-    const int JB = JO * B;
+    const int JB = (J + selfdot) * B;
     hipLaunchKernelGGL(k_reduce_chunks, dim3((JB + 3) / 4), dim3(256), 0, st, partial.as<double2>(),
                        rg.nchunk, JB, out);
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }
 
-int Engine::cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double2 *nrm_out) {
+int Engine::cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double2 *nrm_out,
+                            const ThreeTerm *f) {
     dim3 grid(rg.nchunk, rg.ncoltile);
+    const ThreeTerm none{};
     if (cplx)
         hipLaunchKernelGGL((k_cgs_update_norm<true>), grid, dim3(256), 0, st, rg, W.as<double>(), slot(0),
-                           stride, J, h, mask, partial.as<double2>());
+                           stride, J, h, f ? *f : none, mask, partial.as<double2>());
     else
         hipLaunchKernelGGL((k_cgs_update_norm<false>), grid, dim3(256), 0, st, rg, W.as<double>(), slot(0),
-                           stride, J, h, mask, partial.as<double2>());
+                           stride, J, h, f ? *f : none, mask, partial.as<double2>());
     QS3_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_reduce_chunks, dim3((B + 3) / 4), dim3(256), 0, st, partial.as<double2>(), rg.nchunk,
                        B, nrm_out);
@@ -627,22 +676,20 @@ int Engine::step(int x, int prev) {
     QS3_TRY(apply(slot(x), W.as<double>()));
     QS3_TRY(multidot(slot(x), 1, W.as<double>(), alpha.as<double2>(), 0, colmask));
     double *betap = ab_hist.as<double>() + (size_t)slots * B + (size_t)(prev < 0 ? 0 : prev) * B;
-    if (cplx)
-        hipLaunchKernelGGL(k_lanczos_update<true>, grid1(ne), dim3(256), 0, st, ne, B,
-                           W.as<double>(), slot(x), prev >= 0 ? slot(prev) : nullptr,
-                           alpha.as<double2>(), betap, colmask);
-    else
-        hipLaunchKernelGGL(k_lanczos_update<false>, grid1(ne), dim3(256), 0, st, ne, B,
-                           W.as<double>(), slot(x), prev >= 0 ? slot(prev) : nullptr,
-                           alpha.as<double2>(), betap, colmask);
-    QS3_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_copy_re, grid1(B), dim3(256), 0, st, B, alpha.as<double2>(),
                        ab_hist.as<double>() + (size_t)x * B);
     double2 *h = hvec.as<double2>();
     double2 *n_before = h + (size_t)(x + 1) * B;  // the self-dot output of the first pass
     if (reorth > 0) {
-        QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 1, colmask));
-        QS3_TRY(cgs_update_norm(x + 1, h, colmask, nrm2.as<double2>()));
+        // W' = W - alpha psi_x - beta psi_prev is formed on the fly inside
+        // the first Gram-Schmidt pass (dots) and its update (stored there)
+        ThreeTerm f;
+        f.P0 = slot(x);
+        f.P1 = prev >= 0 ? slot(prev) : nullptr;
+        f.alpha = alpha.as<double2>();
+        f.beta = betap;
+        QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 1, colmask, &f));
+        QS3_TRY(cgs_update_norm(x + 1, h, colmask, nrm2.as<double2>(), &f));
         if (reorth > 1) {
             uint8_t *flag = act.as<uint8_t>() + 8 + B;
             hipLaunchKernelGGL(k_dgks_flag, grid1(B), dim3(256), 0, st, B, n_before, nrm2.as<double2>(), colmask,
@@ -655,6 +702,15 @@ int Engine::step(int x, int prev) {
             QS3_HIP(hipGetLastError());
         }
     } else {
+        if (cplx)
+            hipLaunchKernelGGL(k_lanczos_update<true>, grid1(ne), dim3(256), 0, st, ne, B,
+                               W.as<double>(), slot(x), prev >= 0 ? slot(prev) : nullptr,
+                               alpha.as<double2>(), betap, colmask);
+        else
+            hipLaunchKernelGGL(k_lanczos_update<false>, grid1(ne), dim3(256), 0, st, ne, B,
+                               W.as<double>(), slot(x), prev >= 0 ? slot(prev) : nullptr,
+                               alpha.as<double2>(), betap, colmask);
+        QS3_HIP(hipGetLastError());
         QS3_TRY(multidot(W.as<double>(), 1, W.as<double>(), nrm2.as<double2>(), 0, colmask));
     }
     hipLaunchKernelGGL(k_sqrt_to, grid1(B), dim3(256), 0, st, B, nrm2.as<double2>(),

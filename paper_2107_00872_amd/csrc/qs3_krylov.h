@@ -9,6 +9,7 @@
 namespace qs3 {
 
 struct Engine;
+struct ThreeTerm;
 
 // The operator a Lanczos run applies: n rows x B columns, [row][col] layout.
 struct Operator {
@@ -53,8 +54,9 @@ struct Engine {
     double *slot(int j);
     int apply(const double *x, double *y);
     int multidot(const double *X, int J, const double *Y, double2 *out, int selfdot,
-                 const uint8_t *mask);
-    int cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double2 *nrm_out);
+                 const uint8_t *mask, const ThreeTerm *f = nullptr);
+    int cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double2 *nrm_out,
+                        const ThreeTerm *f = nullptr);
     int step(int x, int prev);
     // steps x0..x1-1 (step x0's three-term partner is slot prev_first or none)
     int cycle(int x0, int x1, int prev_first);

@@ -118,3 +118,19 @@ def test_batch_eigs_all_k(qs3, ctx):
         Hk = gen_full_ham_sym_adapt(geo, 3, bonds, list(map(int, s)), list(R), Kv)
         ref = lowest_distinct(np.linalg.eigvalsh(Hk), 2)
         assert np.allclose(ev[b], ref, rtol=1e-10, atol=1e-12), (Kv, ev[b], ref)
+
+
+def test_batch_one_magnon_cube10_all_k(qs3, ctx):
+    """N_down = 1 on the periodic 10x10x10 cube, all 1000 momenta in one
+    batch: each sector is one state whose energy is the one-magnon closed
+    form E_FM - z J Delta / 2 + J sum_a cos k_a (E_FM = 3000 / 4)."""
+    lat = wl.cube(10)
+    L = qs3.Lattice.of(ctx, lat)
+    ks = wl.all_momenta(lat)
+    bat = qs3.Batch(L, 1, ks)
+    assert bat.rows == 1 and all(int(d) == 1 for d in bat.dims)
+    ev, infos, rc = bat.eigs(nev=1, seed=3)
+    assert rc == qs3.QS3_OK
+    k = 2 * np.pi * np.array(ks, dtype=float) / 10.0
+    ref = 750.0 - 3.0 + np.cos(k).sum(axis=1)
+    assert np.allclose(ev[:, 0], ref, rtol=1e-12, atol=1e-12)
