@@ -78,6 +78,20 @@ const char *qs3_last_error(void);
 int qs3_ctx_create(int device, uint64_t hbm_budget_bytes, qs3_ctx **out);
 int qs3_ctx_destroy(qs3_ctx *ctx);
 int qs3_ctx_memory(const qs3_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
+/* How momentum structures built later in this context resolve a hop's target
+ * (its representative and the translation that reaches it, Sec. 3.3).  Two
+ * optional stores, each built when it fits its limit and a quarter of the
+ * unused budget (0 turns a store off):
+ *  - a rank -> (representative, translation) table, 8 bytes per rank of
+ *    C(N, N_down), at most table_max_bytes (default 16 GiB);
+ *  - per-representative hop lists, 8 bytes per (representative, hop slot),
+ *    N_down * (largest site degree) slots per representative, resolved once
+ *    at build, at most hop_list_max_bytes (default 64 GiB).
+ * The batched and single-sector H.v use the hop lists when present, else the
+ * table; the other kernels use the table; without a store every hop is
+ * canonicalised on the fly with a directory search among the
+ * representatives.  Structures already built keep their mode. */
+int qs3_ctx_set_structure_limits(qs3_ctx *ctx, uint64_t table_max_bytes, uint64_t hop_list_max_bytes);
 
 /* ---- lattice (Sec. 2.2 model; bond list as in the paper's FILExxz) ------ */
 /* n_sites = lx*ly*lz (<= 4096).  Bond b couples sites bi[b] != bj[b] (0-based)

@@ -217,6 +217,13 @@ int qs3_ctx_destroy(qs3_ctx *ctx) {
     return QS3_OK;
 }
 
+int qs3_ctx_set_structure_limits(qs3_ctx *ctx, uint64_t table_max_bytes, uint64_t hop_list_max_bytes) {
+    QS3_REQUIRE(ctx, QS3_EINVAL, "ctx is NULL");
+    ctx->table_limit = table_max_bytes;
+    ctx->hop_list_limit = hop_list_max_bytes;
+    return QS3_OK;
+}
+
 int qs3_ctx_memory(const qs3_ctx *ctx, uint64_t *used, uint64_t *budget) {
     QS3_REQUIRE(ctx, QS3_EINVAL, "ctx is NULL");
     if (used) *used = ctx->used.load();

@@ -42,6 +42,8 @@ BatchArgs batch_args(qs3_batch *bat) {
     A.nt_of = bat->ks->nt_of.as<int32_t>();
     A.compat_nt = bat->compat_nt.as<uint8_t>();
     A.table = bat->ks->table.as<uint64_t>();
+    A.hops = bat->ks->hops.as<uint64_t>();
+    A.hmax = bat->ks->hmax;
     A.dir = bat->ks->dir.as<uint32_t>();
     A.dir_shift = bat->ks->dir_shift;
     A.B = bat->B;

@@ -197,7 +197,7 @@ int lanczos_small_K<KI>(qs3_lattice *lat, const BinomTable *bt, qs3_batch *bat, 
 
 #if QS3_INST_K <= 6
 // ------------------------------------------------------------------ momentum batches
-template <typename RT, typename CT, typename OT, bool TABLE>
+template <typename RT, typename CT, typename OT, int MODE>
 static int launch_batch(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
     BatchArgs A = batch_args(bat);
     size_t sh = lds_need<RT>(bat->lat, KI);
@@ -210,7 +210,7 @@ static int launch_batch(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
     using C2 = typename Cplx<CT>::type;
     using O2 = typename Cplx<OT>::type;
 #define QS3_LB(BPL)                                                                             \
-    hipLaunchKernelGGL((k_hv_batch<KI, RT, CT, OT, TABLE, BPL>), dim3(grid), dim3(256), sh, s, A, \
+    hipLaunchKernelGGL((k_hv_batch<KI, RT, CT, OT, MODE, BPL>), dim3(grid), dim3(256), sh, s, A, \
                        tab, (const C2 *)v, (O2 *)w)
     if (per <= 1) QS3_LB(1);
     else if (per <= 2) QS3_LB(2);
@@ -229,8 +229,10 @@ static int launch_batch(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
 
 template <typename RT, typename CT, typename OT>
 static int batch_mode(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
-    if (bat->ks->has_table) return launch_batch<RT, CT, OT, true>(bat, v, w, s);
-    return launch_batch<RT, CT, OT, false>(bat, v, w, s);
+    // hop lists read each row's resolved hops contiguously: preferred
+    if (bat->ks->has_hops) return launch_batch<RT, CT, OT, HOP_LISTS>(bat, v, w, s);
+    if (bat->ks->has_table) return launch_batch<RT, CT, OT, HOP_TABLE>(bat, v, w, s);
+    return launch_batch<RT, CT, OT, HOP_FLY>(bat, v, w, s);
 }
 
 template <typename RT>
@@ -443,7 +445,7 @@ static int build_t(qs3_lattice *lat, const BinomTable &bt, KStructure *ks, hipSt
     uint64_t tbytes = bt.D * sizeof(uint64_t);
     uint64_t used = ctx->used.load();
     uint64_t free_b = ctx->budget > used ? ctx->budget - used : 0;
-    ks->has_table = tbytes <= (16ull << 30) && tbytes <= free_b / 4;
+    ks->has_table = tbytes <= ctx->table_limit && tbytes <= free_b / 4;
     if (ks->has_table) {
         QS3_TRY(ks->table.alloc(ctx, tbytes));
         hipLaunchKernelGGL((k_table<K, RT>), dim3((bt.D + 255) / 256), dim3(256), 0, s, A, tab,
@@ -451,6 +453,28 @@ static int build_t(qs3_lattice *lat, const BinomTable &bt, KStructure *ks, hipSt
                            ks->table.as<uint64_t>());
         QS3_HIP(hipGetLastError());
     }
+#if QS3_INST_K <= 6
+    // and the hops of every representative row, resolved once, when they fit
+    // (K * degree entries per row instead of one per rank; the batched H.v
+    // prefers them, the other kernels use the table or canonicalise)
+    ks->hmax = K * lat->max_degree;
+    const uint64_t hbytes = tot * (uint64_t)ks->hmax * sizeof(uint64_t);
+    used = ctx->used.load();
+    free_b = ctx->budget > used ? ctx->budget - used : 0;
+    ks->has_hops = ks->hmax > 0 && tot > 0 && hbytes <= ctx->hop_list_limit && hbytes <= free_b / 4;
+    if (ks->has_hops) {
+        QS3_TRY(ks->hops.alloc(ctx, hbytes));
+        BatchArgs HA{};
+        HA.L = L;
+        HA.n_reps = tot;
+        HA.reps = ks->reps.as<uint64_t>();
+        HA.dir = ks->dir.as<uint32_t>();
+        HA.dir_shift = ks->dir_shift;
+        hipLaunchKernelGGL((k_hoplist<K, RT>), dim3((tot + 255) / 256), dim3(256), 0, s, HA, tab, ks->hmax,
+                           ks->hops.as<uint64_t>());
+        QS3_HIP(hipGetLastError());
+    }
+#endif
     ks->h_reps.resize(tot);
     ks->h_stab.resize(tot);
     if (tot) {

@@ -214,7 +214,7 @@ __device__ __forceinline__ void hop_of(int h, const int (&off)[K + 1], const int
 // are then broadcast lane by lane with wavefront shuffles and every lane
 // applies them to its own sectors b = lane, lane + G, ... with the phase
 // e^{ik_b.t}; the gather of one hop reads G contiguous complex elements.
-template <int K, typename RT, typename CT, typename OT, bool TABLE, int BPL>
+template <int K, typename RT, typename CT, typename OT, int MODE, int BPL>
 __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restrict__ binom_g,
                                                   const typename Cplx<CT>::type *__restrict__ v,
                                                   typename Cplx<OT>::type *__restrict__ w) {
@@ -281,9 +281,22 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                 hop_of<K>(h, off, c, ptr, &m, &e);
                 const int j = nbr[e];
                 RT rp;
-                if (hr.hop_rt(m, c, R, j, Bn, &rp)) {
-                    int tx, ty, tz;
-                    resolve_hop<K, RT, TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
+                bool hop = true;
+                int tx = 0, ty = 0, tz = 0;
+                if (MODE == HOP_LISTS) {
+                    // resolved once at structure build: occupied targets are ~0
+                    const uint64_t ent = A.hops[u * (uint64_t)A.hmax + h];
+                    hop = ent != ~0ull;
+                    u2 = (uint32_t)ent;
+                    const uint32_t t = (uint32_t)(ent >> 32);
+                    tx = t & 1023u;
+                    ty = (t >> 10) & 1023u;
+                    tz = (t >> 20) & 1023u;
+                } else {
+                    hop = hr.hop_rt(m, c, R, j, Bn, &rp);
+                    if (hop) resolve_hop<K, RT, MODE == HOP_TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
+                }
+                if (hop) {
                     const int s2 = A.stab[u2];
                     nt2 = s2 > 1 ? A.nt_of[u2] : -1;
                     tp = (uint32_t)(tx | (ty << 10) | (tz << 20));
@@ -595,6 +608,42 @@ __global__ __launch_bounds__(256) void k_table(BuildArgs A, const RT *__restrict
     for (int t = 0; t < K; ++t) rr += (uint64_t)Bn.C(best[t], t + 1);
     uint32_t u = (uint32_t)find_rep(reps, dir, shift, rr);
     table[r] = pack_ent(u, tx, ty, tz);
+}
+
+// Hop lists: for representative u, entry h (the row's hops in the kernel's
+// order: down spins ascending, each site's bonds in order) is the packed
+// (representative index, translation) of the hop's target, or ~0 when the
+// target site is occupied; entries nh..hmax-1 are ~0.
+template <int K, typename RT>
+__global__ __launch_bounds__(256) void k_hoplist(BatchArgs A, const RT *__restrict__ binom_g, int hmax,
+                                                 uint64_t *__restrict__ hops) {
+    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= A.n_reps) return;
+    const RT R = (RT)A.reps[u];
+    int c[K > 0 ? K : 1];
+    unrank<K, RT>(R, A.L.N, Bn, c);
+    HopRanker<K, RT> hr;
+    hr.init(c, Bn);
+    uint64_t *out = hops + u * (uint64_t)hmax;
+    int h = 0;
+    StaticFor<0, K>::run([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        for (int e = A.L.ptr[c[m]]; e < A.L.ptr[c[m] + 1]; ++e, ++h) {
+            const int j = A.L.nbr[e];
+            RT rp;
+            uint64_t ent = ~0ull;
+            if (hr.template hop<m>(c, R, j, Bn, &rp)) {
+                uint32_t u2;
+                int tx, ty, tz;
+                resolve_hop<K, RT, false>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
+                ent = pack_ent(u2, tx, ty, tz);
+            }
+            out[h] = ent;
+        }
+    });
+    for (; h < hmax; ++h) out[h] = ~0ull;
 }
 
 // ------------------------------------------------------------------ debug rows

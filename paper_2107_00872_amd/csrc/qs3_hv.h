@@ -7,6 +7,12 @@
 
 namespace qs3 {
 
+// How the batched kernel resolves a hop's target (representative index and
+// translation): canonicalisation and a directory search per hop, a lookup in
+// the rank -> (representative, translation) table, or the per-representative
+// hop lists resolved once when the structure was built.
+enum HopMode { HOP_FLY = 0, HOP_TABLE = 1, HOP_LISTS = 2 };
+
 struct BatchArgs {
     LatArgs L;
     uint64_t n_reps;
@@ -15,6 +21,8 @@ struct BatchArgs {
     const int32_t *nt_of;
     const uint8_t *compat_nt;
     const uint64_t *table;
+    const uint64_t *hops;  // [n_reps][hmax] hop lists, or null
+    int hmax;
     const uint32_t *dir;
     int dir_shift;
     int B, G;

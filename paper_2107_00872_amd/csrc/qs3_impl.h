@@ -71,6 +71,8 @@ struct qs3_ctx {
     uint64_t budget = 0;
     std::atomic<uint64_t> used{0};
     int n_cu = 256;
+    uint64_t table_limit = 16ull << 30;     // largest rank -> (rep, translation) table
+    uint64_t hop_list_limit = 64ull << 30;  // largest per-representative hop lists
     std::mutex mu;
 };
 
@@ -101,6 +103,10 @@ struct KStructure {
     int dir_shift = 0, dir_bits = 0;
     bool has_table = false;
     DevBuf table;  // uint64 [D]
+    // otherwise optionally the resolved hops of every representative row
+    bool has_hops = false;
+    int hmax = 0;  // N_down * most neighbours of a site
+    DevBuf hops;   // uint64 [n_reps * hmax]
     std::vector<uint64_t> h_reps;
     std::vector<uint16_t> h_stab;
     // non-trivial stabilisers: union index and its stabiliser translations

@@ -66,6 +66,7 @@ SIGNATURES = [
     ("qs3_ctx_create", ctypes.c_int, [ctypes.c_int, u64, P]),
     ("qs3_ctx_destroy", ctypes.c_int, [P]),
     ("qs3_ctx_memory", ctypes.c_int, [P, P, P]),
+    ("qs3_ctx_set_structure_limits", ctypes.c_int, [P, u64, u64]),
     ("qs3_lattice_create", ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P]),
     ("qs3_lattice_destroy", ctypes.c_int, [P]),
     ("qs3_lattice_info", ctypes.c_int, [P, P, P]),
@@ -158,6 +159,12 @@ class Context:
         check(lib().qs3_ctx_create(device, budget_bytes, ctypes.byref(h)))
         self.h = h
         self.device = device
+
+    def set_structure_limits(self, table_max_bytes: int, hop_list_max_bytes: int):
+        """Momentum structures built later use a rank table up to
+        table_max_bytes, else hop lists up to hop_list_max_bytes, else
+        canonicalise on the fly (0 turns a store off)."""
+        check(lib().qs3_ctx_set_structure_limits(self.h, int(table_max_bytes), int(hop_list_max_bytes)))
 
     def memory(self):
         u, b = u64(), u64()

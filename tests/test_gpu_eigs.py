@@ -98,6 +98,40 @@ def test_trl_k_vs_dense(qs3, ctx, lat, K):
         sec.close()
 
 
+@pytest.fixture(scope="module")
+def ctx_fly(qs3):
+    c = qs3.Context(0)
+    c.set_structure_limits(0, 0)
+    return c
+
+
+@pytest.mark.parametrize("lat,K", [(wl.square(4), 3), (wl.hypercubic(4, 2, 1), 3)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_trl_k_vs_dense_on_the_fly(qs3, ctx_fly, lat, K):
+    """The same solves with every hop resolved by on-the-fly canonicalisation."""
+    test_trl_k_vs_dense(qs3, ctx_fly, lat, K)
+
+
+def test_batch_eigs_hop_lists(qs3):
+    """Batched solves through per-representative hop lists equal those with
+    the rank table (same kernels otherwise)."""
+    lat = wl.square(6)
+    ks = wl.all_momenta(lat)
+    out = []
+    for lim in [(16 << 30, 0), (0, 1 << 34)]:
+        c = qs3.Context(0)
+        c.set_structure_limits(*lim)
+        L = qs3.Lattice.of(c, lat)
+        bat = qs3.Batch(L, 3, ks)
+        ev, infos, rc = bat.eigs(nev=2, alg=qs3.ALG_TRL, seed=5)
+        assert rc == qs3.QS3_OK
+        out.append(ev)
+        bat.close()
+        L.close()
+        c.close()
+    assert np.array_equal(out[0], out[1])
+
+
 def test_batch_eigs_all_k(qs3, ctx):
     """Every momentum sector of the 6x6 square at N_down = 3 in one batch: the
     lowest two distinct levels per sector match dense diagonalisation."""

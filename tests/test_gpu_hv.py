@@ -46,8 +46,6 @@ def test_u1_matvec_full(qs3, ctx, lat, K):
     L = qs3.Lattice.of(ctx, lat)
     sec = qs3.Sector(L, K)
     assert sec.dim == math.comb(lat.n_sites, K)
-    if sec.dim > 3_000_000:
-        pytest.skip("covered by the sampled test")
     v = torch.empty(sec.dim, dtype=torch.float64, device="cuda")
     sec.start_vector(7, v)
     vh = v.cpu().numpy()
@@ -154,6 +152,46 @@ def test_k_basis_and_matvec(qs3, ctx, dims, lat, K):
         sec.close()
 
 
+@pytest.fixture(scope="module")
+def ctx_fly(qs3):
+    """A context that never builds rank tables: every hop is resolved by
+    on-the-fly canonicalisation and a directory search."""
+    c = qs3.Context(0)
+    c.set_structure_limits(0, 0)
+    yield c
+
+
+@pytest.fixture(scope="module")
+def ctx_hops(qs3):
+    """A context that resolves hops through per-representative hop lists."""
+    c = qs3.Context(0)
+    c.set_structure_limits(0, 1 << 34)
+    yield c
+
+
+@pytest.fixture(scope="module")
+def ctx_table(qs3):
+    """A context that resolves hops through the rank table only."""
+    c = qs3.Context(0)
+    c.set_structure_limits(1 << 34, 0)
+    yield c
+
+
+@pytest.mark.parametrize("dims,lat,K", K_CASES, ids=lambda x: getattr(x, "name", str(x)))
+def test_k_basis_and_matvec_rank_table(qs3, ctx_table, dims, lat, K):
+    test_k_basis_and_matvec(qs3, ctx_table, dims, lat, K)
+
+
+@pytest.mark.parametrize("dims,lat,K", K_CASES, ids=lambda x: getattr(x, "name", str(x)))
+def test_k_basis_and_matvec_on_the_fly(qs3, ctx_fly, dims, lat, K):
+    test_k_basis_and_matvec(qs3, ctx_fly, dims, lat, K)
+
+
+@pytest.mark.parametrize("dims,lat,K", K_CASES, ids=lambda x: getattr(x, "name", str(x)))
+def test_k_basis_and_matvec_hop_lists(qs3, ctx_hops, dims, lat, K):
+    test_k_basis_and_matvec(qs3, ctx_hops, dims, lat, K)
+
+
 def test_k_c2_sampled_sectors(qs3, ctx):
     """C2 10x10 N_down=4 momentum sectors: sector dimensions (Burnside values
     39249 / 39200) and full H.v against the oracle's Alg. 9 for a sample of k."""
@@ -215,6 +253,19 @@ def test_batch_all_k_equals_single_sectors(qs3, ctx, lat, K):
 
 
 _UNI = {}
+
+
+@pytest.mark.parametrize("lat,K", [(wl.square(6), 3), (wl.cube(3), 3), (wl.hypercubic(4, 2, 2), 4)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_batch_all_k_on_the_fly(qs3, ctx_fly, lat, K):
+    test_batch_all_k_equals_single_sectors(qs3, ctx_fly, lat, K)
+
+
+@pytest.mark.parametrize("lat,K", [(wl.square(6), 3), (wl.cube(3), 3), (wl.hypercubic(4, 2, 2), 4),
+                                   (wl.with_disorder(wl.square(4), 9, per_bond=False), 3)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_batch_all_k_hop_lists(qs3, ctx_hops, lat, K):
+    test_batch_all_k_equals_single_sectors(qs3, ctx_hops, lat, K)
 
 
 def _union_ranks(qs3, ctx, L, K, lat):
