@@ -120,8 +120,9 @@ def main():
                     help="c2 (default) is the headline configuration; the others print their own line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(sharding is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (independent "
+              "sectors would shard across GPUs with no exchange; one sector by rank range "
+              "with an all-gather of v per step)", file=sys.stderr)
         sys.exit(2)
     if args.workload != "c2":
         import bench_extra
