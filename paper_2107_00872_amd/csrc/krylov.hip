@@ -93,8 +93,8 @@ __device__ __forceinline__ double2 three_term(double2 w, uint64_t e, const Three
 // partial[(chunk * JO + j) * B + b] (re, im) = sum over the chunk's rows of
 // conj(X_j[r, b]) * Y'[r, b] for j < J (X_j = X + j * stride) and, when
 // selfdot, |Y'[r, b]|^2 at j = J (JO = J + selfdot outputs), with Y' = Y
-// after the three-term part f.  Up to JM outputs accumulate in registers in
-// one pass over the rows (Y read once); more take ceil(JO / JM) passes.
+// after the three-term part f.  Blocks along z take groups of JM outputs
+// (Y is read once per group).
 // Columns with mask[b] == 0 are skipped (their partials are written as zero).
 template <bool CPLX, int JM>
 __global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__restrict__ X,
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__res
     const double fb = (on && f.P0 && f.P1) ? f.beta[b] : 0.0;
     __shared__ double2 red[256][4];
     const T *Yt = (const T *)Y;
-    for (int j0 = 0; j0 < JO; j0 += JM) {
+    for (int j0 = blockIdx.z * JM; j0 < JO; j0 += JM * gridDim.z) {
         double sr[JM], si[JM];
 #pragma unroll
         for (int q = 0; q < JM; ++q) sr[q] = si[q] = 0.0;
@@ -621,31 +621,43 @@ int Engine::apply(const double *x, double *y) {
     return op->apply(x, y, st);
 }
 
+// Row chunking of one multi-dot launch: blocks over (row chunk, column tile,
+// group of 4 outputs), about 1024 blocks in all but at least 64 row chunks
+// (never more chunks than the engine's partial buffer holds).
+static RedGeom dot_geom(const RedGeom &rg, int JO) {
+    RedGeom g = rg;
+    const int nz = (JO + 3) / 4;
+    const uint64_t want = std::max<uint64_t>(64, (1024 + (uint64_t)rg.ncoltile * nz - 1) / ((uint64_t)rg.ncoltile * nz));
+    uint64_t rc = std::max<uint64_t>((uint64_t)g.TR, (g.n + want - 1) / want);
+    rc = (rc + g.TR - 1) / g.TR * g.TR;
+    if (rc < rg.RC) rc = rg.RC;
+    g.RC = rc;
+    g.nchunk = (int)std::max<uint64_t>(1, (g.n + rc - 1) / rc);
+    return g;
+}
+
 template <bool CPLX>
-static void launch_multidot(const RedGeom &rg, hipStream_t st, const double *X, uint64_t stride, int J,
+static void launch_multidot(const RedGeom &g, hipStream_t st, const double *X, uint64_t stride, int J,
                             int selfdot, const double *Y, const ThreeTerm &f, const uint8_t *mask,
                             double2 *partial) {
-    dim3 grid(rg.nchunk, rg.ncoltile);
     const int JO = J + selfdot;
-    if (JO <= 4)
-        hipLaunchKernelGGL((k_multidot<CPLX, 4>), grid, dim3(256), 0, st, rg, X, stride, J, selfdot, Y, f, mask,
-                           partial);
-    else
-        hipLaunchKernelGGL((k_multidot<CPLX, 8>), grid, dim3(256), 0, st, rg, X, stride, J, selfdot, Y, f, mask,
-                           partial);
+    dim3 grid(g.nchunk, g.ncoltile, (JO + 3) / 4);
+    hipLaunchKernelGGL((k_multidot<CPLX, 4>), grid, dim3(256), 0, st, g, X, stride, J, selfdot, Y, f, mask,
+                       partial);
 }
 
 int Engine::multidot(const double *X, int J, const double *Y, double2 *out, int selfdot,
                      const uint8_t *mask, const ThreeTerm *f) {
     const ThreeTerm none{};
+    const RedGeom g = dot_geom(rg, J + selfdot);
     if (cplx)
-        launch_multidot<true>(rg, st, X, stride, J, selfdot, Y, f ? *f : none, mask, partial.as<double2>());
+        launch_multidot<true>(g, st, X, stride, J, selfdot, Y, f ? *f : none, mask, partial.as<double2>());
     else
-        launch_multidot<false>(rg, st, X, stride, J, selfdot, Y, f ? *f : none, mask, partial.as<double2>());
+        launch_multidot<false>(g, st, X, stride, J, selfdot, Y, f ? *f : none, mask, partial.as<double2>());
     QS3_HIP(hipGetLastError());
     const int JB = (J + selfdot) * B;
     hipLaunchKernelGGL(k_reduce_chunks, dim3((JB + 3) / 4), dim3(256), 0, st, partial.as<double2>(),
-                       rg.nchunk, JB, out);
+                       g.nchunk, JB, out);
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }
