@@ -16,7 +16,8 @@ from oracle.hamiltonian import bonds_1based, gen_full_ham
 from oracle.lanczos import lanczos, trl, diag_tri, lowest_distinct, ritz
 from oracle.observables import sz, corr_zz, corr_pm, positions, structure_factors, all_tuples
 from oracle.translation import Geometry, mk_list, gen_full_ham_sym_adapt, expand_to_u1
-from oracle.dynamics import smq_to_vec, smq_u1, continued_fraction
+from oracle.dynamics import (smq_to_vec, smq_u1, continued_fraction, sq_to_vec, sq_u1, n_down_after,
+                             trivial_sz)
 from oracle.rng import splitmix64, start_vector
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -214,3 +215,132 @@ def test_single_magnon_lorentzian():
         S = continued_fraction(a[:1], b[:1], 1.0, om, efm, eta, h)
         w0 = h + e1 - efm
         assert np.abs(S - eta / np.pi / ((om - w0) ** 2 + eta ** 2)).max() < 1e-12
+
+
+def test_sq_u1_all_operators_against_kronecker():
+    """S^-, S^+ and S^z at momentum q, by definition on U(1) amplitudes, equal the
+    2^N Kronecker-product operators N^{-1/2} sum_r e^{-iq.R_r} s^a_r."""
+    N, K = 8, 3
+    SZ, SP = full_ops(N)
+    pos = positions(N, 1, 1)
+    idx = {k: [m for m in range(1 << N) if bin(m).count("1") == k] for k in (K - 1, K, K + 1)}
+    rng = np.random.default_rng(8)
+    phi = rng.normal(size=len(idx[K])) + 1j * rng.normal(size=len(idx[K]))
+    full = np.zeros(1 << N, dtype=complex)
+    full[idx[K]] = phi
+    for Q in (0, 3, 5):
+        q = np.array([2 * np.pi * Q / N, 0, 0])
+        ph = [np.exp(-1j * q[0] * pos[r, 0]) / math.sqrt(N) for r in range(N)]
+        for op, mats in (("-", [m.T for m in SP]), ("+", SP), ("z", SZ)):
+            O = sum(ph[r] * mats[r] for r in range(N))
+            ref = (O @ full)[idx[n_down_after(op, K)]]
+            assert np.abs(sq_u1(N, K, pos, q, phi, op) - ref).max() < 1e-14
+
+
+@pytest.mark.parametrize("op", ["-", "+", "z"])
+def test_sq_scatter_equals_definition_with_stabilisers(op):
+    """The momentum-basis scatter (Alg. 11 and its S^+ / S^z analogues) expanded
+    to the U(1) basis equals the operator applied by definition."""
+    for lat, K in [(wl.chain(6), 2), (wl.square(4), 2), (wl.hypercubic(4, 2, 1), 2), (wl.chain(6), 3)]:
+        geo = Geometry(*lat.dims)
+        pos = positions(*lat.dims)
+        K1 = n_down_after(op, K)
+        for Kv in wl.all_momenta(lat)[:3]:
+            s, R = mk_list(geo, K, Kv)
+            if not s:
+                continue
+            phi = np.random.default_rng(4).normal(size=len(s)) + 0.3j
+            u1 = expand_to_u1(geo, K, s, R, Kv, phi)
+            for Qv in wl.all_momenta(lat)[:4]:
+                kq = tuple((Kv[i] + Qv[i]) % lat.dims[i] for i in range(3))
+                s1, R1 = mk_list(geo, K1, kq)
+                q = 2 * np.pi * np.array(Qv) / np.array(lat.dims)
+                ref = sq_u1(geo.N, K, pos, q, u1, op)
+                got = expand_to_u1(geo, K1, s1, R1, kq, sq_to_vec(geo, K, s, R, Kv, phi, s1, R1, Qv, op)) \
+                    if s1 else np.zeros_like(ref)
+                assert np.abs(got - ref).max() < 1e-13
+
+
+def test_sq_sum_rules():
+    """sum_q |S^a_q phi|^2 = <sum_r s^a_r^+ s^a_r>: N - K (S^-), K (S^+), N/4 (S^z)
+    for a normalised state with K down spins (Fourier completeness)."""
+    lat = wl.hypercubic(3, 3, 1)
+    N, K = 9, 4
+    pos = positions(3, 3, 1)
+    rng = np.random.default_rng(2)
+    phi = rng.normal(size=math.comb(N, K)) + 1j * rng.normal(size=math.comb(N, K))
+    phi /= np.linalg.norm(phi)
+    qs = [2 * np.pi * np.array([kx / 3, ky / 3, 0]) for (kx, ky, kz) in wl.all_momenta(lat)]
+    for op, want in (("-", N - K), ("+", K), ("z", N / 4)):
+        tot = sum(np.vdot(v, v).real for v in (sq_u1(N, K, pos, q, phi, op) for q in qs))
+        assert tot == pytest.approx(want, abs=1e-12)
+
+
+def test_one_magnon_sp_sz_closed_forms():
+    """One magnon |k> (N_down = 1, a single state per k): S^+_q |k> = |FM> exactly
+    when k + q = 0 (and no target state otherwise); |S^z_q |k>|^2 = 1/N for q != 0
+    and (N/2 - 1)^2 / N at q = 0."""
+    lat = wl.square(4)
+    geo = Geometry(4, 4, 1)
+    N = 16
+    for Kv in [(0, 0, 0), (1, 0, 0), (3, 2, 0)]:
+        s, R = mk_list(geo, 1, Kv)
+        assert len(s) == 1
+        for Qv in wl.all_momenta(lat):
+            kq = tuple((Kv[i] + Qv[i]) % 4 for i in range(3))
+            s0, R0 = mk_list(geo, 0, kq)
+            if kq == (0, 0, 0):
+                v = sq_to_vec(geo, 1, s, R, Kv, np.array([1.0 + 0j]), s0, R0, Qv, "+")
+                assert abs(v[0]) == pytest.approx(1.0, abs=1e-13)
+            else:
+                assert not s0
+            s1, R1 = mk_list(geo, 1, kq)
+            w = sq_to_vec(geo, 1, s, R, Kv, np.array([1.0 + 0j]), s1, R1, Qv, "z")
+            want = (N / 2 - 1) ** 2 / N if Qv == (0, 0, 0) else 1.0 / N
+            assert np.vdot(w, w).real == pytest.approx(want, abs=1e-13)
+
+
+@pytest.mark.parametrize("op", ["+", "z"])
+def test_continued_fraction_sp_sz_vs_resolvent_with_field(op):
+    """S^+ / S^z continued fractions equal -(1/pi) Im <psi|(w + E0_h - H'_h + i eta)^-1|psi>
+    with the Zeeman term -h S^z_tot included in both Hamiltonians (fixes the
+    direction of the field shift)."""
+    lat = wl.chain(10)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    N, K = 10, 3
+    H = gen_full_ham(N, K, bonds)
+    e, U = np.linalg.eigh(H)
+    e0, phi = e[0], U[:, 0]
+    K1 = n_down_after(op, K)
+    H1 = gen_full_ham(N, K1, bonds)
+    pos = positions(N, 1, 1)
+    q = np.array([2 * np.pi * 3 / N, 0, 0])
+    psi = sq_u1(N, K, pos, q, phi.astype(complex), op)
+    w = np.vdot(psi, psi).real
+    a, b, _ = lanczos(lambda x: H1 @ x, psi, 80)
+    om = np.linspace(-2, 8, 301)
+    for h, eta in [(0.0, 0.05), (1.5, 0.1)]:
+        S = continued_fraction(a, b, w, om, e0, eta, h, op)
+        e0h = e0 - h * (N / 2 - K)
+        H1h = H1 - h * (N / 2 - K1) * np.eye(H1.shape[0])
+        ref = np.array([-np.imag(np.vdot(psi, np.linalg.solve((o + e0h + 1j * eta) * np.eye(H1.shape[0]) - H1h, psi)))
+                        / np.pi for o in om])
+        assert np.abs(S - ref).max() < 1e-9
+
+
+def test_trivial_sz_component_is_the_q0_response():
+    """At q = 0, S^z_q |gs> = N^{-1/2} M |gs>: its continued fraction is a single
+    Lorentzian at omega = 0 of weight M^2/N, the trivial part subtracted."""
+    lat = wl.square(4)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    N, K = 16, 2
+    H = gen_full_ham(N, K, bonds)
+    e, U = np.linalg.eigh(H)
+    pos = positions(4, 4, 1)
+    psi = sq_u1(N, K, pos, np.zeros(3), U[:, 0].astype(complex), "z")
+    a, b, _ = lanczos(lambda x: H @ x, psi, 5)
+    M = N / 2 - K
+    om = np.linspace(-1, 4, 201)
+    S = continued_fraction(a[:1], b[:1], np.vdot(psi, psi).real, om, e[0], 0.05, 0.0, "z")
+    assert np.vdot(psi, psi).real == pytest.approx(M * M / N, abs=1e-12)
+    assert np.abs(S - trivial_sz(om, 0.05, M, N)).max() < 1e-10
