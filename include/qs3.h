@@ -211,21 +211,41 @@ int qs3_sq(qs3_sector *sec, const void *vec, int n_q, const double *q, double *s
 int qs3_smq(qs3_sector *from, const void *vec_from, qs3_sector *to, const int32_t *qvec,
             void *vec_to, void *stream);
 
+/* The Fourier-transformed spin operators S^a_q = N^{-1/2} sum_r e^{-i q.R_r} s^a_r
+ * (Sec. 3.8; the paper's spsmsz = 2, 1, 3). */
+#define QS3_OP_SMINUS 0   /* lowers S^z: N_down -> N_down + 1, poles move by +h */
+#define QS3_OP_SPLUS  1   /* raises S^z: N_down -> N_down - 1, poles move by -h */
+#define QS3_OP_SZ     2   /* N_down unchanged, no field shift */
+
+/* psi' = S^op_q phi from `from` (N_down = K, momentum k) into `to` (K + 1, K - 1
+ * or K for op = QS3_OP_SMINUS, QS3_OP_SPLUS, QS3_OP_SZ; momentum k + q), as a
+ * gather over the rows of `to` (S^z_q is diagonal in the representatives).
+ * Same vector conventions as qs3_smq; QS3_EINVAL when the sectors do not
+ * match the operator. */
+int qs3_sq_apply(qs3_sector *from, const void *vec_from, qs3_sector *to, int op, const int32_t *qvec,
+                 void *vec_to, void *stream);
+
 /* ---- dynamical structure factor (Sec. 3.9, Eq. (cfe)) -------------------- */
 typedef struct {
     int steps;          /* Lanczos levels of the continued fraction (0 = 300) */
     double eta;         /* Lorentzian broadening */
-    double field;       /* h of the Zeeman term: S^- poles move by +h */
+    double field;       /* h of the Zeeman term -h S^z_tot: the poles move by +h
+                           (S^-), -h (S^+) or 0 (S^z) */
     int precision;      /* QS3_PREC_* */
     int reorth;         /* 1 = full, 0 = none */
+    int op;             /* QS3_OP_SMINUS (0, default), QS3_OP_SPLUS or QS3_OP_SZ */
+    int subtract_trivial; /* S^z only: subtract the trivial q = 0 part
+                           (M^2/N) eta / (pi (omega^2 + eta^2)), M = N/2 - K (Sec. 4.2) */
 } qs3_dsf_opts;
 
-/* S^{-}(q, omega) = -(1/pi) Im <psi'| (z - H)^-1 |psi'> with
- * z = omega - h + E_0 + i eta and psi' = S^-_q |gs>, for n_q momenta qvecs
- * (host, 3 ints each), by the continued fraction of the Lanczos coefficients
- * started from psi'/|psi'|.  gs: momentum sector of the ground state, gs_vec:
- * device complex float64.  Outputs (host): S[n_q*n_omega], alpha/beta
- * [n_q*steps], weight[n_q] = |psi'|^2 = S^{+-}(q). */
+/* S^a(q, omega) = -(1/pi) Im <psi'| (z - H)^-1 |psi'> with psi' = S^a_q |gs>,
+ * a = opts->op, z = omega - shift + E_0 + i eta (shift = +h, -h, 0 for S^-,
+ * S^+, S^z), for n_q momenta qvecs (host, 3 ints each), by the continued
+ * fraction of the Lanczos coefficients started from psi'/|psi'|; all q run in
+ * one batch of target sectors k_0 + q.  gs: momentum sector of the ground
+ * state, gs_vec: device complex float64 (any norm).  Outputs (host):
+ * S[n_q*n_omega], alpha/beta [n_q*steps], weight[n_q] = |psi'|^2/|gs|^2, the
+ * static structure factor <(S^a_q)^+ S^a_q>. */
 int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_t *qvecs,
             const qs3_dsf_opts *opts, int n_omega, const double *omega, double *S,
             double *alpha, double *beta, double *weight, void *stream);

@@ -387,7 +387,83 @@ int smq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double 
     QS3_REQUIRE(!wa && !wb, QS3_EINVAL, "internal: rank width");
     return smq_mode<uint32_t, uint32_t>(src, dst, qmul, phi, out, s);
 }
-#endif
+#endif  // S^-_q targets at most 6 down spins
+
+// S^+_q: source KI down spins, targets KI - 1
+template <typename RTa, typename RTb, bool TABLE>
+static int spq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+                 double *out, hipStream_t s) {
+    SmqArgs S{batch_args(src), batch_args(dst), qmul};
+    const int G = S.dst.G, B = S.dst.B;
+    const int per = (B + G - 1) / G;
+    const uint64_t rows_per = 256 / G;
+    const unsigned grid = (unsigned)((S.dst.n_reps + rows_per - 1) / rows_per);
+    const RTa *ta = src->bt->dev.as<RTa>();
+    const RTb *tb = dst->bt->dev.as<RTb>();
+#define QS3_SPQ(BPL)                                                                                  \
+    hipLaunchKernelGGL((k_spq<KI, RTa, RTb, TABLE, BPL>), dim3(grid), dim3(256), 0, s, S, ta, tb,      \
+                       (const double2 *)phi, (double2 *)out)
+    if (per <= 1) QS3_SPQ(1);
+    else if (per <= 2) QS3_SPQ(2);
+    else if (per <= 4) QS3_SPQ(4);
+    else if (per <= 16) QS3_SPQ(16);
+    else {
+        set_error("at most 1024 momenta per S^+_q batch");
+        return QS3_EINVAL;
+    }
+#undef QS3_SPQ
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+template <typename RTa, typename RTb>
+static int spq_mode(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+                    double *out, hipStream_t s) {
+    if (src->ks->has_table) return spq_t<RTa, RTb, true>(src, dst, qmul, phi, out, s);
+    return spq_t<RTa, RTb, false>(src, dst, qmul, phi, out, s);
+}
+
+template <>
+int spq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+              double *out, hipStream_t s) {
+    if constexpr (KI == 0) {
+        set_error("S^+_q needs N_down >= 1");
+        return QS3_EINVAL;
+    } else {
+        const bool wa = src->bt->wide, wb = dst->bt->wide;
+        if constexpr (KI >= 4) {
+            if (wa && wb) return spq_mode<uint64_t, uint64_t>(src, dst, qmul, phi, out, s);
+        }
+        if constexpr (KI >= 3) {
+            if (wa && !wb) return spq_mode<uint64_t, uint32_t>(src, dst, qmul, phi, out, s);
+        }
+        QS3_REQUIRE(!wa && !wb, QS3_EINVAL, "internal: rank width");
+        return spq_mode<uint32_t, uint32_t>(src, dst, qmul, phi, out, s);
+    }
+}
+
+// S^z_q: source and targets share the KI-down structure
+template <typename RT>
+static int szq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+                 double *out, hipStream_t s) {
+    SmqArgs S{batch_args(src), batch_args(dst), qmul};
+    const uint64_t n = S.dst.n_reps * (uint64_t)S.dst.B;
+    if (n == 0) return QS3_OK;
+    hipLaunchKernelGGL((k_szq<KI, RT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, S,
+                       src->bt->dev.as<RT>(), (const double2 *)phi, (double2 *)out);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+template <>
+int szq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+              double *out, hipStream_t s) {
+    QS3_REQUIRE(src->ks == dst->ks, QS3_EINVAL, "internal: S^z_q keeps the structure");
+    if constexpr (WIDE_OK) {
+        if (src->bt->wide) return szq_t<uint64_t>(src, dst, qmul, phi, out, s);
+    }
+    return szq_t<uint32_t>(src, dst, qmul, phi, out, s);
+}
 
 // ------------------------------------------------------------------ structure build
 template <typename RT>

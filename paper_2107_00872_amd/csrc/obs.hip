@@ -56,6 +56,30 @@ static int smq_any(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const do
 #undef QS3_SQ
 }
 
+// S^op_q from the source batch (one sector) into the target batch
+static int sq_any(int op, qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+                  double *out, hipStream_t s) {
+    if (op == QS3_OP_SMINUS) return smq_any(src, dst, qmul, phi, out, s);
+#define QS3_SP(k) spq_K<(k > 6 ? 6 : k)>(src, dst, qmul, phi, out, s)
+#define QS3_SZ(k) szq_K<(k > 6 ? 6 : k)>(src, dst, qmul, phi, out, s)
+    if (op == QS3_OP_SPLUS) {
+        QS3_REQUIRE(src->K >= 1 && src->K <= 6, QS3_EINVAL, "S^+_q needs 1 <= N_down <= 6");
+        QS3_SW7(src->K, QS3_SP)
+    }
+    if (op == QS3_OP_SZ) {
+        QS3_REQUIRE(src->K <= 6, QS3_EINVAL, "S^z_q needs N_down <= 6");
+        QS3_SW7(src->K, QS3_SZ)
+    }
+#undef QS3_SP
+#undef QS3_SZ
+    set_error("unknown spin operator");
+    return QS3_EINVAL;
+}
+
+static int n_down_after(int op, int K) {
+    return op == QS3_OP_SMINUS ? K + 1 : (op == QS3_OP_SPLUS ? K - 1 : K);
+}
+
 // ---- shared helpers
 static int vec_norm2(qs3_sector *sec, const void *vec, double *out, hipStream_t s) {
     // |vec|^2 through the engine's deterministic reduction
@@ -291,12 +315,14 @@ int qs3_sq(qs3_sector *sec, const void *vec, int n_q, const double *qv, double *
     return QS3_OK;
 }
 
-int qs3_smq(qs3_sector *from, const void *vec_from, qs3_sector *to, const int32_t *qvec, void *vec_to,
-            void *stream) {
+int qs3_sq_apply(qs3_sector *from, const void *vec_from, qs3_sector *to, int op, const int32_t *qvec,
+                 void *vec_to, void *stream) {
     QS3_REQUIRE(from && to && vec_from && vec_to && qvec, QS3_EINVAL, "NULL argument");
-    QS3_REQUIRE(from->has_k && to->has_k, QS3_EINVAL, "S^-_q acts between momentum sectors");
-    QS3_REQUIRE(from->lat == to->lat && to->K == from->K + 1, QS3_EINVAL,
-                "target sector must be the same lattice with N_down + 1");
+    QS3_REQUIRE(op == QS3_OP_SMINUS || op == QS3_OP_SPLUS || op == QS3_OP_SZ, QS3_EINVAL,
+                "unknown spin operator");
+    QS3_REQUIRE(from->has_k && to->has_k, QS3_EINVAL, "S^a_q acts between momentum sectors");
+    QS3_REQUIRE(from->lat == to->lat && to->K == n_down_after(op, from->K), QS3_EINVAL,
+                "target sector must be the same lattice with N_down + 1 (S^-), - 1 (S^+) or + 0 (S^z)");
     qs3_lattice *lat = from->lat;
     const int L[3] = {lat->lx, lat->ly, lat->lz};
     for (int a = 0; a < 3; ++a)
@@ -314,10 +340,15 @@ int qs3_smq(qs3_sector *from, const void *vec_from, qs3_sector *to, const int32_
     QS3_TRY(dq.alloc(lat->ctx, sizeof(qm)));
     QS3_HIP(hipMemcpyAsync(dq.ptr, qm, sizeof(qm), hipMemcpyHostToDevice, s));
     QS3_TRY(scatter_compact(from, (const double *)vec_from, ua.as<double>(), s));
-    QS3_TRY(smq_any(from->bat, to->bat, dq.as<int32_t>(), ua.as<double>(), ub.as<double>(), s));
+    QS3_TRY(sq_any(op, from->bat, to->bat, dq.as<int32_t>(), ua.as<double>(), ub.as<double>(), s));
     QS3_TRY(gather_compact(to, ub.as<double>(), (double *)vec_to, s));
     QS3_HIP(hipStreamSynchronize(s));
     return QS3_OK;
+}
+
+int qs3_smq(qs3_sector *from, const void *vec_from, qs3_sector *to, const int32_t *qvec, void *vec_to,
+            void *stream) {
+    return qs3_sq_apply(from, vec_from, to, QS3_OP_SMINUS, qvec, vec_to, stream);
 }
 
 int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_t *qvecs,
@@ -325,7 +356,12 @@ int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_
             double *beta, double *weight, void *stream) {
     QS3_REQUIRE(gs && gs_vec && qvecs && opts && n_q > 0 && n_omega >= 0, QS3_EINVAL, "bad argument");
     QS3_REQUIRE(gs->has_k, QS3_EINVAL, "the ground state must be a momentum-sector vector");
-    QS3_REQUIRE(gs->K <= 5, QS3_EINVAL, "S^- needs N_down + 1 <= 6");
+    const int op = opts->op;
+    QS3_REQUIRE(op == QS3_OP_SMINUS || op == QS3_OP_SPLUS || op == QS3_OP_SZ, QS3_EINVAL,
+                "unknown spin operator");
+    const int K1 = n_down_after(op, gs->K);
+    QS3_REQUIRE(K1 >= 0 && K1 <= 6 && K1 <= gs->lat->N, QS3_EINVAL,
+                "the target N_down must lie in 0..6");
     qs3_lattice *lat = gs->lat;
     hipSetDevice(lat->ctx->device);
     hipStream_t s = (hipStream_t)stream;
@@ -341,7 +377,7 @@ int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_
             qm[3 * b + a] = (int)((long)qa * (M / L[a]) % M);
         }
     qs3_batch *tb = nullptr;
-    QS3_TRY(qs3_batch_create(lat, gs->K + 1, n_q, kt.data(), &tb));
+    QS3_TRY(qs3_batch_create(lat, K1, n_q, kt.data(), &tb));
     std::unique_ptr<qs3_batch, int (*)(qs3_batch *)> tb_guard(tb, qs3_batch_destroy);
     DevBuf ua, psi, dq;
     QS3_TRY(ua.alloc(lat->ctx, sizeof(double) * 2 * std::max<uint64_t>(gs->bat->ks->n_reps, 1)));
@@ -353,7 +389,7 @@ int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_
     double g2 = 0;
     QS3_TRY(vec_norm2(gs, gs_vec, &g2, s));
     QS3_REQUIRE(g2 > 0 && std::isfinite(g2), QS3_ENUMERIC, "zero or non-finite ground state");
-    QS3_TRY(smq_any(gs->bat, tb, dq.as<int32_t>(), ua.as<double>(), psi.as<double>(), s));
+    QS3_TRY(sq_any(op, gs->bat, tb, dq.as<int32_t>(), ua.as<double>(), psi.as<double>(), s));
     // Lanczos from psi'/|psi'| in every target sector (Alg. 10, lines 3-11)
     struct TOp : Operator {
         qs3_batch *b;
@@ -366,15 +402,21 @@ int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_
         int apply_f32in(const float *x, double *y, hipStream_t st) override {
             return hv_batch(b, x, QS3_C64, y, QS3_C128, st);
         }
-    } op;
-    op.b = tb;
+    } top;
+    top.b = tb;
     Engine E;
-    QS3_TRY(E.init(lat->ctx, &op, steps + 1, opts->precision, opts->reorth ? 2 : 0, s));
+    QS3_TRY(E.init(lat->ctx, &top, steps + 1, opts->precision, opts->reorth ? 2 : 0, s));
     std::vector<double> a, bb, n0;
     std::vector<int> done;
     QS3_TRY(run_lanczos(E, psi.as<double>(), steps, a, bb, n0, done));
     const double pi = std::acos(-1.0);
+    // the field moves the poles by the Zeeman change of the operator
+    const double shift = op == QS3_OP_SMINUS ? opts->field : (op == QS3_OP_SPLUS ? -opts->field : 0.0);
+    const double Mz = 0.5 * lat->N - gs->K;
     for (int q = 0; q < n_q; ++q) {
+        bool q0 = true;
+        for (int a = 0; a < 3; ++a) q0 &= (((qvecs[3 * q + a] % L[a]) + L[a]) % L[a]) == 0;
+        const bool trivial = op == QS3_OP_SZ && opts->subtract_trivial && q0;
         const double w = n0[q] * n0[q] / g2;
         if (weight) weight[q] = w;
         if (alpha)
@@ -383,18 +425,21 @@ int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_
             for (int x = 0; x < steps; ++x) beta[(size_t)q * steps + x] = bb[(size_t)q * steps + x];
         const int m = (w > 0) ? done[q] : 0;
         for (int k = 0; k < n_omega; ++k) {
+            const double triv = trivial ? (Mz * Mz / lat->N) * opts->eta /
+                                              (pi * (omega[k] * omega[k] + opts->eta * opts->eta))
+                                        : 0.0;
             if (m == 0) {
-                S[(size_t)q * n_omega + k] = 0.0;
+                S[(size_t)q * n_omega + k] = -triv;
                 continue;
             }
-            const std::complex<double> z(omega[k] - opts->field + e0, opts->eta);
+            const std::complex<double> z(omega[k] - shift + e0, opts->eta);
             std::complex<double> g = 0.0;
             for (int i = m - 1; i >= 0; --i) {
                 const std::complex<double> tail =
                     (i < m - 1) ? bb[(size_t)q * steps + i] * bb[(size_t)q * steps + i] * g : 0.0;
                 g = 1.0 / (z - a[(size_t)q * steps + i] - tail);
             }
-            S[(size_t)q * n_omega + k] = -(w * g).imag() / pi;
+            S[(size_t)q * n_omega + k] = -(w * g).imag() / pi - triv;
         }
     }
     return QS3_OK;

@@ -292,4 +292,130 @@ __global__ __launch_bounds__(256) void k_smq(SmqArgs S, const RTa *__restrict__ 
     }
 }
 
+// S^+_q as a gather (Sec. 3.8: the procedure of Alg. 11 for S^+).  Target
+// rows are the representatives beta of the (K-1)-down structure, columns b
+// the sectors k + q_b.  For every up site r0 of beta, a' = beta plus r0 has
+// the representative alpha = T^t a' in the K-down structure and contributes
+//   e^{-i q_b.R_r0 + i k.t} sqrt(s_alpha / (N s_beta)) phi_alpha.
+template <int K, typename RTa, typename RTb, bool TABLE, int BPL>
+__global__ __launch_bounds__(256) void k_spq(SmqArgs S, const RTa *__restrict__ binom_a,
+                                             const RTb *__restrict__ binom_b,
+                                             const double2 *__restrict__ phi,
+                                             double2 *__restrict__ out) {
+    constexpr int K1 = K - 1;
+    const BatchArgs &A = S.src;
+    const BatchArgs &D = S.dst;
+    Binom<RTa> Ba{binom_a, A.L.N + 1};
+    Binom<RTb> Bb{binom_b, A.L.N + 1};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    const int G = D.G, B = D.B;
+    const int lane = threadIdx.x % G, slot = threadIdx.x / G;
+    const int rows_per = blockDim.x / G;
+    const uint64_t u = (uint64_t)blockIdx.x * rows_per + slot;
+    if (u >= D.n_reps) return;
+    const int sb = D.stab[u];
+    const int ntb = sb > 1 ? D.nt_of[u] : -1;
+    int c[K1 > 0 ? K1 : 1];
+    if (K1 > 0) unrank<K1, RTb>((RTb)D.reps[u], A.L.N, Bb, c);
+    double accr[BPL], acci[BPL];
+#pragma unroll
+    for (int i = 0; i < BPL; ++i) accr[i] = acci[i] = 0.0;
+    const double isb = 1.0 / (A.L.sqrt_tab[sb] * sqrt((double)A.L.N));
+    int m = 0;  // down spins of beta below r0
+    for (int r0 = 0; r0 < A.L.N; ++r0) {
+        if (m < K1 && c[m] == r0) {
+            ++m;
+            continue;
+        }
+        int a[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) a[t] = t < m ? c[t] : (t == m ? r0 : c[t > 0 ? t - 1 : 0]);
+        uint32_t ua;
+        int tx, ty, tz;
+        if (TABLE) {
+            RTa r = 0;
+#pragma unroll
+            for (int t = 0; t < K; ++t) r += Ba.C(a[t], t + 1);
+            const uint64_t ent = A.table[r];
+            ua = (uint32_t)ent;
+            const uint32_t tt = (uint32_t)(ent >> 32);
+            tx = tt & 1023u;
+            ty = (tt >> 10) & 1023u;
+            tz = (tt >> 20) & 1023u;
+        } else {
+            int best[K];
+            canonicalize<K>(a, g, best, tx, ty, tz);
+            uint64_t r = 0;
+#pragma unroll
+            for (int t = 0; t < K; ++t) r += (uint64_t)Ba.C(best[t], t + 1);
+            ua = (uint32_t)find_rep(A.reps, A.dir, A.dir_shift, r);
+        }
+        const int sa = A.stab[ua];
+        if (sa > 1 && !A.compat_nt[A.nt_of[ua]]) continue;
+        const double2 f = phi[ua];
+        const double coef = A.L.sqrt_tab[sa] * isb;
+        const uint32_t pr0 = g.coords[r0];
+        const int x0 = pr0 & 1023u, y0 = (pr0 >> 10) & 1023u, z0 = (pr0 >> 20) & 1023u;
+        const int Pk = A.kmul[0] * tx + A.kmul[1] * ty + A.kmul[2] * tz;
+#pragma unroll
+        for (int i = 0; i < BPL; ++i) {
+            const int b = lane + i * G;
+            if (b >= B) continue;
+            int P = Pk - (S.qmul[3 * b] * x0 + S.qmul[3 * b + 1] * y0 + S.qmul[3 * b + 2] * z0);
+            P %= A.M;
+            if (P < 0) P += A.M;
+            const double2 ph = A.phase[P];
+            accr[i] += coef * (ph.x * f.x - ph.y * f.y);
+            acci[i] += coef * (ph.x * f.y + ph.y * f.x);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < BPL; ++i) {
+        const int b = lane + i * G;
+        if (b >= B) continue;
+        const bool ok = ntb < 0 || D.compat_nt[(size_t)ntb * B + b];
+        out[u * B + b] = ok ? make_double2(accr[i], acci[i]) : make_double2(0.0, 0.0);
+    }
+}
+
+// S^z_q on a momentum sector (Sec. 3.8 for S^z): s^z_r leaves every state in
+// place, so source (sector k) and target (k + q_b) share the representatives
+// and the map is diagonal: row u of sector b is
+//   phi_u N^{-1/2} (N/2 [q_b = 0] - sum_{r down in u} e^{-i q_b.R_r})
+// on rows compatible with both sectors, 0 elsewhere.
+template <int K, typename RT>
+__global__ __launch_bounds__(256) void k_szq(SmqArgs S, const RT *__restrict__ binom,
+                                             const double2 *__restrict__ phi,
+                                             double2 *__restrict__ out) {
+    const BatchArgs &A = S.src;
+    const BatchArgs &D = S.dst;
+    Binom<RT> Bn{binom, A.L.N + 1};
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= D.n_reps * (uint64_t)D.B) return;
+    const uint64_t u = e / (uint64_t)D.B;
+    const int b = (int)(e - u * (uint64_t)D.B);
+    const int su = D.stab[u];
+    const bool ok = su == 1 || (A.compat_nt[A.nt_of[u]] && D.compat_nt[(size_t)D.nt_of[u] * D.B + b]);
+    double2 o = make_double2(0.0, 0.0);
+    if (ok) {
+        int c[K > 0 ? K : 1];
+        if (K > 0) unrank<K, RT>((RT)D.reps[u], A.L.N, Bn, c);
+        const int qx = S.qmul[3 * b], qy = S.qmul[3 * b + 1], qz = S.qmul[3 * b + 2];
+        double sr = (qx == 0 && qy == 0 && qz == 0) ? 0.5 * A.L.N : 0.0, si = 0.0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            const uint32_t p = A.L.coords[c[m]];
+            int P = qx * (int)(p & 1023u) + qy * (int)((p >> 10) & 1023u) + qz * (int)((p >> 20) & 1023u);
+            P %= A.M;
+            const double2 ph = A.phase[P];  // e^{+i q.R}: subtract its conjugate
+            sr -= ph.x;
+            si += ph.y;
+        }
+        const double inv = 1.0 / sqrt((double)A.L.N);
+        const double2 f = phi[u];
+        o = make_double2(inv * (sr * f.x - si * f.y), inv * (sr * f.y + si * f.x));
+    }
+    out[e] = o;
+}
+
 }  // namespace qs3

@@ -18,6 +18,7 @@ QS3_OK, QS3_EINVAL, QS3_ENOMEM, QS3_ENOCONV, QS3_ENUMERIC, QS3_EDEVICE = 0, -1, 
 QS3_EBUSY, QS3_ENOTFOUND, QS3_ECANCELED = -6, -7, -8
 F64, F32, C128, C64 = 0, 1, 2, 3
 ALG_LANCZOS, ALG_TRL = 0, 1
+OP_SMINUS, OP_SPLUS, OP_SZ = 0, 1, 2
 PREC_F64, PREC_F32MV = 0, 1
 
 P = ctypes.c_void_p
@@ -38,7 +39,7 @@ class EigsInfo(ctypes.Structure):
 
 class DsfOpts(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int), ("eta", dbl), ("field", dbl), ("precision", ctypes.c_int),
-                ("reorth", ctypes.c_int)]
+                ("reorth", ctypes.c_int), ("op", ctypes.c_int), ("subtract_trivial", ctypes.c_int)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -83,6 +84,7 @@ SIGNATURES = [
     ("qs3_sisj", ctypes.c_int, [P, P, ctypes.c_int, P, P, P, P, P]),
     ("qs3_sq", ctypes.c_int, [P, P, ctypes.c_int, P, P, P, P, P]),
     ("qs3_smq", ctypes.c_int, [P, P, P, P, P, P]),
+    ("qs3_sq_apply", ctypes.c_int, [P, P, P, ctypes.c_int, P, P, P]),
     ("qs3_dsf", ctypes.c_int, [P, P, dbl, ctypes.c_int, P, P, ctypes.c_int, P, P, P, P, P, P]),
     ("qs3_batch_create", ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, P]),
     ("qs3_batch_destroy", ctypes.c_int, [P]),
@@ -305,8 +307,14 @@ class Sector:
         check(lib().qs3_smq(self.h, _ptr(vec), to.h, _ptr(qv), _ptr(out), _stream(stream)))
         return out
 
+    def sq_apply(self, vec, to: "Sector", op, qvec, out, stream=None):
+        """out = S^op_q vec in the sector `to` (op = OP_SMINUS, OP_SPLUS, OP_SZ)."""
+        qv = np.array(qvec, dtype=np.int32)
+        check(lib().qs3_sq_apply(self.h, _ptr(vec), to.h, op, _ptr(qv), _ptr(out), _stream(stream)))
+        return out
+
     def dsf(self, gs_vec, e0, qvecs, omega, steps=300, eta=0.05, field=0.0, precision=PREC_F64,
-            reorth=1, stream=None):
+            reorth=1, op=OP_SMINUS, subtract_trivial=False, stream=None):
         qv = np.ascontiguousarray(qvecs, dtype=np.int32).reshape(-1, 3)
         om = np.ascontiguousarray(omega, dtype=np.float64)
         nq, nw = qv.shape[0], om.shape[0]
@@ -314,7 +322,7 @@ class Sector:
         a = np.zeros(nq * steps)
         b = np.zeros(nq * steps)
         w = np.zeros(nq)
-        o = DsfOpts(steps, eta, field, precision, reorth)
+        o = DsfOpts(steps, eta, field, precision, reorth, op, 1 if subtract_trivial else 0)
         check(lib().qs3_dsf(self.h, _ptr(gs_vec), e0, nq, _ptr(qv), ctypes.byref(o), nw, _ptr(om),
                             _ptr(S), _ptr(a), _ptr(b), _ptr(w), _stream(stream)))
         return S.reshape(nq, nw), a.reshape(nq, steps), b.reshape(nq, steps), w

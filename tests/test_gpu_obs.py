@@ -1,5 +1,6 @@
-"""GPU observables (Sec. 3.6, 4.2), S^-_q (Alg. 11) and the continued-fraction
-S(q, omega) (Eq. (cfe)) against the oracle on the same input vectors.
+"""GPU observables (Sec. 3.6, 4.2), S^-_q, S^+_q and S^z_q (Sec. 3.8, Alg. 11)
+and the continued-fraction S(q, omega) (Eq. (cfe)) against the oracle on the
+same input vectors.
 
 Tolerances: correlations and structure factors are sums of |phi|^2-weighted
 terms of size <= 1 over at most C(N, K) states; 1e-12 absolute covers their
@@ -13,7 +14,7 @@ import pytest
 
 import workloads as wl
 from oracle import native as orc
-from oracle.dynamics import continued_fraction, smq_to_vec
+from oracle.dynamics import continued_fraction, smq_to_vec, sq_to_vec, n_down_after, trivial_sz
 from oracle.lanczos import lanczos as orc_lanczos
 from oracle.observables import corr_pm, corr_zz, positions, structure_factors, sz
 from oracle.translation import Geometry, expand_to_u1, gen_full_ham_sym_adapt, mk_list
@@ -179,3 +180,111 @@ def test_dsf_small_vs_oracle(qs3, ctx):
         Sref = continued_fraction(oa, ob, wq, omega, res.evals[0], 0.1, 2.0)
         assert np.abs(S[qi] - Sref).max() < 1e-8 * max(1.0, np.abs(Sref).max())
     assert tot == pytest.approx(lat.n_sites - K, abs=1e-10)   # sum_q S^{+-}(q) = N - K
+
+
+SQ_CASES = [(wl.square(4), 2), (wl.chain(8), 3), (wl.hypercubic(4, 2, 1), 3), (wl.cube(3), 2), (wl.chain(6), 1)]
+
+
+def _sq_parity(qs3, ctx, lat, K, op):
+    code = {"-": qs3.OP_SMINUS, "+": qs3.OP_SPLUS, "z": qs3.OP_SZ}[op]
+    geo = Geometry(*lat.dims)
+    L = qs3.Lattice.of(ctx, lat)
+    K1 = n_down_after(op, K)
+    for Kv in wl.all_momenta(lat)[:3]:
+        s, R = mk_list(geo, K, Kv)
+        if not s:
+            continue
+        src = qs3.Sector(L, K, Kv)
+        rng = np.random.default_rng(11)
+        phi = rng.normal(size=len(s)) + 1j * rng.normal(size=len(s))
+        X = torch.from_numpy(phi).cuda()
+        for Qv in wl.all_momenta(lat)[:6]:
+            kq = tuple((Kv[a] + Qv[a]) % lat.dims[a] for a in range(3))
+            s1, R1 = mk_list(geo, K1, kq)
+            if not s1:
+                continue
+            dst = qs3.Sector(L, K1, kq)
+            assert dst.dim == len(s1)
+            out = torch.empty(dst.dim, dtype=torch.complex128, device="cuda")
+            src.sq_apply(X, dst, code, Qv, out)
+            ref = sq_to_vec(geo, K, s, R, Kv, phi, s1, R1, Qv, op)
+            scale = np.abs(phi).max() * max(1, lat.n_sites if op != "-" else K + 1)
+            assert np.abs(out.cpu().numpy() - ref).max() < 1e-13 * scale
+            dst.close()
+        src.close()
+
+
+@pytest.mark.parametrize("op", ["+", "z"])
+@pytest.mark.parametrize("lat,K", SQ_CASES, ids=lambda x: getattr(x, "name", str(x)))
+def test_sp_sz_gather_vs_scatter(qs3, ctx, lat, K, op):
+    """S^+_q and S^z_q as gathers over the target representatives equal the
+    oracle's scatter (the procedure of Alg. 11 for S^+ and S^z)."""
+    _sq_parity(qs3, ctx, lat, K, op)
+
+
+def test_sp_gather_on_the_fly(qs3):
+    """The S^+_q gather with every source canonicalised on the fly."""
+    c = qs3.Context(0)
+    c.set_structure_limits(0, 0)
+    _sq_parity(qs3, c, wl.hypercubic(4, 2, 1), 3, "+")
+    c.close()
+
+
+@pytest.mark.parametrize("op", ["+", "z"])
+def test_dsf_sp_sz_vs_oracle(qs3, ctx, op):
+    """4x4 square, N_down = 3 ground state at its lowest k: S^+(q, omega) and
+    S^z(q, omega) for all q at h = 1.5 against the oracle (its scatter, dense k+q
+    blocks, its Lanczos and continued fraction); sum rules sum_q S^{-+}(q) = K and
+    sum_q S^{zz}(q) = N/4; the trivial q = 0 longitudinal part subtracts to 0."""
+    code = {"+": qs3.OP_SPLUS, "z": qs3.OP_SZ}[op]
+    lat = wl.square(4)
+    L = qs3.Lattice.of(ctx, lat)
+    geo = Geometry(*lat.dims)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    ks = wl.all_momenta(lat)
+    K = 3
+    K1 = n_down_after(op, K)
+    best = None
+    for Kv in ks:
+        s, R = mk_list(geo, K, Kv)
+        e = np.linalg.eigvalsh(gen_full_ham_sym_adapt(geo, K, bonds, s, R, Kv))[0]
+        if best is None or e < best[0] - 1e-10:
+            best = (e, Kv)
+    e0, k0 = best
+    gs = qs3.Sector(L, K, k0)
+    X = torch.empty(gs.dim, dtype=torch.complex128, device="cuda")
+    res = gs.eigs(nev=1, evecs=X, seed=9)
+    assert res.evals[0] == pytest.approx(e0, abs=1e-10)
+    omega = np.linspace(-2, 8, 401)
+    steps, eta, h = 30, 0.1, 1.5
+    S, a, b, w = gs.dsf(X, res.evals[0], ks, omega, steps=steps, eta=eta, field=h, op=code)
+    phi = X.cpu().numpy()
+    phi = phi / np.linalg.norm(phi)
+    sigma, R = mk_list(geo, K, k0)
+    tot = 0.0
+    for qi, Qv in enumerate(ks):
+        kq = tuple((k0[a_] + Qv[a_]) % lat.dims[a_] for a_ in range(3))
+        s1, R1 = mk_list(geo, K1, kq)
+        if not s1:
+            assert w[qi] == 0.0
+            continue
+        psi = sq_to_vec(geo, K, sigma, R, k0, phi, s1, R1, Qv, op)
+        wq = float(np.vdot(psi, psi).real)
+        assert w[qi] == pytest.approx(wq, abs=1e-12)
+        tot += wq
+        if wq < 1e-20:
+            continue
+        Hk = gen_full_ham_sym_adapt(geo, K1, bonds, s1, R1, kq)
+        m = min(steps, len(s1))
+        oa, ob, _ = orc_lanczos(lambda x: Hk @ x, psi, m)
+        eff = next((i + 1 for i in range(len(ob)) if ob[i] < 1e-8 * 8), len(ob))
+        assert np.abs(a[qi, :eff] - oa[:eff]).max() < 1e-10
+        Sref = continued_fraction(oa[:eff], ob[:eff], wq, omega, res.evals[0], eta, h, op)
+        assert np.abs(S[qi] - Sref).max() < 1e-8 * max(1.0, np.abs(Sref).max())
+    assert tot == pytest.approx(K if op == "+" else lat.n_sites / 4, abs=1e-10)
+    if op == "z":
+        S2, _, _, w2 = gs.dsf(X, res.evals[0], [(0, 0, 0)], omega, steps=steps, eta=eta, field=h, op=code,
+                              subtract_trivial=True)
+        M = lat.n_sites / 2 - K
+        assert w2[0] == pytest.approx(M * M / lat.n_sites, abs=1e-12)
+        assert np.abs(S2[0]).max() < 1e-8 * trivial_sz(np.zeros(1), eta, M, lat.n_sites)[0]
