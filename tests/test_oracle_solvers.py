@@ -19,6 +19,7 @@ from oracle.translation import Geometry, mk_list, gen_full_ham_sym_adapt, expand
 from oracle.dynamics import (smq_to_vec, smq_u1, continued_fraction, sq_to_vec, sq_u1, n_down_after,
                              trivial_sz)
 from oracle.rng import splitmix64, start_vector
+from oracle.thermal import thermal
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -344,3 +345,61 @@ def test_trivial_sz_component_is_the_q0_response():
     S = continued_fraction(a[:1], b[:1], np.vdot(psi, psi).real, om, e[0], 0.05, 0.0, "z")
     assert np.vdot(psi, psi).real == pytest.approx(M * M / N, abs=1e-12)
     assert np.abs(S - trivial_sz(om, 0.05, M, N)).max() < 1e-10
+
+
+def _all_levels(lat, Kmax=None, use_k=True):
+    """Every level of every (N_down, k) sector from the oracle's dense blocks,
+    with its S^z_tot."""
+    geo = Geometry(*lat.dims)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    N = lat.n_sites
+    E, Sz = [], []
+    for K in range(0, (Kmax if Kmax is not None else N) + 1):
+        if use_k:
+            for Kv in wl.all_momenta(lat):
+                s, R = mk_list(geo, K, Kv)
+                if s:
+                    ev = np.linalg.eigvalsh(gen_full_ham_sym_adapt(geo, K, bonds, s, R, Kv))
+                    E += list(ev)
+                    Sz += [N / 2 - K] * len(ev)
+        else:
+            ev = np.linalg.eigvalsh(gen_full_ham(N, K, bonds))
+            E += list(ev)
+            Sz += [N / 2 - K] * len(ev)
+    return np.array(E), np.array(Sz)
+
+
+def test_sector_spectra_make_the_full_spectrum():
+    """The union of all (N_down, k) sector spectra is the spectrum of the 2^N
+    Kronecker-product Hamiltonian (chain of 8 with disorder: U(1) sectors; the
+    uniform chain of 8: momentum sectors)."""
+    for lat, use_k in [(wl.with_disorder(wl.chain(8), seed=5), False), (wl.chain(8), True)]:
+        N = lat.n_sites
+        SZ, SP = full_ops(N)
+        H = sum(j * 0.5 * (SP[i] @ SP[k].T + SP[i].T @ SP[k]) + jz * SZ[i] @ SZ[k]
+                for i, k, j, jz in zip(lat.bi, lat.bj, lat.jxy, lat.jz))
+        E, Sz = _all_levels(lat, use_k=use_k)
+        assert len(E) == 1 << N
+        assert np.abs(np.sort(E) - np.linalg.eigvalsh(H)).max() < 1e-12
+
+
+def test_thermal_limits_and_closed_forms():
+    """ln Z -> N ln 2, E -> 0, C ~ beta^2 Tr H^2 / 2^N at high temperature
+    (Tr H^2 / 2^N = sum_b J_b^2 (2 + Delta_b^2) / 16 + h^2 N / 4); free spins in a
+    field: Z = (2 cosh(beta h / 2))^N, M = (N/2) tanh(beta h / 2)."""
+    lat = wl.with_disorder(wl.chain(8), seed=3)
+    N = lat.n_sites
+    E, Sz = _all_levels(lat, use_k=False)
+    h = 0.7
+    tr2 = sum(j * j * (2 + (jz / j) ** 2) / 16 for j, jz in zip(lat.jxy, lat.jz)) + h * h * N / 4
+    b = 1e-4
+    t = thermal(E, Sz, np.array([0.0, b]), h)
+    assert t["lnZ"][0] == pytest.approx(N * math.log(2), abs=1e-12)
+    assert abs(t["energy"][0]) < 1e-12 and abs(t["mag"][0]) < 1e-12
+    assert t["heat"][1] == pytest.approx(b * b * tr2, rel=1e-3)
+    free = wl.chain(8, J=0.0)
+    E0, Sz0 = _all_levels(free, use_k=False)
+    for beta in (0.3, 2.0):
+        t = thermal(E0, Sz0, np.array([beta]), h)
+        assert t["lnZ"][0] == pytest.approx(N * math.log(2 * math.cosh(beta * h / 2)), abs=1e-11)
+        assert t["mag"][0] == pytest.approx(N / 2 * math.tanh(beta * h / 2), abs=1e-11)
