@@ -16,6 +16,7 @@ c5  serving: Poisson arrivals of random solve requests (workloads.serving_stream
 from __future__ import annotations
 
 import math
+import os
 import time
 
 import numpy as np
@@ -216,6 +217,56 @@ def szq(args):
     out["sp"]["sum_rule"] = K
     out["value"] = out["sz"]["q_per_s"]
     out["unit"] = "q/s (300-level continued fraction, float64)"
+    return out
+
+
+def thermal(args):
+    """Full diagonalisation near saturation (Sec. 3.4): every momentum sector of
+    the periodic 10x10 square with N_down <= 3 (dims 1, 1, 50/49, 1617 per k),
+    then Z, energy, specific heat and magnetisation (Eq. (ens)) over a
+    temperature grid at the saturation field h = 4 and just below it."""
+    ctx = _ctx()
+    lat = wl.square(10)
+    L = qs3.Lattice.of(ctx, lat)
+    ks = wl.all_momenta(lat)
+    N = lat.n_sites
+    E, Sz = [], []
+    t0 = time.perf_counter()
+    nsec, tmax = 0, 0.0
+    for K in range(4):
+        for k in ks:
+            sec = qs3.Sector(L, K, k)
+            if sec.dim:
+                ts = time.perf_counter()
+                ev = sec.full_diag()
+                tmax = max(tmax, time.perf_counter() - ts)
+                E += list(ev)
+                Sz += [N / 2 - K] * len(ev)
+                nsec += 1
+            sec.close()
+    t_diag = time.perf_counter() - t0
+    T = np.linspace(0.05, 2.0, 40)
+    out = {"metric": "full diagonalisation of all sectors with N_down <= 3 + thermal averages", "workload": "thermal",
+           "sectors": nsec, "levels": len(E), "seconds": t_diag, "max_sector_s": tmax,
+           "value": nsec / t_diag, "unit": "sectors/s (full diagonalisation, float64)"}
+    for h in (3.5, 4.0):
+        t = qs3.thermal(E, Sz, 1.0 / T, h)
+        out[f"h{h}"] = {"T": T[::8].tolist(), "mag_per_site": (t["mag"][::8] / N).tolist(),
+                        "heat_per_site": (t["heat"][::8] / N).tolist()}
+    # the oracle's dense eigensolver on one N_down = 3 sector (host), for scale
+    try:
+        from oracle.translation import Geometry, gen_full_ham_sym_adapt, mk_list
+        from oracle.hamiltonian import bonds_1based
+        geo = Geometry(*lat.dims)
+        s_, R_ = mk_list(geo, 3, (1, 0, 0))
+        Hk = gen_full_ham_sym_adapt(geo, 3, bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz), s_, R_, (1, 0, 0))
+        tc = time.perf_counter()
+        np.linalg.eigvalsh(Hk)
+        out["cpu_baseline"] = {"value": time.perf_counter() - tc, "unit": "s per N_down = 3 sector (eigenvalues)",
+                               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                               "kind": "oracle", "sample": "numpy eigvalsh of the oracle's dense k = (1,0) block"}
+    except Exception as exc:
+        out["cpu_baseline_error"] = str(exc)
     return out
 
 

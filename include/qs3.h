@@ -189,6 +189,29 @@ int qs3_lanczos(qs3_sector *sec, const void *v0, int steps, int precision, int r
                 uint64_t seed, double *alpha, double *beta, double *norm0, int *done,
                 void *stream);
 
+/* ---- full diagonalisation and thermal averages (Sec. 3.4, Eq. (ens)) ----- */
+/* The dense Hamiltonian block of the sector (the matrix of Alg. 4 / Alg. 8),
+ * formed on the device from the same hop rules as qs3_matvec: H (device,
+ * caller-owned) receives dim x dim elements of the sector's float64 type
+ * (QS3_F64 fixed N_down, QS3_C128 momentum), column major (element (i, j) at
+ * j*dim + i).  dim <= 46340. */
+int qs3_dense(qs3_sector *sec, void *H, void *stream);
+/* Every eigenvalue of the sector, ascending (evals: host, dim doubles), and
+ * when evecs is not NULL the eigenvectors as its columns (device, dim x dim
+ * column major, the sector's float64 type), by the ROCm library's dense
+ * Hermitian eigensolver (divide and conquer; the paper uses LAPACK's) on the
+ * block of qs3_dense.  dim <= 46340; QS3_ENUMERIC if the solver fails. */
+int qs3_full_diag(qs3_sector *sec, double *evals, void *evecs, void *stream);
+/* Thermal averages over n levels (Eq. (ens)): energies E (without the field)
+ * and S^z_tot values Sz (N/2 - N_down of each level's sector), field h (the
+ * Zeeman term -h S^z_tot).  For each inverse temperature beta[t] >= 0: ln Z,
+ * energy <H - h S^z_tot>, specific heat beta^2 (<E^2> - <E>^2),
+ * magnetisation <S^z_tot>, susceptibility beta (<S^z^2> - <S^z>^2).  Host
+ * arrays; outputs may be NULL.  Sectors left out (e.g. large N_down near
+ * saturation) are simply absent from the sums. */
+int qs3_thermal(uint64_t n, const double *E, const double *Sz, double h, int n_beta, const double *beta,
+                double *lnZ, double *energy, double *heat, double *mag, double *chi);
+
 /* ---- observables (Sec. 3.6 and Sec. 4.2) -------------------------------- */
 /* <s^z_i> for i = 0..N-1 of the state vec (device, float64 type, any norm;
  * the result is normalised).  In a momentum sector the translation-averaged

@@ -465,6 +465,30 @@ int szq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double 
     return szq_t<uint32_t>(src, dst, qmul, phi, out, s);
 }
 
+// ------------------------------------------------------------------ dense blocks
+#if QS3_INST_K <= 6
+template <typename RT, bool TABLE>
+static int dense_k_t(qs3_sector *sec, const int64_t *u2c, double *A, hipStream_t s) {
+    BatchArgs B = batch_args(sec->bat);
+    const unsigned grid = (unsigned)((B.n_reps + 255) / 256);
+    hipLaunchKernelGGL((k_dense_k<KI, RT, TABLE>), dim3(grid), dim3(256), 0, s, B, sec->bt->dev.as<RT>(), u2c,
+                       (uint64_t)sec->dim, (double2 *)A);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+template <>
+int dense_k_K<KI>(qs3_sector *sec, const int64_t *u2c, double *A, hipStream_t s) {
+    if (sec->bat->ks->n_reps == 0 || sec->dim == 0) return QS3_OK;
+    const bool tabm = sec->bat->ks->has_table;
+    if constexpr (WIDE_OK) {
+        if (sec->bt->wide)
+            return tabm ? dense_k_t<uint64_t, true>(sec, u2c, A, s) : dense_k_t<uint64_t, false>(sec, u2c, A, s);
+    }
+    return tabm ? dense_k_t<uint32_t, true>(sec, u2c, A, s) : dense_k_t<uint32_t, false>(sec, u2c, A, s);
+}
+#endif
+
 // ------------------------------------------------------------------ structure build
 template <typename RT>
 static int build_t(qs3_lattice *lat, const BinomTable &bt, KStructure *ks, hipStream_t s) {
@@ -571,5 +595,25 @@ int build_kstruct_K<KI>(qs3_lattice *lat, const BinomTable &bt, KStructure *ks, 
     return build_t<uint32_t>(lat, bt, ks, s);
 }
 #endif
+
+// dense fixed-N_down blocks (every N_down)
+template <>
+int dense_u1_K<KI>(qs3_sector *sec, double *A, hipStream_t s) {
+    const uint64_t d = sec->dim;
+    if (d == 0) return QS3_OK;
+    const unsigned grid = (unsigned)((d + 255) / 256);
+    if constexpr (WIDE_OK) {
+        if (sec->bt->wide) {
+            hipLaunchKernelGGL((k_dense_u1<KI, uint64_t>), dim3(grid), dim3(256), 0, s, lat_args(sec->lat),
+                               sec->bt->dev.as<uint64_t>(), (uint64_t)d, A);
+            QS3_HIP(hipGetLastError());
+            return QS3_OK;
+        }
+    }
+    hipLaunchKernelGGL((k_dense_u1<KI, uint32_t>), dim3(grid), dim3(256), 0, s, lat_args(sec->lat),
+                       sec->bt->dev.as<uint32_t>(), (uint32_t)d, A);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
 
 }  // namespace qs3

@@ -646,6 +646,77 @@ __global__ __launch_bounds__(256) void k_hoplist(BatchArgs A, const RT *__restri
     for (; h < hmax; ++h) out[h] = ~0ull;
 }
 
+// ------------------------------------------------------------------ dense blocks
+// The dense Hamiltonian block of a sector (the matrix Alg. 4 / Alg. 8 build),
+// column major (element (i, j) at j * d + i), one row per thread from the
+// same hop rules as H.v; A must be zero on entry.  Fixed N_down:
+template <int K, typename RT>
+__global__ __launch_bounds__(256) void k_dense_u1(LatArgs L, const RT *__restrict__ binom_g, RT D,
+                                                  double *__restrict__ A) {
+    Binom<RT> Bn{binom_g, L.N + 1};
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= (uint64_t)D) return;
+    const uint64_t d = (uint64_t)D;
+    int c[K > 0 ? K : 1];
+    unrank<K, RT>((RT)r, L.N, Bn, c);
+    HopRanker<K, RT> hr;
+    hr.init(c, Bn);
+    double dz = 0.0;
+    StaticFor<0, K>::run([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        for (int e = L.ptr[c[m]]; e < L.ptr[c[m] + 1]; ++e) {
+            RT rp;
+            if (!hr.template hop<m>(c, (RT)r, (int)L.nbr[e], Bn, &rp)) continue;
+            A[(uint64_t)rp * d + r] += L.uniform ? L.u_jxy_h : L.jxy_h[e];
+            dz += L.uniform ? L.u_jz_h : L.jz_h[e];
+        }
+    });
+    A[r * d + r] += L.ez4 - dz;
+}
+
+// Momentum sector (a batch of one): row u of the union is basis state
+// u2c[u] (-1: not in the sector); elements as in k_hv_batch.
+template <int K, typename RT, bool TABLE>
+__global__ __launch_bounds__(256) void k_dense_k(BatchArgs A, const RT *__restrict__ binom_g,
+                                                 const int64_t *__restrict__ u2c, uint64_t d,
+                                                 double2 *__restrict__ M) {
+    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= A.n_reps) return;
+    const int64_t i = u2c[u];
+    if (i < 0) return;
+    const RT R = (RT)A.reps[u];
+    int c[K > 0 ? K : 1];
+    unrank<K, RT>(R, A.L.N, Bn, c);
+    HopRanker<K, RT> hr;
+    hr.init(c, Bn);
+    const double isq = 1.0 / A.L.sqrt_tab[A.stab[u]];
+    double dz = 0.0;
+    StaticFor<0, K>::run([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        for (int e = A.L.ptr[c[m]]; e < A.L.ptr[c[m] + 1]; ++e) {
+            const int j = A.L.nbr[e];
+            RT rp;
+            if (!hr.template hop<m>(c, R, j, Bn, &rp)) continue;
+            uint32_t u2;
+            int tx, ty, tz;
+            resolve_hop<K, RT, TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
+            dz += A.L.uniform ? A.L.u_jz_h : A.L.jz_h[e];
+            const int64_t jc = u2c[u2];
+            if (jc < 0) continue;
+            const double coef = (A.L.uniform ? A.L.u_jxy_h : A.L.jxy_h[e]) * A.L.sqrt_tab[A.stab[u2]] * isq;
+            int P = A.kmul[0] * tx + A.kmul[1] * ty + A.kmul[2] * tz;
+            P %= A.M;
+            const double2 ph = A.phase[P];
+            double2 &dst = M[(uint64_t)jc * d + (uint64_t)i];
+            dst.x += coef * ph.x;
+            dst.y += coef * ph.y;
+        }
+    });
+    M[(uint64_t)i * d + (uint64_t)i].x += A.L.ez4 - dz;
+}
+
 // ------------------------------------------------------------------ debug rows
 template <int K, typename RT>
 __global__ void k_row_u1(LatArgs L, const RT *binom_g, RT row, int cap, int64_t *cols,

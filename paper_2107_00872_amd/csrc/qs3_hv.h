@@ -72,6 +72,12 @@ int row_k_K(qs3_sector *sec, uint64_t u, int cap, int64_t *cols, double *vals, d
             int *nnz);
 template <int K>
 int build_kstruct_K(qs3_lattice *lat, const BinomTable &bt, KStructure *ks, hipStream_t s);
+// Dense sector blocks, column major, added into A (zero on entry): fixed
+// N_down (real) and momentum sectors (complex, u2c: union row -> basis index).
+template <int K>
+int dense_u1_K(qs3_sector *sec, double *A, hipStream_t s);
+template <int K>
+int dense_k_K(qs3_sector *sec, const int64_t *u2c, double *A, hipStream_t s);
 
 }  // namespace qs3
 

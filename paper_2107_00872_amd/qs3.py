@@ -80,6 +80,9 @@ SIGNATURES = [
     ("qs3_row", ctypes.c_int, [P, u64, ctypes.c_int, P, P, P, P]),
     ("qs3_eigs", ctypes.c_int, [P, P, P, P, P, P]),
     ("qs3_lanczos", ctypes.c_int, [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, u64, P, P, P, P, P]),
+    ("qs3_dense", ctypes.c_int, [P, P, P]),
+    ("qs3_full_diag", ctypes.c_int, [P, P, P, P]),
+    ("qs3_thermal", ctypes.c_int, [u64, P, P, dbl, ctypes.c_int, P, P, P, P, P, P]),
     ("qs3_sz", ctypes.c_int, [P, P, P, P]),
     ("qs3_sisj", ctypes.c_int, [P, P, ctypes.c_int, P, P, P, P, P]),
     ("qs3_sq", ctypes.c_int, [P, P, ctypes.c_int, P, P, P, P, P]),
@@ -270,6 +273,22 @@ class Sector:
         check(rc, allow=(QS3_OK, QS3_ENOCONV))
         return EigsResult(ev[:nev], info, rc)
 
+    def dense(self, out=None, stream=None):
+        """The dense block, column major (a torch tensor dim x dim: out[j, i] = H[i, j])."""
+        import torch
+        if out is None:
+            dt = torch.complex128 if self.is_complex else torch.float64
+            out = torch.empty(self.dim, self.dim, dtype=dt, device="cuda")
+        check(lib().qs3_dense(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def full_diag(self, evecs=None, stream=None):
+        """All eigenvalues (ascending); eigenvectors into evecs (dim x dim column
+        major: evecs[j] is eigenvector j) when given."""
+        ev = np.zeros(max(self.dim, 1))
+        check(lib().qs3_full_diag(self.h, _ptr(ev), _ptr(evecs), _stream(stream)))
+        return ev[:self.dim]
+
     def lanczos(self, steps, v0=None, precision=PREC_F64, reorth=1, seed=1, stream=None):
         a = np.zeros(steps)
         b = np.zeros(steps)
@@ -410,3 +429,15 @@ class Server:
         if self.h:
             lib().qs3_server_destroy(self.h)
             self.h = None
+
+
+def thermal(E, Sz, beta, h=0.0):
+    """Thermal averages (Eq. (ens)) of the levels E with S^z_tot values Sz: a dict
+    of arrays over beta (lnZ, energy, heat, mag, chi)."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    Sz = np.ascontiguousarray(Sz, dtype=np.float64)
+    b = np.ascontiguousarray(np.atleast_1d(beta), dtype=np.float64)
+    out = {k: np.zeros(len(b)) for k in ("lnZ", "energy", "heat", "mag", "chi")}
+    check(lib().qs3_thermal(len(E), _ptr(E), _ptr(Sz), float(h), len(b), _ptr(b), _ptr(out["lnZ"]),
+                            _ptr(out["energy"]), _ptr(out["heat"]), _ptr(out["mag"]), _ptr(out["chi"])))
+    return out
