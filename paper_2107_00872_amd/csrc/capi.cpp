@@ -8,6 +8,7 @@
 #include <numeric>
 #include <unordered_map>
 
+#include "qs3_device.h"
 #include "qs3_impl.h"
 #include "qs3_krylov.h"
 
@@ -83,18 +84,19 @@ int get_binom(qs3_lattice *lat, int K, std::shared_ptr<BinomTable> *out) {
     bt->D = bt->C(N, K);
     QS3_REQUIRE(bt->D < (1ull << 62), QS3_EINVAL, "sector dimension exceeds 2^62");
     bt->wide = bt->D >= (1ull << 32);
-    // device columns m = 2..K of C(c, m), c = 0..N
+    // device columns m = 2..K of C(c, m), c = 0..N, column m at (m - 2) << sh
     const int ncol = std::max(K - 1, 0);
     const size_t esz = bt->wide ? 8 : 4;
-    QS3_TRY(bt->dev.alloc(lat->ctx, std::max<size_t>(esz * ncol * (N + 1), 16)));
+    const size_t stride = (size_t)1 << binom_shift(N);
+    QS3_TRY(bt->dev.alloc(lat->ctx, std::max<size_t>(esz * ncol * stride, 16)));
     if (ncol) {
-        std::vector<unsigned char> buf(esz * ncol * (N + 1));
+        std::vector<unsigned char> buf(esz * ncol * stride, 0);
         for (int m = 2; m <= K; ++m)
             for (int c = 0; c <= N; ++c) {
                 uint64_t v = bt->C(c, m);
                 if (v > bt->D) v = bt->D;  // only entries above C(N, K) are never looked up usefully
-                if (bt->wide) ((uint64_t *)buf.data())[(size_t)(m - 2) * (N + 1) + c] = v;
-                else ((uint32_t *)buf.data())[(size_t)(m - 2) * (N + 1) + c] = (uint32_t)v;
+                if (bt->wide) ((uint64_t *)buf.data())[(size_t)(m - 2) * stride + c] = v;
+                else ((uint32_t *)buf.data())[(size_t)(m - 2) * stride + c] = (uint32_t)v;
             }
         QS3_HIP(hipMemcpy(bt->dev.ptr, buf.data(), buf.size(), hipMemcpyHostToDevice));
     }

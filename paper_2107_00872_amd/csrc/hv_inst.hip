@@ -21,7 +21,7 @@ constexpr bool WIDE_OK = KI >= 3;
 
 template <typename RT>
 static size_t lds_need(const qs3_lattice *lat, int K) {
-    size_t ntab = K >= 2 ? (size_t)(K - 1) * (lat->N + 1) : 0;
+    size_t ntab = K >= 2 ? (size_t)(K - 1) << binom_shift(lat->N) : 0;
     return ((ntab * sizeof(RT) + 15) & ~size_t(15)) + sizeof(int) * (lat->N + 1) +
            sizeof(uint16_t) * lat->h_nbr.size() + 16;
 }

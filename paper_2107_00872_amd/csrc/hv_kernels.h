@@ -49,7 +49,7 @@ template <typename RT>
 __device__ __forceinline__ void load_lds_tables(unsigned char *smem, const LatArgs &L,
                                                 const RT *binom_g, int K, const RT **tab,
                                                 const int **ptr, const uint16_t **nbr) {
-    int ntab = K >= 2 ? (K - 1) * (L.N + 1) : 0;
+    int ntab = K >= 2 ? (K - 1) << binom_shift(L.N) : 0;
     RT *s_tab = (RT *)smem;
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) s_tab[i] = binom_g[i];
     int *s_ptr = (int *)(smem + ((ntab * sizeof(RT) + 15) & ~size_t(15)));
@@ -64,7 +64,7 @@ __device__ __forceinline__ void load_lds_tables(unsigned char *smem, const LatAr
 
 template <typename RT>
 static size_t lds_bytes(const qs3_lattice *lat, int K) {
-    size_t ntab = K >= 2 ? (size_t)(K - 1) * (lat->N + 1) : 0;
+    size_t ntab = K >= 2 ? (size_t)(K - 1) << binom_shift(lat->N) : 0;
     return ((ntab * sizeof(RT) + 15) & ~size_t(15)) + sizeof(int) * (lat->N + 1) +
            sizeof(uint16_t) * lat->h_nbr.size() + 16;
 }
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_hv_u1(LatArgs L, const RT *__restrict__
     const int *ptr;
     const uint16_t *nbr;
     load_lds_tables<RT>(smem, L, binom_g, K, &tab, &ptr, &nbr);
-    Binom<RT> Bn{tab, L.N + 1};
+    Binom<RT> Bn{tab, binom_shift(L.N)};
 
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const uint64_t ntiles = ((uint64_t)D + 255) / 256;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
     const int *ptr;
     const uint16_t *nbr;
     load_lds_tables<RT>(smem, A.L, binom_g, K, &tab, &ptr, &nbr);
-    Binom<RT> Bn{tab, A.L.N + 1};
+    Binom<RT> Bn{tab, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
 
     const int G = A.G, B = A.B;
@@ -469,7 +469,7 @@ __device__ __forceinline__ bool is_orbit_min(const int (&c)[K > 0 ? K : 1], cons
 template <int K, typename RT>
 __global__ __launch_bounds__(256) void k_count_reps(BuildArgs A, const RT *__restrict__ binom_g,
                                                     unsigned long long *counts) {
-    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
     const uint64_t lo = (uint64_t)blockIdx.x * A.chunk;
     const uint64_t hi = min(A.D, lo + A.chunk);
@@ -493,7 +493,7 @@ template <int K, typename RT>
 __global__ __launch_bounds__(256) void k_write_reps(BuildArgs A, const RT *__restrict__ binom_g,
                                                     const unsigned long long *offsets,
                                                     uint64_t *reps) {
-    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
     const uint64_t lo = (uint64_t)blockIdx.x * A.chunk;
     const uint64_t hi = min(A.D, lo + A.chunk);
@@ -527,7 +527,7 @@ template <int K, typename RT>
 __global__ __launch_bounds__(256) void k_stab(LatArgs L, const RT *__restrict__ binom_g,
                                               uint64_t n_reps, const uint64_t *__restrict__ reps,
                                               uint16_t *stab) {
-    Binom<RT> Bn{binom_g, L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(L.N)};
     Geom g{L.lx, L.ly, L.lz, L.lx * L.ly, L.coords};
     uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n_reps) return;
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(256) void k_table(BuildArgs A, const RT *__restrict
                                                const uint64_t *__restrict__ reps,
                                                const uint32_t *__restrict__ dir, int shift,
                                                uint64_t *table) {
-    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
     uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= A.D) return;
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(256) void k_table(BuildArgs A, const RT *__restrict
 template <int K, typename RT>
 __global__ __launch_bounds__(256) void k_hoplist(BatchArgs A, const RT *__restrict__ binom_g, int hmax,
                                                  uint64_t *__restrict__ hops) {
-    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
     const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= A.n_reps) return;
@@ -653,7 +653,7 @@ __global__ __launch_bounds__(256) void k_hoplist(BatchArgs A, const RT *__restri
 template <int K, typename RT>
 __global__ __launch_bounds__(256) void k_dense_u1(LatArgs L, const RT *__restrict__ binom_g, RT D,
                                                   double *__restrict__ A) {
-    Binom<RT> Bn{binom_g, L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(L.N)};
     const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= (uint64_t)D) return;
     const uint64_t d = (uint64_t)D;
@@ -680,7 +680,7 @@ template <int K, typename RT, bool TABLE>
 __global__ __launch_bounds__(256) void k_dense_k(BatchArgs A, const RT *__restrict__ binom_g,
                                                  const int64_t *__restrict__ u2c, uint64_t d,
                                                  double2 *__restrict__ M) {
-    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
     const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= A.n_reps) return;
@@ -721,7 +721,7 @@ __global__ __launch_bounds__(256) void k_dense_k(BatchArgs A, const RT *__restri
 template <int K, typename RT>
 __global__ void k_row_u1(LatArgs L, const RT *binom_g, RT row, int cap, int64_t *cols,
                          double *vals, double *diag, int *nnz) {
-    Binom<RT> Bn{binom_g, L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(L.N)};
     int c[K > 0 ? K : 1];
     unrank<K, RT>(row, L.N, Bn, c);
     HopRanker<K, RT> hr;
@@ -751,7 +751,7 @@ __global__ void k_row_u1(LatArgs L, const RT *binom_g, RT row, int cap, int64_t 
 template <int K, typename RT, bool TABLE>
 __global__ void k_row_k(BatchArgs A, const RT *binom_g, uint64_t u, int cap, int64_t *cols,
                         double *vals, double *diag, int *nnz) {
-    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
     const RT R = (RT)A.reps[u];
     const int su = A.stab[u];
@@ -881,7 +881,7 @@ __global__ __launch_bounds__(1024) void k_lanczos_small(SmallArgs S, BatchArgs A
     const int *ptr;
     const uint16_t *nbr;
     load_lds_tables<RT>(smem, A.L, binom_g, K, &tab, &ptr, &nbr);
-    Binom<RT> Bn{tab, A.L.N + 1};
+    Binom<RT> Bn{tab, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;

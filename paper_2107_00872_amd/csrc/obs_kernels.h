@@ -41,7 +41,7 @@ template <int K, typename RT>
 __global__ __launch_bounds__(256) void k_site_prob(LatArgs L, const RT *__restrict__ binom_g, uint64_t cnt,
                                                    int nchunk, const double *__restrict__ phi,
                                                    double2 *__restrict__ partial) {
-    Binom<RT> Bn{binom_g, L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(L.N)};
     const int i = blockIdx.x;
     const uint64_t per = (cnt + nchunk - 1) / nchunk;
     const uint64_t s0 = per * blockIdx.y, s1 = min(cnt, s0 + per);
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_pair_u1(LatArgs L, const RT *__restrict
                                                  uint64_t cnt_q, uint64_t cnt_pm, int nchunk,
                                                  const double *__restrict__ phi,
                                                  double2 *__restrict__ partial) {
-    Binom<RT> Bn{binom_g, L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(L.N)};
     const int p = blockIdx.x;
     const int i = pi[p], j = pj[p];
     const int lo = min(i, j), hi = max(i, j);
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_corr_k(BatchArgs A, const RT *__restric
                                                 const int32_t *__restrict__ disp, int nchunk,
                                                 const double2 *__restrict__ phi,
                                                 double2 *__restrict__ partial) {
-    Binom<RT> Bn{binom_g, A.L.N + 1};
+    Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
     const int dd = blockIdx.x;
     const int dp = disp[dd];
@@ -223,8 +223,8 @@ __global__ __launch_bounds__(256) void k_smq(SmqArgs S, const RTa *__restrict__ 
     constexpr int K1 = K + 1;
     const BatchArgs &A = S.src;
     const BatchArgs &D = S.dst;
-    Binom<RTa> Ba{binom_a, A.L.N + 1};
-    Binom<RTb> Bb{binom_b, A.L.N + 1};
+    Binom<RTa> Ba{binom_a, binom_shift(A.L.N)};
+    Binom<RTb> Bb{binom_b, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
     const int G = D.G, B = D.B;
     const int lane = threadIdx.x % G, slot = threadIdx.x / G;
@@ -305,8 +305,8 @@ __global__ __launch_bounds__(256) void k_spq(SmqArgs S, const RTa *__restrict__ 
     constexpr int K1 = K - 1;
     const BatchArgs &A = S.src;
     const BatchArgs &D = S.dst;
-    Binom<RTa> Ba{binom_a, A.L.N + 1};
-    Binom<RTb> Bb{binom_b, A.L.N + 1};
+    Binom<RTa> Ba{binom_a, binom_shift(A.L.N)};
+    Binom<RTb> Bb{binom_b, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
     const int G = D.G, B = D.B;
     const int lane = threadIdx.x % G, slot = threadIdx.x / G;
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void k_szq(SmqArgs S, const RT *__restrict__ b
                                              double2 *__restrict__ out) {
     const BatchArgs &A = S.src;
     const BatchArgs &D = S.dst;
-    Binom<RT> Bn{binom, A.L.N + 1};
+    Binom<RT> Bn{binom, binom_shift(A.L.N)};
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= D.n_reps * (uint64_t)D.B) return;
     const uint64_t u = e / (uint64_t)D.B;

@@ -32,11 +32,18 @@ struct StaticFor<K, K> {
 template <typename RT>
 struct Binom {
     const RT *tab;
-    int np1;  // N + 1
+    int sh;  // column m starts at (m - 2) << sh (2^sh > N, so an index is a shift and an add)
     __host__ __device__ __forceinline__ RT C(int c, int m) const {
-        return m == 1 ? (RT)c : tab[(m - 2) * np1 + c];
+        return m == 1 ? (RT)c : tab[((m - 2) << sh) + c];
     }
 };
+
+// log2 of the binomial column stride for N sites: the smallest 2^sh > N.
+__host__ __device__ __forceinline__ int binom_shift(int N) {
+    int sh = 0;
+    while ((1 << sh) <= N) ++sh;
+    return sh;
+}
 
 // Unrank (Sec. 3.1, the inverse of Eq. (a_of_n); Alg. 1 with 0-based ranks):
 // for m = K..2 the largest c in [m-1, hi] with C(c, m) <= r, then c_1 = r.
