@@ -215,6 +215,7 @@ int qs3_ctx_create(int device, uint64_t hbm_budget_bytes, qs3_ctx **out) {
 }
 
 int qs3_ctx_destroy(qs3_ctx *ctx) {
+    if (ctx) qs3::blas_release(ctx);
     delete ctx;
     return QS3_OK;
 }

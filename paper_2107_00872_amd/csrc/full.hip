@@ -65,6 +65,24 @@ static int build_dense(qs3_sector *sec, void *A, hipStream_t s) {
     return QS3_OK;
 }
 
+void *blas_on(qs3_ctx *ctx, hipStream_t s) {
+    if (!ctx->blas) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
+        ctx->blas = h;
+    }
+    rocblas_set_stream((rocblas_handle)ctx->blas, s);
+    return ctx->blas;
+}
+
+void blas_release(qs3_ctx *ctx) {
+    if (ctx->blas) {
+        hipSetDevice(ctx->device);
+        rocblas_destroy_handle((rocblas_handle)ctx->blas);
+        ctx->blas = nullptr;
+    }
+}
+
 }  // namespace qs3
 
 using namespace qs3;
@@ -99,9 +117,9 @@ int qs3_full_diag(qs3_sector *sec, double *evals, void *evecs, void *stream) {
     QS3_TRY(dE.alloc(sec->lat->ctx, sizeof(double) * d));
     QS3_TRY(dinfo.alloc(sec->lat->ctx, sizeof(rocblas_int)));
     QS3_TRY(build_dense(sec, A, s));
-    rocblas_handle h = nullptr;
-    QS3_REQUIRE(rocblas_create_handle(&h) == rocblas_status_success, QS3_EDEVICE, "rocblas handle");
-    rocblas_set_stream(h, s);
+    std::lock_guard<std::mutex> lock(sec->lat->ctx->blas_mu);
+    rocblas_handle h = (rocblas_handle)blas_on(sec->lat->ctx, s);
+    QS3_REQUIRE(h, QS3_EDEVICE, "rocblas handle");
     // eigenvalues only: divide and conquer; with eigenvectors: the QR
     // iteration, which keeps degenerate eigenspaces finite
     rocblas_status st;
@@ -125,7 +143,6 @@ int qs3_full_diag(qs3_sector *sec, double *evals, void *evecs, void *stream) {
     hipError_t e1 = hipMemcpyAsync(evals, dvals.ptr, sizeof(double) * d, hipMemcpyDeviceToHost, s);
     hipError_t e2 = hipMemcpyAsync(&info, dinfo.ptr, sizeof(rocblas_int), hipMemcpyDeviceToHost, s);
     hipError_t e3 = hipStreamSynchronize(s);
-    rocblas_destroy_handle(h);
     QS3_REQUIRE(st == rocblas_status_success, QS3_EDEVICE, "dense eigensolver failed to launch");
     QS3_HIP(e1);
     QS3_HIP(e2);

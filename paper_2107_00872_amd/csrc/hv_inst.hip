@@ -110,10 +110,59 @@ int row_u1_K<KI>(qs3_sector *sec, uint64_t row, int cap, int64_t *cols, double *
 
 
 // ------------------------------------------------------------------ observables (fixed N_down)
+// All pair sums pm_ij at once as the Gram matrix of the factor of k_pm_rows
+// (chunks of at most 256 MB of factor; per chunk, split-row tile partials and
+// their ordered sum, added to G on the host), then read out for the requested
+// pairs (hpi < hpj, host).
+template <typename RT>
+static int pm_gram(qs3_sector *sec, const double *phi, int npairs, const int32_t *hpi, const int32_t *hpj,
+                   std::vector<double> &pm, hipStream_t s) {
+    constexpr int K = KI;
+    qs3_ctx *ctx = sec->lat->ctx;
+    const int N = sec->lat->N;
+    const BinomTable &bt = *sec->bt;
+    const uint64_t nb = bt.C(N, K - 1);
+    const uint64_t nc = std::max<uint64_t>(1, std::min<uint64_t>(nb, (32ull << 20) / (uint64_t)N));
+    const int nt = (N + 63) / 64;
+    std::vector<int2> tiles;
+    for (int a = 0; a < nt; ++a)
+        for (int b = a; b < nt; ++b) tiles.push_back(make_int2(a, b));
+    const int ntp = (int)tiles.size();
+    const int max_chunks = std::max(1, 2048 / ntp);
+    DevBuf U, G, P, T;
+    QS3_TRY(U.alloc(ctx, sizeof(double) * nc * N));
+    QS3_TRY(G.alloc(ctx, sizeof(double) * (size_t)N * N));
+    QS3_TRY(P.alloc(ctx, sizeof(double) * 4096 * (size_t)ntp * max_chunks));
+    QS3_TRY(T.alloc(ctx, sizeof(int2) * (size_t)ntp));
+    QS3_HIP(hipMemcpyAsync(T.ptr, tiles.data(), sizeof(int2) * ntp, hipMemcpyHostToDevice, s));
+    std::vector<double> acc((size_t)N * N, 0.0), hG((size_t)N * N);
+    for (uint64_t b0 = 0; b0 < nb; b0 += nc) {
+        const uint64_t m = std::min(nc, nb - b0);
+        hipLaunchKernelGGL((k_pm_rows<K, RT>), dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, N,
+                           sec->bt->dev.as<RT>(), b0, m, phi, U.as<double>());
+        QS3_HIP(hipGetLastError());
+        // rows per chunk: a multiple of 16, at most max_chunks chunks
+        uint64_t rc = std::max<uint64_t>(16, (m + max_chunks - 1) / max_chunks);
+        rc = (rc + 15) / 16 * 16;
+        const int nchunk = (int)((m + rc - 1) / rc);
+        hipLaunchKernelGGL(k_gram_tiles<64>, dim3(nchunk, ntp), dim3(256), 0, s, U.as<double>(), m, N, rc,
+                           T.as<int2>(), ntp, P.as<double>());
+        QS3_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_gram_reduce<64>, dim3((unsigned)(((uint64_t)ntp * 4096 + 255) / 256)), dim3(256), 0, s,
+                           P.as<double>(), nchunk, T.as<int2>(), ntp, N, G.as<double>());
+        QS3_HIP(hipGetLastError());
+        QS3_HIP(hipMemcpyAsync(hG.data(), G.ptr, sizeof(double) * hG.size(), hipMemcpyDeviceToHost, s));
+        QS3_HIP(hipStreamSynchronize(s));
+        for (size_t e = 0; e < hG.size(); ++e) acc[e] += hG[e];
+    }
+    for (int t = 0; t < npairs; ++t) pm[t] = acc[(size_t)hpi[t] + (size_t)hpj[t] * N];
+    return QS3_OK;
+}
+
 template <typename RT>
 static int obs_u1_t(qs3_sector *sec, const double *phi, int npairs, const int32_t *pi,
                     const int32_t *pj, std::vector<double> &p_site, std::vector<double> &q,
-                    std::vector<double> &pm, hipStream_t s) {
+                    std::vector<double> &pm, hipStream_t s, const int32_t *hpi, const int32_t *hpj) {
     constexpr int K = KI;
     qs3_lattice *lat = sec->lat;
     const int N = lat->N;
@@ -139,7 +188,10 @@ static int obs_u1_t(qs3_sector *sec, const double *phi, int npairs, const int32_
             for (int c = 0; c < nchunk; ++c) p_site[i] += h[(size_t)i * nchunk + c].x;
     }
     if (npairs > 0) {
-        const uint64_t cq = K >= 2 ? bt.C(N - 2, K - 2) : 0, cpm = bt.C(N - 2, K - 1);
+        // many pairs (host pairs given): the S^+S^- sums come from one Gram
+        // matrix over all sites instead of one subset loop per pair
+        const bool gram = hpi && hpj && npairs >= N;
+        const uint64_t cq = K >= 2 ? bt.C(N - 2, K - 2) : 0, cpm = gram ? 0 : bt.C(N - 2, K - 1);
         const uint64_t cmax = std::max(cq, cpm);
         const int nchunk = (int)std::max<uint64_t>(1, std::min<uint64_t>((cmax + 4095) / 4096,
                                                                           (4096 + npairs - 1) / npairs));
@@ -156,6 +208,7 @@ static int obs_u1_t(qs3_sector *sec, const double *phi, int npairs, const int32_
                 q[p] += h[(size_t)p * nchunk + c].x;
                 pm[p] += h[(size_t)p * nchunk + c].y;
             }
+        if (gram) QS3_TRY(pm_gram<RT>(sec, phi, npairs, hpi, hpj, pm, s));
     }
     return QS3_OK;
 }
@@ -163,11 +216,11 @@ static int obs_u1_t(qs3_sector *sec, const double *phi, int npairs, const int32_
 template <>
 int obs_u1_K<KI>(qs3_sector *sec, const double *phi, int npairs, const int32_t *pi,
                  const int32_t *pj, std::vector<double> &p_site, std::vector<double> &q,
-                 std::vector<double> &pm, hipStream_t s) {
+                 std::vector<double> &pm, hipStream_t s, const int32_t *hpi, const int32_t *hpj) {
     if constexpr (WIDE_OK) {
-        if (sec->bt->wide) return obs_u1_t<uint64_t>(sec, phi, npairs, pi, pj, p_site, q, pm, s);
+        if (sec->bt->wide) return obs_u1_t<uint64_t>(sec, phi, npairs, pi, pj, p_site, q, pm, s, hpi, hpj);
     }
-    return obs_u1_t<uint32_t>(sec, phi, npairs, pi, pj, p_site, q, pm, s);
+    return obs_u1_t<uint32_t>(sec, phi, npairs, pi, pj, p_site, q, pm, s, hpi, hpj);
 }
 
 // ------------------------------------------------------------------ small sectors

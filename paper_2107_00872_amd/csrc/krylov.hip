@@ -335,47 +335,72 @@ __global__ void k_copy_re(int B, const double2 *__restrict__ in, double *__restr
 
 // Out_y = sum_{x < NX} X_x * C[x][y][b] for y < NY (C real, per column, the
 // column index fastest so a wavefront's coefficient loads are contiguous),
-// masked by active[b].
-template <bool CPLX, int NYT>
+// masked by active[b].  Each thread takes RPT elements of one column, RPT
+// equal row blocks apart, so that every coefficient it loads serves RPT rows.
+template <bool CPLX, int NYT, int RPT>
 __global__ __launch_bounds__(256) void k_rotate(uint64_t ne, int B, const double *__restrict__ X,
                                                 uint64_t stride, int NX, const double *__restrict__ Cm,
                                                 int NY, double *__restrict__ Out,
                                                 const uint8_t *__restrict__ active) {
-    uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= ne) return;
+    const uint64_t rows = ne / (uint64_t)B;
+    const uint64_t part = (rows + RPT - 1) / RPT * (uint64_t)B;  // elements per row block
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= part) return;
     const int b = (int)(e % (uint64_t)B);
     if (active && !active[b]) return;
+    uint64_t ei[RPT];
+    bool ok[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        ei[k] = e + (uint64_t)k * part;
+        ok[k] = ei[k] < ne;
+    }
     const double *Cb = Cm + b;
     const size_t cs = (size_t)B;  // stride between consecutive (x, y) coefficients
     for (int y0 = 0; y0 < NY; y0 += NYT) {
-        double ar[NYT], ai[NYT];
+        double ar[RPT][NYT], ai[RPT][NYT];
 #pragma unroll
-        for (int q = 0; q < NYT; ++q) ar[q] = ai[q] = 0.0;
+        for (int k = 0; k < RPT; ++k)
+#pragma unroll
+            for (int q = 0; q < NYT; ++q) ar[k][q] = ai[k][q] = 0.0;
         for (int x = 0; x < NX; ++x) {
-            if (CPLX) {
-                const double2 v = ((const double2 *)(X + (size_t)x * stride))[e];
+            double vr[RPT], vi[RPT];
 #pragma unroll
-                for (int q = 0; q < NYT; ++q) {
-                    if (y0 + q < NY) {
-                        const double c = Cb[((size_t)x * NY + y0 + q) * cs];
-                        ar[q] += v.x * c;
-                        ai[q] += v.y * c;
+            for (int k = 0; k < RPT; ++k) {
+                vr[k] = vi[k] = 0.0;
+                if (ok[k]) {
+                    if (CPLX) {
+                        const double2 v = ((const double2 *)(X + (size_t)x * stride))[ei[k]];
+                        vr[k] = v.x;
+                        vi[k] = v.y;
+                    } else {
+                        vr[k] = X[(size_t)x * stride + ei[k]];
                     }
                 }
-            } else {
-                const double v = X[(size_t)x * stride + e];
+            }
 #pragma unroll
-                for (int q = 0; q < NYT; ++q)
-                    if (y0 + q < NY) ar[q] += v * Cb[((size_t)x * NY + y0 + q) * cs];
+            for (int q = 0; q < NYT; ++q) {
+                if (y0 + q < NY) {
+                    const double c = Cb[((size_t)x * NY + y0 + q) * cs];
+#pragma unroll
+                    for (int k = 0; k < RPT; ++k) {
+                        ar[k][q] += vr[k] * c;
+                        if (CPLX) ai[k][q] += vi[k] * c;
+                    }
+                }
             }
         }
 #pragma unroll
         for (int q = 0; q < NYT; ++q) {
             if (y0 + q >= NY) break;
-            if (CPLX)
-                ((double2 *)(Out + (size_t)(y0 + q) * stride))[e] = make_double2(ar[q], ai[q]);
-            else
-                Out[(size_t)(y0 + q) * stride + e] = ar[q];
+#pragma unroll
+            for (int k = 0; k < RPT; ++k) {
+                if (!ok[k]) continue;
+                if (CPLX)
+                    ((double2 *)(Out + (size_t)(y0 + q) * stride))[ei[k]] = make_double2(ar[k][q], ai[k][q]);
+                else
+                    Out[(size_t)(y0 + q) * stride + ei[k]] = ar[k][q];
+            }
         }
     }
 }
@@ -812,11 +837,13 @@ int Engine::read_ab(int x0, int x1, std::vector<double> &a, std::vector<double> 
 }
 
 int Engine::rotate_dev(int from_slot, int NX, const double *dC, int NY, int to_slot, const uint8_t *act_dev) {
+    constexpr int RPT = 2;
+    const uint64_t part = (n + RPT - 1) / RPT * (uint64_t)B;
     if (cplx)
-        hipLaunchKernelGGL((k_rotate<true, 16>), grid1(ne), dim3(256), 0, st, ne, B, slot(from_slot),
+        hipLaunchKernelGGL((k_rotate<true, 16, RPT>), grid1(part), dim3(256), 0, st, ne, B, slot(from_slot),
                            stride, NX, dC, NY, slot(to_slot), act_dev);
     else
-        hipLaunchKernelGGL((k_rotate<false, 16>), grid1(ne), dim3(256), 0, st, ne, B, slot(from_slot),
+        hipLaunchKernelGGL((k_rotate<false, 16, RPT>), grid1(part), dim3(256), 0, st, ne, B, slot(from_slot),
                            stride, NX, dC, NY, slot(to_slot), act_dev);
     QS3_HIP(hipGetLastError());
     return QS3_OK;

@@ -35,8 +35,9 @@ namespace qs3 {
     return QS3_EINVAL;
 
 static int obs_u1(qs3_sector *sec, const double *phi, int npairs, const int32_t *pi, const int32_t *pj,
-                  std::vector<double> &p, std::vector<double> &q, std::vector<double> &pm, hipStream_t s) {
-#define QS3_OU1(k) obs_u1_K<k>(sec, phi, npairs, pi, pj, p, q, pm, s)
+                  std::vector<double> &p, std::vector<double> &q, std::vector<double> &pm, hipStream_t s,
+                  const int32_t *hpi = nullptr, const int32_t *hpj = nullptr) {
+#define QS3_OU1(k) obs_u1_K<k>(sec, phi, npairs, pi, pj, p, q, pm, s, hpi, hpj)
     QS3_SW7(sec->K, QS3_OU1)
 #undef QS3_OU1
 }
@@ -226,7 +227,8 @@ int qs3_sisj(qs3_sector *sec, const void *vec, int n_pairs, const int32_t *pi, c
         QS3_HIP(hipMemcpyAsync(dpj.ptr, hj_.data(), sizeof(int32_t) * np, hipMemcpyHostToDevice, s));
     }
     std::vector<double> p, q, pmv;
-    QS3_TRY(obs_u1(sec, (const double *)vec, np, dpi.as<int32_t>(), dpj.as<int32_t>(), p, q, pmv, s));
+    QS3_TRY(obs_u1(sec, (const double *)vec, np, dpi.as<int32_t>(), dpj.as<int32_t>(), p, q, pmv, s, hi_.data(),
+                   hj_.data()));
     for (int t = 0; t < n_pairs; ++t) {
         if (pi[t] == pj[t]) {
             zz[t] = 0.25;

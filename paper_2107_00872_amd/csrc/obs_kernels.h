@@ -112,6 +112,130 @@ __global__ __launch_bounds__(256) void k_pair_u1(LatArgs L, const RT *__restrict
     block_sum2(make_double2(aq, apm), &partial[(size_t)blockIdx.x * nchunk + blockIdx.y]);
 }
 
+// One chunk of the Gram factor of <S^+_i S^-_j> (fixed N_down, real phi):
+// for the (K-1)-subsets beta of ranks b0 .. b0 + nc - 1 and every site r,
+// U[r * nc + (beta - b0)] = phi(beta + {r}) when r is not in beta, else 0.
+// Then sum_beta U[beta][i] U[beta][j] = sum_S phi(S + i) phi(S + j) over the
+// (K-1)-subsets S avoiding i and j, the pair sum of Sec. 3.6 for i != j.  With
+// r inserted at position p of beta's sorted sites e, its rank is
+// sum_{m<p} C(e_m, m+1) + C(r, p+1) + sum_{m>=p} C(e_m, m+2); the two sums
+// move by one term each time r passes a site of beta.
+template <int K, typename RT>
+__global__ __launch_bounds__(256) void k_pm_rows(int N, const RT *__restrict__ binom_g, uint64_t b0, uint64_t nc,
+                                                 const double *__restrict__ phi, double *__restrict__ U) {
+    constexpr int M = K - 1;
+    Binom<RT> Bn{binom_g, binom_shift(N)};
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc) return;
+    int e[M > 0 ? M : 1];
+    RT low = 0, high = 0;
+    RT cl[M > 0 ? M : 1], ch[M > 0 ? M : 1];
+    if constexpr (M > 0) {
+        unrank<M, RT>((RT)(b0 + t), N, Bn, e);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            cl[m] = Bn.C(e[m], m + 1);
+            ch[m] = Bn.C(e[m], m + 2);
+            high += ch[m];
+        }
+    }
+    int p = 0;
+    int nxt = M > 0 ? e[0] : N;
+    for (int r = 0; r < N; ++r) {
+        double v = 0.0;
+        if (r == nxt) {
+            // r is in beta: step past it
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                if (m == p) {
+                    low += cl[m];
+                    high -= ch[m];
+                }
+            ++p;
+            nxt = N;
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                if (m == p) nxt = e[m];
+        } else {
+            v = phi[low + Bn.C(r, p + 1) + high];
+        }
+        U[(size_t)r * nc + t] = v;
+    }
+}
+
+// Gram matrix of the factor above, split over row chunks: block (c, t) takes
+// rows [c * rc, (c + 1) * rc) of U (nc x N, column major) and the 64 x 64 tile
+// pair t = (ti <= tj) of G = U^T U, 16 x 16 threads with 4 x 4 outputs each,
+// staging 16 rows of both column panels in LDS per pass.
+// part[((c * ntp + t) * 64 + i) * 64 + j] = the chunk's sum for G[64 ti + i][64 tj + j].
+template <int TS>
+__global__ __launch_bounds__(256) void k_gram_tiles(const double *__restrict__ U, uint64_t nc, int N, uint64_t rc,
+                                                    const int2 *__restrict__ tiles, int ntp,
+                                                    double *__restrict__ part) {
+    static_assert(TS == 64, "one thread per 4 x 4 outputs of a 64 x 64 tile");
+    __shared__ double As[16][64], Bs[16][64];
+    const int2 tp = tiles[blockIdx.y];
+    const int i0 = tp.x * 64, j0 = tp.y * 64;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const uint64_t r0 = (uint64_t)blockIdx.x * rc;
+    const uint64_t r1 = r0 + rc < nc ? r0 + rc : nc;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (uint64_t k0 = r0; k0 < r1; k0 += 16) {
+        // 2 x 16 x 64 loads by 256 threads: k fastest, so 16 consecutive rows
+        // of one column are contiguous
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = threadIdx.x + q * 256;  // 0 .. 1023
+            const int k = idx & 15, c = idx >> 4;   // c: 0 .. 63
+            const uint64_t kr = k0 + k;
+            const int ci = i0 + c, cj = j0 + c;
+            As[k][c] = (kr < r1 && ci < N) ? U[(size_t)ci * nc + kr] : 0.0;
+            Bs[k][c] = (kr < r1 && cj < N) ? U[(size_t)cj * nc + kr] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            double a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = As[k][ty * 4 + q];
+                b[q] = Bs[k][tx * 4 + q];
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+        }
+        __syncthreads();
+    }
+    double *out = part + ((size_t)blockIdx.x * ntp + blockIdx.y) * 4096;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) out[(ty * 4 + x) * 64 + tx * 4 + y] = acc[x][y];
+}
+
+// G[i + j N] (and G[j + i N]) = sum over the chunks, in chunk order, of the
+// tile partials: one thread per element of every tile pair.
+template <int TS>
+__global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ part, int nchunk,
+                                                     const int2 *__restrict__ tiles, int ntp, int N,
+                                                     double *__restrict__ G) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (uint64_t)ntp * 4096) return;
+    const int t = (int)(e >> 12), w = (int)(e & 4095);
+    const int i = tiles[t].x * 64 + (w >> 6), j = tiles[t].y * 64 + (w & 63);
+    if (i >= N || j >= N) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += part[((size_t)c * ntp + t) * 4096 + w];
+    G[(size_t)i + (size_t)j * N] = s;
+    G[(size_t)j + (size_t)i * N] = s;
+}
+
 // Momentum sector (union layout, one column): for displacement d = disp[dd]
 // (packed dx | dy<<10 | dz<<20) accumulate over the rows of the chunk
 //   zz: |phi_u|^2 * #{pairs of down spins at displacement d}

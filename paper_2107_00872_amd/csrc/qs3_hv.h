@@ -86,11 +86,14 @@ namespace qs3 {
 // Observables (obs_kernels.h), instantiated per N_down in hv_inst.hip.
 // Fixed-N_down sector, real vector phi (device): p_site[i] = sum_{a ∋ i}
 // |phi_a|^2; for pairs (pi, pj device, i != j): q[p] = sum_{a ∋ i, j} |phi_a|^2,
-// pm[p] = sum_S phi(S+j) phi(S+i).  Host outputs.
+// pm[p] = sum_S phi(S+j) phi(S+i).  Host outputs.  hpi, hpj: the same pairs
+// on the host with hpi < hpj, or null (then every pair runs its own subset
+// loops; with them and at least N pairs, pm comes from one Gram matrix).
 template <int K>
 int obs_u1_K(qs3_sector *sec, const double *phi, int npairs, const int32_t *pi,
              const int32_t *pj, std::vector<double> &p_site, std::vector<double> &q,
-             std::vector<double> &pm, hipStream_t s);
+             std::vector<double> &pm, hipStream_t s, const int32_t *hpi = nullptr,
+             const int32_t *hpj = nullptr);
 // Momentum sector in union layout: per displacement (packed, device) the sums
 // zz (pair counts weighted by |phi|^2), nrm = |phi|^2 and pm (complex).
 template <int K>

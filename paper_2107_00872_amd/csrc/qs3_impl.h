@@ -74,6 +74,8 @@ struct qs3_ctx {
     uint64_t table_limit = 16ull << 30;     // largest rank -> (rep, translation) table
     uint64_t hop_list_limit = 64ull << 30;  // largest per-representative hop lists
     std::mutex mu;
+    void *blas = nullptr;  // rocBLAS handle, created on first use
+    std::mutex blas_mu;    // held while a call is bound to the handle
 };
 
 namespace qs3 {
@@ -195,6 +197,10 @@ namespace qs3 {
 
 // ---- kernels' launchers (hv.hip) ----
 int hv_u1(qs3_sector *sec, const void *v, int vtype, void *w, int wtype, hipStream_t s);
+// The context's rocBLAS handle (a rocblas_handle), created on first use and
+// bound to stream s; the caller holds ctx->blas_mu.  Null on failure.
+void *blas_on(qs3_ctx *ctx, hipStream_t s);
+void blas_release(qs3_ctx *ctx);
 int hv_batch(qs3_batch *bat, const void *v, int vtype, void *w, int wtype, hipStream_t s);
 int row_u1(qs3_sector *sec, uint64_t row, int cap, int64_t *cols, double *vals, double *diag,
            int *nnz);
