@@ -76,6 +76,53 @@ def test_u1_observables(qs3, ctx, lat, K):
         assert szz.sum() == pytest.approx(N / 4, abs=1e-10)
 
 
+@pytest.mark.parametrize("lat,K", [(wl.chain(10), 3), (wl.with_disorder(wl.chain(12), 2), 4)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_u1_pair_subset_vs_oracle(qs3, ctx, lat, K):
+    """Fewer than N pairs take the per-pair subset loops (all pairs take the
+    Gram-matrix form): both against the oracle's pair sums."""
+    L = qs3.Lattice.of(ctx, lat)
+    sec = qs3.Sector(L, K)
+    N = lat.n_sites
+    X = torch.empty(sec.dim, dtype=torch.float64, device="cuda")
+    sec.eigs(nev=1, evecs=X, seed=2)
+    phi = X.cpu().numpy()
+    rzz, rpm = corr_zz(phi, N, K), corr_pm(phi, N, K)
+    pi = [0, 3, 5, N - 1, 2, 7]
+    pj = [1, 0, 9, 4, 2, N - 2]
+    zz, pm = sec.sisj(X, pi, pj)
+    for t, (i, j) in enumerate(zip(pi, pj)):
+        assert abs(zz[t] - rzz[i, j]) < 1e-12 and abs(pm[t] - rpm[i, j]) < 1e-12, (i, j)
+
+
+@pytest.mark.parametrize("n_sites,K", [(100, 4), (200, 4)])
+def test_u1_gram_pairs_vs_subset_loops(qs3, ctx, n_sites, K):
+    """The Gram form at full size (10x10-square sites at N_down = 4: one factor
+    chunk, two column tiles; a 200-site chain: eight chunks of the factor and
+    a ragged fourth tile) against the per-pair subset loops on sampled pairs,
+    for a seeded random state."""
+    lat = wl.square(10) if n_sites == 100 else wl.chain(n_sites)
+    L = qs3.Lattice.of(ctx, lat)
+    sec = qs3.Sector(L, K)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    X = torch.randn(int(sec.dim), dtype=torch.float64, device="cuda", generator=g)
+    X /= X.norm()
+    pi, pj = all_pairs(n_sites)
+    zz, pm = sec.sisj(X, pi, pj)
+    rng = np.random.default_rng(5)
+    sample = rng.choice(n_sites * n_sites, size=3 * (n_sites - 1), replace=False)
+    for c in range(3):
+        idx = sample[c * (n_sites - 1):(c + 1) * (n_sites - 1)]
+        zs, ps = sec.sisj(X, [pi[t] for t in idx], [pj[t] for t in idx])
+        assert np.abs(ps - pm[idx]).max() < 1e-15 * max(1.0, np.abs(pm).max()) + 1e-17
+        assert np.abs(zs - zz[idx]).max() < 1e-14
+    # the matrix is symmetric and its diagonal <S+_i S-_i> = 1/2 + <S^z_i>
+    # sums to N - N_down for any normalised state
+    P = pm.real.reshape(n_sites, n_sites)
+    assert np.allclose(P, P.T, atol=1e-15)
+    assert np.trace(P) == pytest.approx(n_sites - K, abs=1e-10)
+
+
 @pytest.mark.parametrize("lat,K", [(wl.square(4), 3), (wl.chain(8), 3), (wl.hypercubic(4, 2, 1), 2)],
                          ids=lambda x: getattr(x, "name", str(x)))
 def test_k_observables_translation_averaged(qs3, ctx, lat, K):
