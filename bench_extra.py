@@ -160,18 +160,27 @@ def c4(args):
            "degenerate_k": int(sum(abs(ev[b, 0] - r.evals[0]) < 1e-10 for b in range(len(ks)))),
            "gs_seconds": t_gs}
     S = {}
-    for prec, name in [(qs3.PREC_F64, "f64"), (qs3.PREC_F32MV, "f32mv")]:
+    for prec, ro, name in [(qs3.PREC_F64, qs3.REORTH_FULL, "f64"), (qs3.PREC_F32MV, qs3.REORTH_FULL, "f32mv"),
+                           (qs3.PREC_F64, qs3.REORTH_PARTIAL, "f64_partial"),
+                           (qs3.PREC_F32MV, qs3.REORTH_PARTIAL, "f32mv_partial")]:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         Sq, a, b, w = gs.dsf(X, r.evals[0], ks, omega, steps=300, eta=0.05, field=4.0, precision=prec,
-                             stream=stream)
+                             reorth=ro, stream=stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        S[name] = Sq
+        S[name] = (Sq, a, b)
         out[name] = {"seconds": dt, "q_per_s": len(ks) / dt, "sum_weights": float(w.sum()),
                      "integral_check": float(np.trapezoid(Sq, omega, axis=1).sum())}
-    out["f32mv"]["max_abs_dS_vs_f64"] = float(np.abs(S["f32mv"] - S["f64"]).max())
-    out["f32mv"]["max_S"] = float(np.abs(S["f64"]).max())
+    ref, ra, rb = S["f64"]
+    out["max_S"] = float(np.abs(ref).max())
+    for name in ("f32mv", "f64_partial", "f32mv_partial"):
+        Sq, a, b = S[name]
+        out[name]["max_abs_dS_vs_f64"] = float(np.abs(Sq - ref).max())
+    for name in ("f64_partial",):
+        Sq, a, b = S[name]
+        out[name]["max_abs_dalpha_vs_full"] = float(np.abs(a - ra).max())
+        out[name]["max_abs_dbeta_vs_full"] = float(np.abs(b - rb).max())
     out["value"] = out["f64"]["q_per_s"]
     out["unit"] = "q/s (300-level continued fraction, float64)"
     return out

@@ -142,6 +142,17 @@ int qs3_row(qs3_sector *sec, uint64_t row, int cap, int64_t *cols, double *vals,
 /* ---- eigensolver (Sec. 3.7, Alg. 10) ------------------------------------ */
 #define QS3_ALG_LANCZOS 0   /* conventional Lanczos, `steps` steps, no restart */
 #define QS3_ALG_TRL     1   /* thick-restart Lanczos */
+#define QS3_REORTH_NONE    0  /* three-term recurrence only */
+#define QS3_REORTH_FULL    1  /* classical Gram-Schmidt against every earlier
+                                 vector at every step, a second pass where the
+                                 first cancelled more than half the norm */
+#define QS3_REORTH_PARTIAL 2  /* plain Lanczos only (thick restart and sectors
+                                 small enough for one workgroup run FULL):
+                                 Simon's recurrence estimates the overlaps of
+                                 each new vector with the earlier ones, and a
+                                 Gram-Schmidt pass against all of them runs at
+                                 the steps where an estimate exceeds sqrt(eps)
+                                 and at the step after (semi-orthogonality) */
 #define QS3_PREC_F64    0   /* float64 everywhere */
 #define QS3_PREC_F32MV  1   /* float32 matvec (float32 row accumulation), float64
                                recurrence, reorthogonalisation and eigensolves */
@@ -156,7 +167,7 @@ typedef struct {
     double tol;         /* residual tolerance relative to max(1, |e|) (0 = 1e-9) */
     uint64_t seed;      /* start vector seed */
     int precision;      /* QS3_PREC_* */
-    int reorth;         /* 1 = full (classical Gram-Schmidt, twice), 0 = none */
+    int reorth;         /* QS3_REORTH_* (TRL: FULL or PARTIAL, both full) */
 } qs3_eigs_opts;
 
 typedef struct {
@@ -181,7 +192,7 @@ int qs3_eigs(qs3_sector *sec, const qs3_eigs_opts *opts, double *evals, void *ev
              qs3_eigs_info *info, void *stream);
 
 /* Plain Lanczos coefficients from v0 (device, float64 type of the sector; or
- * NULL for the seeded start vector): alpha[0..steps-1], beta[0..steps-1]
+ * NULL for the seeded start vector), reorth = QS3_REORTH_*: alpha[0..steps-1], beta[0..steps-1]
  * (beta[x] = norm of the (x+2)-th vector before normalisation) and
  * *norm0 = |v0|.  Host outputs.  Stops early at an invariant subspace: *done
  * receives the number of steps taken. */
@@ -255,7 +266,7 @@ typedef struct {
     double field;       /* h of the Zeeman term -h S^z_tot: the poles move by +h
                            (S^-), -h (S^+) or 0 (S^z) */
     int precision;      /* QS3_PREC_* */
-    int reorth;         /* 1 = full, 0 = none */
+    int reorth;         /* QS3_REORTH_* */
     int op;             /* QS3_OP_SMINUS (0, default), QS3_OP_SPLUS or QS3_OP_SZ */
     int subtract_trivial; /* S^z only: subtract the trivial q = 0 part
                            (M^2/N) eta / (pi (omega^2 + eta^2)), M = N/2 - K (Sec. 4.2) */

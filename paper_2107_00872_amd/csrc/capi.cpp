@@ -703,7 +703,9 @@ int qs3_lanczos(qs3_sector *sec, const void *v0, int steps, int precision, int r
     if (sec->has_k) op.reset(new BatchOp(sec->bat));
     else op.reset(new U1Op(sec));
     Engine E;
-    QS3_TRY(E.init(ctx, op.get(), steps + 1, precision, reorth ? 2 : 0, s));
+    QS3_REQUIRE(reorth >= QS3_REORTH_NONE && reorth <= QS3_REORTH_PARTIAL, QS3_EINVAL,
+                "unknown reorthogonalisation mode");
+    QS3_TRY(E.init(ctx, op.get(), steps + 1, precision, engine_reorth(reorth, false), s));
     DevBuf vb;
     QS3_TRY(vb.alloc(ctx, sizeof(double) * E.stride));
     if (v0) {

@@ -220,6 +220,56 @@ __global__ void k_dgks_flag(int B, const double2 *__restrict__ before, const dou
     if (b < B) flag[b] = (after[b].x < 0.5 * before[b].x && (!mask || mask[b])) ? 1 : 0;
 }
 
+// Partial reorthogonalisation: Simon's recurrence for the overlaps
+// w_{j,k} ~ <psi_j, psi_k> of plain Lanczos, one thread per column.  om holds
+// two rows per column ([parity][k][B], row j at parity j & 1, w_{j,j} = 1);
+// ab: alpha at [k * B + b], beta_k (the coupling of psi_k and psi_{k+1}) at
+// [(slots + k) * B + b]; nrm2: |W|^2 after the three-term update of step x, so
+// beta_x = |W|.  Writes row x + 1:
+//   beta_x w_{x+1,k} = beta_k w_{x,k+1} + (alpha_k - alpha_x) w_{x,k}
+//                      + beta_{k-1} w_{x,k-1} - beta_{x-1} w_{x-1,k}  (k < x)
+// plus a rounding term eps1 (beta_k + beta_x) of the sign of the sum,
+// w_{x+1,x} = eps1, w_{x+1,x+1} = 1.  Where some |w_{x+1,k}| exceeds sqrt(eps)
+// the column is flagged for a Gram-Schmidt pass against psi_0..psi_x now and
+// at the next step, and its row is reset to eps1.
+__global__ void k_omega(int B, int x, const double *__restrict__ ab, int slots, const double2 *__restrict__ nrm2,
+                        double *__restrict__ om, int ostride, const uint8_t *__restrict__ mask,
+                        uint8_t *__restrict__ force, uint8_t *__restrict__ flag, double eps1) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double *cur = om + ((size_t)(x & 1) * ostride) * B + b;
+    double *nxt = om + ((size_t)((x + 1) & 1) * ostride) * B + b;
+    if (x == 0) cur[0] = 1.0;
+    if (mask && !mask[b]) {
+        flag[b] = 0;
+        return;
+    }
+    const double bx = sqrt(fmax(nrm2[b].x, 0.0));
+    const double ax = ab[(size_t)x * B + b];
+    const double bxm = x > 0 ? ab[(size_t)(slots + x - 1) * B + b] : 0.0;
+    double worst = 0.0;
+    double prev_cur = 0.0;  // w_{x,k-1}
+    for (int k = 0; k < x; ++k) {
+        const double ck = cur[(size_t)k * B], ck1 = cur[(size_t)(k + 1) * B];
+        const double bk = ab[(size_t)(slots + k) * B + b];
+        const double bkm = k > 0 ? ab[(size_t)(slots + k - 1) * B + b] : 0.0;
+        double t = bk * ck1 + (ab[(size_t)k * B + b] - ax) * ck + bkm * prev_cur - bxm * nxt[(size_t)k * B];
+        t += copysign(eps1 * (bk + bx), t);
+        const double w = bx > 0.0 ? t / bx : INFINITY;
+        prev_cur = ck;
+        nxt[(size_t)k * B] = w;
+        worst = fmax(worst, fabs(w));
+    }
+    const bool over = !(worst <= 1.4901161193847656e-8);  // sqrt(eps); NaN/inf count as over
+    const bool fl = over || force[b];
+    force[b] = over && !force[b];
+    if (fl)
+        for (int k = 0; k < x; ++k) nxt[(size_t)k * B] = eps1;
+    nxt[(size_t)x * B] = eps1;
+    nxt[(size_t)(x + 1) * B] = 1.0;
+    flag[b] = fl;
+}
+
 __global__ void k_merge_norm(int B, const uint8_t *__restrict__ flag, const double2 *__restrict__ n2,
                              double2 *__restrict__ n1) {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -629,7 +679,11 @@ int Engine::init(qs3_ctx *c, Operator *o, int slots_, int precision_, int reorth
     QS3_TRY(alpha.alloc(ctx, sizeof(double2) * (size_t)B));
     QS3_TRY(nrm2.alloc(ctx, sizeof(double2) * (size_t)B));
     QS3_TRY(ab_hist.alloc(ctx, sizeof(double) * 2 * (size_t)slots * B));
-    QS3_TRY(act.alloc(ctx, 2 * (size_t)B + 16));
+    QS3_TRY(act.alloc(ctx, 3 * (size_t)B + 16));
+    if (reorth == 3) {
+        QS3_TRY(om.alloc(ctx, sizeof(double) * 2 * (size_t)(slots + 1) * B));
+        QS3_HIP(hipMemsetAsync(act.ptr, 0, 3 * (size_t)B + 16, st));
+    }
     return QS3_OK;
 }
 
@@ -717,7 +771,7 @@ int Engine::step(int x, int prev) {
                        ab_hist.as<double>() + (size_t)x * B);
     double2 *h = hvec.as<double2>();
     double2 *n_before = h + (size_t)(x + 1) * B;  // the self-dot output of the first pass
-    if (reorth > 0) {
+    if (reorth == 1 || reorth == 2) {
         // W' = W - alpha psi_x - beta psi_prev is formed on the fly inside
         // the first Gram-Schmidt pass (dots) and its update (stored there)
         ThreeTerm f;
@@ -739,6 +793,8 @@ int Engine::step(int x, int prev) {
             QS3_HIP(hipGetLastError());
         }
     } else {
+        // three-term recurrence (and with reorth == 3 the partial
+        // reorthogonalisation below)
         if (cplx)
             hipLaunchKernelGGL(k_lanczos_update<true>, grid1(ne), dim3(256), 0, st, ne, B,
                                W.as<double>(), slot(x), prev >= 0 ? slot(prev) : nullptr,
@@ -749,6 +805,19 @@ int Engine::step(int x, int prev) {
                                alpha.as<double2>(), betap, colmask);
         QS3_HIP(hipGetLastError());
         QS3_TRY(multidot(W.as<double>(), 1, W.as<double>(), nrm2.as<double2>(), 0, colmask));
+        if (reorth == 3) {
+            uint8_t *flag = act.as<uint8_t>() + 8 + B, *force = act.as<uint8_t>() + 8 + 2 * B;
+            const double eps1 = 2.220446049250313e-16 * std::sqrt((double)n);
+            hipLaunchKernelGGL(k_omega, grid1(B), dim3(256), 0, st, B, x, ab_hist.as<double>(), slots,
+                               nrm2.as<double2>(), om.as<double>(), slots + 1, colmask, force, flag, eps1);
+            QS3_HIP(hipGetLastError());
+            double2 *h = hvec.as<double2>();
+            QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 0, flag));
+            double2 *n2 = h + (size_t)(x + 1) * B;
+            QS3_TRY(cgs_update_norm(x + 1, h, flag, n2));
+            hipLaunchKernelGGL(k_merge_norm, grid1(B), dim3(256), 0, st, B, flag, n2, nrm2.as<double2>());
+            QS3_HIP(hipGetLastError());
+        }
     }
     hipLaunchKernelGGL(k_sqrt_to, grid1(B), dim3(256), 0, st, B, nrm2.as<double2>(),
                        ab_hist.as<double>() + (size_t)slots * B + (size_t)x * B);
@@ -864,7 +933,7 @@ int Engine::gather_columns_into(Engine &dst, int from_slot, int to_slot, const i
 }
 
 void Engine::release() {
-    for (DevBuf *b : {&Psi, &W, &X32, &partial, &hvec, &alpha, &nrm2, &ab_hist, &act}) b->release();
+    for (DevBuf *b : {&Psi, &W, &X32, &partial, &hvec, &alpha, &nrm2, &ab_hist, &act, &om}) b->release();
 }
 
 // ------------------------------------------------------------------ host-side solver logic
@@ -1098,7 +1167,7 @@ int SolveRun::slots_for(const qs3_eigs_opts &o) {
 
 int SolveRun::init(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &opts, hipStream_t s) {
     o = opts;
-    QS3_TRY(root.init(ctx, op, slots_for(o), o.precision, o.reorth ? 2 : 0, s));
+    QS3_TRY(root.init(ctx, op, slots_for(o), o.precision, engine_reorth(o.reorth, o.alg == QS3_ALG_TRL), s));
     B = root.B;
     const int NX = o.alg == QS3_ALG_TRL ? o.nm : o.steps;
     const int NY = o.alg == QS3_ALG_TRL ? o.nk : o.nev;

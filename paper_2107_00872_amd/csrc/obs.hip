@@ -407,7 +407,9 @@ int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_
     } top;
     top.b = tb;
     Engine E;
-    QS3_TRY(E.init(lat->ctx, &top, steps + 1, opts->precision, opts->reorth ? 2 : 0, s));
+    QS3_REQUIRE(opts->reorth >= QS3_REORTH_NONE && opts->reorth <= QS3_REORTH_PARTIAL, QS3_EINVAL,
+                "unknown reorthogonalisation mode");
+    QS3_TRY(E.init(lat->ctx, &top, steps + 1, opts->precision, engine_reorth(opts->reorth, false), s));
     std::vector<double> a, bb, n0;
     std::vector<int> done;
     QS3_TRY(run_lanczos(E, psi.as<double>(), steps, a, bb, n0, done));

@@ -38,6 +38,14 @@ struct RedGeom {
     int ncoltile;
 };
 
+// The engine's reorthogonalisation mode for an option value QS3_REORTH_*:
+// 0 none, 2 full with the second pass where needed, 3 partial (plain Lanczos
+// only; a restarted solve keeps full).
+inline int engine_reorth(int opt, bool restarted) {
+    if (opt == QS3_REORTH_NONE) return 0;
+    return (opt == QS3_REORTH_PARTIAL && !restarted) ? 3 : 2;
+}
+
 struct Engine {
     qs3_ctx *ctx = nullptr;
     Operator *op = nullptr;
@@ -48,7 +56,7 @@ struct Engine {
     int n_matvec = 0;
     const uint8_t *colmask = nullptr;  // device: columns still iterating (null = all)
     RedGeom rg{};
-    DevBuf Psi, W, X32, partial, hvec, alpha, nrm2, ab_hist, act;
+    DevBuf Psi, W, X32, partial, hvec, alpha, nrm2, ab_hist, act, om;
     ~Engine();
     int init(qs3_ctx *c, Operator *o, int slots, int precision, int reorth, hipStream_t s);
     double *slot(int j);
@@ -176,8 +184,10 @@ inline int fill_opts(qs3_eigs_opts &o, uint64_t min_dim) {
     QS3_REQUIRE(o.nev <= 16, QS3_EINVAL, "nev must be <= 16");
     QS3_REQUIRE(o.precision == QS3_PREC_F64 || o.precision == QS3_PREC_F32MV, QS3_EINVAL,
                 "unknown precision");
+    QS3_REQUIRE(o.reorth >= QS3_REORTH_NONE && o.reorth <= QS3_REORTH_PARTIAL, QS3_EINVAL,
+                "unknown reorthogonalisation mode");
     if (o.alg == QS3_ALG_TRL) {
-        QS3_REQUIRE(o.reorth != 0, QS3_EINVAL, "thick restart needs reorthogonalisation");
+        QS3_REQUIRE(o.reorth != QS3_REORTH_NONE, QS3_EINVAL, "thick restart needs reorthogonalisation");
         QS3_REQUIRE(o.nk > o.nev - 1 && o.nm > o.nk, QS3_EINVAL, "need nev <= nk < nm");
         if ((uint64_t)o.nm > min_dim) {
             // the Krylov space would exhaust the sector: plain Lanczos over it

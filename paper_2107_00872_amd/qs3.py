@@ -18,6 +18,7 @@ QS3_OK, QS3_EINVAL, QS3_ENOMEM, QS3_ENOCONV, QS3_ENUMERIC, QS3_EDEVICE = 0, -1, 
 QS3_EBUSY, QS3_ENOTFOUND, QS3_ECANCELED = -6, -7, -8
 F64, F32, C128, C64 = 0, 1, 2, 3
 ALG_LANCZOS, ALG_TRL = 0, 1
+REORTH_NONE, REORTH_FULL, REORTH_PARTIAL = 0, 1, 2
 OP_SMINUS, OP_SPLUS, OP_SZ = 0, 1, 2
 PREC_F64, PREC_F32MV = 0, 1
 

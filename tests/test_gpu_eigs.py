@@ -57,6 +57,30 @@ def test_c1_lanczos_100_steps(qs3, ctx):
     assert np.allclose(r32.evals, ref, rtol=1e-5, atol=0)
 
 
+def test_lanczos_partial_reorthogonalisation(qs3, ctx):
+    """300 plain Lanczos steps on the periodic 24-site chain at N_down = 6 (dim
+    134,596: the streaming engine, not the one-workgroup kernel) with partial
+    reorthogonalisation: the Ritz values of T agree with those of the fully
+    reorthogonalised run and hold no spurious copies, which the run without
+    reorthogonalisation does; the lowest equals the thick-restart ground state."""
+    lat = wl.chain(24)
+    L = qs3.Lattice.of(ctx, lat)
+    sec = qs3.Sector(L, 6)
+
+    def ritz(ro):
+        a, b, n0, done = sec.lanczos(300, reorth=ro, seed=3)
+        assert done == 300
+        T = np.diag(a) + np.diag(b[:-1], 1) + np.diag(b[:-1], -1)
+        return np.linalg.eigvalsh(T)
+
+    full, part, none = ritz(qs3.REORTH_FULL), ritz(qs3.REORTH_PARTIAL), ritz(qs3.REORTH_NONE)
+    assert np.abs(part[:8] - full[:8]).max() < 1e-10
+    gs = sec.eigs(nev=1, seed=1).evals[0]
+    assert part[0] == pytest.approx(gs, abs=1e-10)
+    # the unreorthogonalised run repeats the converged ground level
+    assert abs(none[1] - none[0]) < 1e-8 and abs(full[1] - full[0]) > 1e-3
+
+
 @pytest.mark.parametrize("lat,K,nev", [(wl.chain(16), 3, 4), (wl.square(4), 4, 3),
                                        (wl.with_disorder(wl.chain(14), 2), 4, 3), (wl.square(6), 2, 5)],
                          ids=lambda x: getattr(x, "name", str(x)))
