@@ -152,6 +152,53 @@ def test_k_basis_and_matvec(qs3, ctx, dims, lat, K):
         sec.close()
 
 
+def test_k_sector_64bit_ranks_cube10_k4(qs3, ctx):
+    """The periodic 10^3 cube at N_down = 4, k = 0: C(1000, 4) = 4.1e10 ranks
+    (64-bit ranks, hop lists).  Sampled representatives are orbit minima with
+    the oracle's stabiliser sizes (Alg. 5/7 at N = 1000); the uniform
+    superposition sqrt(N / s_a) per representative -- (S^-_tot)^4 of the
+    ferromagnet -- is an eigenvector with E_FM = 3000 / 4; H is Hermitian on
+    seeded random vectors."""
+    from oracle.translation import Geometry, check_state
+    lat = wl.cube(10)
+    L = qs3.Lattice.of(ctx, lat)
+    sec = qs3.Sector(L, 4, (0, 0, 0))
+    ranks, stab = sec.basis()
+    N = lat.n_sites
+    assert ranks.dtype == np.uint64 and int(ranks[-1]) >= 2 ** 32
+    # Burnside: the number of orbits is the mean number of states a
+    # translation fixes, C(N/o, K/o) for a translation of order o dividing K
+    fixed = 0
+    for tx in range(10):
+        for ty in range(10):
+            for tz in range(10):
+                o = math.lcm(10 // math.gcd(tx, 10), 10 // math.gcd(ty, 10), 10 // math.gcd(tz, 10))
+                fixed += math.comb(N // o, 4 // o) if 4 % o == 0 else 0
+    assert fixed % N == 0 and sec.dim == fixed // N
+    rng = np.random.default_rng(7)
+    idx = np.unique(np.concatenate([rng.integers(0, sec.dim, size=60), [0, sec.dim - 1]]))
+    geo = Geometry(10, 10, 10)
+    reps1 = ranks[idx].astype(np.uint64) + np.uint64(1)
+    mins, _ = orc.representative((10, 10, 10), 4, reps1)
+    assert np.array_equal(mins, reps1)
+    for i in idx[:20]:
+        assert check_state(geo, int(ranks[i]) + 1, 4, (0, 0, 0)) == pytest.approx(N * int(stab[i]), abs=1e-6)
+    phi = torch.from_numpy(np.sqrt(N / stab.astype(np.float64))).to(torch.complex128).cuda()
+    w = torch.empty_like(phi)
+    sec.matvec(phi, w)
+    assert (w - 750.0 * phi).abs().max().item() <= 1e-10 * 750.0 * phi.abs().max().item()
+    u = torch.empty_like(phi)
+    v = torch.empty_like(phi)
+    sec.start_vector(1, u)
+    sec.start_vector(2, v)
+    hu, hv = torch.empty_like(u), torch.empty_like(v)
+    sec.matvec(u, hu)
+    sec.matvec(v, hv)
+    lhs, rhs = torch.vdot(u, hv).item(), torch.vdot(hu, v).item()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    sec.close()
+
+
 @pytest.fixture(scope="module")
 def ctx_fly(qs3):
     """A context that never builds rank tables: every hop is resolved by
