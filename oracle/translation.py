@@ -2,12 +2,17 @@
 Alg. 6 (mk_list), Alg. 7 (representative), Alg. 8 (dense k-block) and Alg. 9
 (on-the-fly H.v in the k basis).
 
-The paper writes the chain; the lattice here is Lx x Ly x Lz with periodic
-boundaries and the translation group Z_Lx x Z_Ly x Z_Lz.
-READING: site r (1-based) has coordinates (x, y, z) with
-r - 1 = x + Lx*(y + Ly*z); translation number j = 1..N is the vector
-t_j = coords(j mod N), so j = N is the identity, as T^N = 1 on the chain.
-k = 2*pi*(Kx/Lx, Ky/Ly, Kz/Lz) and k.t = 2*pi*(Kx tx/Lx + Ky ty/Ly + Kz tz/Lz).
+The paper writes the chain; the lattice here is Lx x Ly x Lz unit cells of
+S sites each, with periodic boundaries and the translation group
+Z_Lx x Z_Ly x Z_Lz acting on the cells (S > 1 is the multi-site unit cell the
+paper names as future work, Sec. 5).
+READING: site r (1-based) has sublattice s and cell coordinates (x, y, z) with
+r - 1 = s + S*(x + Lx*(y + Ly*z)) (S = 1: x-fastest as before); translation
+number j = 1..N_T (N_T = Lx Ly Lz) is the vector t_j = cell coordinates of
+j mod N_T, so j = N_T is the identity, as T^N = 1 on the chain; a
+translation keeps the sublattice.  k = 2*pi*(Kx/Lx, Ky/Ly, Kz/Lz) and
+k.t = 2*pi*(Kx tx/Lx + Ky ty/Ly + Kz tz/Lz); the orbit normalisation is over
+the N_T translations.
 """
 from __future__ import annotations
 
@@ -21,28 +26,33 @@ from .hamiltonian import row_terms
 
 
 class Geometry:
-    def __init__(self, lx: int, ly: int = 1, lz: int = 1):
-        self.lx, self.ly, self.lz = lx, ly, lz
-        self.N = lx * ly * lz
+    def __init__(self, lx: int, ly: int = 1, lz: int = 1, ns: int = 1):
+        self.lx, self.ly, self.lz, self.ns = lx, ly, lz, ns
+        self.NT = lx * ly * lz          # translations
+        self.N = ns * self.NT           # sites
 
     def coords(self, r: int):
-        """1-based site -> (x, y, z)."""
-        i = r - 1
-        return i % self.lx, (i // self.lx) % self.ly, i // (self.lx * self.ly)
+        """1-based site -> cell coordinates (x, y, z)."""
+        c = (r - 1) // self.ns
+        return c % self.lx, (c // self.lx) % self.ly, c // (self.lx * self.ly)
 
-    def site(self, x, y, z) -> int:
-        return 1 + (x % self.lx) + self.lx * ((y % self.ly) + self.ly * (z % self.lz))
+    def sublattice(self, r: int) -> int:
+        return (r - 1) % self.ns
+
+    def site(self, x, y, z, s: int = 0) -> int:
+        return 1 + s + self.ns * ((x % self.lx) + self.lx * ((y % self.ly) + self.ly * (z % self.lz)))
 
     def t(self, j: int):
-        """Translation vector of translation number j = 1..N (j = N: identity)."""
-        return self.coords((j % self.N) + 1)
+        """Translation vector of translation number j = 1..N_T (j = N_T: identity)."""
+        c = j % self.NT
+        return c % self.lx, (c // self.lx) % self.ly, c // (self.lx * self.ly)
 
     def shift_func(self, n, t):
         """The tuple of T^t|n>: every down spin moves by t (unsorted)."""
         out = []
         for r in n:
             x, y, z = self.coords(r)
-            out.append(self.site(x + t[0], y + t[1], z + t[2]))
+            out.append(self.site(x + t[0], y + t[1], z + t[2], self.sublattice(r)))
         return out
 
     def kdot(self, K, t) -> float:
@@ -71,7 +81,7 @@ def check_state(geo: Geometry, a: int, K: int, Kvec) -> float:
     n = f_bar(a, K, geo.N)
     cstar = 0j
     nc = 0
-    for j in range(1, geo.N + 1):
+    for j in range(1, geo.NT + 1):
         t = geo.t(j)
         a2 = F(insertion_sort(geo.shift_func(n, t)))
         if a2 < a:
@@ -79,7 +89,7 @@ def check_state(geo: Geometry, a: int, K: int, Kvec) -> float:
         if a2 == a:
             cstar += cmath.exp(1j * geo.kdot(Kvec, t))
             nc += 1
-    Nak = abs(cstar) ** 2 * geo.N / nc
+    Nak = abs(cstar) ** 2 * geo.NT / nc
     return Nak if Nak > 1e-8 else 0.0
 
 
@@ -98,9 +108,9 @@ def representative(geo: Geometry, a_n: int, K: int):
     """Alg. 7: (min rank over the orbit of a_n, l) with T^{t_l} a_n = rep.
     Ties keep the last j (the printed "<=")."""
     rep = a_n
-    ell = geo.N
+    ell = geo.NT
     n = f_bar(a_n, K, geo.N)
-    for j in range(1, geo.N + 1):
+    for j in range(1, geo.NT + 1):
         a = F(insertion_sort(geo.shift_func(n, geo.t(j))))
         if a <= rep:
             rep, ell = a, j
@@ -173,7 +183,7 @@ def expand_to_u1(geo: Geometry, K: int, sigma, R, Kvec, phi: np.ndarray) -> np.n
     out = np.zeros(C(geo.N, K), dtype=np.complex128)
     for alpha, a in enumerate(sigma):
         n = f_bar(a, K, geo.N)
-        for j in range(1, geo.N + 1):
+        for j in range(1, geo.NT + 1):
             t = geo.t(j)
             b = F(insertion_sort(geo.shift_func(n, t)))
             out[b - 1] += phi[alpha] * cmath.exp(-1j * geo.kdot(Kvec, t)) / R[alpha]

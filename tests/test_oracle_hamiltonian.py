@@ -83,8 +83,10 @@ def test_row_nnz_formula_and_mean():
 
 
 def T_matrix(lat, K, t):
-    """Translation by t on popcount-K masks (ascending mask order)."""
+    """Translation of the unit cells by t on popcount-K masks (ascending mask
+    order); a site keeps its place in the cell."""
     lx, ly, lz = lat.dims
+    ns = lat.ns
     N = lat.n_sites
     ms = masks(N, K)
     idx = {m: i for i, m in enumerate(ms)}
@@ -93,8 +95,9 @@ def T_matrix(lat, K, t):
         out = 0
         for i in range(N):
             if m >> i & 1:
-                x, y, z = i % lx, (i // lx) % ly, i // (lx * ly)
-                j = (x + t[0]) % lx + lx * (((y + t[1]) % ly) + ly * ((z + t[2]) % lz))
+                sub, cell = i % ns, i // ns
+                x, y, z = cell % lx, (cell // lx) % ly, cell // (lx * ly)
+                j = sub + ns * ((x + t[0]) % lx + lx * (((y + t[1]) % ly) + ly * ((z + t[2]) % lz)))
                 out |= 1 << j
         T[idx[out], c] = 1.0
     return T
@@ -158,6 +161,60 @@ def test_k_block_projector_and_translation_eigenvalue(lat, K):
         B = nat.Bonds.of(lat)
         sc, Rc = nat.mk_list(lat.dims, K, Kv)
         assert np.abs(nat.hv_k(lat.dims, K, Kv, B, sc, Rc, phi) - Hk @ phi).max() < 1e-13
+
+
+CELL_LATS = [(wl.kagome(2, 2), 3), (wl.kagome(2, 2), 4), (wl.honeycomb(3, 2), 3),
+             (wl.honeycomb(2, 2), 2), (wl.with_disorder(wl.kagome(2, 2), seed=4, per_bond=False), 2)]
+
+
+def _order(t, dims):
+    return math.lcm(*(L // math.gcd(ti, L) for ti, L in zip(t, dims)))
+
+
+@pytest.mark.parametrize("lat,K", CELL_LATS, ids=lambda x: getattr(x, "name", str(x)))
+def test_multisite_cells_k_blocks(lat, K):
+    """Several sites per unit cell (translations act on the cells): sector
+    dimensions follow Burnside over the N_T cell translations, every k block
+    is Hermitian, the union of the k spectra is the fixed-N_down spectrum, the
+    projector check holds and expanded k vectors carry e^{ik.t} under T^t."""
+    lx, ly, lz = lat.dims
+    geo = Geometry(lx, ly, lz, lat.ns)
+    assert geo.N == lat.n_sites and geo.NT == lx * ly * lz
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    Hb = bitmask_H(lat, K)
+    ev = np.linalg.eigvalsh(Hb)
+    ts = [(tx, ty, tz) for tz in range(lz) for ty in range(ly) for tx in range(lx)]
+    Ts = {t: T_matrix(lat, K, t) for t in ts}
+    N, NT = lat.n_sites, geo.NT
+    allev = []
+    total = 0
+    for Kv in wl.all_momenta(lat):
+        kdot = lambda t: 2 * np.pi * (Kv[0] * t[0] / lx + Kv[1] * t[1] / ly + Kv[2] * t[2] / lz)
+        s, R = mk_list(geo, K, Kv)
+        # Burnside with characters: a translation of order o splits the sites
+        # into N/o cycles of length o
+        d = sum(np.exp(1j * kdot(t)) * (math.comb(N // _order(t, lat.dims), K // _order(t, lat.dims))
+                                        if K % _order(t, lat.dims) == 0 else 0) for t in ts) / NT
+        assert abs(d.imag) < 1e-9 and round(d.real) == len(s)
+        total += len(s)
+        P = sum(np.exp(-1j * kdot(t)) * Ts[t] for t in ts) / NT
+        u, sv, _ = np.linalg.svd(P)
+        Q = u[:, sv > 0.5]
+        assert Q.shape[1] == len(s)
+        if not s:
+            continue
+        Hk = gen_full_ham_sym_adapt(geo, K, bonds, s, R, Kv)
+        assert np.abs(Hk - Hk.conj().T).max() < 1e-13
+        e2 = np.linalg.eigvalsh(Hk)
+        assert np.abs(np.linalg.eigvalsh(Q.conj().T @ Hb @ Q) - e2).max() < 1e-12
+        allev.extend(e2)
+        phi = np.random.default_rng(2).normal(size=len(s)) + 1j * np.random.default_rng(3).normal(size=len(s))
+        u1 = expand_to_u1(geo, K, s, R, Kv, phi)
+        for t in ts[1:3]:
+            assert np.abs(Ts[t] @ u1 - np.exp(1j * kdot(t)) * u1).max() < 1e-12
+        assert np.abs(expand_to_u1(geo, K, s, R, Kv, Hk @ phi) - Hb @ u1).max() < 1e-12
+    assert total == math.comb(N, K)
+    assert np.abs(np.sort(allev) - ev).max() < 1e-12
 
 
 @pytest.mark.parametrize("lat", [wl.chain(16), wl.square(6), wl.cube(4), wl.square(10, J=1.0, Delta=0.7)])

@@ -5,7 +5,9 @@ This module holds no arithmetic of the method: it only writes down lattices
 random draws.  Both the HIP library and the CPU oracle receive what it returns
 as plain arrays.
 
-Site numbering: site i <-> (x, y, z) with i = x + Lx*(y + Ly*z), all 0-based.
+Site numbering: site i <-> (x, y, z) with i = x + Lx*(y + Ly*z), all 0-based;
+with S sites per unit cell (kagome, honeycomb), i = s + S*(x + Lx*(y + Ly*z))
+for sublattice s of cell (x, y, z).
 A bond is (i, j, Jxy, Jz) with the XXZ convention of the paper's model
 (Sec. 2.2): J > 0 is antiferromagnetic.
 """
@@ -26,10 +28,11 @@ class Lattice:
     jxy: np.ndarray     # float64 [n_bonds]
     jz: np.ndarray      # float64 [n_bonds]
     translation_invariant: bool = True
+    ns: int = 1         # sites per unit cell
 
     @property
     def n_sites(self) -> int:
-        return self.lx * self.ly * self.lz
+        return self.ns * self.lx * self.ly * self.lz
 
     @property
     def n_bonds(self) -> int:
@@ -89,6 +92,43 @@ def square(L: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
 
 def cube(L: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
     return hypercubic(L, L, L, J, Delta, name=f"cube{L}^3")
+
+
+def _cell_lattice(name: str, ns: int, lx: int, ly: int, links, J: float, Delta: float) -> Lattice:
+    """Periodic lx x ly cells of ns sites; links: (s, t, dx, dy) couples
+    sublattice s of cell (x, y) with sublattice t of cell (x + dx, y + dy)."""
+    seen = set()
+    uniq = []
+    for y in range(ly):
+        for x in range(lx):
+            for (s, t, dx, dy) in links:
+                i = s + ns * site_index(x, y, 0, lx, ly)
+                j = t + ns * site_index((x + dx) % lx, (y + dy) % ly, 0, lx, ly)
+                key = (min(i, j), max(i, j))
+                if i == j or key in seen:
+                    continue
+                seen.add(key)
+                uniq.append(key)
+    bi = np.array([b[0] for b in uniq], dtype=np.int32)
+    bj = np.array([b[1] for b in uniq], dtype=np.int32)
+    nb = len(uniq)
+    return Lattice(name, lx, ly, 1, bi, bj, np.full(nb, float(J)), np.full(nb, float(J) * float(Delta)),
+                   True, ns)
+
+
+def kagome(lx: int, ly: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
+    """Kagome lattice: triangular Bravais lattice (a1, a2) with sublattices
+    0 at 0, 1 at a1/2, 2 at a2/2; each site has 4 neighbours (two up and two
+    down triangles).  Needs lx, ly >= 2."""
+    links = [(0, 1, 0, 0), (0, 2, 0, 0), (1, 2, 0, 0),      # up triangle of the cell
+             (1, 0, 1, 0), (2, 0, 0, 1), (1, 2, 1, -1)]     # down triangles
+    return _cell_lattice(f"kagome{lx}x{ly}", 3, lx, ly, links, J, Delta)
+
+
+def honeycomb(lx: int, ly: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
+    """Honeycomb lattice: two sublattices, each site with 3 neighbours."""
+    links = [(0, 1, 0, 0), (1, 0, 1, 0), (1, 0, 0, 1)]
+    return _cell_lattice(f"honeycomb{lx}x{ly}", 2, lx, ly, links, J, Delta)
 
 
 def with_disorder(lat: Lattice, seed: int, jlo: float = 0.5, jhi: float = 1.5,
