@@ -102,6 +102,19 @@ int qs3_ctx_set_structure_limits(qs3_ctx *ctx, uint64_t table_max_bytes, uint64_
 int qs3_lattice_create(qs3_ctx *ctx, int lx, int ly, int lz, int n_bonds, const int32_t *bi,
                        const int32_t *bj, const double *jxy, const double *jz,
                        qs3_lattice **out);
+/* Unit cells of n_sub sites (1 <= n_sub <= 4; the multi-site unit cell that
+ * Sec. 5 names as future work, e.g. kagome 3, honeycomb 2): n_sites = n_sub *
+ * lx*ly*lz with site = s + n_sub*(x + lx*(y + ly*z)) for place s of cell
+ * (x, y, z).  Translations move whole cells and keep s, so momentum sectors
+ * are over the lx*ly*lz cell translations (orbit normalisation N_T s_a with
+ * N_T = lx*ly*lz).  Fixed-N_down sectors take every entry point; momentum
+ * sectors take H.v, eigensolvers, dense blocks and full diagonalisation,
+ * while the observables that need site positions (qs3_sz/qs3_sisj on
+ * momentum sectors, qs3_sq, qs3_sq_apply, qs3_smq, qs3_dsf) return QS3_EINVAL
+ * when n_sub > 1.  qs3_lattice_create is this call with n_sub = 1. */
+int qs3_lattice_create_cells(qs3_ctx *ctx, int n_sub, int lx, int ly, int lz, int n_bonds,
+                             const int32_t *bi, const int32_t *bj, const double *jxy,
+                             const double *jz, qs3_lattice **out);
 int qs3_lattice_destroy(qs3_lattice *lat);
 int qs3_lattice_info(const qs3_lattice *lat, int *n_sites, int *translation_invariant);
 

@@ -147,9 +147,10 @@ int get_kstruct(qs3_lattice *lat, int K, std::shared_ptr<KStructure> *out, hipSt
             for (int ty = 0; ty < lat->ly; ++ty)
                 for (int tx = 0; tx < lat->lx; ++tx) {
                     for (int m = 0; m < K; ++m) {
-                        int s0 = c[m], x = s0 % lat->lx, y = (s0 / lat->lx) % lat->ly,
-                            z = s0 / (lat->lx * lat->ly);
-                        img[m] = (x + tx) % lat->lx + lat->lx * (((y + ty) % lat->ly) + lat->ly * ((z + tz) % lat->lz));
+                        const int ns = lat->ns, sub = c[m] % ns, cell = c[m] / ns;
+                        const int x = cell % lat->lx, y = (cell / lat->lx) % lat->ly, z = cell / (lat->lx * lat->ly);
+                        img[m] = sub + ns * ((x + tx) % lat->lx +
+                                             lat->lx * (((y + ty) % lat->ly) + lat->ly * ((z + tz) % lat->lz)));
                     }
                     std::sort(img.begin(), img.begin() + K);
                     if (std::equal(img.begin(), img.begin() + K, c.begin()))
@@ -236,10 +237,17 @@ int qs3_ctx_memory(const qs3_ctx *ctx, uint64_t *used, uint64_t *budget) {
 
 int qs3_lattice_create(qs3_ctx *ctx, int lx, int ly, int lz, int n_bonds, const int32_t *bi,
                        const int32_t *bj, const double *jxy, const double *jz, qs3_lattice **out) {
+    return qs3_lattice_create_cells(ctx, 1, lx, ly, lz, n_bonds, bi, bj, jxy, jz, out);
+}
+
+int qs3_lattice_create_cells(qs3_ctx *ctx, int n_sub, int lx, int ly, int lz, int n_bonds, const int32_t *bi,
+                             const int32_t *bj, const double *jxy, const double *jz, qs3_lattice **out) {
     QS3_REQUIRE(ctx && out, QS3_EINVAL, "NULL argument");
     QS3_REQUIRE(lx >= 1 && ly >= 1 && lz >= 1 && lx < 1024 && ly < 1024 && lz < 1024, QS3_EINVAL,
                 "lattice lengths must be in [1, 1023]");
-    const long N = (long)lx * ly * lz;
+    QS3_REQUIRE(n_sub >= 1 && n_sub <= 4, QS3_EINVAL, "sites per unit cell must be in [1, 4]");
+    const int ns = n_sub;
+    const long N = (long)ns * lx * ly * lz;
     QS3_REQUIRE(N <= MAX_SITES, QS3_EINVAL, "at most 4096 sites");
     QS3_REQUIRE(n_bonds >= 0 && (n_bonds == 0 || (bi && bj && jxy && jz)), QS3_EINVAL, "bad bonds");
     DeviceGuard dg(ctx->device);
@@ -248,6 +256,7 @@ int qs3_lattice_create(qs3_ctx *ctx, int lx, int ly, int lz, int n_bonds, const 
     lat->lx = lx;
     lat->ly = ly;
     lat->lz = lz;
+    lat->ns = ns;
     lat->N = (int)N;
     lat->n_bonds = n_bonds;
     std::vector<std::vector<int>> adj(N);
@@ -301,11 +310,12 @@ int qs3_lattice_create(qs3_ctx *ctx, int lx, int ly, int lz, int n_bonds, const 
         }
         bool inv = true;
         auto tr = [&](int s, int ax) {
-            int x = s % lx, y = (s / lx) % ly, z = s / (lx * ly);
+            const int sub = s % ns, cell = s / ns;
+            int x = cell % lx, y = (cell / lx) % ly, z = cell / (lx * ly);
             if (ax == 0) x = (x + 1) % lx;
             if (ax == 1) y = (y + 1) % ly;
             if (ax == 2) z = (z + 1) % lz;
-            return x + lx * (y + ly * z);
+            return sub + ns * (x + lx * (y + ly * z));
         };
         for (int ax = 0; ax < 3 && inv; ++ax) {
             for (auto &kv : bonds) {
@@ -322,8 +332,9 @@ int qs3_lattice_create(qs3_ctx *ctx, int lx, int ly, int lz, int n_bonds, const 
     }
     std::vector<uint32_t> coords(N);
     for (long s = 0; s < N; ++s) {
-        uint32_t x = s % lx, y = (s / lx) % ly, z = s / (lx * ly);
-        coords[s] = x | (y << 10) | (z << 20);
+        const long cell = s / ns;
+        uint32_t x = cell % lx, y = (cell / lx) % ly, z = cell / (lx * ly), sub = (uint32_t)(s % ns);
+        coords[s] = x | (y << 10) | (z << 20) | (sub << 30);
     }
     std::vector<double> sq(N + 1);
     for (long s = 0; s <= N; ++s) sq[s] = std::sqrt((double)s);

@@ -29,6 +29,7 @@ LatArgs lat_args(const qs3_lattice *lat) {
     L.u_jz_h = lat->u_jz_h;
     L.ez4 = lat->ez4;
     L.coords = lat->d_coords.as<uint32_t>();
+    L.ns = lat->ns;
     L.sqrt_tab = lat->d_sqrt.as<double>();
     return L;
 }

@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
     const uint16_t *nbr;
     load_lds_tables<RT>(smem, A.L, binom_g, K, &tab, &ptr, &nbr);
     Binom<RT> Bn{tab, binom_shift(A.L.N)};
-    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
 
     const int G = A.G, B = A.B;
     const bool UNIF = A.L.uniform != 0;
@@ -423,13 +423,14 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
 template <int K, typename RT>
 __device__ __forceinline__ bool is_orbit_min(const int (&c)[K > 0 ? K : 1], const Geom &g) {
     // early-exit variant of canonicalize(): is c itself the minimum image?
-    int x[K > 0 ? K : 1], y[K > 0 ? K : 1], z[K > 0 ? K : 1];
+    int x[K > 0 ? K : 1], y[K > 0 ? K : 1], z[K > 0 ? K : 1], sb[K > 0 ? K : 1];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
         uint32_t p = g.coords[c[m]];
         x[m] = p & 1023u;
         y[m] = (p >> 10) & 1023u;
         z[m] = (p >> 20) & 1023u;
+        sb[m] = (int)(p >> 30);
     }
     // c must have coordinate 0 occupied on every axis
     bool hx = g.lx == 1, hy = g.ly == 1, hz = g.lz == 1;
@@ -451,8 +452,8 @@ __device__ __forceinline__ bool is_orbit_min(const int (&c)[K > 0 ? K : 1], cons
                 int img[K > 0 ? K : 1];
 #pragma unroll
                 for (int m = 0; m < K; ++m)
-                    img[m] = wrap_add(x[m], tx, g.lx) + g.lx * wrap_add(y[m], ty, g.ly) +
-                             g.lxy * wrap_add(z[m], tz, g.lz);
+                    img[m] = sb[m] + g.ns * (wrap_add(x[m], tx, g.lx) + g.lx * wrap_add(y[m], ty, g.ly) +
+                                             g.lxy * wrap_add(z[m], tz, g.lz));
                 sortK<K>(img);
                 int cmp = 0;
 #pragma unroll
@@ -470,7 +471,7 @@ template <int K, typename RT>
 __global__ __launch_bounds__(256) void k_count_reps(BuildArgs A, const RT *__restrict__ binom_g,
                                                     unsigned long long *counts) {
     Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
-    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
     const uint64_t lo = (uint64_t)blockIdx.x * A.chunk;
     const uint64_t hi = min(A.D, lo + A.chunk);
     unsigned long long cnt = 0;
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(256) void k_write_reps(BuildArgs A, const RT *__res
                                                     const unsigned long long *offsets,
                                                     uint64_t *reps) {
     Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
-    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
     const uint64_t lo = (uint64_t)blockIdx.x * A.chunk;
     const uint64_t hi = min(A.D, lo + A.chunk);
     __shared__ unsigned int wave_cnt[4];
@@ -528,18 +529,19 @@ __global__ __launch_bounds__(256) void k_stab(LatArgs L, const RT *__restrict__ 
                                               uint64_t n_reps, const uint64_t *__restrict__ reps,
                                               uint16_t *stab) {
     Binom<RT> Bn{binom_g, binom_shift(L.N)};
-    Geom g{L.lx, L.ly, L.lz, L.lx * L.ly, L.coords};
+    Geom g{L.lx, L.ly, L.lz, L.lx * L.ly, L.coords, L.ns};
     uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n_reps) return;
     int c[K > 0 ? K : 1];
     unrank<K, RT>((RT)reps[u], L.N, Bn, c);
-    int x[K > 0 ? K : 1], y[K > 0 ? K : 1], z[K > 0 ? K : 1];
+    int x[K > 0 ? K : 1], y[K > 0 ? K : 1], z[K > 0 ? K : 1], sb[K > 0 ? K : 1];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
         uint32_t p = g.coords[c[m]];
         x[m] = p & 1023u;
         y[m] = (p >> 10) & 1023u;
         z[m] = (p >> 20) & 1023u;
+        sb[m] = (int)(p >> 30);
     }
     // every stabiliser element maps the representative onto itself, so it is
     // one of the candidate shifts; count each distinct shift once (first spin
@@ -564,8 +566,8 @@ __global__ __launch_bounds__(256) void k_stab(LatArgs L, const RT *__restrict__ 
                 int img[K > 0 ? K : 1];
 #pragma unroll
                 for (int m = 0; m < K; ++m)
-                    img[m] = wrap_add(x[m], tx, g.lx) + g.lx * wrap_add(y[m], ty, g.ly) +
-                             g.lxy * wrap_add(z[m], tz, g.lz);
+                    img[m] = sb[m] + g.ns * (wrap_add(x[m], tx, g.lx) + g.lx * wrap_add(y[m], ty, g.ly) +
+                                             g.lxy * wrap_add(z[m], tz, g.lz));
                 sortK<K>(img);
                 bool eq = true;
 #pragma unroll
@@ -574,7 +576,7 @@ __global__ __launch_bounds__(256) void k_stab(LatArgs L, const RT *__restrict__ 
             }
         }
     }
-    stab[u] = (uint16_t)(K == 0 ? L.N : count);
+    stab[u] = (uint16_t)(K == 0 ? L.lx * L.ly * L.lz : count);
 }
 
 static __global__ void k_dir(uint64_t n_reps, const uint64_t *__restrict__ reps, int shift, uint64_t nb,
@@ -596,7 +598,7 @@ __global__ __launch_bounds__(256) void k_table(BuildArgs A, const RT *__restrict
                                                const uint32_t *__restrict__ dir, int shift,
                                                uint64_t *table) {
     Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
-    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
     uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= A.D) return;
     int c[K > 0 ? K : 1], best[K > 0 ? K : 1];
@@ -618,7 +620,7 @@ template <int K, typename RT>
 __global__ __launch_bounds__(256) void k_hoplist(BatchArgs A, const RT *__restrict__ binom_g, int hmax,
                                                  uint64_t *__restrict__ hops) {
     Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
-    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
     const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= A.n_reps) return;
     const RT R = (RT)A.reps[u];
@@ -681,7 +683,7 @@ __global__ __launch_bounds__(256) void k_dense_k(BatchArgs A, const RT *__restri
                                                  const int64_t *__restrict__ u2c, uint64_t d,
                                                  double2 *__restrict__ M) {
     Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
-    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
     const uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= A.n_reps) return;
     const int64_t i = u2c[u];
@@ -752,7 +754,7 @@ template <int K, typename RT, bool TABLE>
 __global__ void k_row_k(BatchArgs A, const RT *binom_g, uint64_t u, int cap, int64_t *cols,
                         double *vals, double *diag, int *nnz) {
     Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
-    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
     const RT R = (RT)A.reps[u];
     const int su = A.stab[u];
     int c[K > 0 ? K : 1];
@@ -882,7 +884,7 @@ __global__ __launch_bounds__(1024) void k_lanczos_small(SmallArgs S, BatchArgs A
     const uint16_t *nbr;
     load_lds_tables<RT>(smem, A.L, binom_g, K, &tab, &ptr, &nbr);
     Binom<RT> Bn{tab, binom_shift(A.L.N)};
-    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
     const uint64_t n = S.n;

@@ -168,6 +168,7 @@ int qs3_sz(qs3_sector *sec, const void *vec, double *out, void *stream) {
     double n2 = 0;
     QS3_TRY(vec_norm2(sec, vec, &n2, s));
     QS3_REQUIRE(n2 > 0 && std::isfinite(n2), QS3_ENUMERIC, "zero or non-finite state");
+    QS3_REQUIRE(!sec->has_k || sec->lat->ns == 1, QS3_EINVAL, "momentum-sector observables need one site per unit cell");
     if (sec->has_k) {
         // the translation-averaged s^z_r is (1/N) sum_r s^z_r = M / N in the sector
         for (int i = 0; i < N; ++i) out[i] = (0.5 * N - sec->K) / N;
@@ -187,6 +188,7 @@ int qs3_sisj(qs3_sector *sec, const void *vec, int n_pairs, const int32_t *pi, c
     const int N = sec->lat->N;
     for (int p = 0; p < n_pairs; ++p)
         QS3_REQUIRE(pi[p] >= 0 && pi[p] < N && pj[p] >= 0 && pj[p] < N, QS3_EINVAL, "site out of range");
+    QS3_REQUIRE(!sec->has_k || sec->lat->ns == 1, QS3_EINVAL, "momentum-sector observables need one site per unit cell");
     if (sec->has_k) {
         std::vector<double> Czz;
         std::vector<std::complex<double>> Cpm;
@@ -253,6 +255,7 @@ int qs3_sq(qs3_sector *sec, const void *vec, int n_q, const double *qv, double *
     hipSetDevice(sec->lat->ctx->device);
     hipStream_t s = (hipStream_t)stream;
     qs3_lattice *lat = sec->lat;
+    QS3_REQUIRE(lat->ns == 1, QS3_EINVAL, "S(q) needs one site per unit cell (site positions are cell positions)");
     const int N = lat->N;
     std::vector<double> R(3 * N);
     for (int r = 0; r < N; ++r) {
@@ -323,6 +326,7 @@ int qs3_sq_apply(qs3_sector *from, const void *vec_from, qs3_sector *to, int op,
     QS3_REQUIRE(op == QS3_OP_SMINUS || op == QS3_OP_SPLUS || op == QS3_OP_SZ, QS3_EINVAL,
                 "unknown spin operator");
     QS3_REQUIRE(from->has_k && to->has_k, QS3_EINVAL, "S^a_q acts between momentum sectors");
+    QS3_REQUIRE(from->lat->ns == 1, QS3_EINVAL, "S^a_q needs one site per unit cell");
     QS3_REQUIRE(from->lat == to->lat && to->K == n_down_after(op, from->K), QS3_EINVAL,
                 "target sector must be the same lattice with N_down + 1 (S^-), - 1 (S^+) or + 0 (S^z)");
     qs3_lattice *lat = from->lat;
@@ -358,6 +362,7 @@ int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_
             double *beta, double *weight, void *stream) {
     QS3_REQUIRE(gs && gs_vec && qvecs && opts && n_q > 0 && n_omega >= 0, QS3_EINVAL, "bad argument");
     QS3_REQUIRE(gs->has_k, QS3_EINVAL, "the ground state must be a momentum-sector vector");
+    QS3_REQUIRE(gs->lat->ns == 1, QS3_EINVAL, "S(q, omega) needs one site per unit cell");
     const int op = opts->op;
     QS3_REQUIRE(op == QS3_OP_SMINUS || op == QS3_OP_SPLUS || op == QS3_OP_SZ, QS3_EINVAL,
                 "unknown spin operator");

@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k_corr_k(BatchArgs A, const RT *__restric
                                                 const double2 *__restrict__ phi,
                                                 double2 *__restrict__ partial) {
     Binom<RT> Bn{binom_g, binom_shift(A.L.N)};
-    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
     const int dd = blockIdx.x;
     const int dp = disp[dd];
     const int dx = dp & 1023, dy = (dp >> 10) & 1023, dz = (dp >> 20) & 1023;
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void k_smq(SmqArgs S, const RTa *__restrict__ 
     const BatchArgs &D = S.dst;
     Binom<RTa> Ba{binom_a, binom_shift(A.L.N)};
     Binom<RTb> Bb{binom_b, binom_shift(A.L.N)};
-    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
     const int G = D.G, B = D.B;
     const int lane = threadIdx.x % G, slot = threadIdx.x / G;
     const int rows_per = blockDim.x / G;
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(256) void k_spq(SmqArgs S, const RTa *__restrict__ 
     const BatchArgs &D = S.dst;
     Binom<RTa> Ba{binom_a, binom_shift(A.L.N)};
     Binom<RTb> Bb{binom_b, binom_shift(A.L.N)};
-    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
     const int G = D.G, B = D.B;
     const int lane = threadIdx.x % G, slot = threadIdx.x / G;
     const int rows_per = blockDim.x / G;

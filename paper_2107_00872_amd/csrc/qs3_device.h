@@ -131,10 +131,13 @@ struct HopRanker {
 };
 
 // ---------------------------------------------------------------------------
-// Lattice geometry for translations.  coords[s] packs (x | y<<10 | z<<20).
+// Lattice geometry for translations.  coords[i] packs the cell coordinates
+// and the place in the cell of site i = s + ns * (x + lx * (y + ly * z)):
+// x | y<<10 | z<<20 | s<<30.  Translations move cells and keep s.
 struct Geom {
     int lx, ly, lz, lxy;
     const uint32_t *coords;
+    int ns;
 };
 
 __host__ __device__ __forceinline__ int wrap_add(int a, int b, int L) {
@@ -159,21 +162,23 @@ __host__ __device__ __forceinline__ void sortK(int (&a)[K > 0 ? K : 1]) {
 // The representative of the orbit of the sorted tuple c (Sec. 3.3: the minimum
 // rank over all translations) and a translation t with T^t c = rep.  The rank
 // order is colex, i.e. tuples compare from their largest element down, and an
-// image of minimum rank has coordinate 0 occupied along every axis (otherwise
-// shifting that axis by -1 lowers every index), so only the shifts that move
+// image of minimum rank has cell coordinate 0 occupied along every axis
+// (otherwise shifting that axis by -1 lowers every index by ns), so only the
+// shifts that move
 // some down spin to coordinate 0 on each axis are candidates: K^D images
 // instead of the N of Alg. 7.
 template <int K>
 __host__ __device__ __forceinline__ void canonicalize(const int (&c)[K > 0 ? K : 1], const Geom &g,
                                              int (&best)[K > 0 ? K : 1], int &btx, int &bty,
                                              int &btz) {
-    int x[K > 0 ? K : 1], y[K > 0 ? K : 1], z[K > 0 ? K : 1];
+    int x[K > 0 ? K : 1], y[K > 0 ? K : 1], z[K > 0 ? K : 1], sb[K > 0 ? K : 1];
 #pragma unroll
     for (int m = 0; m < K; ++m) {
         uint32_t p = g.coords[c[m]];
         x[m] = p & 1023u;
         y[m] = (p >> 10) & 1023u;
         z[m] = (p >> 20) & 1023u;
+        sb[m] = (int)(p >> 30);
         best[m] = c[m];
     }
     btx = bty = btz = 0;
@@ -187,8 +192,8 @@ __host__ __device__ __forceinline__ void canonicalize(const int (&c)[K > 0 ? K :
                 int img[K > 0 ? K : 1];
 #pragma unroll
                 for (int m = 0; m < K; ++m)
-                    img[m] = wrap_add(x[m], tx, g.lx) + g.lx * wrap_add(y[m], ty, g.ly) +
-                             g.lxy * wrap_add(z[m], tz, g.lz);
+                    img[m] = sb[m] + g.ns * (wrap_add(x[m], tx, g.lx) + g.lx * wrap_add(y[m], ty, g.ly) +
+                                             g.lxy * wrap_add(z[m], tz, g.lz));
                 sortK<K>(img);
                 // colex comparison from the top
                 int cmp = 0;

@@ -122,6 +122,7 @@ struct KStructure {
 struct qs3_lattice {
     qs3_ctx *ctx = nullptr;
     int lx = 1, ly = 1, lz = 1, N = 0;
+    int ns = 1;  // sites per unit cell: site = s + ns * (x + lx * (y + ly * z))
     int n_bonds = 0;
     std::vector<int> bi, bj;
     std::vector<double> jxy, jz;
@@ -149,6 +150,7 @@ int get_kstruct(qs3_lattice *lat, int K, std::shared_ptr<KStructure> *out, hipSt
 // Device view of a lattice handed to kernels by value.
 struct LatArgs {
     int N, lx, ly, lz;
+    int ns;  // sites per unit cell (translations act on cells)
     const int *ptr;
     const uint16_t *nbr;
     const double *jxy_h, *jz_h;

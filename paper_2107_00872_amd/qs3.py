@@ -70,6 +70,8 @@ SIGNATURES = [
     ("qs3_ctx_memory", ctypes.c_int, [P, P, P]),
     ("qs3_ctx_set_structure_limits", ctypes.c_int, [P, u64, u64]),
     ("qs3_lattice_create", ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P]),
+    ("qs3_lattice_create_cells", ctypes.c_int,
+     [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P]),
     ("qs3_lattice_destroy", ctypes.c_int, [P]),
     ("qs3_lattice_info", ctypes.c_int, [P, P, P]),
     ("qs3_sector_create", ctypes.c_int, [P, ctypes.c_int, P, P]),
@@ -184,23 +186,24 @@ class Context:
 
 
 class Lattice:
-    def __init__(self, ctx: Context, lx, ly, lz, bi, bj, jxy, jz):
+    def __init__(self, ctx: Context, lx, ly, lz, bi, bj, jxy, jz, ns: int = 1):
         self.ctx = ctx
         self.dims = (int(lx), int(ly), int(lz))
+        self.ns = int(ns)
         self._bi = np.ascontiguousarray(bi, dtype=np.int32)
         self._bj = np.ascontiguousarray(bj, dtype=np.int32)
         self._jxy = np.ascontiguousarray(jxy, dtype=np.float64)
         self._jz = np.ascontiguousarray(jz, dtype=np.float64)
         h = ctypes.c_void_p()
-        check(lib().qs3_lattice_create(ctx.h, self.dims[0], self.dims[1], self.dims[2], len(self._bi),
-                                       _ptr(self._bi), _ptr(self._bj), _ptr(self._jxy), _ptr(self._jz),
-                                       ctypes.byref(h)))
+        check(lib().qs3_lattice_create_cells(ctx.h, self.ns, self.dims[0], self.dims[1], self.dims[2],
+                                             len(self._bi), _ptr(self._bi), _ptr(self._bj), _ptr(self._jxy),
+                                             _ptr(self._jz), ctypes.byref(h)))
         self.h = h
 
     @classmethod
     def of(cls, ctx: Context, lat):
         """From a workloads.Lattice."""
-        return cls(ctx, lat.lx, lat.ly, lat.lz, lat.bi, lat.bj, lat.jxy, lat.jz)
+        return cls(ctx, lat.lx, lat.ly, lat.lz, lat.bi, lat.bj, lat.jxy, lat.jz, getattr(lat, "ns", 1))
 
     def info(self):
         n, ti = ctypes.c_int(), ctypes.c_int()

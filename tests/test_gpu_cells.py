@@ -1,0 +1,146 @@
+"""Momentum sectors on lattices with several sites per unit cell (kagome,
+honeycomb): translations act on the cells.  Representatives and stabilisers
+bit-exact against the oracle's Alg. 5/6 over the cell translations, H.v and
+the dense block against the oracle's Alg. 8 block, the batched launch over
+all momenta, eigensolvers against dense diagonalisation, and the entry points
+that need one site per cell refuse."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.hamiltonian import bonds_1based
+from oracle.lanczos import lowest_distinct
+from oracle.translation import Geometry, gen_full_ham_sym_adapt, mk_list
+from tolerances import hv_tol
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CELLS = [(wl.kagome(2, 2), 3), (wl.kagome(2, 2), 4), (wl.honeycomb(3, 2), 3), (wl.kagome(3, 3), 2),
+         (wl.honeycomb(2, 2), 0), (wl.with_disorder(wl.kagome(2, 3), seed=6, per_bond=False), 3)]
+
+
+@pytest.fixture(scope="module")
+def qs3():
+    from paper_2107_00872_amd import qs3 as q
+    assert torch.cuda.is_available()
+    return q
+
+
+def _contexts(qs3):
+    c_tab = qs3.Context(0)
+    c_tab.set_structure_limits(1 << 34, 0)
+    c_hops = qs3.Context(0)
+    c_hops.set_structure_limits(0, 1 << 34)
+    c_fly = qs3.Context(0)
+    c_fly.set_structure_limits(0, 0)
+    return {"table": c_tab, "hops": c_hops, "fly": c_fly}
+
+
+_REF = {}
+
+
+def _oracle(lat, K):
+    key = (lat.name, K)
+    if key not in _REF:
+        geo = Geometry(lat.lx, lat.ly, lat.lz, lat.ns)
+        bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+        out = {}
+        for Kv in wl.all_momenta(lat):
+            s, R = mk_list(geo, K, Kv)
+            H = gen_full_ham_sym_adapt(geo, K, bonds, s, R, Kv) if s else None
+            out[Kv] = (np.array(s, dtype=np.int64), np.array(R), H)
+        _REF[key] = (geo, out)
+    return _REF[key]
+
+
+@pytest.mark.parametrize("mode", ["table", "hops", "fly"])
+@pytest.mark.parametrize("lat,K", CELLS, ids=lambda x: getattr(x, "name", str(x)))
+def test_cells_basis_matvec_dense(qs3, lat, K, mode):
+    ctx = _contexts(qs3)[mode]
+    L = qs3.Lattice.of(ctx, lat)
+    assert L.info() == (lat.n_sites, True)
+    geo, ref = _oracle(lat, K)
+    scale = max(1.0, float(np.abs(lat.jxy).max()), float(np.abs(lat.jz).max()))
+    for Kv, (sigma, R, Hk) in ref.items():
+        if len(sigma) == 0:
+            continue
+        sec = qs3.Sector(L, K, Kv)
+        assert sec.dim == len(sigma)
+        ranks, stab = sec.basis()
+        assert np.array_equal(ranks, sigma - 1)
+        assert np.allclose(R * R, geo.NT * stab.astype(float), rtol=0, atol=1e-9)
+        v = torch.empty(sec.dim, dtype=torch.complex128, device="cuda")
+        sec.start_vector(3, v)
+        w = torch.empty_like(v)
+        sec.matvec(v, w)
+        vh = v.cpu().numpy()
+        assert np.abs(w.cpu().numpy() - Hk @ vh).max() <= hv_tol(lat, np.abs(vh).max() * 1.5)
+        D = sec.dense().cpu().numpy().T  # column major
+        assert np.abs(D - Hk).max() <= 1e-13 * scale * 8
+        sec.close()
+    L.close()
+
+
+@pytest.mark.parametrize("lat,K", CELLS[:4], ids=lambda x: getattr(x, "name", str(x)))
+def test_cells_batch_and_eigs(qs3, lat, K):
+    """All momenta in one batched launch equal the single sectors; lowest two
+    distinct levels per sector (batched thick restart) and the sector spectra
+    (full diagonalisation) against the oracle's blocks."""
+    ctx = qs3.Context(0)
+    L = qs3.Lattice.of(ctx, lat)
+    geo, ref = _oracle(lat, K)
+    ks = wl.all_momenta(lat)
+    bat = qs3.Batch(L, K, ks)
+    rng = np.random.default_rng(4)
+    vh = rng.normal(size=(bat.rows, bat.B)) + 1j * rng.normal(size=(bat.rows, bat.B))
+    v = torch.from_numpy(vh).cuda()
+    w = torch.empty_like(v)
+    bat.matvec(v, w)
+    wh = w.cpu().numpy()
+    sec0 = qs3.Sector(L, K, (0, 0, 0))
+    uni, _ = sec0.basis()
+    sec0.close()
+    for b, Kv in enumerate(ks):
+        sigma, R, Hk = ref[Kv]
+        assert bat.dims[b] == len(sigma)
+        if len(sigma) == 0:
+            continue
+        pos = np.searchsorted(uni, sigma - 1)
+        assert np.array_equal(uni[pos], sigma - 1)
+        assert np.abs(wh[pos, b] - Hk @ vh[pos, b]).max() <= hv_tol(lat, np.abs(vh).max() * 1.5)
+    ev, infos, rc = bat.eigs(nev=2, seed=5)
+    assert rc == qs3.QS3_OK
+    for b, Kv in enumerate(ks):
+        sigma, R, Hk = ref[Kv]
+        if len(sigma) == 0:
+            continue
+        full = np.linalg.eigvalsh(Hk)
+        want = lowest_distinct(full, 2)
+        got = ev[b, :len(want)]
+        assert np.allclose(got, want, rtol=1e-10, atol=1e-10), (Kv, got, want)
+        sec = qs3.Sector(L, K, Kv)
+        assert np.abs(sec.full_diag() - full).max() < 1e-11 * max(1.0, np.abs(full).max())
+        sec.close()
+    bat.close()
+
+
+def test_cells_refuse_position_observables(qs3):
+    ctx = qs3.Context(0)
+    lat = wl.kagome(2, 2)
+    L = qs3.Lattice.of(ctx, lat)
+    sec = qs3.Sector(L, 2, (1, 0, 0))
+    v = torch.empty(sec.dim, dtype=torch.complex128, device="cuda")
+    sec.start_vector(1, v)
+    for call in (lambda: sec.sz(v), lambda: sec.sisj(v, [0], [1]),
+                 lambda: sec.sq(v, [[0.0, 0.0, 0.0]])):
+        with pytest.raises(qs3.QS3Error) as e:
+            call()
+        assert e.value.code == qs3.QS3_EINVAL
+    # the fixed-N_down sector of the same lattice takes every observable but S(q)
+    u1 = qs3.Sector(L, 2)
+    x = torch.empty(u1.dim, dtype=torch.float64, device="cuda")
+    u1.eigs(nev=1, evecs=x, seed=1)
+    assert u1.sz(x).sum() == pytest.approx(lat.n_sites / 2 - 2, abs=1e-12)
+    with pytest.raises(qs3.QS3Error):
+        u1.sq(x, [[0.0, 0.0, 0.0]])
