@@ -139,6 +139,76 @@ def c3(args):
     return out
 
 
+def cells(args):
+    """Several sites per unit cell: the 12 x 12 kagome lattice (432 sites,
+    J = Delta = 1) at N_down = 3, all 144 momenta in one batch (about 92k
+    representatives each): batched H.v rate, batched float64 ground states,
+    a sample one sector at a time, and the cross-check min_k E_0(k) = E_0 of
+    the fixed-N_down sector (dim C(432, 3))."""
+    ctx = _ctx()
+    lat = wl.kagome(12, 12)
+    L = qs3.Lattice.of(ctx, lat)
+    ks = wl.all_momenta(lat)
+    K = 3
+    NT = lat.lx * lat.ly * lat.lz
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    bat = qs3.Batch(L, K, ks)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    v = torch.zeros(bat.rows, bat.B, dtype=torch.complex128, device="cuda")
+    v.real.uniform_(-1, 1)
+    w = torch.empty_like(v)
+    bat.matvec(v, w, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        bat.matvec(v, w, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    t_mv = e0.elapsed_time(e1) / 10e3
+    # off-diagonal entries per row: the mean over the sector's states,
+    # N_b 2K(N-K) / (N(N-1)); per row and sector 16 B for each gathered
+    # entry, the row's own v and its w
+    N = lat.n_sites
+    nhops_row = lat.n_bonds * 2 * K * (N - K) / (N * (N - 1))
+    alg_bytes = 16.0 * (2 + nhops_row) * bat.rows * bat.B
+    del v, w
+    torch.cuda.empty_cache()
+    out = {"metric": "batched E(k), kagome 12x12 N_down=3, 144 momenta", "workload": "cells",
+           "sites": lat.n_sites, "rows": bat.rows, "sectors": bat.B, "setup_s": t_setup,
+           "matvec_ms": t_mv * 1e3, "matvec_sector_rows_per_s": bat.rows * bat.B / t_mv,
+           "matvec_alg_GBs": alg_bytes / t_mv / 1e9, "hops_per_row": nhops_row}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev, infos, rc = bat.eigs(nev=1, seed=1, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    mv = np.array([i.n_matvec for i in infos])
+    out["f64"] = {"seconds": dt, "solves_per_s": bat.B / dt, "matvecs_max": int(mv.max()),
+                  "matvecs_p50": float(np.median(mv)), "converged": int(sum(i.converged for i in infos)),
+                  "rc": rc, "E_min": float(ev[:, 0].min())}
+    sample = sorted(np.random.default_rng(7).choice(len(ks), 10, replace=False).tolist())
+    secs = [qs3.Sector(L, K, ks[b]) for b in sample]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev_s = [secs[i].eigs(nev=1, seed=1 + b, stream=stream) for i, b in enumerate(sample)]
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    for sc in secs:
+        sc.close()
+    e_s = np.array([r.evals[0] for r in ev_s])
+    out["f64_one_at_a_time"] = {"seconds": t_s, "solves_per_s": len(sample) / t_s,
+                                "max_rel_diff_vs_batched": float(np.max(np.abs(e_s - ev[sample, 0]) / np.abs(e_s)))}
+    full = qs3.Sector(L, K)
+    r = full.eigs(nev=1, seed=1, stream=stream)
+    out["E0_fixed_N_down"] = float(r.evals[0])
+    out["min_k_E0_minus_E0"] = float(ev[:, 0].min() - r.evals[0])
+    out["value"] = out["f64"]["solves_per_s"]
+    out["unit"] = "sector solves/s (float64)"
+    return out
+
+
 def c4(args):
     ctx = _ctx()
     lat = wl.square(10)
