@@ -199,3 +199,32 @@ def test_check_state_compatibility():
     assert check_state(geo, a, 2, (2, 0, 0)) == pytest.approx(12.0)
     assert check_state(geo, a, 2, (1, 0, 0)) == 0.0
     assert check_state(geo, F((1, 2)), 2, (1, 0, 0)) == pytest.approx(6.0)
+
+
+@pytest.mark.parametrize("make,ns,deg", [(lambda: wl.kagome(3, 4), 3, 4), (lambda: wl.honeycomb(4, 3), 2, 3),
+                                         (lambda: wl.kagome(2, 2), 3, 4)])
+def test_cell_lattices(make, ns, deg):
+    """The unit-cell workloads: sites = ns * cells, every site has the
+    lattice's coordination, each bond appears once, and the bond set is mapped
+    onto itself by a translation of the cells (sublattice kept)."""
+    lat = make()
+    assert lat.ns == ns and lat.n_sites == ns * lat.lx * lat.ly
+    d = np.zeros(lat.n_sites, int)
+    seen = set()
+    for i, j in zip(lat.bi, lat.bj):
+        key = (min(i, j), max(i, j))
+        assert key not in seen and i != j
+        seen.add(key)
+        d[i] += 1
+        d[j] += 1
+    assert np.all(d == deg)
+    assert lat.n_bonds == lat.n_sites * deg // 2
+
+    def tr(i, ax):
+        s, c = i % ns, i // ns
+        x, y = c % lat.lx, c // lat.lx
+        x, y = ((x + 1) % lat.lx, y) if ax == 0 else (x, (y + 1) % lat.ly)
+        return s + ns * (x + lat.lx * y)
+    for ax in (0, 1):
+        moved = {(min(tr(i, ax), tr(j, ax)), max(tr(i, ax), tr(j, ax))) for i, j in seen}
+        assert moved == seen
