@@ -107,14 +107,18 @@ int qs3_lattice_create(qs3_ctx *ctx, int lx, int ly, int lz, int n_bonds, const 
  * lx*ly*lz with site = s + n_sub*(x + lx*(y + ly*z)) for place s of cell
  * (x, y, z).  Translations move whole cells and keep s, so momentum sectors
  * are over the lx*ly*lz cell translations (orbit normalisation N_T s_a with
- * N_T = lx*ly*lz).  Fixed-N_down sectors take every entry point; momentum
- * sectors take H.v, eigensolvers, dense blocks and full diagonalisation,
- * while the observables that need site positions (qs3_sz/qs3_sisj on
- * momentum sectors, qs3_sq, qs3_sq_apply, qs3_smq, qs3_dsf) return QS3_EINVAL
- * when n_sub > 1.  qs3_lattice_create is this call with n_sub = 1. */
+ * N_T = lx*ly*lz).  Every entry point takes such lattices except
+ * qs3_sq_apply, qs3_smq and qs3_dsf, which return QS3_EINVAL when n_sub > 1;
+ * momentum-sector correlations are averaged over cell translations per pair
+ * of places.  qs3_lattice_create is this call with n_sub = 1. */
 int qs3_lattice_create_cells(qs3_ctx *ctx, int n_sub, int lx, int ly, int lz, int n_bonds,
                              const int32_t *bi, const int32_t *bj, const double *jxy,
                              const double *jz, qs3_lattice **out);
+/* Positions of the n_sub places within a cell, in units of the cell vectors
+ * (offsets: host, n_sub x 3, copied; default all 0).  Site s + n_sub*(x +
+ * lx*(y + ly*z)) sits at (x, y, z) + offsets[s]; qs3_sq uses these positions
+ * in e^{-i q.R}. */
+int qs3_lattice_set_basis(qs3_lattice *lat, const double *offsets);
 int qs3_lattice_destroy(qs3_lattice *lat);
 int qs3_lattice_info(const qs3_lattice *lat, int *n_sites, int *translation_invariant);
 
@@ -242,14 +246,18 @@ int qs3_thermal(uint64_t n, const double *E, const double *Sz, double h, int n_b
  * operator gives M/N on every site. */
 int qs3_sz(qs3_sector *sec, const void *vec, double *out, void *stream);
 /* <s^z_i s^z_j> and <s^+_i s^-_j> for n_pairs host pairs (i[p], j[p]); in a
- * momentum sector the translation average (1/N) sum_t of the pair moved by t
- * (Sec. 3.6).  pm is complex (re, im interleaved, 2*n_pairs doubles).  i == j
+ * momentum sector the translation average (1/N_T) sum_t of the pair moved by
+ * the cell translation t (Sec. 3.6).  pm is complex (re, im interleaved, 2*n_pairs doubles).  i == j
  * gives 1/4 and 1/2 + <s^z_i>. */
 int qs3_sisj(qs3_sector *sec, const void *vec, int n_pairs, const int32_t *i, const int32_t *j,
              double *zz, double *pm, void *stream);
 /* Static structure factors at n_q momenta q (host, 3 doubles each):
  * S^zz(q), S^{+-}(q) = <(S^-_q)^+ S^-_q> and S(q) = <S_{-q}.S_q> with
- * S^a_q = N^{-1/2} sum_r e^{-i q.R_r} s^a_r, R_r the site coordinates. */
+ * S^a_q = N^{-1/2} sum_r e^{-i q.R_r} s^a_r, R_r the site position (cell
+ * coordinates plus the place's offset, qs3_lattice_set_basis).  In a
+ * momentum sector the sum runs over the translation-averaged correlations
+ * with displacements taken within one period, which equals the definition for
+ * q on the lattice's momentum grid 2 pi (Kx/lx, Ky/ly, Kz/lz). */
 int qs3_sq(qs3_sector *sec, const void *vec, int n_q, const double *q, double *szz,
            double *spm, double *stot, void *stream);
 /* psi' = S^-_q phi (Sec. 3.8, Alg. 11) from `from` (N_down = K, momentum k)

@@ -257,6 +257,7 @@ int qs3_lattice_create_cells(qs3_ctx *ctx, int n_sub, int lx, int ly, int lz, in
     lat->ly = ly;
     lat->lz = lz;
     lat->ns = ns;
+    lat->basis.assign(3 * (size_t)ns, 0.0);
     lat->N = (int)N;
     lat->n_bonds = n_bonds;
     std::vector<std::vector<int>> adj(N);
@@ -367,6 +368,13 @@ int qs3_lattice_destroy(qs3_lattice *lat) {
         DeviceGuard dg(lat->ctx->device);
         delete lat;
     }
+    return QS3_OK;
+}
+
+int qs3_lattice_set_basis(qs3_lattice *lat, const double *offsets) {
+    QS3_REQUIRE(lat && offsets, QS3_EINVAL, "NULL argument");
+    for (int i = 0; i < 3 * lat->ns; ++i) QS3_REQUIRE(std::isfinite(offsets[i]), QS3_EINVAL, "non-finite offset");
+    lat->basis.assign(offsets, offsets + 3 * lat->ns);
     return QS3_OK;
 }
 

@@ -106,52 +106,75 @@ static int vec_norm2(qs3_sector *sec, const void *vec, double *out, hipStream_t 
 // Translation-averaged correlations of a momentum-sector state for every
 // displacement d: Czz[d] = (1/N) <sum_r s^z_r s^z_{r+d}>,
 // Cpm[d] = (1/N) <sum_r s^+_r s^-_{r+d}> (Sec. 3.6).
+// Translation-averaged correlations of a momentum-sector vector for every
+// pair class (place s of a cell, place t of the cell d further on), index
+// (s * ns + t) * N_T + d:
+//   Czz = <s^z_(r,s) s^z_(r+d,t)>, Cpm = <s^+_(r,s) s^-_(r+d,t)>,
+// and rho[s] = <number of down spins at place s> / N_T.
 static int k_correlations(qs3_sector *sec, const void *vec, std::vector<double> &Czz,
-                          std::vector<std::complex<double>> &Cpm, hipStream_t s) {
+                          std::vector<std::complex<double>> &Cpm, std::vector<double> &rho, hipStream_t s) {
     qs3_lattice *lat = sec->lat;
-    const int N = lat->N;
+    const int ns = lat->ns, NT = lat->lx * lat->ly * lat->lz, nc = ns * ns * NT;
     DevBuf un, dd;
     QS3_TRY(un.alloc(lat->ctx, sizeof(double) * 2 * std::max<uint64_t>(sec->bat->ks->n_reps, 1)));
     QS3_TRY(scatter_compact(sec, (const double *)vec, un.as<double>(), s));
-    std::vector<int32_t> disp(N);
-    for (int d = 0; d < N; ++d) {
-        int x = d % lat->lx, y = (d / lat->lx) % lat->ly, z = d / (lat->lx * lat->ly);
-        disp[d] = x | (y << 10) | (z << 20);
-    }
-    QS3_TRY(dd.alloc(lat->ctx, sizeof(int32_t) * N));
-    QS3_HIP(hipMemcpyAsync(dd.ptr, disp.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
+    std::vector<int32_t> disp(nc);
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b)
+            for (int d = 0; d < NT; ++d) disp[((size_t)a * ns + b) * NT + d] = d | (a << 24) | (b << 28);
+    QS3_TRY(dd.alloc(lat->ctx, sizeof(int32_t) * nc));
+    QS3_HIP(hipMemcpyAsync(dd.ptr, disp.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
     std::vector<double> zz, nr, pr, pim;
-    QS3_TRY(corr_k(sec, un.as<double>(), N, dd.as<int32_t>(), zz, nr, pr, pim, s));
+    QS3_TRY(corr_k(sec, un.as<double>(), nc, dd.as<int32_t>(), zz, nr, pr, pim, s));
     const double n2 = nr[0];
     QS3_REQUIRE(n2 > 0 && std::isfinite(n2), QS3_ENUMERIC, "zero or non-finite state");
-    const int K = sec->K;
-    Czz.assign(N, 0.0);
-    Cpm.assign(N, 0.0);
-    for (int d = 0; d < N; ++d) {
-        if (d == 0) {
-            Czz[d] = 0.25;
-            Cpm[d] = 0.5 + (0.5 * N - K) / N;  // s^+_r s^-_r = 1/2 + s^z_r
-        } else {
-            Czz[d] = (0.25 * N - K + zz[d] / n2) / N;
-            Cpm[d] = std::complex<double>(pr[d], pim[d]) / (n2 * N);
-        }
-    }
+    // a down spin is its own partner in the class (s, s, 0): those sums count the spins
+    rho.assign(ns, 0.0);
+    for (int a = 0; a < ns; ++a) rho[a] = zz[((size_t)a * ns + a) * NT] / (n2 * NT);
+    Czz.assign(nc, 0.0);
+    Cpm.assign(nc, 0.0);
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b)
+            for (int d = 0; d < NT; ++d) {
+                const size_t i = ((size_t)a * ns + b) * NT + d;
+                if (a == b && d == 0) {
+                    Czz[i] = 0.25;
+                    Cpm[i] = 1.0 - rho[a];  // s^+_r s^-_r = 1/2 + s^z_r
+                } else {
+                    Czz[i] = 0.25 - 0.5 * (rho[a] + rho[b]) + zz[i] / (n2 * NT);
+                    Cpm[i] = std::complex<double>(pr[i], pim[i]) / (n2 * NT);
+                }
+            }
     return QS3_OK;
 }
 
-static void coords_of(const qs3_lattice *lat, int s, int &x, int &y, int &z) {
-    x = s % lat->lx;
-    y = (s / lat->lx) % lat->ly;
-    z = s / (lat->lx * lat->ly);
+// cell coordinates and place of site i
+static void cell_of(const qs3_lattice *lat, int i, int &x, int &y, int &z, int &p) {
+    p = i % lat->ns;
+    const int c = i / lat->ns;
+    x = c % lat->lx;
+    y = (c / lat->lx) % lat->ly;
+    z = c / (lat->lx * lat->ly);
 }
 
-static int disp_index(const qs3_lattice *lat, int i, int j) {
-    int xi, yi, zi, xj, yj, zj;
-    coords_of(lat, i, xi, yi, zi);
-    coords_of(lat, j, xj, yj, zj);
-    int dx = (xj - xi + lat->lx) % lat->lx, dy = (yj - yi + lat->ly) % lat->ly,
-        dz = (zj - zi + lat->lz) % lat->lz;
-    return dx + lat->lx * (dy + lat->ly * dz);
+// pair class index (see k_correlations) of the sites (i, j)
+static size_t pair_class(const qs3_lattice *lat, int i, int j) {
+    int xi, yi, zi, pi, xj, yj, zj, pj;
+    cell_of(lat, i, xi, yi, zi, pi);
+    cell_of(lat, j, xj, yj, zj, pj);
+    const int dx = (xj - xi + lat->lx) % lat->lx, dy = (yj - yi + lat->ly) % lat->ly,
+              dz = (zj - zi + lat->lz) % lat->lz;
+    const size_t NT = (size_t)lat->lx * lat->ly * lat->lz;
+    return ((size_t)pi * lat->ns + pj) * NT + dx + (size_t)lat->lx * (dy + (size_t)lat->ly * dz);
+}
+
+// position of site i: its cell's coordinates plus its place's offset
+static void position_of(const qs3_lattice *lat, int i, double *R) {
+    int x, y, z, p;
+    cell_of(lat, i, x, y, z, p);
+    R[0] = x + lat->basis[3 * p];
+    R[1] = y + lat->basis[3 * p + 1];
+    R[2] = z + lat->basis[3 * p + 2];
 }
 
 }  // namespace qs3
@@ -168,10 +191,17 @@ int qs3_sz(qs3_sector *sec, const void *vec, double *out, void *stream) {
     double n2 = 0;
     QS3_TRY(vec_norm2(sec, vec, &n2, s));
     QS3_REQUIRE(n2 > 0 && std::isfinite(n2), QS3_ENUMERIC, "zero or non-finite state");
-    QS3_REQUIRE(!sec->has_k || sec->lat->ns == 1, QS3_EINVAL, "momentum-sector observables need one site per unit cell");
     if (sec->has_k) {
-        // the translation-averaged s^z_r is (1/N) sum_r s^z_r = M / N in the sector
-        for (int i = 0; i < N; ++i) out[i] = (0.5 * N - sec->K) / N;
+        if (sec->lat->ns == 1) {
+            // the translation-averaged s^z_r is (1/N) sum_r s^z_r = M / N in the sector
+            for (int i = 0; i < N; ++i) out[i] = (0.5 * N - sec->K) / N;
+            return QS3_OK;
+        }
+        // several places per cell: 1/2 - (down spins at the site's place) / N_T
+        std::vector<double> Czz, rho;
+        std::vector<std::complex<double>> Cpm;
+        QS3_TRY(k_correlations(sec, vec, Czz, Cpm, rho, s));
+        for (int i = 0; i < N; ++i) out[i] = 0.5 - rho[i % sec->lat->ns];
         return QS3_OK;
     }
     std::vector<double> p, q, pm;
@@ -188,13 +218,12 @@ int qs3_sisj(qs3_sector *sec, const void *vec, int n_pairs, const int32_t *pi, c
     const int N = sec->lat->N;
     for (int p = 0; p < n_pairs; ++p)
         QS3_REQUIRE(pi[p] >= 0 && pi[p] < N && pj[p] >= 0 && pj[p] < N, QS3_EINVAL, "site out of range");
-    QS3_REQUIRE(!sec->has_k || sec->lat->ns == 1, QS3_EINVAL, "momentum-sector observables need one site per unit cell");
     if (sec->has_k) {
-        std::vector<double> Czz;
+        std::vector<double> Czz, rho;
         std::vector<std::complex<double>> Cpm;
-        QS3_TRY(k_correlations(sec, vec, Czz, Cpm, s));
+        QS3_TRY(k_correlations(sec, vec, Czz, Cpm, rho, s));
         for (int p = 0; p < n_pairs; ++p) {
-            int d = disp_index(sec->lat, pi[p], pj[p]);
+            const size_t d = pair_class(sec->lat, pi[p], pj[p]);
             zz[p] = Czz[d];
             pm[2 * p] = Cpm[d].real();
             pm[2 * p + 1] = Cpm[d].imag();
@@ -255,37 +284,37 @@ int qs3_sq(qs3_sector *sec, const void *vec, int n_q, const double *qv, double *
     hipSetDevice(sec->lat->ctx->device);
     hipStream_t s = (hipStream_t)stream;
     qs3_lattice *lat = sec->lat;
-    QS3_REQUIRE(lat->ns == 1, QS3_EINVAL, "S(q) needs one site per unit cell (site positions are cell positions)");
     const int N = lat->N;
     std::vector<double> R(3 * N);
-    for (int r = 0; r < N; ++r) {
-        int x, y, z;
-        coords_of(lat, r, x, y, z);
-        R[3 * r] = x;
-        R[3 * r + 1] = y;
-        R[3 * r + 2] = z;
-    }
+    for (int r = 0; r < N; ++r) position_of(lat, r, &R[3 * r]);
     if (sec->has_k) {
-        // S(q) = sum_d e^{-i q.d} C(d) with the translation-averaged C
-        std::vector<double> Czz;
+        // S(q) = (1/ns) sum over pair classes (s, t, d) of e^{-i q.(R_(d,t) - R_(0,s))} C(s, t, d)
+        // with the translation-averaged C
+        std::vector<double> Czz, rho;
         std::vector<std::complex<double>> Cpm;
-        QS3_TRY(k_correlations(sec, vec, Czz, Cpm, s));
-        const double szv = (0.5 * N - sec->K) / N;
+        QS3_TRY(k_correlations(sec, vec, Czz, Cpm, rho, s));
+        const int ns = lat->ns, NT = lat->lx * lat->ly * lat->lz;
         for (int k = 0; k < n_q; ++k) {
             std::complex<double> a = 0, b = 0, c = 0;
-            for (int d = 0; d < N; ++d) {
-                const double ph = qv[3 * k] * R[3 * d] + qv[3 * k + 1] * R[3 * d + 1] + qv[3 * k + 2] * R[3 * d + 2];
-                const std::complex<double> e(std::cos(ph), -std::sin(ph));
-                a += e * Czz[d];
-                b += e * Cpm[d];
-                // <s^-_r s^+_{r+d}> = <s^+_{r+d} s^-_r> = conj? -> C^{-+}(d) = Cpm(-d) for d != 0
-                const int md = (d == 0) ? 0 : disp_index(lat, d, 0);
-                const std::complex<double> cmp = (d == 0) ? std::complex<double>(0.5 - szv) : Cpm[md];
-                c += e * cmp;
-            }
-            szz[k] = a.real();
-            spm[k] = b.real();
-            stot[k] = a.real() + 0.5 * (b.real() + c.real());
+            for (int p0 = 0; p0 < ns; ++p0)
+                for (int p1 = 0; p1 < ns; ++p1)
+                    for (int d = 0; d < NT; ++d) {
+                        const int j = p1 + ns * d;  // place p1 of cell d
+                        double ph = 0;
+                        for (int ax = 0; ax < 3; ++ax) ph += qv[3 * k + ax] * (R[3 * j + ax] - R[3 * p0 + ax]);
+                        const std::complex<double> e(std::cos(ph), -std::sin(ph));
+                        const size_t i = ((size_t)p0 * ns + p1) * NT + d;
+                        a += e * Czz[i];
+                        b += e * Cpm[i];
+                        // <s^-_(0,p0) s^+_(d,p1)> = <s^+_(d,p1) s^-_(0,p0)> (class (p1, p0, -d));
+                        // on one site 1/2 - s^z = rho
+                        const std::complex<double> mp =
+                            (p0 == p1 && d == 0) ? std::complex<double>(rho[p0]) : Cpm[pair_class(lat, j, p0)];
+                        c += e * mp;
+                    }
+            szz[k] = a.real() / ns;
+            spm[k] = b.real() / ns;
+            stot[k] = (a.real() + 0.5 * (b.real() + c.real())) / ns;
         }
         return QS3_OK;
     }

@@ -236,11 +236,13 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ 
     G[(size_t)j + (size_t)i * N] = s;
 }
 
-// Momentum sector (union layout, one column): for displacement d = disp[dd]
-// (packed dx | dy<<10 | dz<<20) accumulate over the rows of the chunk
-//   zz: |phi_u|^2 * #{pairs of down spins at displacement d}
-//   pm: conj(phi_u) * (O_d phi)_u with O_d = sum_r s^+_r s^-_{r+d}; the pull
-//       form applies O_d^+ (a down spin at c moves to c - d) with the
+// Momentum sector (union layout, one column): for the pair class disp[dd]
+// (packed cell displacement d | s<<24 | t<<28: place s of a cell and place t
+// of the cell d further on) accumulate over the rows of the chunk
+//   zz: |phi_u|^2 * #{down spins at (r, s) whose partner (r + d, t) is down}
+//   pm: conj(phi_u) * (O_d phi)_u with O_d = sum_r s^+_(r,s) s^-_(r+d,t); the pull
+//       form applies O_d^+ (a down spin at place t of cell r moves to place s
+//       of cell r - d) with the
 //       momentum-basis element e^{ik.t} sqrt(s'/s_u)
 //   nrm: |phi_u|^2
 // grid = (n_disp, nchunk); partial[(dd * nchunk + chunk) * 2 + {0,1}].
@@ -253,7 +255,8 @@ __global__ __launch_bounds__(256) void k_corr_k(BatchArgs A, const RT *__restric
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
     const int dd = blockIdx.x;
     const int dp = disp[dd];
-    const int dx = dp & 1023, dy = (dp >> 10) & 1023, dz = (dp >> 20) & 1023;
+    const int dcell = dp & 0xffffff, ss = (dp >> 24) & 15, tt = (dp >> 28) & 15;
+    const int dx = dcell % g.lx, dy = (dcell / g.lx) % g.ly, dz = dcell / g.lxy;
     const uint64_t per = (A.n_reps + nchunk - 1) / nchunk;
     const uint64_t u0 = per * blockIdx.y, u1 = min(A.n_reps, u0 + per);
     double azz = 0, anr = 0, apr = 0, api = 0;
@@ -269,10 +272,16 @@ __global__ __launch_bounds__(256) void k_corr_k(BatchArgs A, const RT *__restric
 #pragma unroll
         for (int m = 0; m < K; ++m) {
             const uint32_t pc = g.coords[c[m]];
-            const int x = pc & 1023u, y = (pc >> 10) & 1023u, z = (pc >> 20) & 1023u;
-            tr[m] = wrap_add(x, dx, g.lx) + g.lx * wrap_add(y, dy, g.ly) + g.lxy * wrap_add(z, dz, g.lz);
-            back[m] = wrap_add(x, dx ? g.lx - dx : 0, g.lx) + g.lx * wrap_add(y, dy ? g.ly - dy : 0, g.ly) +
-                      g.lxy * wrap_add(z, dz ? g.lz - dz : 0, g.lz);
+            const int x = pc & 1023u, y = (pc >> 10) & 1023u, z = (pc >> 20) & 1023u, sm = (int)(pc >> 30);
+            // partner of a down spin at place s of cell r: place t of cell r + d
+            tr[m] = sm == ss ? tt + g.ns * (wrap_add(x, dx, g.lx) + g.lx * wrap_add(y, dy, g.ly) +
+                                            g.lxy * wrap_add(z, dz, g.lz))
+                             : -1;
+            // O_d^+ moves a down spin at place t of cell r to place s of cell r - d
+            back[m] = sm == tt ? ss + g.ns * (wrap_add(x, dx ? g.lx - dx : 0, g.lx) +
+                                              g.lx * wrap_add(y, dy ? g.ly - dy : 0, g.ly) +
+                                              g.lxy * wrap_add(z, dz ? g.lz - dz : 0, g.lz))
+                               : -1;
         }
         int npair = 0;
 #pragma unroll
@@ -289,7 +298,7 @@ __global__ __launch_bounds__(256) void k_corr_k(BatchArgs A, const RT *__restric
             constexpr int m = decltype(mc)::value;
             RT rp;
             const int j = back[m];
-            if (!hr.template hop<m>(c, R, j, Bn, &rp)) return;
+            if (j < 0 || !hr.template hop<m>(c, R, j, Bn, &rp)) return;
             uint32_t u2;
             int tx, ty, tz;
             resolve_hop<K, RT, TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);

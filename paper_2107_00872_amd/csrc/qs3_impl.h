@@ -123,6 +123,7 @@ struct qs3_lattice {
     qs3_ctx *ctx = nullptr;
     int lx = 1, ly = 1, lz = 1, N = 0;
     int ns = 1;  // sites per unit cell: site = s + ns * (x + lx * (y + ly * z))
+    std::vector<double> basis;  // ns x 3: place s in its cell, in cell-vector units (default 0)
     int n_bonds = 0;
     std::vector<int> bi, bj;
     std::vector<double> jxy, jz;

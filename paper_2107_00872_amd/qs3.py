@@ -73,6 +73,7 @@ SIGNATURES = [
     ("qs3_lattice_create_cells", ctypes.c_int,
      [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P]),
     ("qs3_lattice_destroy", ctypes.c_int, [P]),
+    ("qs3_lattice_set_basis", ctypes.c_int, [P, P]),
     ("qs3_lattice_info", ctypes.c_int, [P, P, P]),
     ("qs3_sector_create", ctypes.c_int, [P, ctypes.c_int, P, P]),
     ("qs3_sector_destroy", ctypes.c_int, [P]),
@@ -203,7 +204,15 @@ class Lattice:
     @classmethod
     def of(cls, ctx: Context, lat):
         """From a workloads.Lattice."""
-        return cls(ctx, lat.lx, lat.ly, lat.lz, lat.bi, lat.bj, lat.jxy, lat.jz, getattr(lat, "ns", 1))
+        L = cls(ctx, lat.lx, lat.ly, lat.lz, lat.bi, lat.bj, lat.jxy, lat.jz, getattr(lat, "ns", 1))
+        if getattr(lat, "basis", ()):
+            L.set_basis(lat.basis)
+        return L
+
+    def set_basis(self, offsets):
+        """Positions of the places in a cell (ns x 3, cell-vector units)."""
+        self._basis = np.ascontiguousarray(offsets, dtype=np.float64).reshape(self.ns, 3)
+        check(lib().qs3_lattice_set_basis(self.h, _ptr(self._basis)))
 
     def info(self):
         n, ti = ctypes.c_int(), ctypes.c_int()

@@ -125,22 +125,75 @@ def test_cells_batch_and_eigs(qs3, lat, K):
     bat.close()
 
 
-def test_cells_refuse_position_observables(qs3):
+@pytest.mark.parametrize("lat,K", [(wl.kagome(2, 2), 3), (wl.honeycomb(3, 2), 3), (wl.kagome(2, 2), 4)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_cells_observables_vs_oracle(qs3, lat, K):
+    """<S^z_i>, <S^z_i S^z_j>, <S^+_i S^-_j> and S(q) (positions with the places'
+    offsets) of momentum-sector states against the oracle's U(1) observables
+    of the same states expanded by Eq. (akstate) (a momentum eigenstate's
+    correlations are translation invariant, so the translation-averaged
+    values are the plain ones); the fixed-N_down sector's S(q) against the
+    oracle's with the same positions."""
+    from oracle.observables import corr_pm, corr_zz, structure_factors, sz
+    from oracle.translation import expand_to_u1
+    ctx = qs3.Context(0)
+    L = qs3.Lattice.of(ctx, lat)
+    geo, ref = _oracle(lat, K)
+    N = lat.n_sites
+    R = np.zeros((N, 3))
+    for i in range(N):
+        s_, c = i % lat.ns, i // lat.ns
+        R[i] = (c % lat.lx, (c // lat.lx) % lat.ly, 0)
+        R[i] += lat.basis[s_]
+    # momenta of the cell lattice (the translation-averaged form sums over
+    # displacements within one period, so S(q) of a momentum sector is taken
+    # on this grid), plus a point off the grid for the fixed-N_down sector
+    qs = np.array([[2 * np.pi * kx / lat.lx, 2 * np.pi * ky / lat.ly, 0.0] for kx in range(lat.lx)
+                   for ky in range(lat.ly)])
+    qs_off = np.vstack([qs, [[1.3, -0.7, 0.0]]])
+    pi = [i for i in range(N) for j in range(N)]
+    pj = [j for i in range(N) for j in range(N)]
+    for Kv in list(ref)[:4]:
+        sigma, Rk, Hk = ref[Kv]
+        if len(sigma) == 0:
+            continue
+        sec = qs3.Sector(L, K, Kv)
+        X = torch.empty(sec.dim, dtype=torch.complex128, device="cuda")
+        sec.eigs(nev=1, evecs=X, seed=2)
+        phi = X.cpu().numpy()
+        u1 = expand_to_u1(geo, K, list(sigma), list(Rk), Kv, phi)
+        rsz, rzz, rpm = sz(u1, N, K), corr_zz(u1, N, K), corr_pm(u1, N, K)
+        assert np.abs(sec.sz(X) - rsz).max() < 1e-12
+        zz, pm = sec.sisj(X, pi, pj)
+        assert np.abs(zz - rzz.reshape(-1)).max() < 1e-12
+        assert np.abs(pm - rpm.reshape(-1)).max() < 1e-12
+        szz, spm, stot = sec.sq(X, qs)
+        rs = structure_factors(rzz, rpm, rsz, R, qs)
+        assert np.abs(szz - rs[:, 0]).max() < 1e-11
+        assert np.abs(spm - rs[:, 1]).max() < 1e-11
+        assert np.abs(stot - rs[:, 2]).max() < 1e-11
+        sec.close()
+    u1s = qs3.Sector(L, K)
+    x = torch.empty(u1s.dim, dtype=torch.float64, device="cuda")
+    u1s.eigs(nev=1, evecs=x, seed=1)
+    ph = x.cpu().numpy()
+    szz, spm, stot = u1s.sq(x, qs_off)
+    rs = structure_factors(corr_zz(ph, N, K), corr_pm(ph, N, K), sz(ph, N, K), R, qs_off)
+    assert np.abs(np.stack([szz, spm, stot], 1) - rs).max() < 1e-11
+
+
+def test_cells_refuse_spin_operators(qs3):
     ctx = qs3.Context(0)
     lat = wl.kagome(2, 2)
     L = qs3.Lattice.of(ctx, lat)
     sec = qs3.Sector(L, 2, (1, 0, 0))
+    dst = qs3.Sector(L, 3, (1, 0, 0))
     v = torch.empty(sec.dim, dtype=torch.complex128, device="cuda")
     sec.start_vector(1, v)
-    for call in (lambda: sec.sz(v), lambda: sec.sisj(v, [0], [1]),
-                 lambda: sec.sq(v, [[0.0, 0.0, 0.0]])):
-        with pytest.raises(qs3.QS3Error) as e:
-            call()
-        assert e.value.code == qs3.QS3_EINVAL
-    # the fixed-N_down sector of the same lattice takes every observable but S(q)
-    u1 = qs3.Sector(L, 2)
-    x = torch.empty(u1.dim, dtype=torch.float64, device="cuda")
-    u1.eigs(nev=1, evecs=x, seed=1)
-    assert u1.sz(x).sum() == pytest.approx(lat.n_sites / 2 - 2, abs=1e-12)
-    with pytest.raises(qs3.QS3Error):
-        u1.sq(x, [[0.0, 0.0, 0.0]])
+    out = torch.empty(dst.dim, dtype=torch.complex128, device="cuda")
+    with pytest.raises(qs3.QS3Error) as e:
+        sec.smq(v, dst, (0, 0, 0), out)
+    assert e.value.code == qs3.QS3_EINVAL
+    with pytest.raises(qs3.QS3Error) as e:
+        sec.dsf(v, 0.0, [(0, 0, 0)], np.linspace(0, 1, 5), steps=5)
+    assert e.value.code == qs3.QS3_EINVAL

@@ -29,6 +29,7 @@ class Lattice:
     jz: np.ndarray      # float64 [n_bonds]
     translation_invariant: bool = True
     ns: int = 1         # sites per unit cell
+    basis: tuple = ()   # positions of the places in a cell (cell-vector units), () = all at 0
 
     @property
     def n_sites(self) -> int:
@@ -94,7 +95,8 @@ def cube(L: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
     return hypercubic(L, L, L, J, Delta, name=f"cube{L}^3")
 
 
-def _cell_lattice(name: str, ns: int, lx: int, ly: int, links, J: float, Delta: float) -> Lattice:
+def _cell_lattice(name: str, ns: int, lx: int, ly: int, links, J: float, Delta: float,
+                  basis: tuple = ()) -> Lattice:
     """Periodic lx x ly cells of ns sites; links: (s, t, dx, dy) couples
     sublattice s of cell (x, y) with sublattice t of cell (x + dx, y + dy)."""
     seen = set()
@@ -113,7 +115,7 @@ def _cell_lattice(name: str, ns: int, lx: int, ly: int, links, J: float, Delta: 
     bj = np.array([b[1] for b in uniq], dtype=np.int32)
     nb = len(uniq)
     return Lattice(name, lx, ly, 1, bi, bj, np.full(nb, float(J)), np.full(nb, float(J) * float(Delta)),
-                   True, ns)
+                   True, ns, basis)
 
 
 def kagome(lx: int, ly: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
@@ -122,13 +124,15 @@ def kagome(lx: int, ly: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
     down triangles).  Needs lx, ly >= 2."""
     links = [(0, 1, 0, 0), (0, 2, 0, 0), (1, 2, 0, 0),      # up triangle of the cell
              (1, 0, 1, 0), (2, 0, 0, 1), (1, 2, 1, -1)]     # down triangles
-    return _cell_lattice(f"kagome{lx}x{ly}", 3, lx, ly, links, J, Delta)
+    return _cell_lattice(f"kagome{lx}x{ly}", 3, lx, ly, links, J, Delta,
+                         ((0.0, 0.0, 0.0), (0.5, 0.0, 0.0), (0.0, 0.5, 0.0)))
 
 
 def honeycomb(lx: int, ly: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
     """Honeycomb lattice: two sublattices, each site with 3 neighbours."""
     links = [(0, 1, 0, 0), (1, 0, 1, 0), (1, 0, 0, 1)]
-    return _cell_lattice(f"honeycomb{lx}x{ly}", 2, lx, ly, links, J, Delta)
+    return _cell_lattice(f"honeycomb{lx}x{ly}", 2, lx, ly, links, J, Delta,
+                         ((0.0, 0.0, 0.0), (1.0 / 3.0, 1.0 / 3.0, 0.0)))
 
 
 def with_disorder(lat: Lattice, seed: int, jlo: float = 0.5, jhi: float = 1.5,
