@@ -37,8 +37,11 @@ def sq_to_vec(geo: Geometry, K: int, sigma, R, Kvec, phi, sigma1, R1, Qvec, op: 
     READING: the printed factor sqrt(R'_beta / (R_alpha N)) with R = sqrt(N_{a,k})
     is the same garble as in Alg. 8/9; the derivation after Eq. (sq_phi) gives
     sqrt(N'_beta / (N_alpha N)) = R'_beta / (R_alpha sqrt(N)), used here.
-    The site phase is e^{-i q.R_r} with R_r the coordinates of site r (site 1 at
-    the origin); k + q is taken index-wise modulo (Lx, Ly, Lz).
+    The site phase is e^{-i q.R_r} with R_r the position of site r (site 1 at
+    the origin; with several sites per cell, the cell's coordinates plus the
+    place's offset, and q = 2 pi (Qx/Lx, Qy/Ly, Qz/Lz) for the given integers);
+    k + q is taken index-wise modulo (Lx, Ly, Lz).  The element's N is the
+    number of sites (the N_T of the two orbit normalisations cancel).
     """
     K1 = n_down_after(op, K)
     d1 = len(sigma1)
@@ -46,7 +49,7 @@ def sq_to_vec(geo: Geometry, K: int, sigma, R, Kvec, phi, sigma1, R1, Qvec, op: 
     kq = tuple(Kvec[i] + Qvec[i] for i in range(3))
     sqN = math.sqrt(geo.N)
     for r in range(1, geo.N + 1):
-        Rr = geo.coords(r)
+        Rr = geo.position(r)
         for alpha, a in enumerate(sigma):
             n = f_bar(a, K, geo.N)
             p, f = is_down(r, n)

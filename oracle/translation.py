@@ -26,10 +26,18 @@ from .hamiltonian import row_terms
 
 
 class Geometry:
-    def __init__(self, lx: int, ly: int = 1, lz: int = 1, ns: int = 1):
+    def __init__(self, lx: int, ly: int = 1, lz: int = 1, ns: int = 1, basis=None):
         self.lx, self.ly, self.lz, self.ns = lx, ly, lz, ns
         self.NT = lx * ly * lz          # translations
         self.N = ns * self.NT           # sites
+        # place s of a cell sits at the cell's coordinates + basis[s] (cell-vector units)
+        self.basis = [tuple(map(float, b)) for b in basis] if basis else [(0.0, 0.0, 0.0)] * ns
+
+    def position(self, r: int):
+        """1-based site -> position (cell coordinates + the place's offset)."""
+        x, y, z = self.coords(r)
+        b = self.basis[self.sublattice(r)]
+        return x + b[0], y + b[1], z + b[2]
 
     def coords(self, r: int):
         """1-based site -> cell coordinates (x, y, z)."""

@@ -262,6 +262,31 @@ def test_sq_scatter_equals_definition_with_stabilisers(op):
                 assert np.abs(got - ref).max() < 1e-13
 
 
+@pytest.mark.parametrize("op", ["-", "+", "z"])
+def test_sq_scatter_equals_definition_unit_cells(op):
+    """Several sites per cell: the scatter expanded to the U(1) basis equals
+    S^op_q applied by definition with positions = cell coordinates + the
+    places' offsets (kagome, honeycomb)."""
+    for lat, K in [(wl.kagome(2, 2), 2), (wl.honeycomb(2, 2), 3), (wl.kagome(2, 2), 1)]:
+        geo = Geometry(lat.lx, lat.ly, lat.lz, lat.ns, lat.basis)
+        pos = np.array([geo.position(r) for r in range(1, geo.N + 1)])
+        K1 = n_down_after(op, K)
+        for Kv in wl.all_momenta(lat)[:3]:
+            s, R = mk_list(geo, K, Kv)
+            if not s:
+                continue
+            phi = np.random.default_rng(6).normal(size=len(s)) + 0.2j
+            u1 = expand_to_u1(geo, K, s, R, Kv, phi)
+            for Qv in wl.all_momenta(lat):
+                kq = tuple((Kv[i] + Qv[i]) % lat.dims[i] for i in range(3))
+                s1, R1 = mk_list(geo, K1, kq)
+                q = 2 * np.pi * np.array(Qv) / np.array(lat.dims)
+                ref = sq_u1(geo.N, K, pos, q, u1, op)
+                got = expand_to_u1(geo, K1, s1, R1, kq, sq_to_vec(geo, K, s, R, Kv, phi, s1, R1, Qv, op)) \
+                    if s1 else np.zeros_like(ref)
+                assert np.abs(got - ref).max() < 1e-13
+
+
 def test_sq_sum_rules():
     """sum_q |S^a_q phi|^2 = <sum_r s^a_r^+ s^a_r>: N - K (S^-), K (S^+), N/4 (S^z)
     for a normalised state with K down spins (Fourier completeness)."""
