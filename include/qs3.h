@@ -107,10 +107,11 @@ int qs3_lattice_create(qs3_ctx *ctx, int lx, int ly, int lz, int n_bonds, const 
  * lx*ly*lz with site = s + n_sub*(x + lx*(y + ly*z)) for place s of cell
  * (x, y, z).  Translations move whole cells and keep s, so momentum sectors
  * are over the lx*ly*lz cell translations (orbit normalisation N_T s_a with
- * N_T = lx*ly*lz).  Every entry point takes such lattices except
- * qs3_sq_apply, qs3_smq and qs3_dsf, which return QS3_EINVAL when n_sub > 1;
- * momentum-sector correlations are averaged over cell translations per pair
- * of places.  qs3_lattice_create is this call with n_sub = 1. */
+ * N_T = lx*ly*lz).  Every entry point takes such lattices: momentum-sector
+ * correlations are averaged over cell translations per pair of places, and
+ * S^a_q uses the sites' positions (qs3_lattice_set_basis) with q = 2 pi
+ * (Qx/lx, Qy/ly, Qz/lz), Q taken modulo the lengths.  qs3_lattice_create is
+ * this call with n_sub = 1. */
 int qs3_lattice_create_cells(qs3_ctx *ctx, int n_sub, int lx, int ly, int lz, int n_bonds,
                              const int32_t *bi, const int32_t *bj, const double *jxy,
                              const double *jz, qs3_lattice **out);

@@ -395,9 +395,9 @@ int corr_k_K<KI>(qs3_sector *sec, const double *phi_union, int ndisp, const int3
 
 #if QS3_INST_K <= 5
 template <typename RTa, typename RTb, bool TABLE>
-static int smq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+static int smq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph, const double *phi,
                  double *out, hipStream_t s) {
-    SmqArgs S{batch_args(src), batch_args(dst), qmul};
+    SmqArgs S{batch_args(src), batch_args(dst), qmul, subph};
     const int G = S.dst.G, B = S.dst.B;
     const int per = (B + G - 1) / G;
     const uint64_t rows_per = 256 / G;
@@ -421,32 +421,32 @@ static int smq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const doub
 }
 
 template <typename RTa, typename RTb>
-static int smq_mode(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+static int smq_mode(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph, const double *phi,
                     double *out, hipStream_t s) {
-    if (src->ks->has_table) return smq_t<RTa, RTb, true>(src, dst, qmul, phi, out, s);
-    return smq_t<RTa, RTb, false>(src, dst, qmul, phi, out, s);
+    if (src->ks->has_table) return smq_t<RTa, RTb, true>(src, dst, qmul, subph, phi, out, s);
+    return smq_t<RTa, RTb, false>(src, dst, qmul, subph, phi, out, s);
 }
 
 template <>
-int smq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+int smq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph, const double *phi,
               double *out, hipStream_t s) {
     const bool wa = src->bt->wide, wb = dst->bt->wide;
     if constexpr (KI >= 3) {
-        if (wa && wb) return smq_mode<uint64_t, uint64_t>(src, dst, qmul, phi, out, s);
+        if (wa && wb) return smq_mode<uint64_t, uint64_t>(src, dst, qmul, subph, phi, out, s);
     }
     if constexpr (KI >= 2) {
-        if (!wa && wb) return smq_mode<uint32_t, uint64_t>(src, dst, qmul, phi, out, s);
+        if (!wa && wb) return smq_mode<uint32_t, uint64_t>(src, dst, qmul, subph, phi, out, s);
     }
     QS3_REQUIRE(!wa && !wb, QS3_EINVAL, "internal: rank width");
-    return smq_mode<uint32_t, uint32_t>(src, dst, qmul, phi, out, s);
+    return smq_mode<uint32_t, uint32_t>(src, dst, qmul, subph, phi, out, s);
 }
 #endif  // S^-_q targets at most 6 down spins
 
 // S^+_q: source KI down spins, targets KI - 1
 template <typename RTa, typename RTb, bool TABLE>
-static int spq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+static int spq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph, const double *phi,
                  double *out, hipStream_t s) {
-    SmqArgs S{batch_args(src), batch_args(dst), qmul};
+    SmqArgs S{batch_args(src), batch_args(dst), qmul, subph};
     const int G = S.dst.G, B = S.dst.B;
     const int per = (B + G - 1) / G;
     const uint64_t rows_per = 256 / G;
@@ -470,14 +470,14 @@ static int spq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const doub
 }
 
 template <typename RTa, typename RTb>
-static int spq_mode(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+static int spq_mode(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph, const double *phi,
                     double *out, hipStream_t s) {
-    if (src->ks->has_table) return spq_t<RTa, RTb, true>(src, dst, qmul, phi, out, s);
-    return spq_t<RTa, RTb, false>(src, dst, qmul, phi, out, s);
+    if (src->ks->has_table) return spq_t<RTa, RTb, true>(src, dst, qmul, subph, phi, out, s);
+    return spq_t<RTa, RTb, false>(src, dst, qmul, subph, phi, out, s);
 }
 
 template <>
-int spq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+int spq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph, const double *phi,
               double *out, hipStream_t s) {
     if constexpr (KI == 0) {
         set_error("S^+_q needs N_down >= 1");
@@ -485,21 +485,21 @@ int spq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double 
     } else {
         const bool wa = src->bt->wide, wb = dst->bt->wide;
         if constexpr (KI >= 4) {
-            if (wa && wb) return spq_mode<uint64_t, uint64_t>(src, dst, qmul, phi, out, s);
+            if (wa && wb) return spq_mode<uint64_t, uint64_t>(src, dst, qmul, subph, phi, out, s);
         }
         if constexpr (KI >= 3) {
-            if (wa && !wb) return spq_mode<uint64_t, uint32_t>(src, dst, qmul, phi, out, s);
+            if (wa && !wb) return spq_mode<uint64_t, uint32_t>(src, dst, qmul, subph, phi, out, s);
         }
         QS3_REQUIRE(!wa && !wb, QS3_EINVAL, "internal: rank width");
-        return spq_mode<uint32_t, uint32_t>(src, dst, qmul, phi, out, s);
+        return spq_mode<uint32_t, uint32_t>(src, dst, qmul, subph, phi, out, s);
     }
 }
 
 // S^z_q: source and targets share the KI-down structure
 template <typename RT>
-static int szq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+static int szq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph, const double *phi,
                  double *out, hipStream_t s) {
-    SmqArgs S{batch_args(src), batch_args(dst), qmul};
+    SmqArgs S{batch_args(src), batch_args(dst), qmul, subph};
     const uint64_t n = S.dst.n_reps * (uint64_t)S.dst.B;
     if (n == 0) return QS3_OK;
     hipLaunchKernelGGL((k_szq<KI, RT>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, S,
@@ -509,13 +509,13 @@ static int szq_t(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const doub
 }
 
 template <>
-int szq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+int szq_K<KI>(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph, const double *phi,
               double *out, hipStream_t s) {
     QS3_REQUIRE(src->ks == dst->ks, QS3_EINVAL, "internal: S^z_q keeps the structure");
     if constexpr (WIDE_OK) {
-        if (src->bt->wide) return szq_t<uint64_t>(src, dst, qmul, phi, out, s);
+        if (src->bt->wide) return szq_t<uint64_t>(src, dst, qmul, subph, phi, out, s);
     }
-    return szq_t<uint32_t>(src, dst, qmul, phi, out, s);
+    return szq_t<uint32_t>(src, dst, qmul, subph, phi, out, s);
 }
 
 // ------------------------------------------------------------------ dense blocks

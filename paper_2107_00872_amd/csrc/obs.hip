@@ -49,20 +49,20 @@ static int corr_k(qs3_sector *sec, const double *phi, int nd, const int32_t *dis
 #undef QS3_CK
 }
 
-static int smq_any(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi, double *out,
+static int smq_any(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph, const double *phi, double *out,
                    hipStream_t s) {
-#define QS3_SQ(k) smq_K<(k > 5 ? 5 : k)>(src, dst, qmul, phi, out, s)
+#define QS3_SQ(k) smq_K<(k > 5 ? 5 : k)>(src, dst, qmul, subph, phi, out, s)
     QS3_REQUIRE(src->K <= 5, QS3_EINVAL, "S^-_q needs N_down + 1 <= 6");
     QS3_SW7(src->K, QS3_SQ)
 #undef QS3_SQ
 }
 
 // S^op_q from the source batch (one sector) into the target batch
-static int sq_any(int op, qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi,
+static int sq_any(int op, qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph, const double *phi,
                   double *out, hipStream_t s) {
-    if (op == QS3_OP_SMINUS) return smq_any(src, dst, qmul, phi, out, s);
-#define QS3_SP(k) spq_K<(k > 6 ? 6 : k)>(src, dst, qmul, phi, out, s)
-#define QS3_SZ(k) szq_K<(k > 6 ? 6 : k)>(src, dst, qmul, phi, out, s)
+    if (op == QS3_OP_SMINUS) return smq_any(src, dst, qmul, subph, phi, out, s);
+#define QS3_SP(k) spq_K<(k > 6 ? 6 : k)>(src, dst, qmul, subph, phi, out, s)
+#define QS3_SZ(k) szq_K<(k > 6 ? 6 : k)>(src, dst, qmul, subph, phi, out, s)
     if (op == QS3_OP_SPLUS) {
         QS3_REQUIRE(src->K >= 1 && src->K <= 6, QS3_EINVAL, "S^+_q needs 1 <= N_down <= 6");
         QS3_SW7(src->K, QS3_SP)
@@ -166,6 +166,26 @@ static size_t pair_class(const qs3_lattice *lat, int i, int j) {
               dz = (zj - zi + lat->lz) % lat->lz;
     const size_t NT = (size_t)lat->lx * lat->ly * lat->lz;
     return ((size_t)pi * lat->ns + pj) * NT + dx + (size_t)lat->lx * (dy + (size_t)lat->ly * dz);
+}
+
+// e^{-i q_b . offset_s} for the momenta qvecs (3 ints each, taken modulo the
+// lattice lengths) and every place s of a cell, into dev ([b][s], double2)
+static int sub_phases(const qs3_lattice *lat, int n_q, const int32_t *qvecs, DevBuf &dev, hipStream_t s) {
+    const int ns = lat->ns;
+    const int L[3] = {lat->lx, lat->ly, lat->lz};
+    std::vector<double2> h((size_t)n_q * ns);
+    for (int b = 0; b < n_q; ++b)
+        for (int p = 0; p < ns; ++p) {
+            double ph = 0;
+            for (int a = 0; a < 3; ++a) {
+                const int qa = ((qvecs[3 * b + a] % L[a]) + L[a]) % L[a];
+                ph += 2.0 * M_PI * qa * lat->basis[3 * p + a] / L[a];
+            }
+            h[(size_t)b * ns + p] = ph == 0.0 ? make_double2(1.0, 0.0) : make_double2(std::cos(ph), -std::sin(ph));
+        }
+    QS3_TRY(dev.alloc(lat->ctx, sizeof(double2) * h.size()));
+    QS3_HIP(hipMemcpyAsync(dev.ptr, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice, s));
+    return QS3_OK;
 }
 
 // position of site i: its cell's coordinates plus its place's offset
@@ -355,7 +375,6 @@ int qs3_sq_apply(qs3_sector *from, const void *vec_from, qs3_sector *to, int op,
     QS3_REQUIRE(op == QS3_OP_SMINUS || op == QS3_OP_SPLUS || op == QS3_OP_SZ, QS3_EINVAL,
                 "unknown spin operator");
     QS3_REQUIRE(from->has_k && to->has_k, QS3_EINVAL, "S^a_q acts between momentum sectors");
-    QS3_REQUIRE(from->lat->ns == 1, QS3_EINVAL, "S^a_q needs one site per unit cell");
     QS3_REQUIRE(from->lat == to->lat && to->K == n_down_after(op, from->K), QS3_EINVAL,
                 "target sector must be the same lattice with N_down + 1 (S^-), - 1 (S^+) or + 0 (S^z)");
     qs3_lattice *lat = from->lat;
@@ -374,8 +393,10 @@ int qs3_sq_apply(qs3_sector *from, const void *vec_from, qs3_sector *to, int op,
     QS3_TRY(ub.alloc(lat->ctx, sizeof(double) * 2 * std::max<uint64_t>(to->bat->ks->n_reps, 1)));
     QS3_TRY(dq.alloc(lat->ctx, sizeof(qm)));
     QS3_HIP(hipMemcpyAsync(dq.ptr, qm, sizeof(qm), hipMemcpyHostToDevice, s));
+    DevBuf sp;
+    QS3_TRY(sub_phases(lat, 1, qvec, sp, s));
     QS3_TRY(scatter_compact(from, (const double *)vec_from, ua.as<double>(), s));
-    QS3_TRY(sq_any(op, from->bat, to->bat, dq.as<int32_t>(), ua.as<double>(), ub.as<double>(), s));
+    QS3_TRY(sq_any(op, from->bat, to->bat, dq.as<int32_t>(), sp.as<double2>(), ua.as<double>(), ub.as<double>(), s));
     QS3_TRY(gather_compact(to, ub.as<double>(), (double *)vec_to, s));
     QS3_HIP(hipStreamSynchronize(s));
     return QS3_OK;
@@ -391,7 +412,6 @@ int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_
             double *beta, double *weight, void *stream) {
     QS3_REQUIRE(gs && gs_vec && qvecs && opts && n_q > 0 && n_omega >= 0, QS3_EINVAL, "bad argument");
     QS3_REQUIRE(gs->has_k, QS3_EINVAL, "the ground state must be a momentum-sector vector");
-    QS3_REQUIRE(gs->lat->ns == 1, QS3_EINVAL, "S(q, omega) needs one site per unit cell");
     const int op = opts->op;
     QS3_REQUIRE(op == QS3_OP_SMINUS || op == QS3_OP_SPLUS || op == QS3_OP_SZ, QS3_EINVAL,
                 "unknown spin operator");
@@ -425,7 +445,9 @@ int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_
     double g2 = 0;
     QS3_TRY(vec_norm2(gs, gs_vec, &g2, s));
     QS3_REQUIRE(g2 > 0 && std::isfinite(g2), QS3_ENUMERIC, "zero or non-finite ground state");
-    QS3_TRY(sq_any(op, gs->bat, tb, dq.as<int32_t>(), ua.as<double>(), psi.as<double>(), s));
+    DevBuf sp;
+    QS3_TRY(sub_phases(lat, n_q, qvecs, sp, s));
+    QS3_TRY(sq_any(op, gs->bat, tb, dq.as<int32_t>(), sp.as<double2>(), ua.as<double>(), psi.as<double>(), s));
     // Lanczos from psi'/|psi'| in every target sector (Alg. 10, lines 3-11)
     struct TOp : Operator {
         qs3_batch *b;

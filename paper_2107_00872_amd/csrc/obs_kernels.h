@@ -346,6 +346,7 @@ struct SmqArgs {
     BatchArgs src;    // K-down structure, source sector (B = 1)
     BatchArgs dst;    // (K+1)-down structure, target sectors (B = n_q)
     const int32_t *qmul;  // 3 * B: Q_a (M / L_a) mod M
+    const double2 *subph;  // B * ns: e^{-i q_b . offset_s} of the places in a cell (1 for one site per cell)
 };
 
 template <int K, typename RTa, typename RTb, bool TABLE, int BPL>
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(256) void k_smq(SmqArgs S, const RTa *__restrict__ 
         const double2 f = phi[ua];
         const double coef = A.L.sqrt_tab[sa] * isb;
         const uint32_t pr0 = g.coords[c[m]];
-        const int x0 = pr0 & 1023u, y0 = (pr0 >> 10) & 1023u, z0 = (pr0 >> 20) & 1023u;
+        const int x0 = pr0 & 1023u, y0 = (pr0 >> 10) & 1023u, z0 = (pr0 >> 20) & 1023u, s0 = (int)(pr0 >> 30);
         const int Pk = A.kmul[0] * tx + A.kmul[1] * ty + A.kmul[2] * tz;
 #pragma unroll
         for (int i = 0; i < BPL; ++i) {
@@ -411,7 +412,8 @@ __global__ __launch_bounds__(256) void k_smq(SmqArgs S, const RTa *__restrict__ 
             int P = Pk - (S.qmul[3 * b] * x0 + S.qmul[3 * b + 1] * y0 + S.qmul[3 * b + 2] * z0);
             P %= A.M;
             if (P < 0) P += A.M;
-            const double2 ph = A.phase[P];
+            const double2 pc = A.phase[P], so = S.subph[b * g.ns + s0];
+            const double2 ph = make_double2(pc.x * so.x - pc.y * so.y, pc.x * so.y + pc.y * so.x);
             accr[i] += coef * (ph.x * f.x - ph.y * f.y);
             acci[i] += coef * (ph.x * f.y + ph.y * f.x);
         }
@@ -488,7 +490,7 @@ __global__ __launch_bounds__(256) void k_spq(SmqArgs S, const RTa *__restrict__ 
         const double2 f = phi[ua];
         const double coef = A.L.sqrt_tab[sa] * isb;
         const uint32_t pr0 = g.coords[r0];
-        const int x0 = pr0 & 1023u, y0 = (pr0 >> 10) & 1023u, z0 = (pr0 >> 20) & 1023u;
+        const int x0 = pr0 & 1023u, y0 = (pr0 >> 10) & 1023u, z0 = (pr0 >> 20) & 1023u, s0 = (int)(pr0 >> 30);
         const int Pk = A.kmul[0] * tx + A.kmul[1] * ty + A.kmul[2] * tz;
 #pragma unroll
         for (int i = 0; i < BPL; ++i) {
@@ -497,7 +499,8 @@ __global__ __launch_bounds__(256) void k_spq(SmqArgs S, const RTa *__restrict__ 
             int P = Pk - (S.qmul[3 * b] * x0 + S.qmul[3 * b + 1] * y0 + S.qmul[3 * b + 2] * z0);
             P %= A.M;
             if (P < 0) P += A.M;
-            const double2 ph = A.phase[P];
+            const double2 pc = A.phase[P], so = S.subph[b * g.ns + s0];
+            const double2 ph = make_double2(pc.x * so.x - pc.y * so.y, pc.x * so.y + pc.y * so.x);
             accr[i] += coef * (ph.x * f.x - ph.y * f.y);
             acci[i] += coef * (ph.x * f.y + ph.y * f.x);
         }
@@ -540,9 +543,10 @@ __global__ __launch_bounds__(256) void k_szq(SmqArgs S, const RT *__restrict__ b
             const uint32_t p = A.L.coords[c[m]];
             int P = qx * (int)(p & 1023u) + qy * (int)((p >> 10) & 1023u) + qz * (int)((p >> 20) & 1023u);
             P %= A.M;
-            const double2 ph = A.phase[P];  // e^{+i q.R}: subtract its conjugate
-            sr -= ph.x;
-            si += ph.y;
+            // e^{-i q.R} = conj(e^{+i q.x_cell}) * e^{-i q.offset}, subtracted
+            const double2 pc = A.phase[P], so = S.subph[b * A.L.ns + (int)(p >> 30)];
+            sr -= pc.x * so.x + pc.y * so.y;
+            si -= pc.x * so.y - pc.y * so.x;
         }
         const double inv = 1.0 / sqrt((double)A.L.N);
         const double2 f = phi[u];

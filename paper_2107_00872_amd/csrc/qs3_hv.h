@@ -101,17 +101,21 @@ int corr_k_K(qs3_sector *sec, const double *phi_union, int ndisp, const int32_t 
              std::vector<double> &zz, std::vector<double> &nrm, std::vector<double> &pm_re,
              std::vector<double> &pm_im, hipStream_t s);
 // S^-_q gather from the source sector (batch of one, union layout) into the
-// target batch (union layout [row][sector]); qmul: device, 3 ints per target.
+// target batch (union layout [row][sector]); qmul: device, 3 ints per target;
+// subph: device, e^{-i q.offset_s} per target and place in a cell.
 // S^+_q (source K down spins, targets K - 1) and S^z_q (source and targets
 // of one K-down structure), same conventions.
 template <int K>
-int spq_K(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi_union,
+int spq_K(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph,
+          const double *phi_union,
           double *out_union, hipStream_t s);
 template <int K>
-int szq_K(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi_union,
+int szq_K(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph,
+          const double *phi_union,
           double *out_union, hipStream_t s);
 template <int K>
-int smq_K(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double *phi_union,
+int smq_K(qs3_batch *src, qs3_batch *dst, const int32_t *qmul, const double2 *subph,
+          const double *phi_union,
           double *out_union, hipStream_t s);
 
 }  // namespace qs3

@@ -182,18 +182,83 @@ def test_cells_observables_vs_oracle(qs3, lat, K):
     assert np.abs(np.stack([szz, spm, stot], 1) - rs).max() < 1e-11
 
 
-def test_cells_refuse_spin_operators(qs3):
+@pytest.mark.parametrize("op", ["-", "+", "z"])
+@pytest.mark.parametrize("lat,K", [(wl.kagome(2, 2), 2), (wl.honeycomb(2, 2), 3), (wl.kagome(2, 3), 1)],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_cells_sq_gather_vs_oracle(qs3, lat, K, op):
+    """S^-_q, S^+_q and S^z_q between momentum sectors of a lattice with several
+    sites per cell (positions with the places' offsets): the device's gather
+    against the oracle's scatter for every q."""
+    from oracle.dynamics import n_down_after, sq_to_vec
+    code = {"-": qs3.OP_SMINUS, "+": qs3.OP_SPLUS, "z": qs3.OP_SZ}[op]
+    ctx = qs3.Context(0)
+    L = qs3.Lattice.of(ctx, lat)
+    geo = Geometry(lat.lx, lat.ly, lat.lz, lat.ns, lat.basis)
+    K1 = n_down_after(op, K)
+    for Kv in wl.all_momenta(lat)[:3]:
+        s_, R = mk_list(geo, K, Kv)
+        if not s_:
+            continue
+        src = qs3.Sector(L, K, Kv)
+        rng = np.random.default_rng(13)
+        phi = rng.normal(size=len(s_)) + 1j * rng.normal(size=len(s_))
+        X = torch.from_numpy(phi).cuda()
+        for Qv in wl.all_momenta(lat):
+            kq = tuple((Kv[a] + Qv[a]) % lat.dims[a] for a in range(3))
+            s1, R1 = mk_list(geo, K1, kq)
+            if not s1:
+                continue
+            dst = qs3.Sector(L, K1, kq)
+            out = torch.empty(dst.dim, dtype=torch.complex128, device="cuda")
+            src.sq_apply(X, dst, code, Qv, out)
+            ref = sq_to_vec(geo, K, s_, R, Kv, phi, s1, R1, Qv, op)
+            scale = np.abs(phi).max() * max(1, lat.n_sites if op != "-" else K + 1)
+            assert np.abs(out.cpu().numpy() - ref).max() < 1e-13 * scale, (Kv, Qv)
+            dst.close()
+        src.close()
+
+
+def test_cells_dsf_vs_oracle(qs3):
+    """S^-(q, omega) on the 2x2 kagome cluster from its N_down = 1 ground state,
+    all 4 q, 20 levels: weights, Lanczos coefficients and the continued
+    fraction against the oracle (S^-_q by the scatter, Lanczos on the dense
+    k + q blocks).  (The one-site sum rule sum_q S^{+-}(q) = N - K does not
+    carry over: within a cell the places' offsets leave q-dependent phases.)"""
+    from oracle.dynamics import continued_fraction, sq_to_vec
+    from oracle.lanczos import lanczos as orc_lanczos
     ctx = qs3.Context(0)
     lat = wl.kagome(2, 2)
     L = qs3.Lattice.of(ctx, lat)
-    sec = qs3.Sector(L, 2, (1, 0, 0))
-    dst = qs3.Sector(L, 3, (1, 0, 0))
-    v = torch.empty(sec.dim, dtype=torch.complex128, device="cuda")
-    sec.start_vector(1, v)
-    out = torch.empty(dst.dim, dtype=torch.complex128, device="cuda")
-    with pytest.raises(qs3.QS3Error) as e:
-        sec.smq(v, dst, (0, 0, 0), out)
-    assert e.value.code == qs3.QS3_EINVAL
-    with pytest.raises(qs3.QS3Error) as e:
-        sec.dsf(v, 0.0, [(0, 0, 0)], np.linspace(0, 1, 5), steps=5)
-    assert e.value.code == qs3.QS3_EINVAL
+    geo = Geometry(lat.lx, lat.ly, lat.lz, lat.ns, lat.basis)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    ks = wl.all_momenta(lat)
+    K = 1
+    best = None
+    for Kv in ks:
+        s_, R = mk_list(geo, K, Kv)
+        e = np.linalg.eigvalsh(gen_full_ham_sym_adapt(geo, K, bonds, s_, R, Kv))[0]
+        if best is None or e < best[0] - 1e-10:
+            best = (e, Kv)
+    e0, k0 = best
+    gs = qs3.Sector(L, K, k0)
+    X = torch.empty(gs.dim, dtype=torch.complex128, device="cuda")
+    res = gs.eigs(nev=1, evecs=X, seed=3)
+    assert res.evals[0] == pytest.approx(e0, abs=1e-10)
+    omega = np.linspace(-2, 8, 301)
+    steps = 20
+    S, a, b, w = gs.dsf(X, res.evals[0], ks, omega, steps=steps, eta=0.1, field=1.0)
+    phi = X.cpu().numpy()
+    sigma, R = mk_list(geo, K, k0)
+    for qi, Qv in enumerate(ks):
+        kq = tuple((k0[a_] + Qv[a_]) % lat.dims[a_] for a_ in range(3))
+        s1, R1 = mk_list(geo, K + 1, kq)
+        psi = sq_to_vec(geo, K, sigma, R, k0, phi, s1, R1, Qv, "-")
+        wq = float(np.vdot(psi, psi).real) / float(np.vdot(phi, phi).real)
+        assert w[qi] == pytest.approx(wq, abs=1e-12)
+        Hk = gen_full_ham_sym_adapt(geo, K + 1, bonds, s1, R1, kq)
+        m = min(steps, len(s1))
+        oa, ob, _ = orc_lanczos(lambda x: Hk @ x, psi, m)
+        eff = next((i + 1 for i in range(len(ob)) if ob[i] < 1e-8 * 8), len(ob))
+        assert np.abs(a[qi, :eff] - oa[:eff]).max() < 1e-10
+        Sref = continued_fraction(oa[:eff], ob[:eff], wq, omega, res.evals[0], 0.1, 1.0)
+        assert np.abs(S[qi] - Sref).max() < 1e-8 * max(1.0, np.abs(Sref).max())
