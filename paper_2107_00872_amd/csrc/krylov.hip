@@ -1401,7 +1401,7 @@ int SolveRun::advance(bool *done) {
     // from here on the kernels skip the columns that have converged, or the
     // columns still iterating move into a narrower engine
     bool compacted = false;
-    if (Bc > 1 && !want_vecs && 4 * n_next <= Bc) QS3_TRY(compact(act_next, &compacted));
+    if (Bc > 1 && !want_vecs && 4 * n_next <= 3 * Bc) QS3_TRY(compact(act_next, &compacted));
     Engine &En = eng();
     if (compacted) {
         En.colmask = nullptr;

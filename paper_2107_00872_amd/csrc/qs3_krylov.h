@@ -82,7 +82,7 @@ struct Engine {
 // the host part (tridiagonal / arrowhead eigensolves, convergence) and
 // enqueues the next cycle.  Every column is a separate sector and stops
 // changing once it has converged.  When no eigenvectors are wanted and at
-// most a quarter of the columns still iterate, a thick restart moves them
+// most three quarters of the columns still iterate, a thick restart moves them
 // into a narrower engine (the operator restricted to those columns), so the
 // slowest sectors no longer pay for the converged ones.
 struct SolveRun {
