@@ -1,0 +1,110 @@
+"""Pins of the oracle's point-group sectors: the dimension of every (k, chi)
+sector from the character formula over fixed states (no representative code),
+symmetric blocks, the spectra against projectors built in the bitmask basis,
+the expanded vectors transforming with the character, and the 1D blocks'
+levels inside the momentum block's."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle.hamiltonian import bonds_1based
+from oracle.pointgroup import expand_pg, gen_full_ham_pg, mk_list_pg
+from oracle.translation import Geometry, gen_full_ham_sym_adapt, mk_list
+from test_oracle_hamiltonian import bitmask_H, masks
+
+
+def _perm_of(lat, perms, p, t):
+    """Site permutation of T^t P_p (0-based)."""
+    lx, ly, lz = lat.dims
+    out = []
+    for i in range(lat.n_sites):
+        j = int(perms[p][i])
+        x, y, z = j % lx, (j // lx) % ly, j // (lx * ly)
+        out.append((x + t[0]) % lx + lx * (((y + t[1]) % ly) + ly * ((z + t[2]) % lz)))
+    return out
+
+
+def _fixed_states(perm, K):
+    """Number of K-subsets mapped onto themselves: unions of whole cycles."""
+    seen, lens = set(), []
+    for i in range(len(perm)):
+        if i in seen:
+            continue
+        n, j = 0, i
+        while j not in seen:
+            seen.add(j)
+            j = perm[j]
+            n += 1
+        lens.append(n)
+    poly = [1] + [0] * K
+    for ln in lens:
+        new = poly[:]
+        for k in range(K + 1 - ln):
+            new[k + ln] += poly[k]
+        poly = new
+    return poly[K]
+
+
+def _U(lat, K, perm):
+    ms = masks(lat.n_sites, K)
+    idx = {m: i for i, m in enumerate(ms)}
+    U = np.zeros((len(ms), len(ms)))
+    for c, m in enumerate(ms):
+        out = 0
+        for i in range(lat.n_sites):
+            if m >> i & 1:
+                out |= 1 << perm[i]
+        U[idx[out], c] = 1.0
+    return U
+
+
+CASES = [(wl.square(4), 2, (0, 0, 0)), (wl.square(4), 3, (2, 2, 0)),
+         (wl.with_disorder(wl.square(4), seed=3, per_bond=False), 3, (0, 0, 0))]
+
+
+@pytest.mark.parametrize("lat,K,Kv", CASES, ids=lambda x: getattr(x, "name", str(x)))
+def test_c4v_sectors(lat, K, Kv):
+    L = lat.lx
+    perms = wl.c4v_ops(L)
+    geo = Geometry(*lat.dims)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    ts = [(tx, ty, 0) for ty in range(L) for tx in range(L)]
+    kph = lambda t: 1.0 if math.cos(geo.kdot(Kv, t)) > 0 else -1.0
+    fixed = {(p, t): _fixed_states(_perm_of(lat, perms, p, t), K) for p in range(8) for t in ts}
+    G = 8 * len(ts)
+    s_k, R_k = mk_list(geo, K, Kv)
+    ek = np.linalg.eigvalsh(gen_full_ham_sym_adapt(geo, K, bonds, s_k, R_k, Kv))
+    Hb = bitmask_H(lat, K)
+    Us = {(p, t): _U(lat, K, _perm_of(lat, perms, p, t)) for p in range(8) for t in ts}
+    total = 0
+    for name, chars in wl.C4V_CHARS.items():
+        d = round(sum(chars[p] * kph(t) * fixed[(p, t)] for p in range(8) for t in ts))
+        assert d % G == 0
+        d //= G
+        s, R = mk_list_pg(geo, perms, chars, K, Kv)
+        assert len(s) == d, name
+        total += d
+        if not s:
+            continue
+        H = gen_full_ham_pg(geo, perms, chars, K, bonds, s, R, Kv)
+        assert np.abs(H - H.T).max() < 1e-13
+        e = np.linalg.eigvalsh(H)
+        for x in e:
+            assert np.min(np.abs(ek - x)) < 1e-10
+        # projector onto the (k, chi) subspace in the bitmask basis
+        P = sum(chars[p] * kph(t) * Us[(p, t)] for p in range(8) for t in ts) / G
+        u, sv, _ = np.linalg.svd(P)
+        Q = u[:, sv > 0.5]
+        assert Q.shape[1] == d
+        assert np.abs(np.linalg.eigvalsh(Q.T @ Hb @ Q) - e).max() < 1e-12
+        phi = np.random.default_rng(5).normal(size=d)
+        u1 = expand_pg(geo, perms, chars, K, s, R, Kv, phi)
+        # the bitmask order of the masks is the rank order: same basis
+        for (p, t) in [(1, (0, 0, 0)), (4, (1, 0, 0)), (6, (2, 1, 0))]:
+            assert np.abs(Us[(p, t)] @ u1 - chars[p] * kph(t) * u1).max() < 1e-12
+        assert np.abs(expand_pg(geo, perms, chars, K, s, R, Kv, H @ phi) - Hb @ u1).max() < 1e-12
+    dE = round(sum(wl.C4V_E[p] * kph(t) * fixed[(p, t)] for p in range(8) for t in ts)) // G
+    assert total + 2 * dE == len(s_k)

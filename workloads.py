@@ -171,6 +171,34 @@ def random_bonds(n_sites: int, n_bonds: int, seed: int) -> Lattice:
                    False)
 
 
+# one-dimensional representations of C4v on the operations of c4v_ops, in its
+# order (identity, rotations by 90, 180, 270 degrees, mirrors x -> -x and
+# y -> -y, diagonal mirrors (x, y) -> (y, x) and (-y, -x))
+C4V_CHARS = {"A1": (1, 1, 1, 1, 1, 1, 1, 1), "A2": (1, 1, 1, 1, -1, -1, -1, -1),
+             "B1": (1, -1, 1, -1, 1, 1, -1, -1), "B2": (1, -1, 1, -1, -1, -1, 1, 1)}
+# the two-dimensional one (characters only; no basis is built for it)
+C4V_E = (2, 0, -2, 0, 0, 0, 0, 0)
+
+
+def c4v_ops(L: int) -> np.ndarray:
+    """The point group C4v of the periodic L x L square about site 0, as site
+    permutations perm[p][i] (int32, 8 x L^2)."""
+    maps = [lambda x, y: (x, y), lambda x, y: (-y, x), lambda x, y: (-x, -y), lambda x, y: (y, -x),
+            lambda x, y: (-x, y), lambda x, y: (x, -y), lambda x, y: (y, x), lambda x, y: (-y, -x)]
+    out = np.zeros((8, L * L), dtype=np.int32)
+    for p, f in enumerate(maps):
+        for y in range(L):
+            for x in range(L):
+                u, v = f(x, y)
+                out[p, x + L * y] = (u % L) + L * (v % L)
+    return out
+
+
+def inversion_ops(L: int) -> np.ndarray:
+    """Identity and the inversion x -> -x of the periodic chain (2 x L)."""
+    return np.array([[i for i in range(L)], [(-i) % L for i in range(L)]], dtype=np.int32)
+
+
 def all_momenta(lat: Lattice) -> list:
     """Every momentum index triple (Kx, Ky, Kz), Kx fastest."""
     out = []
