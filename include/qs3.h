@@ -66,6 +66,7 @@ typedef struct qs3_lattice qs3_lattice;
 typedef struct qs3_sector qs3_sector;
 typedef struct qs3_batch qs3_batch;
 typedef struct qs3_server qs3_server;
+typedef struct qs3_pg_sector qs3_pg_sector;
 
 const char *qs3_version(void);
 const char *qs3_strerror(int code);
@@ -322,6 +323,42 @@ int qs3_batch_matvec(qs3_batch *bat, const void *v, void *w, int dtype, void *st
  * converges. */
 int qs3_batch_eigs(qs3_batch *bat, const qs3_eigs_opts *opts, double *evals,
                    qs3_eigs_info *info, void *stream);
+
+/* ---- point-group sectors (Sec. 5: point groups beyond translations) ------ */
+/* The sector of the space group G = {T^t P_p} (cell translations t, point
+ * operations p) in a one-dimensional representation with real characters:
+ * chi(T^t P_p) = chars[p] e^{i k.t}, built like the momentum sector of
+ * Sec. 3.3 (Eqs. (ak)-(hak2)) with G in place of the translations.  The
+ * representative of an orbit is its minimum rank, its norm N_a = |sum over the
+ * stabiliser of chi|^2 |G| / |stabiliser|; orbits whose character sum vanishes
+ * are not in the sector.  Vectors are real float64 over the representatives.
+ *  - lat: one site per cell, translation invariant; 1 <= n_down <= min(N, 6);
+ *  - kvec: host, 3 ints, each component 0 or L_a / 2 (k.t = 0 or pi);
+ *  - perms: host, n_ops x N (row p: site r -> perms[p*N + r]), 1 <= n_ops <= 48,
+ *    row 0 the identity; every row a permutation that keeps the couplings,
+ *    conjugates translations into translations with the same e^{i k.t}, and
+ *    the rows closed under composition up to translations, no two differing
+ *    by a translation;
+ *  - chars: host, n_ops values +-1 (chars[0] = 1) that form a representation
+ *    of G together with e^{i k.t}.
+ * Anything else returns QS3_EINVAL before any device work.  The sector's
+ * block is built once on the device (one ELL row of resolved hops per
+ * representative); an empty sector (dim 0) is valid. */
+int qs3_pg_sector_create(qs3_lattice *lat, int n_down, const int32_t *kvec, int n_ops,
+                         const int32_t *perms, const int32_t *chars, qs3_pg_sector **out);
+int qs3_pg_sector_destroy(qs3_pg_sector *sec);
+int qs3_pg_sector_dim(const qs3_pg_sector *sec, uint64_t *dim);
+/* Representatives (0-based ranks, ascending) and N_a, host arrays of dim
+ * entries (either may be NULL). */
+int qs3_pg_sector_basis(const qs3_pg_sector *sec, uint64_t *ranks, double *norms);
+/* v (device, dim float64) := entries uniform in [-1, 1) from seed. */
+int qs3_pg_start_vector(qs3_pg_sector *sec, uint64_t seed, double *v, void *stream);
+/* w := H v, device float64, dim entries each, no aliasing. */
+int qs3_pg_matvec(qs3_pg_sector *sec, const double *v, double *w, void *stream);
+/* As qs3_eigs (QS3_PREC_F64 only); evecs: device, dim x nev (vector y at
+ * y*dim), or NULL. */
+int qs3_pg_eigs(qs3_pg_sector *sec, const qs3_eigs_opts *opts, double *evals, double *evecs,
+                qs3_eigs_info *info, void *stream);
 
 /* ---- serving: continuous batching of solve requests ---------------------- */
 typedef struct {

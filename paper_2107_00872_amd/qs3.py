@@ -105,6 +105,13 @@ SIGNATURES = [
     ("qs3_wait", ctypes.c_int, [P, u64, P]),
     ("qs3_cancel", ctypes.c_int, [P, u64]),
     ("qs3_server_clock", dbl, [P]),
+    ("qs3_pg_sector_create", ctypes.c_int, [P, ctypes.c_int, P, ctypes.c_int, P, P, P]),
+    ("qs3_pg_sector_destroy", ctypes.c_int, [P]),
+    ("qs3_pg_sector_dim", ctypes.c_int, [P, P]),
+    ("qs3_pg_sector_basis", ctypes.c_int, [P, P, P]),
+    ("qs3_pg_start_vector", ctypes.c_int, [P, u64, P, P]),
+    ("qs3_pg_matvec", ctypes.c_int, [P, P, P, P]),
+    ("qs3_pg_eigs", ctypes.c_int, [P, P, P, P, P, P]),
 ]
 
 _lib = None
@@ -395,6 +402,56 @@ class Batch:
     def close(self):
         if self.h:
             lib().qs3_batch_destroy(self.h)
+            self.h = None
+
+
+class PGSector:
+    """Sector of translations x point operations in a one-dimensional real
+    representation: perms (n_ops x N site permutations, row 0 the identity),
+    chars (+-1 per operation), k with every component 0 or L/2."""
+
+    def __init__(self, lattice: Lattice, n_down: int, k, perms, chars):
+        self.lattice = lattice
+        self.n_down = n_down
+        self.k = tuple(int(x) for x in k)
+        self._perms = np.ascontiguousarray(perms, dtype=np.int32)
+        self._chars = np.ascontiguousarray(chars, dtype=np.int32)
+        kv = np.array(self.k, dtype=np.int32)
+        h = ctypes.c_void_p()
+        check(lib().qs3_pg_sector_create(lattice.h, n_down, _ptr(kv), self._perms.shape[0], _ptr(self._perms),
+                                         _ptr(self._chars), ctypes.byref(h)))
+        self.h = h
+        d = u64()
+        check(lib().qs3_pg_sector_dim(self.h, ctypes.byref(d)))
+        self.dim = d.value
+
+    def basis(self):
+        """(0-based ranks, N_a) of the representatives."""
+        r = np.zeros(self.dim, dtype=np.uint64)
+        n = np.zeros(self.dim)
+        check(lib().qs3_pg_sector_basis(self.h, _ptr(r), _ptr(n)))
+        return r, n
+
+    def start_vector(self, seed, out, stream=None):
+        check(lib().qs3_pg_start_vector(self.h, seed, _ptr(out), _stream(stream)))
+        return out
+
+    def matvec(self, v, w, stream=None):
+        check(lib().qs3_pg_matvec(self.h, _ptr(v), _ptr(w), _stream(stream)))
+        return w
+
+    def eigs(self, nev=1, evecs=None, stream=None, **kw) -> EigsResult:
+        o = make_opts(nev=nev, **kw)
+        ev = np.zeros(max(nev, 1))
+        info = EigsInfo()
+        rc = lib().qs3_pg_eigs(self.h, ctypes.byref(o), _ptr(ev), _ptr(evecs), ctypes.byref(info),
+                               _stream(stream))
+        check(rc, allow=(QS3_OK, QS3_ENOCONV))
+        return EigsResult(ev[:nev], info, rc)
+
+    def close(self):
+        if self.h:
+            lib().qs3_pg_sector_destroy(self.h)
             self.h = None
 
 
