@@ -9,6 +9,10 @@ c4  periodic 10x10 square, N_down=3 ground state (lowest over the 100 sectors),
     S^-(q, omega) for all 100 q into N_down=4: 300 continued-fraction Lanczos
     levels, eta=0.05, 2000 omega points in [0, 8], field h = 4 (the saturation
     field of the square lattice); float64 and float32-matvec.
+pg  periodic 10x10 square, N_down = 5 and 6, k = 0: the four one-dimensional
+    C4v sectors (translations x point operations) against the momentum sector
+    holding the same ground state: block build, ELL H.v rate and bytes, solve
+    times.
 c5  serving: Poisson arrivals of random solve requests (workloads.serving_stream),
     rate 0.8 / (mean one-at-a-time service time); p50/p99 latency and solves/s
     against the same requests run one at a time.
@@ -17,6 +21,7 @@ from __future__ import annotations
 
 import math
 import os
+import sys
 import time
 
 import numpy as np
@@ -430,3 +435,71 @@ def c5(args):
                       "p50_ms": _pct([r.t_done - r.t_submit for r in res_b], 50) * 1e3,
                       "p99_ms": _pct([r.t_done - r.t_submit for r in res_b], 99) * 1e3,
                       "identical_to_alone": same_b}}
+
+
+def pg(args):
+    """Point-group sectors of the 10 x 10 periodic square (J = Delta = 1) at
+    k = 0 for N_down = 5 and 6: per one-dimensional C4v representation the
+    block build, the ELL H.v (time over 20 calls; bytes: the packed ELL
+    slots, 4 B each, plus 64 B a row) and the
+    float64 ground-state solve; the momentum sector k = 0 solved beside it,
+    whose ground level the A1 block must reproduce."""
+    ctx = _ctx()
+    lat = wl.square(10)
+    L = qs3.Lattice.of(ctx, lat)
+    ops = wl.c4v_ops(10)
+    stream = torch.cuda.current_stream()
+    out = {"metric": "point-group sector build, H.v and solve vs the momentum sector", "workload": "pg",
+           "lattice": lat.name, "group": "C4v x translations", "by_n_down": {}}
+    for K in (5, 6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mom = qs3.Sector(L, K, (0, 0, 0))
+        torch.cuda.synchronize()
+        t_mom_build = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        rm = mom.eigs(nev=1, seed=1, stream=stream)
+        torch.cuda.synchronize()
+        t_mom = time.perf_counter() - t0
+        res = {"momentum": {"dim": mom.dim, "build_s": t_mom_build, "solve_s": t_mom, "E0": float(rm.evals[0]),
+                            "matvecs": rm.info.n_matvec}}
+        mom.close()
+        width = K * 4
+        for name, chars in wl.C4V_CHARS.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sec = qs3.PGSector(L, K, (0, 0, 0), ops, chars)
+            torch.cuda.synchronize()
+            t_build = time.perf_counter() - t0
+            v = torch.empty(sec.dim, dtype=torch.float64, device="cuda")
+            sec.start_vector(1, v, stream=stream)
+            w = torch.empty_like(v)
+            sec.matvec(v, w, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(20):
+                sec.matvec(v, w, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            t_mv = e0.elapsed_time(e1) / 20e3
+            # one exchange constant: 4 B slots, diagonal, x_a, 1/R_a, y_a, each
+            # gathered R_b x_b once, and the R o x staging (read R, x, write)
+            nbytes = sec.dim * (4.0 * width + 64.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = sec.eigs(nev=1, seed=1, stream=stream)
+            torch.cuda.synchronize()
+            t_solve = time.perf_counter() - t0
+            res[name] = {"dim": sec.dim, "build_s": t_build, "matvec_us": t_mv * 1e6,
+                         "matvec_GBs": nbytes / t_mv / 1e9, "solve_s": t_solve, "E0": float(r.evals[0]),
+                         "matvecs": r.info.n_matvec, "rc": r.status}
+            del v, w
+            sec.close()
+            print(f"pg K={K} {name} dim {res[name]['dim']} solve {t_solve:.3f}s", file=sys.stderr, flush=True)
+        res["A1_minus_momentum_E0"] = res["A1"]["E0"] - res["momentum"]["E0"]
+        res["momentum_over_A1_solve"] = t_mom / res["A1"]["solve_s"]
+        out["by_n_down"][K] = res
+        torch.cuda.empty_cache()
+    L.close()
+    ctx.close()
+    return out

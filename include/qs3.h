@@ -353,7 +353,9 @@ int qs3_pg_sector_dim(const qs3_pg_sector *sec, uint64_t *dim);
 int qs3_pg_sector_basis(const qs3_pg_sector *sec, uint64_t *ranks, double *norms);
 /* v (device, dim float64) := entries uniform in [-1, 1) from seed. */
 int qs3_pg_start_vector(qs3_pg_sector *sec, uint64_t seed, double *v, void *stream);
-/* w := H v, device float64, dim entries each, no aliasing. */
+/* w := H v, device float64, dim entries each, no aliasing.  With a single
+ * exchange constant the product stages R o v in a buffer of the sector, so
+ * products (and solves) on one sector must not overlap. */
 int qs3_pg_matvec(qs3_pg_sector *sec, const double *v, double *w, void *stream);
 /* As qs3_eigs (QS3_PREC_F64 only); evecs: device, dim x nev (vector y at
  * y*dim), or NULL. */

@@ -18,7 +18,11 @@
 // character sum, and a second kernel resolves every row's hops once into an
 // ELL block (the sectors are |G| times smaller than the fixed-N_down sector,
 // so storing the block costs less than canonicalising |P| images per hop in
-// every product).  H.v is then one pass over the ELL arrays.
+// every product).  H.v is then one pass over the ELL arrays; with one
+// exchange constant the slots shrink to 4 bytes (column and the character's
+// sign), the norm ratio sqrt(N_b / N_a) factored into R_b x_b and 1 / R_a
+// (R o x staged in a per-sector buffer, so products on one sector must not
+// overlap).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,8 +53,15 @@ struct qs3_pg_sector {
     DevBuf chi;    // int32 [n_ops]
     DevBuf reps;   // uint64 [dim]
     DevBuf rnorm;  // double [dim]: sqrt(N_a)
-    DevBuf col;    // int32 [width * dim], slot-major
-    DevBuf val;    // double [width * dim]
+    // ELL block, slot w of row a at w * dim + a.  Uniform exchange (packed):
+    // col holds b | sign << 31 (sign of chi(g)), padding 0xffffffff, and
+    // H_ab = scale_a * sign * R_b with scale_a = (J/2) / R_a.  Otherwise col
+    // holds b (padding a) and val the element.
+    bool packed = false;
+    DevBuf col;    // uint32 [width * dim]
+    DevBuf val;    // double [width * dim] (not packed)
+    DevBuf scale;  // double [dim] (packed)
+    DevBuf xr;     // double [dim] (packed): R o x of the product in progress
     DevBuf diag;   // double [dim]
 };
 
@@ -129,11 +140,11 @@ __global__ void k_pg_classify(PgArgs P, const RT *binom_g, const uint64_t *__res
 }
 
 // Row a of the sector: diagonal and the resolved hops in ELL slots
-// (slot w of row a at w * dim + a; unused slots hold column a and 0).
-template <int K, typename RT>
+// (slot w of row a at w * dim + a).
+template <int K, typename RT, bool PACKED>
 __global__ void k_pg_ell(PgArgs P, LatArgs L, const RT *binom_g, const uint64_t *__restrict__ reps,
-                         const double *__restrict__ rnorm, uint64_t dim, int width, int32_t *col, double *val,
-                         double *diag) {
+                         const double *__restrict__ rnorm, uint64_t dim, int width, uint32_t *col, double *val,
+                         double *scale, double *diag) {
     const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= dim) return;
     Binom<RT> Bn{binom_g, binom_shift(P.N)};
@@ -162,27 +173,77 @@ __global__ void k_pg_ell(PgArgs P, LatArgs L, const RT *binom_g, const uint64_t 
                 if (reps[mid] < (uint64_t)rb) lo = mid + 1; else hi = mid;
             }
             if (lo == dim || reps[lo] != (uint64_t)rb) continue;  // its character sum vanishes
-            const double v = L.jxy_h[e] * (double)(P.chi[p] * kchar(P, tx, ty, tz)) * rnorm[lo] * inv_ra;
-            col[(uint64_t)w * dim + a] = (int32_t)lo;
-            val[(uint64_t)w * dim + a] = v;
+            const int sgn = P.chi[p] * kchar(P, tx, ty, tz);
+            if (PACKED) {
+                col[(uint64_t)w * dim + a] = (uint32_t)lo | (sgn < 0 ? 0x80000000u : 0u);
+            } else {
+                col[(uint64_t)w * dim + a] = (uint32_t)lo;
+                val[(uint64_t)w * dim + a] = L.jxy_h[e] * (double)sgn * rnorm[lo] * inv_ra;
+            }
             ++w;
         }
     }
     for (; w < width; ++w) {
-        col[(uint64_t)w * dim + a] = (int32_t)a;
-        val[(uint64_t)w * dim + a] = 0.0;
+        col[(uint64_t)w * dim + a] = PACKED ? 0xffffffffu : (uint32_t)a;
+        if (!PACKED) val[(uint64_t)w * dim + a] = 0.0;
     }
+    if (PACKED) scale[a] = L.u_jxy_h * inv_ra;
     diag[a] = L.ez4 - dz;
 }
 
-__global__ void k_pg_spmv(const int32_t *__restrict__ col, const double *__restrict__ val,
+// Slots are taken eight at a time: the column loads of a chunk, then its
+// gathers, so that each thread keeps eight gathers in flight.
+constexpr int PG_CH = 8;
+
+__global__ void k_pg_spmv(const uint32_t *__restrict__ col, const double *__restrict__ val,
                           const double *__restrict__ diag, uint64_t dim, int width,
                           const double *__restrict__ x, double *__restrict__ y) {
     const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= dim) return;
     double acc = diag[a] * x[a];
-    for (int w = 0; w < width; ++w) acc += val[(uint64_t)w * dim + a] * x[col[(uint64_t)w * dim + a]];
+    for (int w0 = 0; w0 < width; w0 += PG_CH) {
+        uint32_t cb[PG_CH];
+        double v[PG_CH], t[PG_CH];
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) {
+            const bool in = w0 + i < width;
+            cb[i] = in ? col[(uint64_t)(w0 + i) * dim + a] : (uint32_t)a;
+            v[i] = in ? val[(uint64_t)(w0 + i) * dim + a] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) t[i] = x[cb[i]];
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) acc += v[i] * t[i];
+    }
     y[a] = acc;
+}
+
+// xr = R o x (the packed form gathers R_b x_b in one load)
+__global__ void k_pg_prescale(const double *__restrict__ rnorm, uint64_t dim, const double *__restrict__ x,
+                              double *__restrict__ xr) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < dim) xr[a] = rnorm[a] * x[a];
+}
+
+// Packed form: y_a = diag_a x_a + scale_a * sum over slots of +-xr_b.
+__global__ void k_pg_spmv_packed(const uint32_t *__restrict__ col, const double *__restrict__ xr,
+                                 const double *__restrict__ scale, const double *__restrict__ diag, uint64_t dim,
+                                 int width, const double *__restrict__ x, double *__restrict__ y) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= dim) return;
+    double acc = 0.0;
+    for (int w0 = 0; w0 < width; w0 += PG_CH) {
+        uint32_t cb[PG_CH];
+        double t[PG_CH];
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) cb[i] = w0 + i < width ? col[(uint64_t)(w0 + i) * dim + a] : 0xffffffffu;
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) t[i] = cb[i] == 0xffffffffu ? 0.0 : xr[cb[i] & 0x7fffffffu];
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) acc += (cb[i] >> 31) ? -t[i] : t[i];
+        if (cb[PG_CH - 1] == 0xffffffffu) break;  // slots fill from 0: the rest is padding
+    }
+    y[a] = diag[a] * x[a] + scale[a] * acc;
 }
 
 __global__ void k_pg_start(const uint64_t *__restrict__ reps, uint64_t dim, uint64_t seed, double *v) {
@@ -219,10 +280,11 @@ int classify_K(qs3_pg_sector *sec, const DevBuf &nt_ok, DevBuf &cs, DevBuf &nm) 
 template <int K, typename RT>
 int ell_K(qs3_pg_sector *sec) {
     if (sec->dim == 0) return QS3_OK;
-    hipLaunchKernelGGL((k_pg_ell<K, RT>), dim3(blocks_for(sec->dim, 128)), dim3(128), 0, 0, pg_args(sec),
-                       lat_args(sec->lat), sec->bt->dev.as<RT>(), sec->reps.as<uint64_t>(),
-                       sec->rnorm.as<double>(), sec->dim, sec->width, sec->col.as<int32_t>(),
-                       sec->val.as<double>(), sec->diag.as<double>());
+    auto kern = sec->packed ? k_pg_ell<K, RT, true> : k_pg_ell<K, RT, false>;
+    hipLaunchKernelGGL(kern, dim3(blocks_for(sec->dim, 128)), dim3(128), 0, 0, pg_args(sec), lat_args(sec->lat),
+                       sec->bt->dev.as<RT>(), sec->reps.as<uint64_t>(), sec->rnorm.as<double>(), sec->dim,
+                       sec->width, sec->col.as<uint32_t>(), sec->val.as<double>(), sec->scale.as<double>(),
+                       sec->diag.as<double>());
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }
@@ -385,8 +447,13 @@ int pg_build(qs3_pg_sector *sec) {
     QS3_TRY(sec->reps.alloc(ctx, sizeof(uint64_t) * d1));
     QS3_TRY(sec->rnorm.alloc(ctx, sizeof(double) * d1));
     QS3_TRY(sec->diag.alloc(ctx, sizeof(double) * d1));
-    QS3_TRY(sec->col.alloc(ctx, sizeof(int32_t) * d1 * std::max(sec->width, 1)));
-    QS3_TRY(sec->val.alloc(ctx, sizeof(double) * d1 * std::max(sec->width, 1)));
+    sec->packed = lat->uniform;
+    QS3_TRY(sec->col.alloc(ctx, sizeof(uint32_t) * d1 * std::max(sec->width, 1)));
+    if (sec->packed) {
+        QS3_TRY(sec->scale.alloc(ctx, sizeof(double) * d1));
+        QS3_TRY(sec->xr.alloc(ctx, sizeof(double) * d1));
+    }
+    else QS3_TRY(sec->val.alloc(ctx, sizeof(double) * d1 * std::max(sec->width, 1)));
     if (sec->dim) {
         std::vector<double> rn(sec->dim);
         for (uint64_t a = 0; a < sec->dim; ++a) rn[a] = std::sqrt(sec->h_norm[a]);
@@ -400,8 +467,15 @@ int pg_build(qs3_pg_sector *sec) {
 
 int pg_apply(qs3_pg_sector *sec, const double *x, double *y, hipStream_t s) {
     if (sec->dim == 0) return QS3_OK;
-    hipLaunchKernelGGL(k_pg_spmv, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s, sec->col.as<int32_t>(),
-                       sec->val.as<double>(), sec->diag.as<double>(), sec->dim, sec->width, x, y);
+    if (sec->packed) {
+        hipLaunchKernelGGL(k_pg_prescale, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s, sec->rnorm.as<double>(),
+                           sec->dim, x, sec->xr.as<double>());
+        hipLaunchKernelGGL(k_pg_spmv_packed, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s,
+                           sec->col.as<uint32_t>(), sec->xr.as<double>(), sec->scale.as<double>(),
+                           sec->diag.as<double>(), sec->dim, sec->width, x, y);
+    } else
+        hipLaunchKernelGGL(k_pg_spmv, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s, sec->col.as<uint32_t>(),
+                           sec->val.as<double>(), sec->diag.as<double>(), sec->dim, sec->width, x, y);
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }

@@ -49,7 +49,8 @@ def _chars(lat):
 
 CASES = [(wl.square(4), 2, (0, 0, 0)), (wl.square(4), 3, (2, 2, 0)), (wl.square(4), 4, (0, 0, 0)),
          (wl.square(6), 2, (3, 3, 0)), (wl.chain(14), 5, (7, 0, 0)), (wl.chain(12), 6, (0, 0, 0)),
-         (wl.with_disorder(wl.square(4), seed=3, per_bond=False), 3, (2, 2, 0))]
+         (wl.with_disorder(wl.square(4), seed=3, per_bond=False), 3, (2, 2, 0)),
+         (wl.square_j1j2(4, 0.45), 3, (2, 2, 0)), (wl.square_j1j2(4, 0.45), 4, (0, 0, 0))]
 
 
 def _tol(H, vmax, width):
@@ -63,7 +64,7 @@ def test_pg_sector_against_oracle(qs3, ctx, lat, K, Kv):
     geo = Geometry(*lat.dims)
     bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
     L = qs3.Lattice.of(ctx, lat)
-    width = K * 2 * (2 if lat.ly > 1 else 1)
+    width = K * 2 * (2 if lat.ly > 1 else 1) * (2 if lat.n_bonds > lat.n_sites * 2 else 1)
     for name, chars in _chars(lat):
         print(f"pg {lat.name} K={K} k={Kv} {name}", flush=True)
         sigma, R = mk_list_pg(geo, perms, chars, K, Kv)

@@ -62,7 +62,8 @@ def _U(lat, K, perm):
 
 
 CASES = [(wl.square(4), 2, (0, 0, 0)), (wl.square(4), 3, (2, 2, 0)),
-         (wl.with_disorder(wl.square(4), seed=3, per_bond=False), 3, (0, 0, 0))]
+         (wl.with_disorder(wl.square(4), seed=3, per_bond=False), 3, (0, 0, 0)),
+         (wl.square_j1j2(4, 0.45), 2, (2, 2, 0))]
 
 
 @pytest.mark.parametrize("lat,K,Kv", CASES, ids=lambda x: getattr(x, "name", str(x)))

@@ -91,6 +91,24 @@ def square(L: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
     return hypercubic(L, L, 1, J, Delta, name=f"square{L}x{L}")
 
 
+def square_j1j2(L: int, J2: float, Delta: float = 1.0) -> Lattice:
+    """Periodic L x L square (L >= 3) with J1 = 1 on the edges and J2 on both
+    diagonals of every plaquette: two exchange constants, the C4v symmetry
+    of the square kept."""
+    base = square(L, 1.0, Delta)
+    di, dj = [], []
+    for y in range(L):
+        for x in range(L):
+            for dy in (1, -1):
+                di.append(x + L * y)
+                dj.append((x + 1) % L + L * ((y + dy) % L))
+    n = len(di)
+    return dataclasses.replace(base, name=f"square{L}x{L}+j2", bi=np.concatenate([base.bi, np.array(di, np.int32)]),
+                               bj=np.concatenate([base.bj, np.array(dj, np.int32)]),
+                               jxy=np.concatenate([base.jxy, np.full(n, J2)]),
+                               jz=np.concatenate([base.jz, np.full(n, J2 * Delta)]))
+
+
 def cube(L: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
     return hypercubic(L, L, L, J, Delta, name=f"cube{L}^3")
 
