@@ -1,5 +1,5 @@
 """Momentum sectors on lattices with several sites per unit cell (kagome,
-honeycomb): translations act on the cells.  Representatives and stabilisers
+honeycomb, pyrochlore): translations act on the cells.  Representatives and stabilisers
 bit-exact against the oracle's Alg. 5/6 over the cell translations, H.v and
 the dense block against the oracle's Alg. 8 block, the batched launch over
 all momenta, eigensolvers against dense diagonalisation, and the entry points
@@ -17,6 +17,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 CELLS = [(wl.kagome(2, 2), 3), (wl.kagome(2, 2), 4), (wl.honeycomb(3, 2), 3), (wl.kagome(3, 3), 2),
+         (wl.pyrochlore(2), 3), (wl.pyrochlore(2), 2),
          (wl.honeycomb(2, 2), 0), (wl.with_disorder(wl.kagome(2, 3), seed=6, per_bond=False), 3)]
 
 
@@ -82,7 +83,7 @@ def test_cells_basis_matvec_dense(qs3, lat, K, mode):
     L.close()
 
 
-@pytest.mark.parametrize("lat,K", CELLS[:4], ids=lambda x: getattr(x, "name", str(x)))
+@pytest.mark.parametrize("lat,K", CELLS[:5], ids=lambda x: getattr(x, "name", str(x)))
 def test_cells_batch_and_eigs(qs3, lat, K):
     """All momenta in one batched launch equal the single sectors; lowest two
     distinct levels per sector (batched thick restart) and the sector spectra
@@ -125,7 +126,8 @@ def test_cells_batch_and_eigs(qs3, lat, K):
     bat.close()
 
 
-@pytest.mark.parametrize("lat,K", [(wl.kagome(2, 2), 3), (wl.honeycomb(3, 2), 3), (wl.kagome(2, 2), 4)],
+@pytest.mark.parametrize("lat,K", [(wl.kagome(2, 2), 3), (wl.honeycomb(3, 2), 3), (wl.kagome(2, 2), 4),
+                                   (wl.pyrochlore(2), 2)],
                          ids=lambda x: getattr(x, "name", str(x)))
 def test_cells_observables_vs_oracle(qs3, lat, K):
     """<S^z_i>, <S^z_i S^z_j>, <S^+_i S^-_j> and S(q) (positions with the places'
@@ -143,14 +145,14 @@ def test_cells_observables_vs_oracle(qs3, lat, K):
     R = np.zeros((N, 3))
     for i in range(N):
         s_, c = i % lat.ns, i // lat.ns
-        R[i] = (c % lat.lx, (c // lat.lx) % lat.ly, 0)
+        R[i] = (c % lat.lx, (c // lat.lx) % lat.ly, c // (lat.lx * lat.ly))
         R[i] += lat.basis[s_]
     # momenta of the cell lattice (the translation-averaged form sums over
     # displacements within one period, so S(q) of a momentum sector is taken
     # on this grid), plus a point off the grid for the fixed-N_down sector
-    qs = np.array([[2 * np.pi * kx / lat.lx, 2 * np.pi * ky / lat.ly, 0.0] for kx in range(lat.lx)
-                   for ky in range(lat.ly)])
-    qs_off = np.vstack([qs, [[1.3, -0.7, 0.0]]])
+    qs = np.array([[2 * np.pi * kx / lat.lx, 2 * np.pi * ky / lat.ly, 2 * np.pi * kz / lat.lz]
+                   for (kx, ky, kz) in wl.all_momenta(lat)])
+    qs_off = np.vstack([qs, [[1.3, -0.7, 0.4]]])
     pi = [i for i in range(N) for j in range(N)]
     pj = [j for i in range(N) for j in range(N)]
     for Kv in list(ref)[:4]:
@@ -183,7 +185,8 @@ def test_cells_observables_vs_oracle(qs3, lat, K):
 
 
 @pytest.mark.parametrize("op", ["-", "+", "z"])
-@pytest.mark.parametrize("lat,K", [(wl.kagome(2, 2), 2), (wl.honeycomb(2, 2), 3), (wl.kagome(2, 3), 1)],
+@pytest.mark.parametrize("lat,K", [(wl.kagome(2, 2), 2), (wl.honeycomb(2, 2), 3), (wl.kagome(2, 3), 1),
+                                   (wl.pyrochlore(2), 2)],
                          ids=lambda x: getattr(x, "name", str(x)))
 def test_cells_sq_gather_vs_oracle(qs3, lat, K, op):
     """S^-_q, S^+_q and S^z_q between momentum sectors of a lattice with several

@@ -202,13 +202,14 @@ def test_check_state_compatibility():
 
 
 @pytest.mark.parametrize("make,ns,deg", [(lambda: wl.kagome(3, 4), 3, 4), (lambda: wl.honeycomb(4, 3), 2, 3),
-                                         (lambda: wl.kagome(2, 2), 3, 4)])
+                                         (lambda: wl.kagome(2, 2), 3, 4), (lambda: wl.pyrochlore(2), 4, 6),
+                                         (lambda: wl.pyrochlore(3), 4, 6)])
 def test_cell_lattices(make, ns, deg):
     """The unit-cell workloads: sites = ns * cells, every site has the
     lattice's coordination, each bond appears once, and the bond set is mapped
     onto itself by a translation of the cells (sublattice kept)."""
     lat = make()
-    assert lat.ns == ns and lat.n_sites == ns * lat.lx * lat.ly
+    assert lat.ns == ns and lat.n_sites == ns * lat.lx * lat.ly * lat.lz
     d = np.zeros(lat.n_sites, int)
     seen = set()
     for i, j in zip(lat.bi, lat.bj):
@@ -222,9 +223,33 @@ def test_cell_lattices(make, ns, deg):
 
     def tr(i, ax):
         s, c = i % ns, i // ns
-        x, y = c % lat.lx, c // lat.lx
-        x, y = ((x + 1) % lat.lx, y) if ax == 0 else (x, (y + 1) % lat.ly)
-        return s + ns * (x + lat.lx * y)
-    for ax in (0, 1):
+        x, y, z = c % lat.lx, (c // lat.lx) % lat.ly, c // (lat.lx * lat.ly)
+        x, y, z = [(v + 1) % L if a == ax else v for a, (v, L) in enumerate(zip((x, y, z), lat.dims))]
+        return s + ns * (x + lat.lx * (y + lat.ly * z))
+    for ax in range(3 if lat.lz > 1 else 2):
         moved = {(min(tr(i, ax), tr(j, ax)), max(tr(i, ax), tr(j, ax))) for i, j in seen}
         assert moved == seen
+
+
+def test_pyrochlore_geometry():
+    """Pyrochlore from its geometry alone: with the fcc cell vectors a1 =
+    (0, 1/2, 1/2), a2 = (1/2, 0, 1/2), a3 = (1/2, 1/2, 0) and the places at
+    0 and a_s / 2, the bonds are exactly the pairs at the nearest-neighbour
+    distance sqrt(2)/4 (minimum image over the periodic 3 x 3 x 3 cells)."""
+    lat = wl.pyrochlore(3)
+    A = np.array([[0, .5, .5], [.5, 0, .5], [.5, .5, 0]])
+    N, L = lat.n_sites, 3
+    frac = np.zeros((N, 3))
+    for i in range(N):
+        s, c = i % 4, i // 4
+        frac[i] = (c % L, (c // L) % L, c // (L * L))
+        frac[i] += np.array(lat.basis[s])
+    pairs = set()
+    for i in range(N):
+        for j in range(i + 1, N):
+            df = frac[j] - frac[i]
+            df -= L * np.round(df / L)
+            if abs(np.linalg.norm(df @ A) - np.sqrt(2) / 4) < 1e-12:
+                pairs.add((i, j))
+    assert pairs == {(min(i, j), max(i, j)) for i, j in zip(lat.bi, lat.bj)}
+

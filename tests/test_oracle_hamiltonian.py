@@ -1,6 +1,7 @@
 """Pins of the oracle's Hamiltonian code (Alg. 4, 8, 9) against an independent
 bitmask construction of the spin operators, Hermiticity, spectra, the
 translation eigenvalue, the one-magnon closed form and SU(2) descent."""
+import itertools
 import math
 
 import numpy as np
@@ -20,7 +21,8 @@ def _build():
 
 
 def masks(N, K):
-    return [m for m in range(1 << N) if bin(m).count("1") == K]
+    """Every popcount-K mask below 2^N, ascending (sorted K-subsets, no rank code)."""
+    return sorted(sum(1 << i for i in c) for c in itertools.combinations(range(N), K))
 
 
 def bitmask_H(lat, K):
@@ -164,7 +166,8 @@ def test_k_block_projector_and_translation_eigenvalue(lat, K):
 
 
 CELL_LATS = [(wl.kagome(2, 2), 3), (wl.kagome(2, 2), 4), (wl.honeycomb(3, 2), 3),
-             (wl.honeycomb(2, 2), 2), (wl.with_disorder(wl.kagome(2, 2), seed=4, per_bond=False), 2)]
+             (wl.honeycomb(2, 2), 2), (wl.with_disorder(wl.kagome(2, 2), seed=4, per_bond=False), 2),
+             (wl.pyrochlore(2), 2)]
 
 
 def _order(t, dims):

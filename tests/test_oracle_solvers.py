@@ -266,8 +266,8 @@ def test_sq_scatter_equals_definition_with_stabilisers(op):
 def test_sq_scatter_equals_definition_unit_cells(op):
     """Several sites per cell: the scatter expanded to the U(1) basis equals
     S^op_q applied by definition with positions = cell coordinates + the
-    places' offsets (kagome, honeycomb)."""
-    for lat, K in [(wl.kagome(2, 2), 2), (wl.honeycomb(2, 2), 3), (wl.kagome(2, 2), 1)]:
+    places' offsets (kagome, honeycomb, pyrochlore)."""
+    for lat, K in [(wl.kagome(2, 2), 2), (wl.honeycomb(2, 2), 3), (wl.kagome(2, 2), 1), (wl.pyrochlore(2), 2)]:
         geo = Geometry(lat.lx, lat.ly, lat.lz, lat.ns, lat.basis)
         pos = np.array([geo.position(r) for r in range(1, geo.N + 1)])
         K1 = n_down_after(op, K)

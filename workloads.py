@@ -114,25 +114,29 @@ def cube(L: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
 
 
 def _cell_lattice(name: str, ns: int, lx: int, ly: int, links, J: float, Delta: float,
-                  basis: tuple = ()) -> Lattice:
-    """Periodic lx x ly cells of ns sites; links: (s, t, dx, dy) couples
-    sublattice s of cell (x, y) with sublattice t of cell (x + dx, y + dy)."""
+                  basis: tuple = (), lz: int = 1) -> Lattice:
+    """Periodic lx x ly x lz cells of ns sites; links: (s, t, dx, dy) or
+    (s, t, dx, dy, dz) couples sublattice s of cell (x, y, z) with sublattice
+    t of cell (x + dx, y + dy, z + dz)."""
     seen = set()
     uniq = []
-    for y in range(ly):
-        for x in range(lx):
-            for (s, t, dx, dy) in links:
-                i = s + ns * site_index(x, y, 0, lx, ly)
-                j = t + ns * site_index((x + dx) % lx, (y + dy) % ly, 0, lx, ly)
-                key = (min(i, j), max(i, j))
-                if i == j or key in seen:
-                    continue
-                seen.add(key)
-                uniq.append(key)
+    for z in range(lz):
+        for y in range(ly):
+            for x in range(lx):
+                for link in links:
+                    s, t, dx, dy = link[:4]
+                    dz = link[4] if len(link) > 4 else 0
+                    i = s + ns * site_index(x, y, z, lx, ly)
+                    j = t + ns * site_index((x + dx) % lx, (y + dy) % ly, (z + dz) % lz, lx, ly)
+                    key = (min(i, j), max(i, j))
+                    if i == j or key in seen:
+                        continue
+                    seen.add(key)
+                    uniq.append(key)
     bi = np.array([b[0] for b in uniq], dtype=np.int32)
     bj = np.array([b[1] for b in uniq], dtype=np.int32)
     nb = len(uniq)
-    return Lattice(name, lx, ly, 1, bi, bj, np.full(nb, float(J)), np.full(nb, float(J) * float(Delta)),
+    return Lattice(name, lx, ly, lz, bi, bj, np.full(nb, float(J)), np.full(nb, float(J) * float(Delta)),
                    True, ns, basis)
 
 
@@ -151,6 +155,20 @@ def honeycomb(lx: int, ly: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
     links = [(0, 1, 0, 0), (1, 0, 1, 0), (1, 0, 0, 1)]
     return _cell_lattice(f"honeycomb{lx}x{ly}", 2, lx, ly, links, J, Delta,
                          ((0.0, 0.0, 0.0), (1.0 / 3.0, 1.0 / 3.0, 0.0)))
+
+
+def pyrochlore(L: int, J: float = 1.0, Delta: float = 1.0) -> Lattice:
+    """Pyrochlore lattice: fcc Bravais lattice (a1, a2, a3) with a tetrahedron
+    of four sublattices, 0 at the cell's origin and s = 1..3 at a_s / 2; every
+    site has 6 neighbours (three in the cell's up tetrahedron, three in a down
+    tetrahedron: sublattice s of cell R with 0 of R + a_s and with t of
+    R + a_s - a_t).  L x L x L cells, L >= 2."""
+    up = [(s, t, 0, 0, 0) for s in range(4) for t in range(s + 1, 4)]
+    e = {1: (1, 0, 0), 2: (0, 1, 0), 3: (0, 0, 1)}
+    down = [(s, 0) + e[s] for s in (1, 2, 3)]
+    down += [(s, t) + tuple(a - b for a, b in zip(e[s], e[t])) for s in (1, 2, 3) for t in (1, 2, 3) if s < t]
+    return _cell_lattice(f"pyrochlore{L}^3", 4, L, L, up + down, J, Delta,
+                         ((0.0, 0.0, 0.0), (0.5, 0.0, 0.0), (0.0, 0.5, 0.0), (0.0, 0.0, 0.5)), lz=L)
 
 
 def with_disorder(lat: Lattice, seed: int, jlo: float = 0.5, jhi: float = 1.5,
