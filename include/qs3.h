@@ -357,6 +357,14 @@ int qs3_pg_start_vector(qs3_pg_sector *sec, uint64_t seed, double *v, void *stre
  * exchange constant the product stages R o v in a buffer of the sector, so
  * products (and solves) on one sector must not overlap. */
 int qs3_pg_matvec(qs3_pg_sector *sec, const double *v, double *w, void *stream);
+/* The same states in the momentum sector: out (device, complex float64,
+ * msec's dim) := sum_a v_a |a, k, chi> in msec's basis, msec the momentum
+ * sector of the same lattice handle, n_down and k (else QS3_EINVAL).  Each
+ * term of the space-group sum is grouped by point operation: P_p a is a
+ * translate T^{-t} u of a representative u, contributing chi(p) e^{i k.t}
+ * sqrt(N_T s_u / N_a) to u (Eq. (akstate) for u).  Every momentum-sector
+ * observable, S^a_q and S(q, omega) then applies to point-group states. */
+int qs3_pg_to_momentum(qs3_pg_sector *sec, const double *v, qs3_sector *msec, void *out, void *stream);
 /* As qs3_eigs (QS3_PREC_F64 only); evecs: device, dim x nev (vector y at
  * y*dim), or NULL. */
 int qs3_pg_eigs(qs3_pg_sector *sec, const qs3_eigs_opts *opts, double *evals, double *evecs,

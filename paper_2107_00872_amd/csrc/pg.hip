@@ -246,6 +246,46 @@ __global__ void k_pg_spmv_packed(const uint32_t *__restrict__ col, const double 
     y[a] = diag[a] * x[a] + scale[a] * acc;
 }
 
+// The momentum-sector amplitudes of sum_a x_a |a, k, chi>: grouping the
+// space-group sum by point operation, T-sum of P_p a = T^{-t} u is
+// e^{i k.t} sqrt(N_T s_u) |u, k>, so u (compact index i) receives
+// x_a / sqrt(N_a) * chi(p) e^{i k.t} sqrt(N_T s_u).  Different
+// representatives a have disjoint orbits, so every i is written by one thread.
+template <int K, typename RT>
+__global__ void k_pg_expand(PgArgs P, const RT *binom_g, const uint64_t *__restrict__ reps,
+                            const double *__restrict__ rnorm, uint64_t dim, const double *__restrict__ x,
+                            const uint64_t *__restrict__ kreps, const uint16_t *__restrict__ kstab,
+                            const int64_t *__restrict__ comp2u, uint64_t kdim, double n_t, double2 *out) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= dim) return;
+    Binom<RT> Bn{binom_g, binom_shift(P.N)};
+    int c[K];
+    unrank<K, RT>((RT)reps[a], P.N, Bn, c);
+    const double xa = x[a] / rnorm[a];
+    for (int p = 0; p < P.n_ops; ++p) {
+        int img[K], can[K];
+#pragma unroll
+        for (int m = 0; m < K; ++m) img[m] = P.perm[p * P.N + c[m]];
+        sortK<K>(img);
+        int tx, ty, tz;
+        canonicalize<K>(img, P.g, can, tx, ty, tz);
+        const uint64_t r = (uint64_t)rank_of<K, RT>(can, Bn);
+        uint64_t lo = 0, hi = kdim;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (kreps[comp2u[mid]] < r) lo = mid + 1; else hi = mid;
+        }
+        if (lo == kdim || kreps[comp2u[lo]] != r) continue;  // not reached for a valid pair of sectors
+        const double sgn = (double)(P.chi[p] * kchar(P, tx, ty, tz));
+        out[lo].x += xa * sgn * sqrt(n_t * (double)kstab[comp2u[lo]]);
+    }
+}
+
+__global__ void k_pg_zero2(uint64_t n, double2 *p) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = make_double2(0.0, 0.0);
+}
+
 __global__ void k_pg_start(const uint64_t *__restrict__ reps, uint64_t dim, uint64_t seed, double *v) {
     const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a < dim) v[a] = u01_pm1(splitmix64(seed, reps[a]));
@@ -294,6 +334,38 @@ int dispatch_rt(qs3_pg_sector *sec, bool ell, const DevBuf *nt_ok, DevBuf *cs, D
     if (sec->bt->wide)
         return ell ? ell_K<K, uint64_t>(sec) : classify_K<K, uint64_t>(sec, *nt_ok, *cs, *nm);
     return ell ? ell_K<K, uint32_t>(sec) : classify_K<K, uint32_t>(sec, *nt_ok, *cs, *nm);
+}
+
+struct ExpandArgs {
+    const double *x;
+    const qs3_sector *msec;
+    double2 *out;
+    hipStream_t s;
+};
+
+template <int K, typename RT>
+int expand_K(qs3_pg_sector *sec, const ExpandArgs &E) {
+    const KStructure &ks = *E.msec->bat->ks;
+    const double n_t = (double)sec->lat->lx * sec->lat->ly * sec->lat->lz;
+    hipLaunchKernelGGL((k_pg_expand<K, RT>), dim3(blocks_for(sec->dim, 128)), dim3(128), 0, E.s, pg_args(sec),
+                       sec->bt->dev.as<RT>(), sec->reps.as<uint64_t>(), sec->rnorm.as<double>(), sec->dim, E.x,
+                       ks.reps.as<uint64_t>(), ks.stab.as<uint16_t>(), E.msec->comp2u.as<int64_t>(), E.msec->dim,
+                       n_t, E.out);
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+int dispatch_expand(qs3_pg_sector *sec, const ExpandArgs &E) {
+    const bool w = sec->bt->wide;
+    switch (sec->K) {
+        case 1: return w ? expand_K<1, uint64_t>(sec, E) : expand_K<1, uint32_t>(sec, E);
+        case 2: return w ? expand_K<2, uint64_t>(sec, E) : expand_K<2, uint32_t>(sec, E);
+        case 3: return w ? expand_K<3, uint64_t>(sec, E) : expand_K<3, uint32_t>(sec, E);
+        case 4: return w ? expand_K<4, uint64_t>(sec, E) : expand_K<4, uint32_t>(sec, E);
+        case 5: return w ? expand_K<5, uint64_t>(sec, E) : expand_K<5, uint32_t>(sec, E);
+        case 6: return w ? expand_K<6, uint64_t>(sec, E) : expand_K<6, uint32_t>(sec, E);
+        default: set_error("n_down out of range"); return QS3_EINVAL;
+    }
 }
 
 int dispatch(qs3_pg_sector *sec, bool ell, const DevBuf *nt_ok = nullptr, DevBuf *cs = nullptr,
@@ -567,6 +639,20 @@ int qs3_pg_matvec(qs3_pg_sector *sec, const double *v, double *w, void *stream) 
     QS3_REQUIRE(v != w, QS3_EINVAL, "v and w must not alias");
     (void)hipSetDevice(sec->lat->ctx->device);
     return pg_apply(sec, v, w, (hipStream_t)stream);
+}
+
+int qs3_pg_to_momentum(qs3_pg_sector *sec, const double *v, qs3_sector *msec, void *out, void *stream) {
+    QS3_REQUIRE(sec && v && msec && out, QS3_EINVAL, "NULL argument");
+    QS3_REQUIRE(msec->has_k && msec->lat == sec->lat && msec->K == sec->K && msec->kv[0] == sec->kv[0] &&
+                    msec->kv[1] == sec->kv[1] && msec->kv[2] == sec->kv[2],
+                QS3_EINVAL, "msec must be the momentum sector of the same lattice, n_down and k");
+    (void)hipSetDevice(sec->lat->ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (msec->dim)
+        hipLaunchKernelGGL(k_pg_zero2, dim3(blocks_for(msec->dim, 256)), dim3(256), 0, s, msec->dim, (double2 *)out);
+    QS3_HIP(hipGetLastError());
+    if (sec->dim == 0 || msec->dim == 0) return QS3_OK;
+    return dispatch_expand(sec, ExpandArgs{v, msec, (double2 *)out, s});
 }
 
 int qs3_pg_eigs(qs3_pg_sector *sec, const qs3_eigs_opts *opts, double *evals, double *evecs,

@@ -112,6 +112,7 @@ SIGNATURES = [
     ("qs3_pg_start_vector", ctypes.c_int, [P, u64, P, P]),
     ("qs3_pg_matvec", ctypes.c_int, [P, P, P, P]),
     ("qs3_pg_eigs", ctypes.c_int, [P, P, P, P, P, P]),
+    ("qs3_pg_to_momentum", ctypes.c_int, [P, P, P, P, P]),
 ]
 
 _lib = None
@@ -448,6 +449,14 @@ class PGSector:
                                _stream(stream))
         check(rc, allow=(QS3_OK, QS3_ENOCONV))
         return EigsResult(ev[:nev], info, rc)
+
+    def to_momentum(self, v, msec, out=None, stream=None):
+        """The vector in the momentum sector msec (same lattice, n_down, k)."""
+        import torch
+        if out is None:
+            out = torch.empty(msec.dim, dtype=torch.complex128, device="cuda")
+        check(lib().qs3_pg_to_momentum(self.h, _ptr(v), msec.h, _ptr(out), _stream(stream)))
+        return out
 
     def close(self):
         if self.h:

@@ -228,3 +228,60 @@ def test_pg_refuses_non_groups(qs3, ctx):
     with pytest.raises(qs3.QS3Error):
         qs3.PGSector(kag, 2, (0, 0, 0), np.arange(12, dtype=np.int32)[None, :], [1])
     kag.close()
+
+
+@pytest.mark.parametrize("lat,K,Kv", [(wl.square(4), 3, (2, 2, 0)), (wl.square(4), 4, (0, 0, 0)),
+                                      (wl.chain(12), 4, (6, 0, 0)), (wl.square_j1j2(4, 0.45), 3, (0, 0, 0))],
+                         ids=lambda x: getattr(x, "name", str(x)))
+def test_pg_to_momentum_against_oracle(qs3, ctx, lat, K, Kv):
+    """A seeded point-group vector carried into the momentum sector: the
+    oracle's expansion by the definition (sum over the space group) projected
+    on the oracle's momentum basis states."""
+    from oracle.pointgroup import expand_pg
+    from oracle.translation import expand_to_u1, mk_list
+    perms = _ops(lat)
+    geo = Geometry(*lat.dims)
+    L = qs3.Lattice.of(ctx, lat)
+    s_k, R_k = mk_list(geo, K, Kv)
+    Bk = np.stack([expand_to_u1(geo, K, s_k, R_k, Kv, np.eye(len(s_k))[i]) for i in range(len(s_k))], axis=1)
+    msec = qs3.Sector(L, K, Kv)
+    assert msec.dim == len(s_k)
+    for name, chars in _chars(lat):
+        sigma, R = mk_list_pg(geo, perms, chars, K, Kv)
+        if not sigma:
+            continue
+        sec = qs3.PGSector(L, K, Kv, perms, chars)
+        phi = np.random.default_rng(17).normal(size=len(sigma))
+        psi = sec.to_momentum(torch.from_numpy(phi).cuda(), msec).cpu().numpy()
+        want = Bk.conj().T @ expand_pg(geo, perms, chars, K, sigma, R, Kv, phi)
+        assert np.abs(psi - want).max() < 1e-12 * max(1.0, np.abs(phi).max()), name
+        sec.close()
+    msec.close()
+    L.close()
+
+
+def test_pg_ground_state_in_momentum_sector(qs3, ctx):
+    """10 x 10 square, N_down = 4, k = 0: the A1 ground state carried into the
+    momentum sector is a unit eigenvector of the momentum block with the same
+    level, and its magnetisation is uniform."""
+    lat = wl.square(10)
+    L = qs3.Lattice.of(ctx, lat)
+    sec = qs3.PGSector(L, 4, (0, 0, 0), wl.c4v_ops(10), wl.C4V_CHARS["A1"])
+    X = torch.zeros(sec.dim, dtype=torch.float64, device="cuda")
+    r = sec.eigs(nev=1, evecs=X, seed=4)
+    msec = qs3.Sector(L, 4, (0, 0, 0))
+    psi = sec.to_momentum(X, msec)
+    w = torch.empty_like(psi)
+    msec.matvec(psi, w)
+    e = r.evals[0]
+    assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-12
+    assert torch.linalg.vector_norm(w - e * psi).item() < 1e-7 * abs(e)
+    sz = msec.sz(psi)
+    assert np.abs(sz - (0.5 - 4 / 100)).max() < 1e-10
+    other = qs3.Sector(L, 4, (5, 5, 0))
+    with pytest.raises(qs3.QS3Error):
+        sec.to_momentum(X, other)
+    other.close()
+    sec.close()
+    msec.close()
+    L.close()
