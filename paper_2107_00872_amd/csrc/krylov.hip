@@ -602,55 +602,116 @@ int gather_compact_f32(qs3_sector *sec, const float *src_union, float *dst, hipS
 }
 
 // ------------------------------------------------------------------ host eigensolver
-// Cyclic Jacobi for a real symmetric n x n matrix A (row-major, destroyed):
-// eigenvalues ascending in e, eigenvectors as columns of V (row-major n x n).
-void jacobi_eig(int n, std::vector<double> &A, std::vector<double> &e, std::vector<double> &V) {
-    V.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+// Eigen-decomposition of a real symmetric n x n matrix A (row-major; A is
+// overwritten): Householder reduction to tridiagonal form with the
+// transformation accumulated, then implicit QL with Wilkinson shifts applied
+// to the columns of that transformation.  e ascending, V[i * n + k] = row i
+// of eigenvector k.
+void sym_eig(int n, std::vector<double> &A, std::vector<double> &e, std::vector<double> &V) {
     auto a = [&](int i, int j) -> double & { return A[(size_t)i * n + j]; };
-    double fro = 0;
-    for (double x : A) fro += x * x;
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0;
-        for (int i = 0; i < n; ++i)
-            for (int j = i + 1; j < n; ++j) off += a(i, j) * a(i, j);
-        if (off <= 1e-34 * fro || off == 0.0) break;
-        for (int p = 0; p < n; ++p) {
-            for (int q = p + 1; q < n; ++q) {
-                const double apq = a(p, q);
-                if (apq == 0.0) continue;
-                const double app = a(p, p), aqq = a(q, q);
-                const double theta = (aqq - app) / (2.0 * apq);
-                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-                for (int k = 0; k < n; ++k) {  // columns p, q
-                    const double akp = a(k, p), akq = a(k, q);
-                    a(k, p) = c * akp - s * akq;
-                    a(k, q) = s * akp + c * akq;
+    // Z holds the transformation column-major (column j at Z + j * n), so
+    // that both updates below run along contiguous columns
+    std::vector<double> Z((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+    std::vector<double> v(n), p(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        // reflector H = I - c v v^T on rows/columns k+1.. that zeroes a(k+2.., k)
+        double tail = 0;
+        for (int i = k + 2; i < n; ++i) tail += a(i, k) * a(i, k);
+        if (tail == 0.0) continue;  // the column is already tridiagonal
+        const double xn = std::sqrt(tail + a(k + 1, k) * a(k + 1, k));
+        const double alpha = a(k + 1, k) > 0 ? -xn : xn;
+        double vn = 0;
+        for (int i = k + 1; i < n; ++i) {
+            v[i] = a(i, k) - (i == k + 1 ? alpha : 0.0);
+            vn += v[i] * v[i];
+        }
+        if (vn == 0.0) continue;
+        const double c = 2.0 / vn;
+        // trailing block: A <- A - v w^T - w v^T, p = c A v, w = p - (c v.p / 2) v
+        double vp = 0;
+        for (int i = k + 1; i < n; ++i) {
+            double s = 0;
+            for (int j = k + 1; j < n; ++j) s += a(i, j) * v[j];
+            p[i] = c * s;
+            vp += v[i] * p[i];
+        }
+        const double K2 = 0.5 * c * vp;
+        for (int i = k + 1; i < n; ++i) p[i] -= K2 * v[i];
+        for (int i = k + 1; i < n; ++i)
+            for (int j = k + 1; j < n; ++j) a(i, j) -= v[i] * p[j] + p[i] * v[j];
+        a(k + 1, k) = a(k, k + 1) = alpha;
+        for (int i = k + 2; i < n; ++i) a(i, k) = a(k, i) = 0.0;
+        // Z <- Z H: every row r loses c (Z_r . v) v
+        std::fill(p.begin(), p.end(), 0.0);
+        for (int j = k + 1; j < n; ++j) {
+            const double *zj = &Z[(size_t)j * n];
+            for (int r = 0; r < n; ++r) p[r] += zj[r] * v[j];
+        }
+        for (int j = k + 1; j < n; ++j) {
+            double *zj = &Z[(size_t)j * n];
+            const double cv = c * v[j];
+            for (int r = 0; r < n; ++r) zj[r] -= cv * p[r];
+        }
+    }
+    std::vector<double> d(n), sub(n, 0.0);
+    for (int i = 0; i < n; ++i) d[i] = a(i, i);
+    for (int i = 0; i + 1 < n; ++i) sub[i] = a(i + 1, i);
+    const double eps = std::numeric_limits<double>::epsilon();
+    for (int l = 0; l < n; ++l) {
+        int iter = 0;
+        for (;;) {
+            int m = l;
+            for (; m + 1 < n; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(sub[m]) <= eps * dd) break;
+            }
+            if (m == l || iter++ > 90) break;
+            double g = (d[l + 1] - d[l]) / (2.0 * sub[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + sub[l] / (g + std::copysign(r, g));
+            double sn = 1.0, cs = 1.0, pp = 0.0;
+            bool underflow = false;
+            for (int i = m - 1; i >= l; --i) {
+                const double f = sn * sub[i], bb = cs * sub[i];
+                r = std::sqrt(f * f + g * g);
+                sub[i + 1] = r;
+                if (r == 0.0) {
+                    d[i + 1] -= pp;
+                    sub[m] = 0.0;
+                    underflow = true;
+                    break;
                 }
-                for (int k = 0; k < n; ++k) {  // rows p, q
-                    const double apk = a(p, k), aqk = a(q, k);
-                    a(p, k) = c * apk - s * aqk;
-                    a(q, k) = s * apk + c * aqk;
-                }
-                for (int k = 0; k < n; ++k) {
-                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-                    V[(size_t)k * n + p] = c * vkp - s * vkq;
-                    V[(size_t)k * n + q] = s * vkp + c * vkq;
+                sn = f / r;
+                cs = g / r;
+                g = d[i + 1] - pp;
+                r = (d[i] - g) * sn + 2.0 * cs * bb;
+                pp = sn * r;
+                d[i + 1] = g + pp;
+                g = cs * r - bb;
+                double *zi = &Z[(size_t)i * n], *zi1 = &Z[(size_t)(i + 1) * n];
+                for (int k = 0; k < n; ++k) {  // the same rotation on columns i, i+1
+                    const double t = zi1[k];
+                    zi1[k] = sn * zi[k] + cs * t;
+                    zi[k] = cs * zi[k] - sn * t;
                 }
             }
+            if (underflow) continue;
+            d[l] -= pp;
+            sub[l] = g;
+            sub[m] = 0.0;
         }
     }
     std::vector<int> idx(n);
     for (int i = 0; i < n; ++i) idx[i] = i;
-    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return a(x, x) < a(y, y); });
+    std::sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
     e.resize(n);
-    std::vector<double> V2((size_t)n * n);
+    V.assign((size_t)n * n, 0.0);
     for (int k = 0; k < n; ++k) {
-        e[k] = a(idx[k], idx[k]);
-        for (int i = 0; i < n; ++i) V2[(size_t)i * n + k] = V[(size_t)i * n + idx[k]];
+        e[k] = d[idx[k]];
+        const double *zk = &Z[(size_t)idx[k] * n];
+        for (int i = 0; i < n; ++i) V[(size_t)i * n + k] = zk[i];
     }
-    V.swap(V2);
 }
 
 // ------------------------------------------------------------------ engine
@@ -1105,7 +1166,9 @@ static void tridiag_vector(int n, const double *d, const double *e, double lam, 
 // a batch: eigensolves of small tridiagonal / arrowhead matrices).
 template <typename F>
 static void parallel_columns(int n, F &&f) {
-    const int nt = std::min(16, std::max(1, n / 8));
+    // about 25 us of host work per column (a 20 x 20 restart eigenproblem):
+    // one thread per 16 columns keeps the thread start-up below the work
+    const int nt = std::min(16, std::max(1, n / 16));
     if (nt <= 1) {
         for (int c = 0; c < n; ++c) f(c);
         return;
@@ -1349,7 +1412,7 @@ int SolveRun::advance(bool *done) {
             for (int y = 0; y < NK; ++y) T[(size_t)y * NM + NK] = T[(size_t)NK * NM + y] = coup[c][y];
             for (int z = NK; z + 1 < NM; ++z) T[(size_t)z * NM + z + 1] = T[(size_t)(z + 1) * NM + z] = be[c][z];
         }
-        jacobi_eig(NM, T, e, V);
+        sym_eig(NM, T, e, V);
         const double bm = be[c][NM - 1];
         std::vector<double> res(NM);
         for (int i = 0; i < NM; ++i) res[i] = std::fabs(bm * V[(size_t)(NM - 1) * NM + i]);

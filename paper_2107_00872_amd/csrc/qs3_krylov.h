@@ -125,7 +125,7 @@ struct SolveRun {
 int solve_blocking(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &o, const double *v0, hipStream_t s,
                    std::vector<double> &evals, std::vector<qs3_eigs_info> &info, double *vec_out);
 
-void jacobi_eig(int n, std::vector<double> &A, std::vector<double> &e, std::vector<double> &V);
+void sym_eig(int n, std::vector<double> &A, std::vector<double> &e, std::vector<double> &V);
 int run_lanczos(Engine &E, const double *v0, int steps, std::vector<double> &a_out,
                 std::vector<double> &b_out, std::vector<double> &norm0, std::vector<int> &done);
 
