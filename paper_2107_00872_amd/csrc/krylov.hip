@@ -180,20 +180,36 @@ __global__ __launch_bounds__(256) void k_cgs_update_norm(RedGeom g, double *__re
     const double fb = (on && f.P0 && f.P1) ? f.beta[b] : 0.0;
     double acc = 0.0;
     if (on) {
-        for (uint64_t r = r0 + tr; r < r1; r += g.TR) {
+        // complex: two rows per pass, so each coefficient load serves both
+        for (uint64_t r = r0 + tr; CPLX && r < r1; r += 2 * (uint64_t)g.TR) {
+            const uint64_t e = r * g.B + b, e2 = (r + g.TR) * g.B + b;
+            const bool two = r + g.TR < r1;
+            double2 w = ((double2 *)W)[e];
+            double2 w2 = two ? ((double2 *)W)[e2] : make_double2(0.0, 0.0);
+            if (f.P0) {
+                w = three_term(w, e, f, fa, fb);
+                if (two) w2 = three_term(w2, e2, f, fa, fb);
+            }
+            for (int jj = 0; jj < J; ++jj) {
+                const double2 *xj = (const double2 *)(X + (size_t)jj * stride);
+                const double2 c = h[(size_t)jj * g.B + b];
+                const double2 x = xj[e];
+                const double2 x2 = two ? xj[e2] : make_double2(0.0, 0.0);
+                w.x -= x.x * c.x - x.y * c.y;
+                w.y -= x.x * c.y + x.y * c.x;
+                w2.x -= x2.x * c.x - x2.y * c.y;
+                w2.y -= x2.x * c.y + x2.y * c.x;
+            }
+            ((double2 *)W)[e] = w;
+            acc += w.x * w.x + w.y * w.y;
+            if (two) {
+                ((double2 *)W)[e2] = w2;
+                acc += w2.x * w2.x + w2.y * w2.y;
+            }
+        }
+        for (uint64_t r = r0 + tr; !CPLX && r < r1; r += g.TR) {
             const uint64_t e = r * g.B + b;
-            if (CPLX) {
-                double2 w = ((double2 *)W)[e];
-                if (f.P0) w = three_term(w, e, f, fa, fb);
-                for (int jj = 0; jj < J; ++jj) {
-                    const double2 x = ((const double2 *)(X + (size_t)jj * stride))[e];
-                    const double2 c = h[(size_t)jj * g.B + b];
-                    w.x -= x.x * c.x - x.y * c.y;
-                    w.y -= x.x * c.y + x.y * c.x;
-                }
-                ((double2 *)W)[e] = w;
-                acc += w.x * w.x + w.y * w.y;
-            } else {
+            {
                 double w = W[e];
                 if (f.P0) w = three_term(w, e, f, fa, fb);
                 for (int jj = 0; jj < J; ++jj) w -= X[(size_t)jj * stride + e] * h[(size_t)jj * g.B + b].x;
