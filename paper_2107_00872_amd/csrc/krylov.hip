@@ -982,15 +982,26 @@ int Engine::read_ab(int x0, int x1, std::vector<double> &a, std::vector<double> 
     return QS3_OK;
 }
 
-int Engine::rotate_dev(int from_slot, int NX, const double *dC, int NY, int to_slot, const uint8_t *act_dev) {
-    constexpr int RPT = 2;
-    const uint64_t part = (n + RPT - 1) / RPT * (uint64_t)B;
+template <int NYT>
+static void launch_rotate(bool cplx, dim3 grid, hipStream_t st, uint64_t ne, int B, const double *X, uint64_t stride,
+                          int NX, const double *dC, int NY, double *out, const uint8_t *act) {
     if (cplx)
-        hipLaunchKernelGGL((k_rotate<true, 16, RPT>), grid1(part), dim3(256), 0, st, ne, B, slot(from_slot),
-                           stride, NX, dC, NY, slot(to_slot), act_dev);
+        hipLaunchKernelGGL((k_rotate<true, NYT, 2>), grid, dim3(256), 0, st, ne, B, X, stride, NX, dC, NY, out, act);
     else
-        hipLaunchKernelGGL((k_rotate<false, 16, RPT>), grid1(part), dim3(256), 0, st, ne, B, slot(from_slot),
-                           stride, NX, dC, NY, slot(to_slot), act_dev);
+        hipLaunchKernelGGL((k_rotate<false, NYT, 2>), grid, dim3(256), 0, st, ne, B, X, stride, NX, dC, NY, out, act);
+}
+
+int Engine::rotate_dev(int from_slot, int NX, const double *dC, int NY, int to_slot, const uint8_t *act_dev) {
+    // two rows per thread; the accumulator tile is the smallest of 8, 12, 16
+    // outputs that holds NY (fewer registers, more waves in flight)
+    const uint64_t part = (n + 1) / 2 * (uint64_t)B;
+    const dim3 grid = grid1(part);
+    if (NY <= 8)
+        launch_rotate<8>(cplx, grid, st, ne, B, slot(from_slot), stride, NX, dC, NY, slot(to_slot), act_dev);
+    else if (NY <= 12)
+        launch_rotate<12>(cplx, grid, st, ne, B, slot(from_slot), stride, NX, dC, NY, slot(to_slot), act_dev);
+    else
+        launch_rotate<16>(cplx, grid, st, ne, B, slot(from_slot), stride, NX, dC, NY, slot(to_slot), act_dev);
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }
