@@ -404,9 +404,11 @@ __global__ void k_copy_re(int B, const double2 *__restrict__ in, double *__restr
 // masked by active[b].  Each thread takes RPT elements of one column, RPT
 // equal row blocks apart, so that every coefficient it loads serves RPT rows.
 template <bool CPLX, int NYT, int RPT>
-__global__ __launch_bounds__(256) void k_rotate(uint64_t ne, int B, const double *__restrict__ X,
+// Out may be X itself when NY <= NYT: a thread then reads every input of its
+// elements before it writes any output, and no other thread touches them.
+__global__ __launch_bounds__(256) void k_rotate(uint64_t ne, int B, const double *X,
                                                 uint64_t stride, int NX, const double *__restrict__ Cm,
-                                                int NY, double *__restrict__ Out,
+                                                int NY, double *Out,
                                                 const uint8_t *__restrict__ active) {
     const uint64_t rows = ne / (uint64_t)B;
     const uint64_t part = (rows + RPT - 1) / RPT * (uint64_t)B;  // elements per row block
@@ -1252,7 +1254,9 @@ SolveRun::~SolveRun() {
 }
 
 int SolveRun::slots_for(const qs3_eigs_opts &o) {
-    return o.alg == QS3_ALG_TRL ? o.nm + 1 + o.nk : o.steps + 1 + o.nev;
+    // thick restart: N_M + 1 basis vectors, plus N_K staging slots for the
+    // rotation only when it cannot run in place (N_K > 16)
+    return o.alg == QS3_ALG_TRL ? o.nm + 1 + (o.nk > 16 ? o.nk : 0) : o.steps + 1 + o.nev;
 }
 
 int SolveRun::init(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &opts, hipStream_t s) {
@@ -1476,12 +1480,18 @@ int SolveRun::advance(bool *done) {
             ++n_next;
         }
     }
-    // Ritz vectors into slots NM+1.., then back into 0..NK-1 (rotated columns)
+    // Ritz vectors into slots 0..NK-1 (rotated columns; through slots NM+1..
+    // when NK needs more than one accumulator tile)
     QS3_HIP(hipMemcpyAsync(dC.ptr, hC, sizeof(double) * (size_t)Bc * NM * NK, hipMemcpyHostToDevice, E.st));
     QS3_HIP(hipMemcpyAsync(dact.ptr, hact, 2 * (size_t)Bc, hipMemcpyHostToDevice, E.st));
     const uint8_t *d_rot = dact.as<uint8_t>(), *d_next = dact.as<uint8_t>() + Bc;
-    QS3_TRY(E.rotate_dev(0, NM, dC.as<double>(), NK, NM + 1, d_rot));
-    for (int y = 0; y < NK; ++y) QS3_TRY(E.copy_slot_dev(NM + 1 + y, y, d_rot));
+    if (NK <= 16) {
+        // one accumulator tile: the rotation can overwrite slots 0..NK-1 in place
+        QS3_TRY(E.rotate_dev(0, NM, dC.as<double>(), NK, 0, d_rot));
+    } else {
+        QS3_TRY(E.rotate_dev(0, NM, dC.as<double>(), NK, NM + 1, d_rot));
+        for (int y = 0; y < NK; ++y) QS3_TRY(E.copy_slot_dev(NM + 1 + y, y, d_rot));
+    }
     if (!any_active || restarts >= o.max_restarts) {
         QS3_HIP(hipEventRecord(ev, E.st));
         phase = 4;

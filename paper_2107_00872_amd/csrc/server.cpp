@@ -84,7 +84,7 @@ static uint64_t footprint(const qs3_request &q, const qs3_eigs_opts &o) {
     const double D = binom_d(N, q.n_down);
     const double rows = q.use_k ? D / N * 1.05 + 64 : D;
     const double elem = q.use_k ? 16.0 : 8.0;
-    const double slots = (o.alg == QS3_ALG_TRL ? o.nm + 1 + o.nk : o.steps + 1 + o.nev) + 2 +
+    const double slots = qs3::SolveRun::slots_for(o) + 2 +
                          (o.precision == QS3_PREC_F32MV ? 0.5 : 0.0);
     double bytes = rows * elem * slots + 4.0 * 1024 * 1024;
     if (q.use_k) {
