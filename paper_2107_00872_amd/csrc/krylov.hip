@@ -118,18 +118,26 @@ __global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__res
 #pragma unroll
         for (int q = 0; q < JM; ++q) sr[q] = si[q] = 0.0;
         if (on) {
-            for (uint64_t r = r0 + tr; r < r1; r += g.TR) {
-                const uint64_t e = r * g.B + b;
-                T y = Yt[e];
-                if (f.P0) y = three_term(y, e, f, fa, fb);
+            // two rows (r, r + TR) per pass, each output summed in row order
+            for (uint64_t r = r0 + tr; r < r1; r += 2 * (uint64_t)g.TR) {
+                const uint64_t e = r * g.B + b, e2 = (r + g.TR) * g.B + b;
+                const bool two = r + g.TR < r1;
+                T y = Yt[e], y2 = two ? Yt[e2] : T{};
+                if (f.P0) {
+                    y = three_term(y, e, f, fa, fb);
+                    if (two) y2 = three_term(y2, e2, f, fa, fb);
+                }
 #pragma unroll
                 for (int q = 0; q < JM; ++q) {
                     const int jj = j0 + q;
                     if (jj < J) {
-                        const T x = ((const T *)(X + (size_t)jj * stride))[e];
+                        const T *xj = (const T *)(X + (size_t)jj * stride);
+                        const T x = xj[e], x2 = two ? xj[e2] : T{};
                         cdot_acc(x, y, sr[q], si[q]);
+                        if (two) cdot_acc(x2, y2, sr[q], si[q]);
                     } else if (jj == J && selfdot) {
                         cdot_acc(y, y, sr[q], si[q]);
+                        if (two) cdot_acc(y2, y2, sr[q], si[q]);
                     }
                 }
             }
@@ -180,7 +188,7 @@ __global__ __launch_bounds__(256) void k_cgs_update_norm(RedGeom g, double *__re
     const double fb = (on && f.P0 && f.P1) ? f.beta[b] : 0.0;
     double acc = 0.0;
     if (on) {
-        // complex: two rows per pass, so each coefficient load serves both
+        // two rows per pass, so each coefficient load serves both
         for (uint64_t r = r0 + tr; CPLX && r < r1; r += 2 * (uint64_t)g.TR) {
             const uint64_t e = r * g.B + b, e2 = (r + g.TR) * g.B + b;
             const bool two = r + g.TR < r1;
@@ -207,14 +215,25 @@ __global__ __launch_bounds__(256) void k_cgs_update_norm(RedGeom g, double *__re
                 acc += w2.x * w2.x + w2.y * w2.y;
             }
         }
-        for (uint64_t r = r0 + tr; !CPLX && r < r1; r += g.TR) {
-            const uint64_t e = r * g.B + b;
-            {
-                double w = W[e];
-                if (f.P0) w = three_term(w, e, f, fa, fb);
-                for (int jj = 0; jj < J; ++jj) w -= X[(size_t)jj * stride + e] * h[(size_t)jj * g.B + b].x;
-                W[e] = w;
-                acc += w * w;
+        for (uint64_t r = r0 + tr; !CPLX && r < r1; r += 2 * (uint64_t)g.TR) {
+            const uint64_t e = r * g.B + b, e2 = (r + g.TR) * g.B + b;
+            const bool two = r + g.TR < r1;
+            double w = W[e], w2 = two ? W[e2] : 0.0;
+            if (f.P0) {
+                w = three_term(w, e, f, fa, fb);
+                if (two) w2 = three_term(w2, e2, f, fa, fb);
+            }
+            for (int jj = 0; jj < J; ++jj) {
+                const double c = h[(size_t)jj * g.B + b].x;
+                const double *xj = X + (size_t)jj * stride;
+                w -= xj[e] * c;
+                if (two) w2 -= xj[e2] * c;
+            }
+            W[e] = w;
+            acc += w * w;
+            if (two) {
+                W[e2] = w2;
+                acc += w2 * w2;
             }
         }
     }
