@@ -305,17 +305,26 @@ __global__ void k_omega(int B, int x, const double *__restrict__ ab, int slots, 
     flag[b] = fl;
 }
 
-__global__ void k_merge_norm(int B, const uint8_t *__restrict__ flag, const double2 *__restrict__ n2,
-                             double2 *__restrict__ n1) {
+// |W|^2 of the flagged columns from their second pass, then beta = |W|
+__global__ void k_merge_sqrt(int B, const uint8_t *__restrict__ flag, const double2 *__restrict__ n2,
+                             double2 *__restrict__ n1, double *__restrict__ beta) {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B && flag[b]) n1[b] = n2[b];
+    if (b >= B) return;
+    double2 v = n1[b];
+    if (flag[b]) {
+        v = n2[b];
+        n1[b] = v;
+    }
+    beta[b] = sqrt(fmax(v.x, 0.0));
 }
 
 // out[j * B + b] = sum_chunk partial[(chunk * J + j) * B + b]: one wavefront
 // per output, lanes take chunks lane, lane+64, ... in order, then a fixed
-// shuffle tree -- deterministic for a given chunking.
+// shuffle tree -- deterministic for a given chunking.  re_out (optional)
+// receives the real parts as well.
 __global__ __launch_bounds__(256) void k_reduce_chunks(const double2 *__restrict__ partial, int nchunk,
-                                                       int JB, double2 *__restrict__ out) {
+                                                       int JB, double2 *__restrict__ out,
+                                                       double *__restrict__ re_out) {
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= JB) return;
@@ -330,7 +339,10 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const double2 *__restrict
         sr += __shfl_down(sr, off, 64);
         si += __shfl_down(si, off, 64);
     }
-    if (lane == 0) out[i] = make_double2(sr, si);
+    if (lane == 0) {
+        out[i] = make_double2(sr, si);
+        if (re_out) re_out[i] = sr;
+    }
 }
 
 // W -= alpha[b] * P0 (+ beta[b] * P1 when P1 != null); alpha, beta real per column.
@@ -411,11 +423,6 @@ __global__ __launch_bounds__(256) void k_scale_out(uint64_t ne, int B, const dou
 __global__ void k_sqrt_to(int B, const double2 *__restrict__ nrm2, double *__restrict__ out) {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < B) out[b] = sqrt(fmax(nrm2[b].x, 0.0));
-}
-
-__global__ void k_copy_re(int B, const double2 *__restrict__ in, double *__restrict__ out) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) out[b] = in[b].x;
 }
 
 // Out_y = sum_{x < NX} X_x * C[x][y][b] for y < NY (C real, per column, the
@@ -824,7 +831,7 @@ static void launch_multidot(const RedGeom &g, hipStream_t st, const double *X, u
 }
 
 int Engine::multidot(const double *X, int J, const double *Y, double2 *out, int selfdot,
-                     const uint8_t *mask, const ThreeTerm *f) {
+                     const uint8_t *mask, const ThreeTerm *f, double *re_out) {
     const ThreeTerm none{};
     const RedGeom g = dot_geom(rg, J + selfdot);
     if (cplx)
@@ -834,7 +841,7 @@ int Engine::multidot(const double *X, int J, const double *Y, double2 *out, int 
     QS3_HIP(hipGetLastError());
     const int JB = (J + selfdot) * B;
     hipLaunchKernelGGL(k_reduce_chunks, dim3((JB + 3) / 4), dim3(256), 0, st, partial.as<double2>(),
-                       g.nchunk, JB, out);
+                       g.nchunk, JB, out, re_out);
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }
@@ -851,7 +858,7 @@ int Engine::cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double
                            stride, J, h, f ? *f : none, mask, partial.as<double2>());
     QS3_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_reduce_chunks, dim3((B + 3) / 4), dim3(256), 0, st, partial.as<double2>(), rg.nchunk,
-                       B, nrm_out);
+                       B, nrm_out, (double *)nullptr);
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }
@@ -863,10 +870,12 @@ int Engine::cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double
 // of |W|^2; the norm is fused into the update.
 int Engine::step(int x, int prev) {
     QS3_TRY(apply(slot(x), W.as<double>()));
-    QS3_TRY(multidot(slot(x), 1, W.as<double>(), alpha.as<double2>(), 0, colmask));
+    // alpha_x, its real part also into the coefficient history
+    QS3_TRY(multidot(slot(x), 1, W.as<double>(), alpha.as<double2>(), 0, colmask, nullptr,
+                     ab_hist.as<double>() + (size_t)x * B));
     double *betap = ab_hist.as<double>() + (size_t)slots * B + (size_t)(prev < 0 ? 0 : prev) * B;
-    hipLaunchKernelGGL(k_copy_re, grid1(B), dim3(256), 0, st, B, alpha.as<double2>(),
-                       ab_hist.as<double>() + (size_t)x * B);
+    double *beta_x = ab_hist.as<double>() + (size_t)slots * B + (size_t)x * B;
+    bool have_beta = false;  // beta_x written by a merge below
     double2 *h = hvec.as<double2>();
     double2 *n_before = h + (size_t)(x + 1) * B;  // the self-dot output of the first pass
     if (reorth == 1 || reorth == 2) {
@@ -887,8 +896,9 @@ int Engine::step(int x, int prev) {
             QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 0, flag));
             double2 *n2 = h + (size_t)(x + 1) * B;
             QS3_TRY(cgs_update_norm(x + 1, h, flag, n2));
-            hipLaunchKernelGGL(k_merge_norm, grid1(B), dim3(256), 0, st, B, flag, n2, nrm2.as<double2>());
+            hipLaunchKernelGGL(k_merge_sqrt, grid1(B), dim3(256), 0, st, B, flag, n2, nrm2.as<double2>(), beta_x);
             QS3_HIP(hipGetLastError());
+            have_beta = true;
         }
     } else {
         // three-term recurrence (and with reorth == 3 the partial
@@ -913,12 +923,13 @@ int Engine::step(int x, int prev) {
             QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 0, flag));
             double2 *n2 = h + (size_t)(x + 1) * B;
             QS3_TRY(cgs_update_norm(x + 1, h, flag, n2));
-            hipLaunchKernelGGL(k_merge_norm, grid1(B), dim3(256), 0, st, B, flag, n2, nrm2.as<double2>());
+            hipLaunchKernelGGL(k_merge_sqrt, grid1(B), dim3(256), 0, st, B, flag, n2, nrm2.as<double2>(), beta_x);
             QS3_HIP(hipGetLastError());
+            have_beta = true;
         }
     }
-    hipLaunchKernelGGL(k_sqrt_to, grid1(B), dim3(256), 0, st, B, nrm2.as<double2>(),
-                       ab_hist.as<double>() + (size_t)slots * B + (size_t)x * B);
+    if (!have_beta)
+        hipLaunchKernelGGL(k_sqrt_to, grid1(B), dim3(256), 0, st, B, nrm2.as<double2>(), beta_x);
     if (cplx)
         hipLaunchKernelGGL(k_scale_out<true>, grid1(ne), dim3(256), 0, st, ne, B, W.as<double>(),
                            slot(x + 1), nrm2.as<double2>(), colmask);

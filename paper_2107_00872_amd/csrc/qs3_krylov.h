@@ -61,8 +61,10 @@ struct Engine {
     int init(qs3_ctx *c, Operator *o, int slots, int precision, int reorth, hipStream_t s);
     double *slot(int j);
     int apply(const double *x, double *y);
+    // out[j * B + b] = <X_j, Y'> (and |Y'|^2 at j = J when selfdot); re_out,
+    // when given, also receives the real parts
     int multidot(const double *X, int J, const double *Y, double2 *out, int selfdot,
-                 const uint8_t *mask, const ThreeTerm *f = nullptr);
+                 const uint8_t *mask, const ThreeTerm *f = nullptr, double *re_out = nullptr);
     int cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double2 *nrm_out,
                         const ThreeTerm *f = nullptr);
     int step(int x, int prev);
