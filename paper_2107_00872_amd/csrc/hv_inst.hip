@@ -253,6 +253,11 @@ int lanczos_small_K<KI>(qs3_lattice *lat, const BinomTable *bt, qs3_batch *bat, 
 template <typename RT, typename CT, typename OT, int MODE>
 static int launch_batch(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
     BatchArgs A = batch_args(bat);
+    // a narrow batch (the few sectors a solve has left) takes 8 lanes per
+    // row: its hops are resolved 8 at a time and 8 gathers stay in flight;
+    // every sector sums its hops in the same order.  A single sector keeps
+    // one lane per row (its gathers would leave the other lanes idle).
+    if (A.B > 1 && A.G < 8) A.G = 8;
     size_t sh = lds_need<RT>(bat->lat, KI);
     QS3_REQUIRE(sh <= 160 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
     const int per = (A.B + A.G - 1) / A.G;
