@@ -81,8 +81,13 @@ def test_lanczos_partial_reorthogonalisation(qs3, ctx):
     assert abs(none[1] - none[0]) < 1e-8 and abs(full[1] - full[0]) > 1e-3
 
 
+# nev = 11 and 12 keep N_K = nev + 5 = 16 and 17 Ritz vectors: the restart
+# rotation in place (one accumulator tile) and through the staging slots (on a
+# disordered chain, whose levels are not degenerate)
 @pytest.mark.parametrize("lat,K,nev", [(wl.chain(16), 3, 4), (wl.square(4), 4, 3),
-                                       (wl.with_disorder(wl.chain(14), 2), 4, 3), (wl.square(6), 2, 5)],
+                                       (wl.with_disorder(wl.chain(14), 2), 4, 3), (wl.square(6), 2, 5),
+                                       (wl.with_disorder(wl.chain(14), 2), 4, 11),
+                                       (wl.with_disorder(wl.chain(14), 2), 4, 12)],
                          ids=lambda x: getattr(x, "name", str(x)))
 def test_trl_u1_vs_dense(qs3, ctx, lat, K, nev):
     L = qs3.Lattice.of(ctx, lat)
