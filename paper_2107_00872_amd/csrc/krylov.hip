@@ -247,14 +247,6 @@ __global__ __launch_bounds__(256) void k_cgs_update_norm(RedGeom g, double *__re
     if (tr == 0 && b < g.B) partial[(size_t)blockIdx.x * g.B + b] = make_double2(red[threadIdx.x], 0.0);
 }
 
-// second Gram-Schmidt pass where the first one cancelled more than half of
-// |W|^2 (Daniel-Gragg-Kaufman-Stewart criterion, eta^2 = 1/2)
-__global__ void k_dgks_flag(int B, const double2 *__restrict__ before, const double2 *__restrict__ after,
-                            const uint8_t *__restrict__ mask, uint8_t *__restrict__ flag) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < B) flag[b] = (after[b].x < 0.5 * before[b].x && (!mask || mask[b])) ? 1 : 0;
-}
-
 // Partial reorthogonalisation: Simon's recurrence for the overlaps
 // w_{j,k} ~ <psi_j, psi_k> of plain Lanczos, one thread per column.  om holds
 // two rows per column ([parity][k][B], row j at parity j & 1, w_{j,j} = 1);
@@ -342,6 +334,34 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const double2 *__restrict
     if (lane == 0) {
         out[i] = make_double2(sr, si);
         if (re_out) re_out[i] = sr;
+    }
+}
+
+// k_reduce_chunks for the norms of a first Gram-Schmidt pass (one output per
+// column) that also sets the second-pass flags: the pass cancelled more than
+// half of |W|^2 (Daniel-Gragg-Kaufman-Stewart criterion, eta^2 = 1/2).
+__global__ __launch_bounds__(256) void k_reduce_norm_dgks(const double2 *__restrict__ partial, int nchunk, int B,
+                                                          double2 *__restrict__ out,
+                                                          const double2 *__restrict__ before,
+                                                          const uint8_t *__restrict__ mask,
+                                                          uint8_t *__restrict__ flag) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= B) return;
+    double sr = 0, si = 0;
+    for (int c = lane; c < nchunk; c += 64) {
+        double2 p = partial[(size_t)c * B + i];
+        sr += p.x;
+        si += p.y;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        sr += __shfl_down(sr, off, 64);
+        si += __shfl_down(si, off, 64);
+    }
+    if (lane == 0) {
+        out[i] = make_double2(sr, si);
+        flag[i] = (sr < 0.5 * before[i].x && (!mask || mask[i])) ? 1 : 0;
     }
 }
 
@@ -847,7 +867,7 @@ int Engine::multidot(const double *X, int J, const double *Y, double2 *out, int 
 }
 
 int Engine::cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double2 *nrm_out,
-                            const ThreeTerm *f) {
+                            const ThreeTerm *f, const double2 *dgks_before, uint8_t *dgks_flag) {
     dim3 grid(rg.nchunk, rg.ncoltile);
     const ThreeTerm none{};
     if (cplx)
@@ -857,8 +877,12 @@ int Engine::cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double
         hipLaunchKernelGGL((k_cgs_update_norm<false>), grid, dim3(256), 0, st, rg, W.as<double>(), slot(0),
                            stride, J, h, f ? *f : none, mask, partial.as<double2>());
     QS3_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((B + 3) / 4), dim3(256), 0, st, partial.as<double2>(), rg.nchunk,
-                       B, nrm_out, (double *)nullptr);
+    if (dgks_flag)
+        hipLaunchKernelGGL(k_reduce_norm_dgks, dim3((B + 3) / 4), dim3(256), 0, st, partial.as<double2>(),
+                           rg.nchunk, B, nrm_out, dgks_before, mask, dgks_flag);
+    else
+        hipLaunchKernelGGL(k_reduce_chunks, dim3((B + 3) / 4), dim3(256), 0, st, partial.as<double2>(), rg.nchunk,
+                           B, nrm_out, (double *)nullptr);
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }
@@ -887,12 +911,10 @@ int Engine::step(int x, int prev) {
         f.alpha = alpha.as<double2>();
         f.beta = betap;
         QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 1, colmask, &f));
-        QS3_TRY(cgs_update_norm(x + 1, h, colmask, nrm2.as<double2>(), &f));
+        uint8_t *flag = act.as<uint8_t>() + 8 + B;
+        // the norm's reduction also sets the second-pass flags
+        QS3_TRY(cgs_update_norm(x + 1, h, colmask, nrm2.as<double2>(), &f, n_before, reorth > 1 ? flag : nullptr));
         if (reorth > 1) {
-            uint8_t *flag = act.as<uint8_t>() + 8 + B;
-            hipLaunchKernelGGL(k_dgks_flag, grid1(B), dim3(256), 0, st, B, n_before, nrm2.as<double2>(), colmask,
-                               flag);
-            QS3_HIP(hipGetLastError());
             QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 0, flag));
             double2 *n2 = h + (size_t)(x + 1) * B;
             QS3_TRY(cgs_update_norm(x + 1, h, flag, n2));

@@ -65,8 +65,11 @@ struct Engine {
     // when given, also receives the real parts
     int multidot(const double *X, int J, const double *Y, double2 *out, int selfdot,
                  const uint8_t *mask, const ThreeTerm *f = nullptr, double *re_out = nullptr);
+    // dgks_flag (optional): also flag the columns whose first pass cancelled
+    // more than half of |W|^2 (dgks_before: |W|^2 before the pass)
     int cgs_update_norm(int J, const double2 *h, const uint8_t *mask, double2 *nrm_out,
-                        const ThreeTerm *f = nullptr);
+                        const ThreeTerm *f = nullptr, const double2 *dgks_before = nullptr,
+                        uint8_t *dgks_flag = nullptr);
     int step(int x, int prev);
     // steps x0..x1-1 (step x0's three-term partner is slot prev_first or none)
     int cycle(int x0, int x1, int prev_first);
