@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="skip the one-sector-at-a-time comparison (shorter profiles)")
     ap.add_argument("--requests", type=int, default=0, help="c5: number of requests (default 40)")
+    ap.add_argument("--cells", default="both", choices=["kagome", "pyrochlore", "both"],
+                    help="cells: which unit-cell lattice to run (default both)")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "szq", "thermal", "cells", "pg"],
                     help="c2 (default) is the headline configuration; the others print their own line")
     args = ap.parse_args()

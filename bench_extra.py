@@ -222,9 +222,13 @@ def cells(args):
     4 neighbours, 144 momenta, about 92k representatives each) and the
     6 x 6 x 6 pyrochlore lattice (864 sites, 6 neighbours, 216 momenta, about
     496k representatives each), J = Delta = 1, N_down = 3."""
+    which = getattr(args, "cells", "both")
+    if which == "pyrochlore":
+        return _cells_run(wl.pyrochlore(6), 3)
     out = _cells_run(wl.kagome(12, 12), 3)
-    torch.cuda.empty_cache()
-    out["pyrochlore"] = _cells_run(wl.pyrochlore(6), 3)
+    if which == "both":
+        torch.cuda.empty_cache()
+        out["pyrochlore"] = _cells_run(wl.pyrochlore(6), 3)
     return out
 
 
