@@ -38,10 +38,14 @@ def ctx(qs3):
 
 
 def _ops(lat):
+    if lat.lz > 1:
+        return wl.oh_ops(lat.lx)
     return wl.c4v_ops(lat.lx) if lat.ly > 1 else wl.inversion_ops(lat.lx)
 
 
 def _chars(lat):
+    if lat.lz > 1:
+        return list(wl.oh_chars().items())
     if lat.ly > 1:
         return list(wl.C4V_CHARS.items())
     return [("even", (1, 1)), ("odd", (1, -1))]
@@ -50,7 +54,8 @@ def _chars(lat):
 CASES = [(wl.square(4), 2, (0, 0, 0)), (wl.square(4), 3, (2, 2, 0)), (wl.square(4), 4, (0, 0, 0)),
          (wl.square(6), 2, (3, 3, 0)), (wl.chain(14), 5, (7, 0, 0)), (wl.chain(12), 6, (0, 0, 0)),
          (wl.with_disorder(wl.square(4), seed=3, per_bond=False), 3, (2, 2, 0)),
-         (wl.square_j1j2(4, 0.45), 3, (2, 2, 0)), (wl.square_j1j2(4, 0.45), 4, (0, 0, 0))]
+         (wl.square_j1j2(4, 0.45), 3, (2, 2, 0)), (wl.square_j1j2(4, 0.45), 4, (0, 0, 0)),
+         (wl.cube(3), 2, (0, 0, 0))]
 
 
 def _tol(H, vmax, width):
@@ -64,7 +69,7 @@ def test_pg_sector_against_oracle(qs3, ctx, lat, K, Kv):
     geo = Geometry(*lat.dims)
     bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
     L = qs3.Lattice.of(ctx, lat)
-    width = K * 2 * (2 if lat.ly > 1 else 1) * (2 if lat.n_bonds > lat.n_sites * 2 else 1)
+    width = K * int(np.bincount(np.concatenate([lat.bi, lat.bj])).max())
     for name, chars in _chars(lat):
         print(f"pg {lat.name} K={K} k={Kv} {name}", flush=True)
         sigma, R = mk_list_pg(geo, perms, chars, K, Kv)
@@ -285,3 +290,55 @@ def test_pg_ground_state_in_momentum_sector(qs3, ctx):
     sec.close()
     msec.close()
     L.close()
+
+
+def test_pg_oh_cube3_n3_a1g_against_oracle(qs3, ctx):
+    """O_h on the 3x3x3 cube at N_down = 3, k = 0, A1g: representatives, norms
+    and the lowest levels against the oracle's block."""
+    lat = wl.cube(3)
+    perms, chars = wl.oh_ops(3), wl.oh_chars()["A1g"]
+    geo = Geometry(*lat.dims)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    sigma, R = mk_list_pg(geo, perms, chars, 3, (0, 0, 0))
+    L = qs3.Lattice.of(ctx, lat)
+    sec = qs3.PGSector(L, 3, (0, 0, 0), perms, chars)
+    ranks, norms = sec.basis()
+    assert np.array_equal(ranks.astype(np.int64), np.array(sigma, dtype=np.int64) - 1)
+    assert np.allclose(norms, np.array(R) ** 2, rtol=1e-13, atol=0)
+    ref = np.linalg.eigvalsh(gen_full_ham_pg(geo, perms, chars, 3, bonds, sigma, R, (0, 0, 0)))
+    res = sec.eigs(nev=3, seed=5)
+    assert np.allclose(res.evals, lowest_distinct(ref, 3), rtol=0, atol=1e-9 * np.abs(ref).max())
+    sec.close()
+    L.close()
+
+
+@pytest.mark.parametrize("Kv", [(0, 0, 0), (5, 5, 5)])
+def test_pg_oh_cube10(qs3, ctx, Kv):
+    """10 x 10 x 10 cube, N_down = 3 (C(1000, 3) = 166,167,000 states): every
+    one-dimensional O_h block lies above the momentum block's ground level,
+    and the lowest A1g state carried into the momentum sector is an eigenvector
+    there with the same level."""
+    lat = wl.cube(10)
+    L = qs3.Lattice.of(ctx, lat)
+    mom = qs3.Sector(L, 3, Kv)
+    e0 = mom.eigs(nev=1, seed=1).evals[0]
+    for name, chars in wl.oh_chars().items():
+        sec = qs3.PGSector(L, 3, Kv, wl.oh_ops(10), chars)
+        print(f"pg cube10 K=3 k={Kv} {name}: dim {sec.dim}", flush=True)
+        if sec.dim == 0:
+            sec.close()
+            continue
+        X = torch.zeros(sec.dim, dtype=torch.float64, device="cuda")
+        r = sec.eigs(nev=1, evecs=X, seed=2)
+        assert r.status == qs3.QS3_OK
+        assert r.evals[0] >= e0 - 1e-9 * abs(e0)
+        if name == "A1g":
+            psi = sec.to_momentum(X, mom)
+            w = torch.empty_like(psi)
+            mom.matvec(psi, w)
+            assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-12
+            assert torch.linalg.vector_norm(w - r.evals[0] * psi).item() < 1e-7 * abs(r.evals[0])
+        sec.close()
+    mom.close()
+    L.close()
+

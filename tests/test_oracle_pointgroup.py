@@ -109,3 +109,43 @@ def test_c4v_sectors(lat, K, Kv):
         assert np.abs(expand_pg(geo, perms, chars, K, s, R, Kv, H @ phi) - Hb @ u1).max() < 1e-12
     dE = round(sum(wl.C4V_E[p] * kph(t) * fixed[(p, t)] for p in range(8) for t in ts)) // G
     assert total + 2 * dE == len(s_k)
+
+
+def test_oh_sectors_cube3():
+    """O_h (48 signed axis permutations) on the periodic 3x3x3 cube at
+    N_down = 2, k = 0: every one-dimensional sector's dimension from the
+    character formula over fixed states, and the non-empty blocks' spectra
+    against the projector onto the (k, chi) subspace in the bitmask basis."""
+    lat = wl.cube(3)
+    K, Kv = 2, (0, 0, 0)
+    perms = wl.oh_ops(3)
+    geo = Geometry(*lat.dims)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    ts = [(tx, ty, tz) for tz in range(3) for ty in range(3) for tx in range(3)]
+    G = len(perms) * len(ts)
+    Hb = bitmask_H(lat, K)
+    ms = masks(lat.n_sites, K)
+    idx = {m: i for i, m in enumerate(ms)}
+    for name, chars in wl.oh_chars().items():
+        d = 0
+        P = np.zeros((len(ms), len(ms)))
+        for p in range(len(perms)):
+            for t in ts:
+                perm = _perm_of(lat, perms, p, t)
+                d += chars[p] * _fixed_states(perm, K)
+                for c, m in enumerate(ms):
+                    out = 0
+                    for i in range(lat.n_sites):
+                        if m >> i & 1:
+                            out |= 1 << perm[i]
+                    P[idx[out], c] += chars[p] / G
+        assert d % G == 0
+        s, R = mk_list_pg(geo, perms, chars, K, Kv)
+        assert len(s) == d // G, name
+        if not s:
+            continue
+        e = np.linalg.eigvalsh(gen_full_ham_pg(geo, perms, chars, K, bonds, s, R, Kv))
+        u, sv, _ = np.linalg.svd(P)
+        Q = u[:, sv > 0.5]
+        assert Q.shape[1] == len(s)
+        assert np.abs(np.linalg.eigvalsh(Q.T @ Hb @ Q) - e).max() < 1e-12

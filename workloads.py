@@ -14,6 +14,7 @@ A bond is (i, j, Jxy, Jz) with the XXZ convention of the paper's model
 from __future__ import annotations
 
 import dataclasses
+import itertools
 import numpy as np
 
 
@@ -233,6 +234,51 @@ def c4v_ops(L: int) -> np.ndarray:
 def inversion_ops(L: int) -> np.ndarray:
     """Identity and the inversion x -> -x of the periodic chain (2 x L)."""
     return np.array([[i for i in range(L)], [(-i) % L for i in range(L)]], dtype=np.int32)
+
+
+def _oh_elements():
+    """The 48 signed axis permutations (sigma, signs) of O_h, identity first."""
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            out.append((perm, signs))
+    out.sort(key=lambda e: (e[0] != (0, 1, 2) or e[1] != (1, 1, 1)))
+    return out
+
+
+def _perm_sign(perm) -> int:
+    inv = sum(1 for i in range(3) for j in range(i + 1, 3) if perm[i] > perm[j])
+    return -1 if inv % 2 else 1
+
+
+def oh_ops(L: int) -> np.ndarray:
+    """The point group O_h of the periodic L x L x L cube about site 0 as site
+    permutations (48 x L^3): (x_0, x_1, x_2) -> (s_a x_{sigma(a)})_a mod L."""
+    els = _oh_elements()
+    out = np.zeros((len(els), L ** 3), dtype=np.int32)
+    for p, (perm, signs) in enumerate(els):
+        for z in range(L):
+            for y in range(L):
+                for x in range(L):
+                    r = (x, y, z)
+                    img = [(signs[a] * r[perm[a]]) % L for a in range(3)]
+                    out[p, x + L * (y + L * z)] = img[0] + L * (img[1] + L * img[2])
+    return out
+
+
+def oh_chars() -> dict:
+    """Characters of the four one-dimensional representations of O_h in the
+    order of oh_ops: A1g 1, A2g sign(sigma), A1u det, A2u sign(sigma) det
+    (det = sign(sigma) times the product of the signs)."""
+    out = {"A1g": [], "A2g": [], "A1u": [], "A2u": []}
+    for perm, signs in _oh_elements():
+        ps = _perm_sign(perm)
+        det = ps * signs[0] * signs[1] * signs[2]
+        out["A1g"].append(1)
+        out["A2g"].append(ps)
+        out["A1u"].append(det)
+        out["A2u"].append(ps * det)
+    return {k: tuple(v) for k, v in out.items()}
 
 
 def all_momenta(lat: Lattice) -> list:
