@@ -12,7 +12,8 @@ c4  periodic 10x10 square, N_down=3 ground state (lowest over the 100 sectors),
 pg  periodic 10x10 square, N_down = 5 and 6, k = 0: the four one-dimensional
     C4v sectors (translations x point operations) against the momentum sector
     holding the same ground state: block build, ELL H.v rate and bytes, solve
-    times.
+    times; and the 10^3 cube's O_h A1g sector at N_down = 4 against its
+    momentum sector.
 c5  serving: Poisson arrivals of random solve requests (workloads.serving_stream),
     rate 0.8 / (mean one-at-a-time service time); p50/p99 latency and solves/s
     against the same requests run one at a time.
@@ -519,5 +520,35 @@ def pg(args):
         out["by_n_down"][K] = res
         torch.cuda.empty_cache()
     L.close()
+    # the cube's O_h (48 operations): 10^3, N_down = 4, k = 0, A1g against the
+    # momentum sector (41.4M rows)
+    cube = wl.cube(10)
+    Lc = qs3.Lattice.of(ctx, cube)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a1g = qs3.PGSector(Lc, 4, (0, 0, 0), wl.oh_ops(10), wl.oh_chars()["A1g"])
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ra = a1g.eigs(nev=1, seed=1, stream=stream)
+    torch.cuda.synchronize()
+    t_a = time.perf_counter() - t0
+    mom = qs3.Sector(Lc, 4, (0, 0, 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rm = mom.eigs(nev=1, seed=1, stream=stream)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter() - t0
+    print(f"pg cube10 N_down=4 A1g dim {a1g.dim} solve {t_a:.3f}s, momentum {mom.dim} {t_m:.3f}s",
+          file=sys.stderr, flush=True)
+    out["cube10_N4_Oh"] = {"A1g": {"dim": a1g.dim, "build_s": t_b, "solve_s": t_a, "E0": float(ra.evals[0]),
+                                   "matvecs": ra.info.n_matvec, "rc": ra.status},
+                           "momentum": {"dim": mom.dim, "solve_s": t_m, "E0": float(rm.evals[0]),
+                                        "matvecs": rm.info.n_matvec},
+                           "A1g_minus_momentum_E0": float(ra.evals[0] - rm.evals[0]),
+                           "momentum_over_A1g_solve": t_m / t_a}
+    a1g.close()
+    mom.close()
+    Lc.close()
     ctx.close()
     return out
