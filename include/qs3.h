@@ -365,8 +365,9 @@ int qs3_pg_matvec(qs3_pg_sector *sec, const double *v, double *w, void *stream);
  * sqrt(N_T s_u / N_a) to u (Eq. (akstate) for u).  Every momentum-sector
  * observable, S^a_q and S(q, omega) then applies to point-group states. */
 int qs3_pg_to_momentum(qs3_pg_sector *sec, const double *v, qs3_sector *msec, void *out, void *stream);
-/* As qs3_eigs (QS3_PREC_F64 only); evecs: device, dim x nev (vector y at
- * y*dim), or NULL. */
+/* As qs3_eigs (QS3_PREC_F64, or QS3_PREC_F32MV: float32 products with the
+ * float32 row sums, float64 recurrences); evecs: device, dim x nev (vector y
+ * at y*dim), or NULL. */
 int qs3_pg_eigs(qs3_pg_sector *sec, const qs3_eigs_opts *opts, double *evals, double *evecs,
                 qs3_eigs_info *info, void *stream);
 

@@ -62,6 +62,7 @@ struct qs3_pg_sector {
     DevBuf val;    // double [width * dim] (not packed)
     DevBuf scale;  // double [dim] (packed)
     DevBuf xr;     // double [dim] (packed): R o x of the product in progress
+    DevBuf xr32;   // float [dim] (packed): the same for float32 products
     DevBuf diag;   // double [dim]
 };
 
@@ -284,6 +285,57 @@ __global__ void k_pg_expand(PgArgs P, const RT *binom_g, const uint64_t *__restr
 __global__ void k_pg_zero2(uint64_t n, double2 *p) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = make_double2(0.0, 0.0);
+}
+
+// float32 products (float64 recurrences around them): float32 inputs, the
+// staged R o x and the row sums in float32, the result stored as float64
+__global__ void k_pg_prescale_f32(const double *__restrict__ rnorm, uint64_t dim, const float *__restrict__ x,
+                                  float *__restrict__ xr) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < dim) xr[a] = (float)(rnorm[a] * (double)x[a]);
+}
+
+__global__ void k_pg_spmv_packed_f32(const uint32_t *__restrict__ col, const float *__restrict__ xr,
+                                     const double *__restrict__ scale, const double *__restrict__ diag, uint64_t dim,
+                                     int width, const float *__restrict__ x, double *__restrict__ y) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= dim) return;
+    float acc = 0.0f;
+    for (int w0 = 0; w0 < width; w0 += PG_CH) {
+        uint32_t cb[PG_CH];
+        float t[PG_CH];
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) cb[i] = w0 + i < width ? col[(uint64_t)(w0 + i) * dim + a] : 0xffffffffu;
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) t[i] = cb[i] == 0xffffffffu ? 0.0f : xr[cb[i] & 0x7fffffffu];
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) acc += (cb[i] >> 31) ? -t[i] : t[i];
+        if (cb[PG_CH - 1] == 0xffffffffu) break;
+    }
+    y[a] = (double)((float)diag[a] * x[a] + (float)scale[a] * acc);
+}
+
+__global__ void k_pg_spmv_f32(const uint32_t *__restrict__ col, const double *__restrict__ val,
+                              const double *__restrict__ diag, uint64_t dim, int width,
+                              const float *__restrict__ x, double *__restrict__ y) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= dim) return;
+    float acc = (float)diag[a] * x[a];
+    for (int w0 = 0; w0 < width; w0 += PG_CH) {
+        uint32_t cb[PG_CH];
+        float v[PG_CH], t[PG_CH];
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) {
+            const bool in = w0 + i < width;
+            cb[i] = in ? col[(uint64_t)(w0 + i) * dim + a] : (uint32_t)a;
+            v[i] = in ? (float)val[(uint64_t)(w0 + i) * dim + a] : 0.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) t[i] = x[cb[i]];
+#pragma unroll
+        for (int i = 0; i < PG_CH; ++i) acc += v[i] * t[i];
+    }
+    y[a] = (double)acc;
 }
 
 __global__ void k_pg_start(const uint64_t *__restrict__ reps, uint64_t dim, uint64_t seed, double *v) {
@@ -524,6 +576,7 @@ int pg_build(qs3_pg_sector *sec) {
     if (sec->packed) {
         QS3_TRY(sec->scale.alloc(ctx, sizeof(double) * d1));
         QS3_TRY(sec->xr.alloc(ctx, sizeof(double) * d1));
+        QS3_TRY(sec->xr32.alloc(ctx, sizeof(float) * d1));
     }
     else QS3_TRY(sec->val.alloc(ctx, sizeof(double) * d1 * std::max(sec->width, 1)));
     if (sec->dim) {
@@ -552,6 +605,22 @@ int pg_apply(qs3_pg_sector *sec, const double *x, double *y, hipStream_t s) {
     return QS3_OK;
 }
 
+int pg_apply_f32(qs3_pg_sector *sec, const float *x, double *y, hipStream_t s) {
+    if (sec->dim == 0) return QS3_OK;
+    if (sec->packed) {
+        hipLaunchKernelGGL(k_pg_prescale_f32, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s,
+                           sec->rnorm.as<double>(), sec->dim, x, sec->xr32.as<float>());
+        hipLaunchKernelGGL(k_pg_spmv_packed_f32, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s,
+                           sec->col.as<uint32_t>(), sec->xr32.as<float>(), sec->scale.as<double>(),
+                           sec->diag.as<double>(), sec->dim, sec->width, x, y);
+    } else {
+        hipLaunchKernelGGL(k_pg_spmv_f32, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s, sec->col.as<uint32_t>(),
+                           sec->val.as<double>(), sec->diag.as<double>(), sec->dim, sec->width, x, y);
+    }
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
 struct PGOp : Operator {
     qs3_pg_sector *sec;
     explicit PGOp(qs3_pg_sector *s) : sec(s) {}
@@ -559,10 +628,7 @@ struct PGOp : Operator {
     int cols() const override { return 1; }
     bool is_complex() const override { return false; }
     int apply(const double *x, double *y, hipStream_t s) override { return pg_apply(sec, x, y, s); }
-    int apply_f32in(const float *, double *, hipStream_t) override {
-        set_error("point-group sectors take float64 vectors only");
-        return QS3_EINVAL;
-    }
+    int apply_f32in(const float *x, double *y, hipStream_t s) override { return pg_apply_f32(sec, x, y, s); }
 };
 
 }  // namespace
@@ -659,7 +725,8 @@ int qs3_pg_eigs(qs3_pg_sector *sec, const qs3_eigs_opts *opts, double *evals, do
                 qs3_eigs_info *info, void *stream) {
     QS3_REQUIRE(sec && opts && evals, QS3_EINVAL, "NULL argument");
     QS3_REQUIRE(sec->dim > 0, QS3_EINVAL, "empty sector");
-    QS3_REQUIRE(opts->precision == QS3_PREC_F64, QS3_EINVAL, "point-group sectors solve in float64 only");
+    QS3_REQUIRE(opts->precision == QS3_PREC_F64 || opts->precision == QS3_PREC_F32MV, QS3_EINVAL,
+                "unknown precision");
     (void)hipSetDevice(sec->lat->ctx->device);
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;

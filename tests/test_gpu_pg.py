@@ -342,3 +342,33 @@ def test_pg_oh_cube10(qs3, ctx, Kv):
     mom.close()
     L.close()
 
+
+
+def test_pg_float32_products(qs3, ctx):
+    """Float32 products (float32 row sums, float64 recurrences) against the
+    float64 solve, to the 1e-5 relative bound stated for float32 products:
+    one exchange constant (packed slots, 10 x 10 square, N_down = 4) and two
+    (J1-J2 4 x 4, against the oracle's block)."""
+    lat = wl.square(10)
+    L = qs3.Lattice.of(ctx, lat)
+    for name in ("A1", "B1"):
+        sec = qs3.PGSector(L, 4, (0, 0, 0), wl.c4v_ops(10), wl.C4V_CHARS[name])
+        e64 = sec.eigs(nev=2, seed=1).evals
+        r32 = sec.eigs(nev=2, seed=1, precision=qs3.PREC_F32MV, tol=1e-5)
+        assert r32.status == qs3.QS3_OK
+        assert np.abs(r32.evals - e64).max() <= 1e-5 * np.abs(e64).max(), (name, r32.evals, e64)
+        sec.close()
+    L.close()
+    lat = wl.square_j1j2(4, 0.45)
+    perms, chars = wl.c4v_ops(4), wl.C4V_CHARS["A1"]
+    geo = Geometry(*lat.dims)
+    sigma, R = mk_list_pg(geo, perms, chars, 4, (0, 0, 0))
+    H = gen_full_ham_pg(geo, perms, chars, 4, bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz), sigma, R, (0, 0, 0))
+    ref = lowest_distinct(np.linalg.eigvalsh(H), 2)
+    L = qs3.Lattice.of(ctx, lat)
+    sec = qs3.PGSector(L, 4, (0, 0, 0), perms, chars)
+    r32 = sec.eigs(nev=2, seed=1, precision=qs3.PREC_F32MV, tol=1e-5)
+    assert r32.status == qs3.QS3_OK
+    assert np.abs(r32.evals - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+    sec.close()
+    L.close()
