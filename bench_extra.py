@@ -512,6 +512,14 @@ def pg(args):
             res[name] = {"dim": sec.dim, "build_s": t_build, "matvec_us": t_mv * 1e6,
                          "matvec_GBs": nbytes / t_mv / 1e9, "solve_s": t_solve, "E0": float(r.evals[0]),
                          "matvecs": r.info.n_matvec, "rc": r.status}
+            if name == "A1":
+                # float32 products, float64 recurrences
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r32 = sec.eigs(nev=1, seed=1, precision=qs3.PREC_F32MV, tol=1e-5, stream=stream)
+                torch.cuda.synchronize()
+                res[name]["f32mv"] = {"solve_s": time.perf_counter() - t0, "matvecs": r32.info.n_matvec,
+                                      "rel_err_vs_f64": float(abs(r32.evals[0] - r.evals[0]) / abs(r.evals[0]))}
             del v, w
             sec.close()
             print(f"pg K={K} {name} dim {res[name]['dim']} solve {t_solve:.3f}s", file=sys.stderr, flush=True)
