@@ -332,7 +332,8 @@ int qs3_batch_eigs(qs3_batch *bat, const qs3_eigs_opts *opts, double *evals,
  * representative of an orbit is its minimum rank, its norm N_a = |sum over the
  * stabiliser of chi|^2 |G| / |stabiliser|; orbits whose character sum vanishes
  * are not in the sector.  Vectors are real float64 over the representatives.
- *  - lat: one site per cell, translation invariant; 1 <= n_down <= min(N, 6);
+ *  - lat: translation invariant (point operations may exchange the places of
+ *    a cell); 1 <= n_down <= min(N, 6);
  *  - kvec: host, 3 ints, each component 0 or L_a / 2 (k.t = 0 or pi);
  *  - perms: host, n_ops x N (row p: site r -> perms[p*N + r]), 1 <= n_ops <= 48,
  *    row 0 the identity; every row a permutation that keeps the couplings,

@@ -3,7 +3,9 @@
 // Sec. 3.3, Eqs. (ak)-(hak2), with the space group G = {T^t P_p} in place of
 // the translation group).
 //
-// Only one-dimensional representations with real characters are built: chi(p)
+// Point operations may exchange the places of a unit cell (translations act
+// on cells).  Only one-dimensional representations with real characters are
+// built: chi(p)
 // = +-1 on the point operations and momenta k with e^{i k.t} = +-1 (each
 // component 0 or pi), so that chi(T^t P_p) = chi(p) e^{i k.t} and the sector
 // is real.  The representative of an orbit is its minimum rank; its norm is
@@ -435,19 +437,25 @@ int dispatch(qs3_pg_sector *sec, bool ell, const DevBuf *nt_ok = nullptr, DevBuf
 
 // ---- host checks of the group (every one an error, never a kernel fault)
 
-// The translation t (cell coordinates) whose site map equals f, or -1.
+// Site r = s + ns * cell moved by the cell translation t (place s kept).
+int shifted_site(const qs3_lattice *lat, int r, const int *t) {
+    const int ns = lat->ns, lx = lat->lx, ly = lat->ly, lz = lat->lz;
+    const int sub = r % ns, c = r / ns;
+    const int x = c % lx, y = (c / lx) % ly, z = c / (lx * ly);
+    return sub + ns * ((x + t[0]) % lx + lx * (((y + t[1]) % ly) + ly * ((z + t[2]) % lz)));
+}
+
+// The cell translation t whose site map equals f, or -1.
 int translation_of(const qs3_lattice *lat, const std::vector<int> &f, int *t) {
-    const int N = lat->N, lx = lat->lx, ly = lat->ly, lz = lat->lz;
-    const int t0 = f[0];  // one site per cell: T^t maps site 0 to site t
-    const int tx = t0 % lx, ty = (t0 / lx) % ly, tz = t0 / (lx * ly);
-    for (int r = 0; r < N; ++r) {
-        const int x = r % lx, y = (r / lx) % ly, z = r / (lx * ly);
-        const int img = (x + tx) % lx + lx * (((y + ty) % ly) + ly * ((z + tz) % lz));
-        if (f[r] != img) return -1;
-    }
-    t[0] = tx;
-    t[1] = ty;
-    t[2] = tz;
+    const int N = lat->N, ns = lat->ns, lx = lat->lx, ly = lat->ly;
+    if (f[0] % ns != 0) return -1;  // place 0 of cell 0 must stay a place 0
+    const int c0 = f[0] / ns;
+    const int tt[3] = {c0 % lx, (c0 / lx) % ly, c0 / (lx * ly)};
+    for (int r = 0; r < N; ++r)
+        if (f[r] != shifted_site(lat, r, tt)) return -1;
+    t[0] = tt[0];
+    t[1] = tt[1];
+    t[2] = tt[2];
     return 0;
 }
 
@@ -501,12 +509,7 @@ int validate_group(const qs3_lattice *lat, const int *kv, int n_ops, const int32
             if (L[d] == 1) continue;
             int u[3] = {0, 0, 0};
             u[d] = 1;
-            for (int r = 0; r < N; ++r) {
-                const int q = Pinv[p][r];
-                const int x = q % L[0], y = (q / L[0]) % L[1], z = q / (L[0] * L[1]);
-                const int tq = (x + u[0]) % L[0] + L[0] * (((y + u[1]) % L[1]) + L[1] * ((z + u[2]) % L[2]));
-                f[r] = P[p][tq];
-            }
+            for (int r = 0; r < N; ++r) f[r] = P[p][shifted_site(lat, Pinv[p][r], u)];
             int t[3];
             QS3_REQUIRE(translation_of(lat, f, t) == 0, QS3_EINVAL,
                         "a point operation does not map translations to translations");
@@ -638,7 +641,6 @@ extern "C" {
 int qs3_pg_sector_create(qs3_lattice *lat, int n_down, const int32_t *kvec, int n_ops, const int32_t *perms,
                          const int32_t *chars, qs3_pg_sector **out) {
     QS3_REQUIRE(lat && kvec && perms && chars && out, QS3_EINVAL, "NULL argument");
-    QS3_REQUIRE(lat->ns == 1, QS3_EINVAL, "point-group sectors need one site per cell");
     QS3_REQUIRE(lat->translation_invariant, QS3_EINVAL, "the lattice is not translation invariant");
     QS3_REQUIRE(n_down >= 1 && n_down <= std::min(lat->N, MAX_K_MOM), QS3_EINVAL,
                 "point-group sectors need 1 <= n_down <= min(N, 6)");

@@ -38,12 +38,16 @@ def ctx(qs3):
 
 
 def _ops(lat):
+    if lat.ns == 2:
+        return wl.honeycomb_inversion_ops(lat.lx, lat.ly)
     if lat.lz > 1:
         return wl.oh_ops(lat.lx)
     return wl.c4v_ops(lat.lx) if lat.ly > 1 else wl.inversion_ops(lat.lx)
 
 
 def _chars(lat):
+    if lat.ns == 2:
+        return [("even", (1, 1)), ("odd", (1, -1))]
     if lat.lz > 1:
         return list(wl.oh_chars().items())
     if lat.ly > 1:
@@ -55,7 +59,7 @@ CASES = [(wl.square(4), 2, (0, 0, 0)), (wl.square(4), 3, (2, 2, 0)), (wl.square(
          (wl.square(6), 2, (3, 3, 0)), (wl.chain(14), 5, (7, 0, 0)), (wl.chain(12), 6, (0, 0, 0)),
          (wl.with_disorder(wl.square(4), seed=3, per_bond=False), 3, (2, 2, 0)),
          (wl.square_j1j2(4, 0.45), 3, (2, 2, 0)), (wl.square_j1j2(4, 0.45), 4, (0, 0, 0)),
-         (wl.cube(3), 2, (0, 0, 0))]
+         (wl.cube(3), 2, (0, 0, 0)), (wl.honeycomb(3, 3), 3, (0, 0, 0)), (wl.honeycomb(4, 4), 3, (2, 2, 0))]
 
 
 def _tol(H, vmax, width):
@@ -66,10 +70,10 @@ def _tol(H, vmax, width):
 @pytest.mark.parametrize("lat,K,Kv", CASES, ids=lambda x: getattr(x, "name", str(x)))
 def test_pg_sector_against_oracle(qs3, ctx, lat, K, Kv):
     perms = _ops(lat)
-    geo = Geometry(*lat.dims)
+    geo = Geometry(lat.lx, lat.ly, lat.lz, lat.ns)
     bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
     L = qs3.Lattice.of(ctx, lat)
-    width = K * int(np.bincount(np.concatenate([lat.bi, lat.bj])).max())
+    width = K * int(np.bincount(np.concatenate([lat.bi, lat.bj])).max())  # ELL slots per row
     for name, chars in _chars(lat):
         print(f"pg {lat.name} K={K} k={Kv} {name}", flush=True)
         sigma, R = mk_list_pg(geo, perms, chars, K, Kv)
@@ -229,14 +233,24 @@ def test_pg_refuses_non_groups(qs3, ctx):
     with pytest.raises(qs3.QS3Error):
         qs3.PGSector(D, 2, (0, 0, 0), ops, A1)
     D.close()
+    # several places per cell: a map that does not keep the couplings is
+    # refused, the identity alone gives the momentum sector
     kag = qs3.Lattice.of(ctx, wl.kagome(2, 2))
+    swap = np.arange(12, dtype=np.int32)
+    swap[[0, 1]] = swap[[1, 0]]
     with pytest.raises(qs3.QS3Error):
-        qs3.PGSector(kag, 2, (0, 0, 0), np.arange(12, dtype=np.int32)[None, :], [1])
+        qs3.PGSector(kag, 2, (0, 0, 0), np.stack([np.arange(12, dtype=np.int32), swap]), [1, 1])
+    ident = qs3.PGSector(kag, 2, (0, 0, 0), np.arange(12, dtype=np.int32)[None, :], [1])
+    mom = qs3.Sector(kag, 2, (0, 0, 0))
+    assert ident.dim == mom.dim
+    ident.close()
+    mom.close()
     kag.close()
 
 
 @pytest.mark.parametrize("lat,K,Kv", [(wl.square(4), 3, (2, 2, 0)), (wl.square(4), 4, (0, 0, 0)),
-                                      (wl.chain(12), 4, (6, 0, 0)), (wl.square_j1j2(4, 0.45), 3, (0, 0, 0))],
+                                      (wl.chain(12), 4, (6, 0, 0)), (wl.square_j1j2(4, 0.45), 3, (0, 0, 0)),
+                                      (wl.honeycomb(4, 4), 2, (2, 2, 0))],
                          ids=lambda x: getattr(x, "name", str(x)))
 def test_pg_to_momentum_against_oracle(qs3, ctx, lat, K, Kv):
     """A seeded point-group vector carried into the momentum sector: the
@@ -245,7 +259,7 @@ def test_pg_to_momentum_against_oracle(qs3, ctx, lat, K, Kv):
     from oracle.pointgroup import expand_pg
     from oracle.translation import expand_to_u1, mk_list
     perms = _ops(lat)
-    geo = Geometry(*lat.dims)
+    geo = Geometry(lat.lx, lat.ly, lat.lz, lat.ns)
     L = qs3.Lattice.of(ctx, lat)
     s_k, R_k = mk_list(geo, K, Kv)
     Bk = np.stack([expand_to_u1(geo, K, s_k, R_k, Kv, np.eye(len(s_k))[i]) for i in range(len(s_k))], axis=1)

@@ -149,3 +149,62 @@ def test_oh_sectors_cube3():
         Q = u[:, sv > 0.5]
         assert Q.shape[1] == len(s)
         assert np.abs(np.linalg.eigvalsh(Q.T @ Hb @ Q) - e).max() < 1e-12
+
+
+def _cell_perm_of(lat, perms, p, t):
+    """Site permutation of T^t P_p on a lattice of lat.ns places per cell."""
+    lx, ly, lz = lat.dims
+    ns = lat.ns
+    out = []
+    for i in range(lat.n_sites):
+        j = int(perms[p][i])
+        s, c = j % ns, j // ns
+        x, y, z = c % lx, (c // lx) % ly, c // (lx * ly)
+        out.append(s + ns * ((x + t[0]) % lx + lx * (((y + t[1]) % ly) + ly * ((z + t[2]) % lz))))
+    return out
+
+
+@pytest.mark.parametrize("L,K,Kv", [(3, 3, (0, 0, 0)), (4, 2, (2, 2, 0)), (4, 2, (0, 2, 0))])
+def test_honeycomb_inversion_sectors(L, K, Kv):
+    """Inversion through a bond centre exchanges the two places of the
+    honeycomb cell: the sector dimensions from the character formula over
+    fixed states, and the blocks' spectra against the projector onto the
+    (k, chi) subspace in the bitmask basis."""
+    lat = wl.honeycomb(L, L)
+    perms = wl.honeycomb_inversion_ops(L, L)
+    geo = Geometry(L, L, 1, 2)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    ts = [(tx, ty, 0) for ty in range(L) for tx in range(L)]
+    G = 2 * len(ts)
+    kph = lambda t: 1.0 if math.cos(geo.kdot(Kv, t)) > 0 else -1.0
+    Hb = bitmask_H(lat, K)
+    ms = masks(lat.n_sites, K)
+    idx = {m: i for i, m in enumerate(ms)}
+    total = 0
+    for chars in ((1, 1), (1, -1)):
+        d = 0
+        P = np.zeros((len(ms), len(ms)))
+        for p in range(2):
+            for t in ts:
+                perm = _cell_perm_of(lat, perms, p, t)
+                ch = chars[p] * kph(t)
+                d += ch * _fixed_states(perm, K)
+                for c, m in enumerate(ms):
+                    out = 0
+                    for i in range(lat.n_sites):
+                        if m >> i & 1:
+                            out |= 1 << perm[i]
+                    P[idx[out], c] += ch / G
+        assert round(d) % G == 0
+        s, R = mk_list_pg(geo, perms, chars, K, Kv)
+        assert len(s) == round(d) // G
+        total += len(s)
+        if not s:
+            continue
+        e = np.linalg.eigvalsh(gen_full_ham_pg(geo, perms, chars, K, bonds, s, R, Kv))
+        u, sv, _ = np.linalg.svd(P)
+        Q = u[:, sv > 0.5]
+        assert Q.shape[1] == len(s)
+        assert np.abs(np.linalg.eigvalsh(Q.T @ Hb @ Q) - e).max() < 1e-12
+    # the two one-dimensional sectors exhaust the momentum sector
+    assert total == len(mk_list(geo, K, Kv)[0])

@@ -236,6 +236,21 @@ def inversion_ops(L: int) -> np.ndarray:
     return np.array([[i for i in range(L)], [(-i) % L for i in range(L)]], dtype=np.int32)
 
 
+def honeycomb_inversion_ops(lx: int, ly: int) -> np.ndarray:
+    """Identity and the inversion through the centre of the bond A(0)-B(0) of
+    the honeycomb lattice (workloads.honeycomb): A at R <-> B at -R, which
+    exchanges the two places of a cell (2 x 2 lx ly)."""
+    N = 2 * lx * ly
+    out = np.zeros((2, N), dtype=np.int32)
+    out[0] = np.arange(N)
+    for y in range(ly):
+        for x in range(lx):
+            c, cm = x + lx * y, ((-x) % lx) + lx * ((-y) % ly)
+            out[1, 2 * c] = 1 + 2 * cm
+            out[1, 2 * c + 1] = 2 * cm
+    return out
+
+
 def _oh_elements():
     """The 48 signed axis permutations (sigma, signs) of O_h, identity first."""
     out = []
