@@ -38,6 +38,8 @@ def ctx(qs3):
 
 
 def _ops(lat):
+    if lat.ns == 3:
+        return wl.kagome_c6v_ops(lat.lx)
     if lat.ns == 2:
         return wl.honeycomb_inversion_ops(lat.lx, lat.ly)
     if lat.lz > 1:
@@ -46,6 +48,8 @@ def _ops(lat):
 
 
 def _chars(lat):
+    if lat.ns == 3:
+        return list(wl.C6V_CHARS.items())
     if lat.ns == 2:
         return [("even", (1, 1)), ("odd", (1, -1))]
     if lat.lz > 1:
@@ -59,7 +63,8 @@ CASES = [(wl.square(4), 2, (0, 0, 0)), (wl.square(4), 3, (2, 2, 0)), (wl.square(
          (wl.square(6), 2, (3, 3, 0)), (wl.chain(14), 5, (7, 0, 0)), (wl.chain(12), 6, (0, 0, 0)),
          (wl.with_disorder(wl.square(4), seed=3, per_bond=False), 3, (2, 2, 0)),
          (wl.square_j1j2(4, 0.45), 3, (2, 2, 0)), (wl.square_j1j2(4, 0.45), 4, (0, 0, 0)),
-         (wl.cube(3), 2, (0, 0, 0)), (wl.honeycomb(3, 3), 3, (0, 0, 0)), (wl.honeycomb(4, 4), 3, (2, 2, 0))]
+         (wl.cube(3), 2, (0, 0, 0)), (wl.honeycomb(3, 3), 3, (0, 0, 0)), (wl.honeycomb(4, 4), 3, (2, 2, 0)),
+         (wl.kagome(2, 2), 3, (0, 0, 0)), (wl.kagome(3, 3), 3, (0, 0, 0))]
 
 
 def _tol(H, vmax, width):
@@ -386,3 +391,32 @@ def test_pg_float32_products(qs3, ctx):
     assert np.abs(r32.evals - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
     sec.close()
     L.close()
+
+
+def test_pg_kagome12_c6v(qs3, ctx):
+    """12 x 12 kagome (432 sites), N_down = 3, k = 0: every one-dimensional
+    C6v block lies above the momentum block's ground level, and the lowest
+    A1 state carried into the momentum sector is an eigenvector there."""
+    lat = wl.kagome(12, 12)
+    L = qs3.Lattice.of(ctx, lat)
+    mom = qs3.Sector(L, 3, (0, 0, 0))
+    e0 = mom.eigs(nev=1, seed=1).evals[0]
+    for name, chars in wl.C6V_CHARS.items():
+        sec = qs3.PGSector(L, 3, (0, 0, 0), wl.kagome_c6v_ops(12), chars)
+        print(f"pg kagome12 K=3 {name}: dim {sec.dim}", flush=True)
+        if sec.dim == 0:
+            sec.close()
+            continue
+        X = torch.zeros(sec.dim, dtype=torch.float64, device="cuda")
+        r = sec.eigs(nev=1, evecs=X, seed=2)
+        assert r.status == qs3.QS3_OK
+        assert r.evals[0] >= e0 - 1e-9 * abs(e0)
+        if name == "A1":
+            psi = sec.to_momentum(X, mom)
+            w = torch.empty_like(psi)
+            mom.matvec(psi, w)
+            assert torch.linalg.vector_norm(w - r.evals[0] * psi).item() < 1e-7 * abs(r.evals[0])
+        sec.close()
+    mom.close()
+    L.close()
+

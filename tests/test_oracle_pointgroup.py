@@ -208,3 +208,54 @@ def test_honeycomb_inversion_sectors(L, K, Kv):
         assert np.abs(np.linalg.eigvalsh(Q.T @ Hb @ Q) - e).max() < 1e-12
     # the two one-dimensional sectors exhaust the momentum sector
     assert total == len(mk_list(geo, K, Kv)[0])
+
+
+def _cell_group_sectors(lat, perms, charsets, K, Kv):
+    """Dimensions from the character formula and projector spectra for a
+    group of cell translations x point operations on lat (any places per cell)."""
+    lx, ly, lz = lat.dims
+    geo = Geometry(lx, ly, lz, lat.ns)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    ts = [(tx, ty, tz) for tz in range(lz) for ty in range(ly) for tx in range(lx)]
+    G = len(perms) * len(ts)
+    kph = lambda t: 1.0 if math.cos(geo.kdot(Kv, t)) > 0 else -1.0
+    Hb = bitmask_H(lat, K)
+    ms = masks(lat.n_sites, K)
+    idx = {m: i for i, m in enumerate(ms)}
+    dims = []
+    for chars in charsets:
+        d = 0
+        P = np.zeros((len(ms), len(ms)))
+        for p in range(len(perms)):
+            for t in ts:
+                perm = _cell_perm_of(lat, perms, p, t)
+                ch = chars[p] * kph(t)
+                d += ch * _fixed_states(perm, K)
+                for c, m in enumerate(ms):
+                    out = 0
+                    for i in range(lat.n_sites):
+                        if m >> i & 1:
+                            out |= 1 << perm[i]
+                    P[idx[out], c] += ch / G
+        assert round(d) % G == 0
+        s, R = mk_list_pg(geo, perms, chars, K, Kv)
+        assert len(s) == round(d) // G
+        dims.append(len(s))
+        if not s:
+            continue
+        e = np.linalg.eigvalsh(gen_full_ham_pg(geo, perms, chars, K, bonds, s, R, Kv))
+        u, sv, _ = np.linalg.svd(P)
+        Q = u[:, sv > 0.5]
+        assert Q.shape[1] == len(s)
+        assert np.abs(np.linalg.eigvalsh(Q.T @ Hb @ Q) - e).max() < 1e-12
+    return dims
+
+
+@pytest.mark.parametrize("L,K", [(2, 3), (3, 2)])
+def test_kagome_c6v_sectors(L, K):
+    """C6v of the kagome lattice about a hexagon centre (rotations and
+    mirrors exchange the three places of a cell): the one-dimensional sectors
+    at k = 0 by the character formula and the projector."""
+    lat = wl.kagome(L, L)
+    dims = _cell_group_sectors(lat, wl.kagome_c6v_ops(L), list(wl.C6V_CHARS.values()), K, (0, 0, 0))
+    assert sum(dims) > 0

@@ -251,6 +251,42 @@ def honeycomb_inversion_ops(lx: int, ly: int) -> np.ndarray:
     return out
 
 
+def kagome_c6v_ops(L: int) -> np.ndarray:
+    """C6v of the periodic L x L kagome lattice (workloads.kagome) about a
+    hexagon centre, as site permutations (12 x 3 L^2): R^k then R^k M for
+    k = 0..5, R the 60-degree rotation and M the mirror exchanging a1 and a2.
+    In doubled coordinates on (a1, a2) the places sit at 2(x, y) + (0, 0),
+    (1, 0), (0, 1), the centre at (1, 1); R: (u, v) -> (-v, u + v)."""
+    d = ((0, 0), (1, 0), (0, 1))
+
+    def site_of(u, v):
+        u %= 2 * L
+        v %= 2 * L
+        for s, (dx, dy) in enumerate(d):
+            if (u - dx) % 2 == 0 and (v - dy) % 2 == 0:
+                return s + 3 * ((u - dx) // 2 + L * ((v - dy) // 2))
+        raise ValueError("not a kagome site")
+
+    out = np.zeros((12, 3 * L * L), dtype=np.int32)
+    for m in (0, 1):
+        for k in range(6):
+            for i in range(3 * L * L):
+                s, c = i % 3, i // 3
+                u, v = 2 * (c % L) + d[s][0] - 1, 2 * (c // L) + d[s][1] - 1
+                if m:
+                    u, v = v, u
+                for _ in range(k):
+                    u, v = -v, u + v
+                out[6 * m + k, i] = site_of(u + 1, v + 1)
+    return out
+
+
+# one-dimensional characters of C6v in the order of kagome_c6v_ops
+C6V_CHARS = {"A1": (1,) * 12, "A2": (1,) * 6 + (-1,) * 6,
+             "B1": tuple((-1) ** k for k in range(6)) * 2,
+             "B2": tuple((-1) ** k for k in range(6)) + tuple(-((-1) ** k) for k in range(6))}
+
+
 def _oh_elements():
     """The 48 signed axis permutations (sigma, signs) of O_h, identity first."""
     out = []
