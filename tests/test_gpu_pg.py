@@ -420,3 +420,33 @@ def test_pg_kagome12_c6v(qs3, ctx):
     mom.close()
     L.close()
 
+
+
+def test_pg_honeycomb_c6v_against_oracle(qs3, ctx):
+    """C6v of the 3x3 honeycomb at N_down = 3, k = 0: every one-dimensional
+    sector's representatives, norms, H.v and lowest level against the
+    oracle's block."""
+    lat = wl.honeycomb(3, 3)
+    perms = wl.honeycomb_c6v_ops(3)
+    geo = Geometry(3, 3, 1, 2)
+    bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
+    L = qs3.Lattice.of(ctx, lat)
+    for name, chars in wl.C6V_CHARS.items():
+        sigma, R = mk_list_pg(geo, perms, chars, 3, (0, 0, 0))
+        sec = qs3.PGSector(L, 3, (0, 0, 0), perms, chars)
+        ranks, norms = sec.basis()
+        assert np.array_equal(ranks.astype(np.int64), np.array(sigma, dtype=np.int64) - 1), name
+        if not sigma:
+            sec.close()
+            continue
+        assert np.allclose(norms, np.array(R) ** 2, rtol=1e-13, atol=0)
+        H = gen_full_ham_pg(geo, perms, chars, 3, bonds, sigma, R, (0, 0, 0))
+        vh = np.random.default_rng(3).normal(size=sec.dim)
+        w = torch.empty(sec.dim, dtype=torch.float64, device="cuda")
+        sec.matvec(torch.from_numpy(vh).cuda(), w)
+        assert np.abs(w.cpu().numpy() - H @ vh).max() <= _tol(H, np.abs(vh).max(), 9)
+        ref = np.linalg.eigvalsh(H)
+        r = sec.eigs(nev=1, seed=2)
+        assert abs(r.evals[0] - ref[0]) <= 1e-9 * max(1.0, abs(ref[0])), name
+        sec.close()
+    L.close()

@@ -259,3 +259,13 @@ def test_kagome_c6v_sectors(L, K):
     lat = wl.kagome(L, L)
     dims = _cell_group_sectors(lat, wl.kagome_c6v_ops(L), list(wl.C6V_CHARS.values()), K, (0, 0, 0))
     assert sum(dims) > 0
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_honeycomb_c6v_sectors(K):
+    """C6v of the 3x3 honeycomb about a hexagon centre (exchanging its two
+    places): the one-dimensional sectors at k = 0 by the character formula
+    and the projector."""
+    lat = wl.honeycomb(3, 3)
+    dims = _cell_group_sectors(lat, wl.honeycomb_c6v_ops(3), list(wl.C6V_CHARS.values()), K, (0, 0, 0))
+    assert sum(dims) > 0

@@ -281,7 +281,37 @@ def kagome_c6v_ops(L: int) -> np.ndarray:
     return out
 
 
-# one-dimensional characters of C6v in the order of kagome_c6v_ops
+def honeycomb_c6v_ops(L: int) -> np.ndarray:
+    """C6v of the periodic L x L honeycomb lattice (workloads.honeycomb) about
+    a hexagon centre, in the order of kagome_c6v_ops.  In tripled coordinates
+    on (a1, a2) the places sit at 3(x, y) and 3(x, y) + (1, 1), the centre at
+    (2, 2); R: (u, v) -> (-v, u + v), M: (u, v) -> (v, u)."""
+    d = ((0, 0), (1, 1))
+
+    def site_of(u, v):
+        u %= 3 * L
+        v %= 3 * L
+        for s, (dx, dy) in enumerate(d):
+            if (u - dx) % 3 == 0 and (v - dy) % 3 == 0:
+                return s + 2 * ((u - dx) // 3 + L * ((v - dy) // 3))
+        raise ValueError("not a honeycomb site")
+
+    out = np.zeros((12, 2 * L * L), dtype=np.int32)
+    for m in (0, 1):
+        for k in range(6):
+            for i in range(2 * L * L):
+                s, c = i % 2, i // 2
+                u, v = 3 * (c % L) + d[s][0] - 2, 3 * (c // L) + d[s][1] - 2
+                if m:
+                    u, v = v, u
+                for _ in range(k):
+                    u, v = -v, u + v
+                out[6 * m + k, i] = site_of(u + 2, v + 2)
+    return out
+
+
+# one-dimensional characters of C6v in the order of kagome_c6v_ops and
+# honeycomb_c6v_ops
 C6V_CHARS = {"A1": (1,) * 12, "A2": (1,) * 6 + (-1,) * 6,
              "B1": tuple((-1) ** k for k in range(6)) * 2,
              "B2": tuple((-1) ** k for k in range(6)) + tuple(-((-1) ** k) for k in range(6))}
