@@ -12,8 +12,8 @@ c4  periodic 10x10 square, N_down=3 ground state (lowest over the 100 sectors),
 pg  periodic 10x10 square, N_down = 5 and 6, k = 0: the four one-dimensional
     C4v sectors (translations x point operations) against the momentum sector
     holding the same ground state: block build, ELL H.v rate and bytes, solve
-    times; and the 10^3 cube's O_h A1g sector at N_down = 4 against its
-    momentum sector.
+    times; and at N_down = 4 the 10^3 cube's O_h A1g sector and the 12 x 12
+    kagome lattice's C6v A1 sector against their momentum sectors.
 c5  serving: Poisson arrivals of random solve requests (workloads.serving_stream),
     rate 0.8 / (mean one-at-a-time service time); p50/p99 latency and solves/s
     against the same requests run one at a time.
@@ -456,6 +456,37 @@ def c5(args):
                       "identical_to_alone": same_b}}
 
 
+def _pg_vs_momentum(ctx, lat, ops, chars, name, stream, K=4):
+    """Build and ground state of one point-group sector against the momentum
+    sector k = 0 of the same lattice and N_down."""
+    Lc = qs3.Lattice.of(ctx, lat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sec = qs3.PGSector(Lc, K, (0, 0, 0), ops, chars)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ra = sec.eigs(nev=1, seed=1, stream=stream)
+    torch.cuda.synchronize()
+    t_a = time.perf_counter() - t0
+    mom = qs3.Sector(Lc, K, (0, 0, 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rm = mom.eigs(nev=1, seed=1, stream=stream)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter() - t0
+    print(f"pg {lat.name} N_down={K} {name} dim {sec.dim} solve {t_a:.3f}s, momentum {mom.dim} {t_m:.3f}s",
+          file=sys.stderr, flush=True)
+    out = {name: {"dim": sec.dim, "build_s": t_b, "solve_s": t_a, "E0": float(ra.evals[0]),
+                  "matvecs": ra.info.n_matvec, "rc": ra.status},
+           "momentum": {"dim": mom.dim, "solve_s": t_m, "E0": float(rm.evals[0]), "matvecs": rm.info.n_matvec},
+           "sector_minus_momentum_E0": float(ra.evals[0] - rm.evals[0]), "momentum_over_sector_solve": t_m / t_a}
+    sec.close()
+    mom.close()
+    Lc.close()
+    return out
+
+
 def pg(args):
     """Point-group sectors of the 10 x 10 periodic square (J = Delta = 1) at
     k = 0 for N_down = 5 and 6: per one-dimensional C4v representation the
@@ -528,35 +559,10 @@ def pg(args):
         out["by_n_down"][K] = res
         torch.cuda.empty_cache()
     L.close()
-    # the cube's O_h (48 operations): 10^3, N_down = 4, k = 0, A1g against the
-    # momentum sector (41.4M rows)
-    cube = wl.cube(10)
-    Lc = qs3.Lattice.of(ctx, cube)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    a1g = qs3.PGSector(Lc, 4, (0, 0, 0), wl.oh_ops(10), wl.oh_chars()["A1g"])
-    torch.cuda.synchronize()
-    t_b = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ra = a1g.eigs(nev=1, seed=1, stream=stream)
-    torch.cuda.synchronize()
-    t_a = time.perf_counter() - t0
-    mom = qs3.Sector(Lc, 4, (0, 0, 0))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rm = mom.eigs(nev=1, seed=1, stream=stream)
-    torch.cuda.synchronize()
-    t_m = time.perf_counter() - t0
-    print(f"pg cube10 N_down=4 A1g dim {a1g.dim} solve {t_a:.3f}s, momentum {mom.dim} {t_m:.3f}s",
-          file=sys.stderr, flush=True)
-    out["cube10_N4_Oh"] = {"A1g": {"dim": a1g.dim, "build_s": t_b, "solve_s": t_a, "E0": float(ra.evals[0]),
-                                   "matvecs": ra.info.n_matvec, "rc": ra.status},
-                           "momentum": {"dim": mom.dim, "solve_s": t_m, "E0": float(rm.evals[0]),
-                                        "matvecs": rm.info.n_matvec},
-                           "A1g_minus_momentum_E0": float(ra.evals[0] - rm.evals[0]),
-                           "momentum_over_A1g_solve": t_m / t_a}
-    a1g.close()
-    mom.close()
-    Lc.close()
+    # the cube's O_h (48 operations) at 10^3 and the kagome lattice's C6v at
+    # 12 x 12, N_down = 4, k = 0: the trivial sector against the momentum sector
+    out["cube10_N4_Oh"] = _pg_vs_momentum(ctx, wl.cube(10), wl.oh_ops(10), wl.oh_chars()["A1g"], "A1g", stream)
+    out["kagome12_N4_C6v"] = _pg_vs_momentum(ctx, wl.kagome(12, 12), wl.kagome_c6v_ops(12), wl.C6V_CHARS["A1"],
+                                             "A1", stream)
     ctx.close()
     return out
