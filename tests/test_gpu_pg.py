@@ -450,3 +450,41 @@ def test_pg_honeycomb_c6v_against_oracle(qs3, ctx):
         assert abs(r.evals[0] - ref[0]) <= 1e-9 * max(1.0, abs(ref[0])), name
         sec.close()
     L.close()
+
+
+def test_pg_ground_state_dsf(qs3, ctx):
+    """S^-(q, omega) of a point-group ground state carried into the momentum
+    sector equals that of the momentum sector's own ground state, on a
+    cluster where exactly one one-dimensional block holds the ground level
+    and every other block (and the next level) lies clearly above it, so the
+    two states differ by a phase only (6 x 6 square, N_down = 2, k = 0)."""
+    lat = wl.square(6)
+    L = qs3.Lattice.of(ctx, lat)
+    mom = qs3.Sector(L, 2, (0, 0, 0))
+    Xk = torch.empty(2 * mom.dim, dtype=torch.complex128, device="cuda")
+    rk = mom.eigs(nev=2, evecs=Xk, seed=1)
+    e0, e1 = rk.evals[0], rk.evals[1]
+    gap = e1 - e0
+    assert gap > 1e-3 * abs(e0)
+    holders = []
+    for name, chars in wl.C4V_CHARS.items():
+        sec = qs3.PGSector(L, 2, (0, 0, 0), wl.c4v_ops(6), chars)
+        if sec.dim == 0:
+            sec.close()
+            continue
+        X = torch.zeros(sec.dim, dtype=torch.float64, device="cuda")
+        r = sec.eigs(nev=1, evecs=X, seed=2)
+        if abs(r.evals[0] - e0) <= 1e-9 * abs(e0):
+            holders.append((name, sec.to_momentum(X, mom)))
+        else:
+            assert r.evals[0] >= e0 + 0.5 * gap
+        sec.close()
+    assert len(holders) == 1
+    qv = [(1, 0, 0), (2, 3, 0), (3, 3, 0)]
+    omega = np.linspace(0.0, 8.0, 200)
+    S_pg, _, _, w_pg = mom.dsf(holders[0][1], e0, qv, omega, steps=40, eta=0.1, field=4.0)
+    S_k, _, _, w_k = mom.dsf(Xk[:mom.dim].contiguous(), e0, qv, omega, steps=40, eta=0.1, field=4.0)
+    assert np.allclose(w_pg, w_k, rtol=1e-8, atol=1e-12)
+    assert np.abs(S_pg - S_k).max() <= 1e-6 * np.abs(S_k).max()
+    mom.close()
+    L.close()
