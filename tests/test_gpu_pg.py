@@ -129,25 +129,31 @@ def _oracle_row(geo, perms, chars, K, bonds, Kv, a):
     return diag, out
 
 
-@pytest.mark.parametrize("K,Kv", [(4, (0, 0, 0)), (4, (5, 5, 0))])
-def test_pg_square10_sampled_rows(qs3, ctx, K, Kv):
-    """10 x 10 periodic square (the bench lattice): rows sampled from orbits
-    the oracle picks (random ranks mapped to their representatives) against
-    the oracle's row, as columns of H (the block is symmetric)."""
-    lat = wl.square(10)
-    perms = wl.c4v_ops(10)
-    geo = Geometry(*lat.dims)
+SAMPLED = [("square10", 4, (0, 0, 0)), ("square10", 4, (5, 5, 0)), ("kagome12", 3, (0, 0, 0))]
+
+
+@pytest.mark.parametrize("which,K,Kv", SAMPLED)
+def test_pg_full_size_sampled_rows(qs3, ctx, which, K, Kv):
+    """Full size (the 10 x 10 square with C4v, the 12 x 12 kagome with C6v):
+    rows sampled from orbits the oracle picks (random ranks mapped to their
+    representatives) against the oracle's row, as columns of H (the block is
+    symmetric)."""
+    if which == "square10":
+        lat, perms, charsets = wl.square(10), wl.c4v_ops(10), list(wl.C4V_CHARS.items())[::3]
+    else:
+        lat, perms, charsets = wl.kagome(12, 12), wl.kagome_c6v_ops(12), list(wl.C6V_CHARS.items())[::3]
+    geo = Geometry(lat.lx, lat.ly, lat.lz, lat.ns)
     bonds = bonds_1based(lat.bi, lat.bj, lat.jxy, lat.jz)
     L = qs3.Lattice.of(ctx, lat)
     rng = np.random.default_rng(2)
-    for name, chars in list(wl.C4V_CHARS.items())[::3]:
-        print(f"pg square10x10 K={K} k={Kv} {name}", flush=True)
+    for name, chars in charsets:
+        print(f"pg {lat.name} K={K} k={Kv} {name}", flush=True)
         sec = qs3.PGSector(L, K, Kv, perms, chars)
         ranks, norms = sec.basis()
         assert sec.dim > 0 and np.all(np.diff(ranks.astype(np.int64)) > 0)
         pos = {int(r): i for i, r in enumerate(ranks)}
         picked = 0
-        while picked < 4:
+        while picked < 3:
             a = representative_pg(geo, perms, int(rng.integers(1, C(geo.N, K) + 1)), K)[0] - 1
             Na = check_state_pg(geo, perms, chars, a + 1, K, Kv)
             if Na == 0:
@@ -163,8 +169,8 @@ def test_pg_square10_sampled_rows(qs3, ctx, K, Kv):
             col = w.cpu().numpy()
             want = np.zeros(sec.dim)
             want[pos[a]] += diag
-            for b, x in row.items():
-                want[pos[b]] += x
+            for bb, x in row.items():
+                want[pos[bb]] += x
             assert np.abs(col - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
         sec.close()
     L.close()
