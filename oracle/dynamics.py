@@ -8,19 +8,20 @@ import math
 
 import numpy as np
 
-from .cns import f_bar, F, is_down
+from .cns import f_bar, F
 from .translation import Geometry, representative, _bsearch_sorted
 
 
-def _flip(op: str, n, r: int, p: int, f: bool):
+def _flip(op: str, n, r: int):
     """The state and matrix element of s^op_r |n> (op = '-', '+', 'z'): s^- puts a
     down spin at an up site r, s^+ removes the down spin at r, s^z multiplies by
     1/2 - [r down].  Returns (tuple, c) or None when s^op_r |n> = 0."""
+    down = r in n
     if op == "-":
-        return None if f else (n[:p] + (r,) + n[p:], 1.0)
+        return None if down else (tuple(sorted(n + (r,))), 1.0)
     if op == "+":
-        return (n[:p - 1] + n[p:], 1.0) if f else None
-    return n, (-0.5 if f else 0.5)
+        return (tuple(x for x in n if x != r), 1.0) if down else None
+    return n, (-0.5 if down else 0.5)
 
 
 def n_down_after(op: str, K: int) -> int:
@@ -52,8 +53,7 @@ def sq_to_vec(geo: Geometry, K: int, sigma, R, Kvec, phi, sigma1, R1, Qvec, op: 
         Rr = geo.position(r)
         for alpha, a in enumerate(sigma):
             n = f_bar(a, K, geo.N)
-            p, f = is_down(r, n)
-            fl = _flip(op, n, r, p, f)
+            fl = _flip(op, n, r)
             if fl is None:
                 continue
             n2, c = fl

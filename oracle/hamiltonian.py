@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .cns import C, F, f_bar, is_down, spin_exchange
+from .cns import C, F, f_bar, hop
 
 
 def bonds_1based(bi, bj, jxy, jz):
@@ -30,18 +30,18 @@ def bonds_1based(bi, bj, jxy, jz):
 
 
 def row_terms(n, bonds):
-    """All terms of row F(n) in the order of Alg. 4 / Alg. 9: returns
-    (diag, [(n', Jxy/2), ...]) where n' are the exchanged tuples."""
+    """All terms of row F(n), bond by bond (the row loop of Alg. 4 / Alg. 9):
+    returns (diag, [(n', Jxy/2), ...]).  A bond with both ends alike adds
+    +Jz/4 to the diagonal; a bond with one end down adds -Jz/4 and the state
+    n' in which that down spin has moved to the other end."""
     diag = 0.0
     offs = []
     for (r, rp, jxy, jz) in bonds:
-        p, f = is_down(r, n)
-        pp, fp = is_down(rp, n)
-        if f == fp:
+        if (r in n) == (rp in n):
             diag += jz / 4.0
         else:
             diag -= jz / 4.0
-            offs.append((spin_exchange(r, p, f, rp, pp, n), jxy / 2.0))
+            offs.append((hop(n, r, rp), jxy / 2.0))
     return diag, offs
 
 

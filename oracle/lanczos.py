@@ -59,7 +59,7 @@ def diag_tri(alpha, beta):
     return np.linalg.eigh(T)
 
 
-def lowest_distinct(values, n: int, cluster_rel: float = 1e-8, residuals=None,
+def lowest_distinct(values, n: int, cluster_rel: float = 1e-10, residuals=None,
                     res_rel: float = 1e-8):
     """READING (degenerate levels): a single-start Krylov space holds one vector per
     eigenspace in exact arithmetic, while rounding lets partner copies of
@@ -67,7 +67,8 @@ def lowest_distinct(values, n: int, cluster_rel: float = 1e-8, residuals=None,
     the n lowest distinct levels among the converged Ritz values: a Ritz value
     counts when its residual estimate |beta_m c_{m,i}| <= res_rel * max(1, |e_i|)
     (when residuals are given), and values within cluster_rel * max(1, |E|) are
-    one level."""
+    one level (1e-10: levels closer than the accuracy asked of an eigenvalue
+    cannot be told apart by it)."""
     vals = np.asarray(values, dtype=np.float64)
     order = np.argsort(vals)
     out = []

@@ -49,6 +49,16 @@ def lib():
         L.orc_row_k.argtypes = [ctypes.c_int] * 4 + [P, ctypes.c_int, P, P, P, P, P, P, i64, i64, P,
                                                      P, P]
         L.orc_smq.argtypes = [ctypes.c_int] * 4 + [P, P, P, i64, P, P, P, i64, P, P, ctypes.c_int]
+        L.orc_kstruct_build.restype = P
+        L.orc_kstruct_build.argtypes = [ctypes.c_int] * 5 + [P, P, P, P, ctypes.c_int]
+        L.orc_kstruct_free.argtypes = [P]
+        L.orc_kstruct_nrep.restype = i64
+        L.orc_kstruct_nrep.argtypes = [P]
+        L.orc_kstruct_nhops.restype = i64
+        L.orc_kstruct_nhops.argtypes = [P]
+        L.orc_kstruct_sector.restype = i64
+        L.orc_kstruct_sector.argtypes = [P, P, P, P, P]
+        L.orc_kstruct_hv.argtypes = [P, P, P, P, i64, P, P, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -127,7 +137,8 @@ def row_u1(N: int, K: int, bonds: Bonds, a: int):
 
 
 def mk_list(dims, K: int, Kvec, nthreads: int = 0):
-    """Alg. 6: (sigma ascending 1-based ranks, R = sqrt(N_{a,k}))."""
+    """The k sector's representatives (sigma ascending 1-based ranks) and
+    R = sqrt(N_{a,k}), from every rank (what Alg. 5/6 compute)."""
     Kv = np.ascontiguousarray(Kvec, dtype=np.int32)
     d = _ok(lib().orc_mk_list(dims[0], dims[1], dims[2], K, _p(Kv), None, None, nthreads))
     sigma = np.zeros(d, dtype=np.uint64)
@@ -184,3 +195,50 @@ def smq(dims, K: int, Kvec, sigma, R, phi, sigma1, R1, Qvec, nthreads: int = 0):
     _ok(lib().orc_smq(dims[0], dims[1], dims[2], K, _p(Kv), _p(sigma), _p(R), sigma.shape[0],
                       _p(phi), _p(sigma1), _p(R1), sigma1.shape[0], _p(Qv), _p(out), nthreads))
     return out
+
+
+class KStruct:
+    """The cached-structure variant: every orbit representative of (lattice,
+    N_down) with its stabiliser and its row's hops resolved once (target
+    representative and translation, by the search over all translations),
+    reused for every momentum and every H.v.  ``sector(K)`` gives a momentum
+    sector (positions, 1-based ranks, R); ``hv`` applies H in it."""
+
+    def __init__(self, dims, K: int, bonds: Bonds, nthreads: int = 0):
+        self.dims, self.K = tuple(dims), K
+        self._h = lib().orc_kstruct_build(dims[0], dims[1], dims[2], K, bonds.n, _p(bonds.r),
+                                          _p(bonds.rp), _p(bonds.jxy), _p(bonds.jz), nthreads)
+        if not self._h:
+            raise ValueError("oracle: structure build failed")
+        self.nrep = int(lib().orc_kstruct_nrep(self._h))
+        self.nhops = int(lib().orc_kstruct_nhops(self._h))
+
+    def sector(self, Kvec):
+        Kv = np.ascontiguousarray(Kvec, dtype=np.int32)
+        d = int(lib().orc_kstruct_sector(self._h, _p(Kv), None, None, None))
+        mem = np.zeros(d, dtype=np.int64)
+        sigma = np.zeros(d, dtype=np.uint64)
+        R = np.zeros(d)
+        lib().orc_kstruct_sector(self._h, _p(Kv), _p(mem), _p(sigma), _p(R))
+        return mem, sigma, R
+
+    def hv(self, Kvec, members, R, phi, nthreads: int = 0):
+        Kv = np.ascontiguousarray(Kvec, dtype=np.int32)
+        members = np.ascontiguousarray(members, dtype=np.int64)
+        R = np.ascontiguousarray(R, dtype=np.float64)
+        phi = np.ascontiguousarray(phi, dtype=np.complex128)
+        out = np.zeros(members.shape[0], dtype=np.complex128)
+        _ok(lib().orc_kstruct_hv(self._h, _p(Kv), _p(members), _p(R), members.shape[0], _p(phi),
+                                 _p(out), nthreads))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().orc_kstruct_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

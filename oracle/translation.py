@@ -1,6 +1,9 @@
-"""Momentum (translation-symmetry) basis, Sec. 3.3: Alg. 5 (check_state),
-Alg. 6 (mk_list), Alg. 7 (representative), Alg. 8 (dense k-block) and Alg. 9
-(on-the-fly H.v in the k basis).
+"""Momentum (translation-symmetry) basis, Sec. 3.3, written from its
+definitions: the orbit of a state under translations, its representative
+(the minimum rank of the orbit), the normalisation N_{a,k} of Eq. (akstate),
+the list of representatives of a sector (what Alg. 5/6 compute), the
+representative search of a hop's target (Alg. 7's result), the dense k-block
+(Alg. 8) and the row-by-row H.v in the k basis (Alg. 9).
 
 The paper writes the chain; the lattice here is Lx x Ly x Lz unit cells of
 S sites each, with periodic boundaries and the translation group
@@ -21,7 +24,7 @@ import math
 
 import numpy as np
 
-from .cns import C, F, f_bar, is_down, spin_exchange
+from .cns import C, F, f_bar
 from .hamiltonian import row_terms
 
 
@@ -67,42 +70,39 @@ class Geometry:
         return 2.0 * math.pi * (K[0] * t[0] / self.lx + K[1] * t[1] / self.ly + K[2] * t[2] / self.lz)
 
 
-def insertion_sort(v):
-    """Ascending insertion sort (the paper's choice for O(1) lengths, Alg. 5)."""
-    v = list(v)
-    for i in range(1, len(v)):
-        x = v[i]
-        j = i - 1
-        while j >= 0 and v[j] > x:
-            v[j + 1] = v[j]
-            j -= 1
-        v[j + 1] = x
-    return tuple(v)
+def translate(geo: Geometry, n, t):
+    """T^t n as an ascending tuple: every down spin moved by the vector t."""
+    return tuple(sorted(geo.shift_func(n, t)))
+
+
+def orbit(geo: Geometry, n):
+    """[(j, rank of T^{t_j} n)] for translation numbers j = 1..N_T."""
+    return [(j, F(translate(geo, n, geo.t(j)))) for j in range(1, geo.NT + 1)]
 
 
 def check_state(geo: Geometry, a: int, K: int, Kvec) -> float:
-    """Alg. 5: N_{a,k} = |c*|^2 N / n_c if a is the minimum rank of its orbit, else 0.
+    """N_{a,k}, the squared norm of the sum in Eq. (akstate) for the orbit
+    minimum a: N_T sum over the stabiliser {t: T^t a = a} of e^{ik.t}, which is
+    N_T |stab| when e^{ik.t} = 1 on the stabiliser and 0 otherwise; 0 when a is
+    not the minimum rank of its orbit (it is then not a representative).
 
     READING: N_{a,k} is tested against 1e-8 instead of 0, since a vanishing
     character sum is only zero up to rounding in floating point.
     """
     n = f_bar(a, K, geo.N)
-    cstar = 0j
-    nc = 0
+    s = 0.0
     for j in range(1, geo.NT + 1):
-        t = geo.t(j)
-        a2 = F(insertion_sort(geo.shift_func(n, t)))
-        if a2 < a:
+        b = F(translate(geo, n, geo.t(j)))
+        if b < a:                    # a is not its orbit's minimum
             return 0.0
-        if a2 == a:
-            cstar += cmath.exp(1j * geo.kdot(Kvec, t))
-            nc += 1
-    Nak = abs(cstar) ** 2 * geo.NT / nc
+        if b == a:                   # t_j is in the stabiliser
+            s += math.cos(geo.kdot(Kvec, geo.t(j)))
+    Nak = s * geo.NT
     return Nak if Nak > 1e-8 else 0.0
 
 
 def mk_list(geo: Geometry, K: int, Kvec):
-    """Alg. 6: representative ranks sigma (ascending) and R = sqrt(N_{a,k})."""
+    """Representative ranks sigma (ascending) of the k sector and R = sqrt(N_{a,k})."""
     sigma, R = [], []
     for a in range(1, C(geo.N, K) + 1):
         Nak = check_state(geo, a, K, Kvec)
@@ -113,20 +113,18 @@ def mk_list(geo: Geometry, K: int, Kvec):
 
 
 def representative(geo: Geometry, a_n: int, K: int):
-    """Alg. 7: (min rank over the orbit of a_n, l) with T^{t_l} a_n = rep.
-    Ties keep the last j (the printed "<=")."""
-    rep = a_n
-    ell = geo.NT
-    n = f_bar(a_n, K, geo.N)
-    for j in range(1, geo.NT + 1):
-        a = F(insertion_sort(geo.shift_func(n, geo.t(j))))
-        if a <= rep:
-            rep, ell = a, j
+    """(minimum rank over the orbit of a_n, the first translation number l
+    with T^{t_l} a_n = that minimum).  READING: any translation reaching the
+    minimum would do; they give the same phase for a compatible k."""
+    orb = orbit(geo, f_bar(a_n, K, geo.N))
+    rep = min(r for _, r in orb)
+    ell = next(j for j, r in orb if r == rep)
     return rep, ell
 
 
 def _bsearch_sorted(sigma, x):
-    """(index 1-based, found) of x in ascending sigma (Alg. 2 on the list)."""
+    """(index 1-based, found) of x in the ascending list sigma (the binary
+    search of Alg. 9)."""
     lo, hi = 0, len(sigma)
     while lo < hi:
         mid = (lo + hi) // 2
@@ -140,8 +138,9 @@ def _bsearch_sorted(sigma, x):
 
 
 def row_terms_k(geo: Geometry, K: int, bonds, sigma, R, Kvec, alpha: int):
-    """Terms of row alpha (1-based) of the k block in the order of Alg. 8/9:
-    (diag, [(alpha', coefficient), ...]).
+    """Terms of row alpha (1-based) of the k block, bond by bond as Alg. 8/9
+    take them: (diag, [(alpha', coefficient), ...]) for the exchanged states
+    whose representative is in sigma.
 
     READING: the printed factor sqrt(R_{alpha'}/R_alpha) with R = sqrt(N_{a,k})
     would be (N'/N)^(1/4); the matrix element of Eq. (hak2) and of the H.v
@@ -193,6 +192,6 @@ def expand_to_u1(geo: Geometry, K: int, sigma, R, Kvec, phi: np.ndarray) -> np.n
         n = f_bar(a, K, geo.N)
         for j in range(1, geo.NT + 1):
             t = geo.t(j)
-            b = F(insertion_sort(geo.shift_func(n, t)))
+            b = F(translate(geo, n, t))
             out[b - 1] += phi[alpha] * cmath.exp(-1j * geo.kdot(Kvec, t)) / R[alpha]
     return out

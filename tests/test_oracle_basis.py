@@ -11,7 +11,7 @@ import pytest
 
 import workloads as wl
 from oracle import native as nat
-from oracle.cns import C, F, binary_search, f_bar, spin_exchange, is_down
+from oracle.cns import C, F, f_bar, hop
 from oracle.translation import Geometry, mk_list, representative, check_state
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
@@ -89,27 +89,18 @@ def test_boundary_and_64bit_ranks():
         assert f_bar(int(a[i]), 4, 1000) == tuple(int(x) for x in n[i])
 
 
-def test_binary_search_alg2():
-    s = [2, 4, 6, 8]
-    assert binary_search(1, s, 1, 4) == (0, False)
-    assert binary_search(2, s, 1, 4) == (1, True)
-    assert binary_search(5, s, 1, 4) == (2, False)
-    assert binary_search(8, s, 1, 4) == (4, True)
-    assert binary_search(100, s, 1, 4) == (4, False)
-
-
-def test_spin_exchange_matches_set_definition():
+def test_hop_matches_bit_operations():
+    """The exchanged state of a bond with one end down is the bitmask with both
+    bond bits flipped (mask ^ (1 << i) ^ (1 << j)): no tuple code involved."""
     N, K = 9, 4
-    for n in itertools.combinations(range(1, N + 1), K):
+    for mask in _gosper_masks(N, K):
+        n = tuple(i + 1 for i in range(N) if mask >> i & 1)
         for r in range(1, N + 1):
             for rp in range(r + 1, N + 1):
-                p, f = is_down(r, n)
-                pp, fp = is_down(rp, n)
-                if f == fp:
+                if ((mask >> (r - 1)) & 1) == ((mask >> (rp - 1)) & 1):
                     continue
-                out = spin_exchange(r, p, f, rp, pp, n)
-                s = set(n) ^ {r, rp}
-                assert out == tuple(sorted(s))
+                m2 = mask ^ (1 << (r - 1)) ^ (1 << (rp - 1))
+                assert hop(n, r, rp) == tuple(i + 1 for i in range(N) if m2 >> i & 1)
 
 
 def _burnside_dim(dims, K, Kvec):
@@ -163,7 +154,8 @@ def test_mk_list_dims_c2_c_oracle(Kvec):
 
 
 def test_representative_is_orbit_minimum_bitmask():
-    """Alg. 7 returns the orbit minimum, computed independently on bitmasks."""
+    """The representative search returns the orbit minimum, computed
+    independently on bitmasks, and a translation reaching it."""
     dims = (4, 3, 1)
     geo = Geometry(*dims)
     N, K = geo.N, 3
@@ -192,7 +184,8 @@ def test_representative_is_orbit_minimum_bitmask():
 
 
 def test_check_state_compatibility():
-    """N_{a,k} = N * |stab| when e^{ik.t} = 1 on the stabiliser, else 0 (Alg. 5)."""
+    """N_{a,k} = N * |stab| when e^{ik.t} = 1 on the stabiliser, else 0 (the
+    norm of Eq. (akstate); Alg. 5 computes the same)."""
     geo = Geometry(6, 1, 1)
     a = F((1, 4))                  # {1, 4} on a 6-ring: stabiliser {0, 3}
     assert check_state(geo, a, 2, (0, 0, 0)) == pytest.approx(12.0)
