@@ -183,7 +183,8 @@ typedef struct {
     int nm;             /* TRL: Krylov size N_M (0 = max(2 nk, 20)) */
     int max_restarts;   /* TRL: I_M (0 = 2000) */
     int steps;          /* LANCZOS: number of steps (0 = 100) */
-    double tol;         /* residual tolerance relative to max(1, |e|) (0 = 1e-9) */
+    double tol;         /* residual tolerance, relative to the scale below
+                           (0 = 1e-10; 1e-6 with QS3_PREC_F32MV) */
     uint64_t seed;      /* start vector seed */
     int precision;      /* QS3_PREC_* */
     int reorth;         /* QS3_REORTH_* (TRL: FULL or PARTIAL, both full) */
@@ -202,9 +203,12 @@ typedef struct {
                            iterating) */
 } qs3_eigs_info;
 
-/* Lowest `nev` distinct levels: a Ritz value counts when its residual estimate
- * |beta_m c_{m,i}| <= tol * max(1, |e_i|), and values closer than
- * 1e-8 * max(1, |e|) are one level.  evals: host, nev doubles (unfound =
+/* Lowest `nev` distinct levels (Alg. 10): a Ritz value counts when its
+ * residual estimate |beta_m c_{m,i}| <= tol * min(max(1, |e_i|), max(1, w)),
+ * w the width of the current Ritz spectrum (a scale that a constant offset of
+ * H does not change, so near-degenerate levels are resolved to about tol * w),
+ * and values closer than 1e-10 * max(1, |e|) are one level (1e-6 with
+ * QS3_PREC_F32MV, whose rounding splits degenerate levels by ~1e-8).  evals: host, nev doubles (unfound =
  * NaN).  evecs: device, dim x nev (vector y at offset y*dim) of the sector's
  * float64 type (QS3_F64 / QS3_C128), or NULL. */
 int qs3_eigs(qs3_sector *sec, const qs3_eigs_opts *opts, double *evals, void *evecs,
@@ -214,7 +218,9 @@ int qs3_eigs(qs3_sector *sec, const qs3_eigs_opts *opts, double *evals, void *ev
  * NULL for the seeded start vector), reorth = QS3_REORTH_*: alpha[0..steps-1], beta[0..steps-1]
  * (beta[x] = norm of the (x+2)-th vector before normalisation) and
  * *norm0 = |v0|.  Host outputs.  Stops early at an invariant subspace: *done
- * receives the number of steps taken. */
+ * receives the number of steps taken.  QS3_ENUMERIC when v0 is zero or not
+ * finite (or a coefficient turns non-finite); the outputs are then left
+ * untouched. */
 int qs3_lanczos(qs3_sector *sec, const void *v0, int steps, int precision, int reorth,
                 uint64_t seed, double *alpha, double *beta, double *norm0, int *done,
                 void *stream);

@@ -27,7 +27,7 @@ def lanczos(matvec, psi1, n_steps: int, reorth: bool = True, reorth_passes: int 
     Stops early (m < n_steps) if beta vanishes (invariant subspace found)."""
     d = psi1.shape[0]
     dtype = np.result_type(psi1.dtype, np.float64)
-    Psi = np.zeros((d, n_steps + 1), dtype=dtype)
+    Psi = np.zeros((d, n_steps + 1), dtype=dtype, order="F")   # columns contiguous
     alpha = np.zeros(n_steps)
     beta = np.zeros(n_steps)
     beta_prev = np.sqrt(np.real(_dot(psi1, psi1)))          # beta_0

@@ -1087,22 +1087,31 @@ static void build_tri(int m, const double *a, const double *b, std::vector<doubl
     }
 }
 
-// The lowest `nev` distinct levels (indices into the ascending e).  Ritz
-// values within 1e-8 max(1, |e|) of the previous level belong to it (partner
-// copies of a degenerate level, which rounding lets emerge, are ignored
-// whether or not they have converged); a level is converged when its lowest
-// Ritz value's residual is <= tol max(1, |e|).  require_conv (fixed-step
-// Lanczos, which cannot iterate further): unconverged values are skipped.
+// The lowest `nev` distinct levels (indices into the ascending e).  A Ritz
+// value has converged when its residual |beta_m c_{m,i}| is at most
+// tol * min(max(1, |e_i|), max(1, spread)), spread = the width of the Ritz
+// spectrum: the scale does not grow with a constant offset of H (the Ising
+// energy of the ferromagnet dominates |e| near saturation), so a level cannot
+// pass while its Ritz vector still mixes with a partner split by more than
+// about tol * spread.  Ritz values within cluster * max(1, |e|) of the
+// previous level belong to it (partner copies of a degenerate level, which
+// rounding lets emerge, are ignored whether or not they have converged):
+// 1e-10 for float64 products, 1e-6 for float32 ones (whose rounding splits a
+// degenerate level by about 1e-8).
+// require_conv (fixed-step Lanczos, which cannot iterate further):
+// unconverged values are skipped.
 static std::vector<int> pick_levels(const std::vector<double> &e, const std::vector<double> &res,
-                                    int nev, double tol, bool require_conv, bool *all_conv) {
+                                    int nev, double tol, double spread, double cluster,
+                                    bool require_conv, bool *all_conv) {
     std::vector<int> out;
     *all_conv = true;
     double last = 0.0;
+    const double ssc = std::max(1.0, spread);
     for (size_t i = 0; i < e.size() && (int)out.size() < nev; ++i) {
         const double sc = std::max(1.0, std::fabs(e[i]));
-        const bool conv = res[i] <= tol * sc;
+        const bool conv = res[i] <= tol * std::min(sc, ssc);
         if (require_conv && !conv) continue;
-        if (!out.empty() && std::fabs(e[i] - last) <= 1e-8 * sc) continue;
+        if (!out.empty() && std::fabs(e[i] - last) <= cluster * sc) continue;
         out.push_back((int)i);
         last = e[i];
         if (!conv) *all_conv = false;
@@ -1110,6 +1119,8 @@ static std::vector<int> pick_levels(const std::vector<double> &e, const std::vec
     if ((int)out.size() < nev) *all_conv = false;
     return out;
 }
+
+static double cluster_rel(const qs3_eigs_opts &o) { return o.precision == QS3_PREC_F32MV ? 1e-6 : 1e-10; }
 
 // Eigenvalues of the symmetric tridiagonal matrix (diagonal d, off-diagonal
 // e[i] coupling i and i+1) by the implicit QL algorithm with Wilkinson-type
@@ -1439,7 +1450,7 @@ int SolveRun::advance(bool *done) {
             std::vector<double> res(m);
             for (int i = 0; i < m; ++i) res[i] = std::fabs(b[m - 1] * zl[i]);
             bool allc;
-            auto lv = pick_levels(e, res, nev, o.tol, true, &allc);
+            auto lv = pick_levels(e, res, nev, o.tol, e.back() - e.front(), cluster_rel(o), true, &allc);
             // a Krylov space that closed (breakdown) or spans every row holds
             // all the levels the start vector reaches: fewer than nev is final
             const bool exhausted = m < S || (uint64_t)S >= E.n;
@@ -1501,7 +1512,8 @@ int SolveRun::advance(bool *done) {
         for (int i = 0; i < NM; ++i) res[i] = std::fabs(bm * V[(size_t)(NM - 1) * NM + i]);
         bool allc;
         auto lv = pick_levels(std::vector<double>(e.begin(), e.begin() + NK),
-                              std::vector<double>(res.begin(), res.begin() + NK), nev, o.tol, false, &allc);
+                              std::vector<double>(res.begin(), res.begin() + NK), nev, o.tol,
+                              e.back() - e.front(), cluster_rel(o), false, &allc);
         for (int x = 0; x < NM; ++x)
             for (int y = 0; y < NK; ++y) hC[((size_t)x * NK + y) * Bc + j] = V[(size_t)x * NM + y];
         for (int y = 0; y < NK; ++y) {

@@ -185,7 +185,7 @@ inline int fill_opts(qs3_eigs_opts &o, uint64_t min_dim) {
     if (o.nm <= 0) o.nm = std::max(2 * o.nk, 20);
     if (o.max_restarts <= 0) o.max_restarts = 2000;
     if (o.steps <= 0) o.steps = 100;
-    if (!(o.tol > 0)) o.tol = 1e-9;
+    if (!(o.tol > 0)) o.tol = o.precision == QS3_PREC_F32MV ? 1e-6 : 1e-10;
     QS3_REQUIRE(o.nev <= 16, QS3_EINVAL, "nev must be <= 16");
     QS3_REQUIRE(o.precision == QS3_PREC_F64 || o.precision == QS3_PREC_F32MV, QS3_EINVAL,
                 "unknown precision");
