@@ -55,6 +55,7 @@ BatchArgs batch_args(qs3_batch *bat) {
     A.invM = 1.0 / bat->M;
     A.phase = bat->phase.as<double2>();
     A.active = bat->active_dev;
+    A.ph_lds_off = -1;
     return A;
 }
 
@@ -63,6 +64,15 @@ int grid_for(qs3_ctx *ctx, uint64_t tiles) {
     uint64_t g = std::min<uint64_t>(tiles, want);
     if (g >= 8) g &= ~uint64_t(7);
     return (int)std::max<uint64_t>(g, 1);
+}
+
+int grid_cover(qs3_ctx *ctx, uint64_t tiles) {
+    // one tile per block while the tiles fill at most 8 blocks per CU (the
+    // count rounded up to whole XCD rounds: no block takes two tiles while
+    // others idle), else 8 blocks per CU
+    const uint64_t want = (uint64_t)ctx->n_cu * 8;
+    if (tiles >= want) return (int)want;
+    return (int)std::max<uint64_t>((tiles + 7) / 8 * 8, 1);
 }
 
 #define QS3_SWITCH_K(K, MAXK, CALL)                     \

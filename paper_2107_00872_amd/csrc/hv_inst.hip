@@ -253,12 +253,45 @@ int lanczos_small_K<KI>(qs3_lattice *lat, const BinomTable *bt, qs3_batch *bat, 
 template <typename RT, typename CT, typename OT, int MODE>
 static int launch_batch(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
     BatchArgs A = batch_args(bat);
+    if (A.B == 1) {
+        // a single sector: one lane per row, the hops of a chunk in flight together
+        using C2 = typename Cplx<CT>::type;
+        using O2 = typename Cplx<OT>::type;
+        if (MODE == HOP_LISTS && A.L.uniform && A.hmax <= 24 && A.M <= PHASE_LDS) {
+            // hop lists with one exchange constant: the entries give every term
+            const int g1 = grid_cover(bat->lat->ctx, (A.n_reps + 255) / 256);
+#define QS3_L1(HM)                                                                                         \
+    hipLaunchKernelGGL((k_hv_one_lists<CT, OT, HM>), dim3(g1), dim3(256), 0, s, A, (const C2 *)v, (O2 *)w)
+            if (A.hmax <= 6) QS3_L1(6);
+            else if (A.hmax <= 8) QS3_L1(8);
+            else if (A.hmax <= 12) QS3_L1(12);
+            else if (A.hmax <= 16) QS3_L1(16);
+            else if (A.hmax <= 18) QS3_L1(18);
+            else QS3_L1(24);
+#undef QS3_L1
+            QS3_HIP(hipGetLastError());
+            return QS3_OK;
+        }
+        size_t sh1 = lds_need<RT>(bat->lat, KI);
+        QS3_REQUIRE(sh1 <= 160 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
+        const int grid1 = grid_cover(bat->lat->ctx, (A.n_reps + 255) / 256);
+        hipLaunchKernelGGL((k_hv_one<KI, RT, CT, OT, MODE>), dim3(grid1), dim3(256), sh1, s, A,
+                           bat->bt->dev.as<RT>(), (const C2 *)v, (O2 *)w);
+        QS3_HIP(hipGetLastError());
+        return QS3_OK;
+    }
     // a narrow batch (the few sectors a solve has left) takes 8 lanes per
     // row: its hops are resolved 8 at a time and 8 gathers stay in flight;
     // every sector sums its hops in the same order.  A single sector keeps
     // one lane per row (its gathers would leave the other lanes idle).
     if (A.B > 1 && A.G < 8) A.G = 8;
     size_t sh = lds_need<RT>(bat->lat, KI);
+    // the phase table after the lattice tables, when it fits
+    const size_t ph_off = (sh + 15) & ~size_t(15);
+    if (A.M <= 4096 && ph_off + 16 * (size_t)A.M <= 64 * 1024) {
+        A.ph_lds_off = (int)ph_off;
+        sh = ph_off + 16 * (size_t)A.M;
+    }
     QS3_REQUIRE(sh <= 160 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
     const int per = (A.B + A.G - 1) / A.G;
     uint64_t rows_per_tile = 256 / A.G;
@@ -267,15 +300,17 @@ static int launch_batch(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
     const RT *tab = bat->bt->dev.as<RT>();
     using C2 = typename Cplx<CT>::type;
     using O2 = typename Cplx<OT>::type;
-#define QS3_LB(BPL)                                                                             \
-    hipLaunchKernelGGL((k_hv_batch<KI, RT, CT, OT, MODE, BPL>), dim3(grid), dim3(256), sh, s, A, \
+#define QS3_LB(BPL, NP)                                                                             \
+    hipLaunchKernelGGL((k_hv_batch<KI, RT, CT, OT, MODE, BPL, NP>), dim3(grid), dim3(256), sh, s, A, \
                        tab, (const C2 *)v, (O2 *)w)
-    if (per <= 1) QS3_LB(1);
-    else if (per <= 2) QS3_LB(2);
-    else if (per <= 4) QS3_LB(4);
-    else if (per <= 8) QS3_LB(8);
-    else if (per <= 16) QS3_LB(16);
-    else if (per <= 32) QS3_LB(32);
+    // a lane's sectors: at most 8 per pass (accumulators and gathers in few
+    // registers), several passes for wider batches
+    if (per <= 1) QS3_LB(1, 1);
+    else if (per <= 2) QS3_LB(2, 1);
+    else if (per <= 4) QS3_LB(4, 1);
+    else if (per <= 8) QS3_LB(8, 1);
+    else if (per <= 16) QS3_LB(8, 2);
+    else if (per <= 32) QS3_LB(8, 4);
     else {
         set_error("batch larger than 2048 sectors");
         return QS3_EINVAL;

@@ -39,6 +39,9 @@ struct Cplx<float> {
     using type = float2;
 };
 
+// phase tables of at most this many entries are staged in LDS
+constexpr int PHASE_LDS = 2048;
+
 __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
     // gfx950 dispatches workgroup b to XCD b % 8; give each XCD one contiguous
     // slice of the logical block range so its L2 sees neighbouring rows.
@@ -212,9 +215,15 @@ __device__ __forceinline__ void hop_of(int h, const int (&off)[K + 1], const int
 // translation (table lookup or canonicalisation), stabiliser ratio -- so the
 // group pays each hop's resolution once and in parallel.  The resolved hops
 // are then broadcast lane by lane with wavefront shuffles and every lane
-// applies them to its own sectors b = lane, lane + G, ... with the phase
-// e^{ik_b.t}; the gather of one hop reads G contiguous complex elements.
-template <int K, typename RT, typename CT, typename OT, int MODE, int BPL>
+// applies them to its own sectors with the phase e^{ik_b.t}; the gather of
+// one hop reads G contiguous complex elements.  A lane's sectors are
+// b = lane + (p * BPL + i) * G for pass p < NP and i < BPL: wide batches run
+// several passes over the row (hops resolved again per pass) so that the
+// accumulators and gathers of one pass fit in few registers.  Each sector
+// sums its hops in hop order whatever BPL, NP and G are.  The phase table
+// e^{2 pi i P / M} is staged in LDS after the lattice tables when
+// A.ph_lds_off >= 0.
+template <int K, typename RT, typename CT, typename OT, int MODE, int BPL, int NP>
 __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restrict__ binom_g,
                                                   const typename Cplx<CT>::type *__restrict__ v,
                                                   typename Cplx<OT>::type *__restrict__ w) {
@@ -225,6 +234,10 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
     const RT *tab;
     const int *ptr;
     const uint16_t *nbr;
+    const bool ph_lds = A.ph_lds_off >= 0;
+    double2 *s_ph = (double2 *)(smem + (ph_lds ? A.ph_lds_off : 0));
+    if (ph_lds)
+        for (int i = threadIdx.x; i < A.M; i += blockDim.x) s_ph[i] = A.phase[i];
     load_lds_tables<RT>(smem, A.L, binom_g, K, &tab, &ptr, &nbr);
     Binom<RT> Bn{tab, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
@@ -234,17 +247,6 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
     const int lane = threadIdx.x % G;
     const int slot = threadIdx.x / G;
     const int rows_per_tile = blockDim.x / G;
-    int kx[BPL], ky[BPL], kz[BPL];
-    bool bval[BPL];
-#pragma unroll
-    for (int i = 0; i < BPL; ++i) {
-        int b = lane + i * G;
-        bval[i] = b < B && (!A.active || A.active[b < B ? b : 0]);
-        int bb = bval[i] ? b : 0;
-        kx[i] = A.kmul[3 * bb];
-        ky[i] = A.kmul[3 * bb + 1];
-        kz[i] = A.kmul[3 * bb + 2];
-    }
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
     const uint64_t ntiles = (A.n_reps + rows_per_tile - 1) / rows_per_tile;
     const uint64_t t0 = ntiles * lb / gridDim.x, t1 = ntiles * (lb + 1) / gridDim.x;
@@ -265,157 +267,388 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
         for (int m = 0; m < K; ++m) off[m + 1] = off[m] + (ptr[c[m] + 1] - ptr[c[m]]);
         const int nh = off[K];
         const CT isq = (CT)(1.0 / A.L.sqrt_tab[su]);
-        CT accr[BPL], acci[BPL];
+#pragma unroll 1
+        for (int pass = 0; pass < NP; ++pass) {
+            int kx[BPL], ky[BPL], kz[BPL];
+            bool bval[BPL];
 #pragma unroll
-        for (int i = 0; i < BPL; ++i) accr[i] = acci[i] = 0;
-        CT dz = 0;
-        for (int base = 0; base < nh; base += G) {
-            // ---- resolve hop base + lane
-            const int h = base + lane;
-            uint32_t u2 = 0, tp = 0;
-            int nt2 = -1;
-            double coef = 0.0, jzv = 0.0;
-            bool ok = false;
-            if (h < nh) {
-                int m, e;
-                hop_of<K>(h, off, c, ptr, &m, &e);
-                const int j = nbr[e];
-                RT rp;
-                bool hop = true;
+            for (int i = 0; i < BPL; ++i) {
+                const int b = lane + (pass * BPL + i) * G;
+                bval[i] = b < B && (!A.active || A.active[b < B ? b : 0]);
+                const int bb = bval[i] ? b : 0;
+                kx[i] = A.kmul[3 * bb];
+                ky[i] = A.kmul[3 * bb + 1];
+                kz[i] = A.kmul[3 * bb + 2];
+            }
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < BPL; ++i) any |= bval[i];
+            // a pass whose sectors are all absent or inactive in every lane of the group
+            if (!__any(any)) continue;
+            CT accr[BPL], acci[BPL];
+#pragma unroll
+            for (int i = 0; i < BPL; ++i) accr[i] = acci[i] = 0;
+            CT dz = 0;
+            for (int base = 0; base < nh; base += G) {
+                // ---- resolve hop base + lane
+                const int h = base + lane;
+                uint32_t u2 = 0, tp = 0;
+                int nt2 = -1;
+                double coef = 0.0, jzv = 0.0;
+                bool ok = false;
+                if (h < nh) {
+                    int m, e;
+                    hop_of<K>(h, off, c, ptr, &m, &e);
+                    const int j = nbr[e];
+                    RT rp;
+                    bool hop = true;
+                    int tx = 0, ty = 0, tz = 0;
+                    if (MODE == HOP_LISTS) {
+                        // resolved once at structure build: occupied targets are ~0
+                        const uint64_t ent = A.hops[u * (uint64_t)A.hmax + h];
+                        hop = ent != ~0ull;
+                        u2 = (uint32_t)ent;
+                        const uint32_t t = (uint32_t)(ent >> 32);
+                        tx = t & 1023u;
+                        ty = (t >> 10) & 1023u;
+                        tz = (t >> 20) & 1023u;
+                    } else {
+                        hop = hr.hop_rt(m, c, R, j, Bn, &rp);
+                        if (hop) resolve_hop<K, RT, MODE == HOP_TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
+                    }
+                    if (hop) {
+                        const int s2 = A.stab[u2];
+                        nt2 = s2 > 1 ? A.nt_of[u2] : -1;
+                        tp = (uint32_t)(tx | (ty << 10) | (tz << 20));
+                        const double jxy = UNIF ? A.L.u_jxy_h : A.L.jxy_h[e];
+                        coef = jxy * (s2 == 1 ? 1.0 : A.L.sqrt_tab[s2]) * (double)isq;  // sqrt(1) = 1
+                        jzv = UNIF ? A.L.u_jz_h : A.L.jz_h[e];
+                        ok = true;
+                    }
+                }
+                // ---- apply the round's hops to this lane's sectors, QC hops at a
+                // time (QC * BPL gathers): their gathers and phase loads are all
+                // issued before any is consumed; a slot that applies nothing reads
+                // element 0 and is dropped by a select.  Groups narrower than QC
+                // go one hop at a time.
+                const int cnt = min(G, nh - base);
+                if (G < QC) {
+                    for (int q = 0; q < cnt; ++q) {
+                        const int bok = __shfl((int)ok, q, G);
+                        if (!bok) continue;
+                        const uint32_t bu = (uint32_t)__shfl((int)u2, q, G);
+                        const uint32_t bt = (uint32_t)__shfl((int)tp, q, G);
+                        const int bnt = __shfl(nt2, q, G);
+                        const CT bc = (CT)__shfl(coef, q, G);
+                        dz += (CT)__shfl(jzv, q, G);
+                        const int tx = bt & 1023u, ty = (bt >> 10) & 1023u, tz = (bt >> 20) & 1023u;
+                        const C2 *vrow = v + (uint64_t)bu * B;
+#pragma unroll
+                        for (int i = 0; i < BPL; ++i) {
+                            if (!bval[i]) continue;
+                            const int b = lane + (pass * BPL + i) * G;
+                            if (bnt >= 0 && !A.compat_nt[(size_t)bnt * B + b]) continue;
+                            int P = kx[i] * tx + ky[i] * ty + kz[i] * tz;
+                            const int qq = (int)((double)P * A.invM);
+                            P -= qq * A.M;
+                            P += (P < 0) ? A.M : 0;
+                            P -= (P >= A.M) ? A.M : 0;
+                            const double2 ph = ph_lds ? s_ph[P] : A.phase[P];
+                            const C2 x = vrow[b];
+                            const CT pr = bc * (CT)ph.x, pi = bc * (CT)ph.y;
+                            accr[i] += pr * x.x - pi * x.y;
+                            acci[i] += pr * x.y + pi * x.x;
+                        }
+                    }
+                    continue;
+                }
+                for (int q0 = 0; q0 < cnt; q0 += QC) {
+                    bool hok[QC];
+                    uint32_t hu[QC];
+                    int htx[QC], hty[QC], htz[QC], hnt[QC];
+                    CT hc[QC];
+#pragma unroll
+                    for (int r = 0; r < QC; ++r) {
+                        const int q = q0 + r;
+                        const int qs = q < cnt ? q : 0;
+                        const int okq = __shfl((int)ok, qs, G);
+                        hok[r] = q < cnt && okq != 0;
+                        hu[r] = (uint32_t)__shfl((int)u2, qs, G);
+                        const uint32_t bt = (uint32_t)__shfl((int)tp, qs, G);
+                        htx[r] = bt & 1023u;
+                        hty[r] = (bt >> 10) & 1023u;
+                        htz[r] = (bt >> 20) & 1023u;
+                        hnt[r] = __shfl(nt2, qs, G);
+                        hc[r] = (CT)__shfl(coef, qs, G);
+                        const CT jz = (CT)__shfl(jzv, qs, G);
+                        if (hok[r]) dz += jz;
+                    }
+                    C2 x[QC][BPL];
+                    int Pi[QC][BPL];
+#pragma unroll
+                    for (int r = 0; r < QC; ++r) {
+#pragma unroll
+                        for (int i = 0; i < BPL; ++i) {
+                            const int b = lane + (pass * BPL + i) * G;
+                            bool use = hok[r] && bval[i];
+                            if (use && hnt[r] >= 0) use = A.compat_nt[(size_t)hnt[r] * B + b] != 0;
+                            int P = kx[i] * htx[r] + ky[i] * hty[r] + kz[i] * htz[r];
+                            const int qq = (int)((double)P * A.invM);
+                            P -= qq * A.M;
+                            P += (P < 0) ? A.M : 0;
+                            P -= (P >= A.M) ? A.M : 0;
+                            const uint64_t idx = use ? (uint64_t)hu[r] * B + b : 0;
+                            x[r][i] = v[idx];
+                            Pi[r][i] = use ? P : 0;
+                            if (!use) {
+                                x[r][i].x = 0;
+                                x[r][i].y = 0;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < QC; ++r) {
+#pragma unroll
+                        for (int i = 0; i < BPL; ++i) {
+                            const double2 ph = ph_lds ? s_ph[Pi[r][i]] : A.phase[Pi[r][i]];
+                            const CT pr = hc[r] * (CT)ph.x, pi = hc[r] * (CT)ph.y;
+                            accr[i] += pr * x[r][i].x - pi * x[r][i].y;
+                            acci[i] += pr * x[r][i].y + pi * x[r][i].x;
+                        }
+                    }
+                }
+            }
+            const CT diag = (CT)A.L.ez4 - dz;
+            O2 *wrow = w + u * B;
+            const C2 *vself = v + u * B;
+#pragma unroll
+            for (int i = 0; i < BPL; ++i) {
+                if (!bval[i]) continue;
+                const int b = lane + (pass * BPL + i) * G;
+                const bool okr = ntu < 0 || A.compat_nt[(size_t)ntu * B + b];
+                O2 o;
+                if (okr) {
+                    C2 x = vself[b];
+                    o.x = (OT)(diag * x.x + accr[i]);
+                    o.y = (OT)(diag * x.y + acci[i]);
+                } else {
+                    o.x = 0;
+                    o.y = 0;
+                }
+                wrow[b] = o;
+            }
+        }
+    }
+}
+
+// A single momentum sector (a batch of one): one lane per representative row,
+// and the row's hops taken QC at a time -- every hop of a chunk is resolved
+// (hop-list entry, table entry or canonicalisation), then its stabiliser,
+// phase and v gathers are all issued before any is consumed, so a row waits
+// for a few memory latencies instead of one per hop.  The sum runs over the
+// hops in the same order and with the same arithmetic as k_hv_batch.
+template <int K, typename RT, typename CT, typename OT, int MODE>
+__global__ __launch_bounds__(256) void k_hv_one(BatchArgs A, const RT *__restrict__ binom_g,
+                                                const typename Cplx<CT>::type *__restrict__ v,
+                                                typename Cplx<OT>::type *__restrict__ w) {
+    using C2 = typename Cplx<CT>::type;
+    using O2 = typename Cplx<OT>::type;
+    constexpr int QC = 8;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const RT *tab;
+    const int *ptr;
+    const uint16_t *nbr;
+    load_lds_tables<RT>(smem, A.L, binom_g, K, &tab, &ptr, &nbr);
+    if (A.active && !A.active[0]) return;  // an inactive sector's rows stay untouched
+    Binom<RT> Bn{tab, binom_shift(A.L.N)};
+    Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
+    const bool UNIF = A.L.uniform != 0;
+    const int kx = A.kmul[0], ky = A.kmul[1], kz = A.kmul[2];
+    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const uint64_t ntiles = (A.n_reps + 255) / 256;
+    const uint64_t t0 = ntiles * lb / gridDim.x, t1 = ntiles * (lb + 1) / gridDim.x;
+    for (uint64_t tile = t0; tile < t1; ++tile) {
+        const uint64_t u = tile * 256 + threadIdx.x;
+        if (u >= A.n_reps) break;
+        const int su = A.stab[u];
+        if (su > 1 && !A.compat_nt[A.nt_of[u]]) {
+            w[u] = O2{0, 0};
+            continue;
+        }
+        const RT R = (RT)A.reps[u];
+        int c[K > 0 ? K : 1];
+        unrank<K, RT>(R, A.L.N, Bn, c);
+        HopRanker<K, RT> hr;
+        hr.init(c, Bn);
+        int off[K + 1];
+        off[0] = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) off[m + 1] = off[m] + (ptr[c[m] + 1] - ptr[c[m]]);
+        const int nh = off[K];
+        const CT isq = (CT)(1.0 / A.L.sqrt_tab[su]);
+        const uint64_t *hrow = MODE == HOP_LISTS ? A.hops + u * (uint64_t)A.hmax : nullptr;
+        CT accr = 0, acci = 0, dz = 0;
+        for (int h0 = 0; h0 < nh; h0 += QC) {
+            bool hok[QC];
+            uint32_t hu[QC];
+            int he[QC], P[QC];
+#pragma unroll
+            for (int r = 0; r < QC; ++r) {
+                const int h = h0 + r;
+                int m = 0, e = 0;
+                if (h < nh) hop_of<K>(h, off, c, ptr, &m, &e);
+                he[r] = e;
+                uint32_t u2 = 0;
                 int tx = 0, ty = 0, tz = 0;
+                bool ok = false;
                 if (MODE == HOP_LISTS) {
-                    // resolved once at structure build: occupied targets are ~0
-                    const uint64_t ent = A.hops[u * (uint64_t)A.hmax + h];
-                    hop = ent != ~0ull;
+                    const uint64_t ent = h < nh ? hrow[h] : ~0ull;
+                    ok = ent != ~0ull;
                     u2 = (uint32_t)ent;
                     const uint32_t t = (uint32_t)(ent >> 32);
                     tx = t & 1023u;
                     ty = (t >> 10) & 1023u;
                     tz = (t >> 20) & 1023u;
-                } else {
-                    hop = hr.hop_rt(m, c, R, j, Bn, &rp);
-                    if (hop) resolve_hop<K, RT, MODE == HOP_TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
+                } else if (h < nh) {
+                    const int j = nbr[e];
+                    RT rp;
+                    ok = hr.hop_rt(m, c, R, j, Bn, &rp);
+                    if (ok) resolve_hop<K, RT, MODE == HOP_TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
                 }
-                if (hop) {
-                    const int s2 = A.stab[u2];
-                    nt2 = s2 > 1 ? A.nt_of[u2] : -1;
-                    tp = (uint32_t)(tx | (ty << 10) | (tz << 20));
-                    const double jxy = UNIF ? A.L.u_jxy_h : A.L.jxy_h[e];
-                    coef = jxy * A.L.sqrt_tab[s2] * (double)isq;
-                    jzv = UNIF ? A.L.u_jz_h : A.L.jz_h[e];
-                    ok = true;
-                }
+                hok[r] = ok;
+                hu[r] = ok ? u2 : (uint32_t)u;
+                int p = kx * tx + ky * ty + kz * tz;
+                const int qq = (int)((double)p * A.invM);
+                p -= qq * A.M;
+                p += (p < 0) ? A.M : 0;
+                p -= (p >= A.M) ? A.M : 0;
+                P[r] = ok ? p : 0;
             }
-            // ---- apply the round's hops to this lane's sectors, QC hops at a
-            // time (QC * BPL gathers): their gathers and phase loads are all
-            // issued before any is consumed; a slot that applies nothing reads
-            // element 0 and is dropped by a select.  Groups narrower than QC
-            // and 32 sectors per lane (too many registers) go one hop at a time.
-            const int cnt = min(G, nh - base);
-            if (BPL >= 32 || G < QC) {
-                for (int q = 0; q < cnt; ++q) {
-                    const int bok = __shfl((int)ok, q, G);
-                    if (!bok) continue;
-                    const uint32_t bu = (uint32_t)__shfl((int)u2, q, G);
-                    const uint32_t bt = (uint32_t)__shfl((int)tp, q, G);
-                    const int bnt = __shfl(nt2, q, G);
-                    const CT bc = (CT)__shfl(coef, q, G);
-                    dz += (CT)__shfl(jzv, q, G);
-                    const int tx = bt & 1023u, ty = (bt >> 10) & 1023u, tz = (bt >> 20) & 1023u;
-                    const C2 *vrow = v + (uint64_t)bu * B;
+            // every gather of the chunk in flight together
+            int s2[QC];
+            C2 x[QC];
+            double2 ph[QC];
 #pragma unroll
-                    for (int i = 0; i < BPL; ++i) {
-                        if (!bval[i]) continue;
-                        const int b = lane + i * G;
-                        if (bnt >= 0 && !A.compat_nt[(size_t)bnt * B + b]) continue;
-                        int P = kx[i] * tx + ky[i] * ty + kz[i] * tz;
-                        const int qq = (int)((double)P * A.invM);
-                        P -= qq * A.M;
-                        P += (P < 0) ? A.M : 0;
-                        P -= (P >= A.M) ? A.M : 0;
-                        const double2 ph = A.phase[P];
-                        const C2 x = vrow[b];
-                        const CT pr = bc * (CT)ph.x, pi = bc * (CT)ph.y;
-                        accr[i] += pr * x.x - pi * x.y;
-                        acci[i] += pr * x.y + pi * x.x;
-                    }
-                }
-                continue;
+            for (int r = 0; r < QC; ++r) {
+                s2[r] = A.stab[hu[r]];
+                x[r] = v[hu[r]];
+                ph[r] = A.phase[P[r]];
             }
-            for (int q0 = 0; q0 < cnt; q0 += QC) {
-                bool hok[QC];
-                uint32_t hu[QC];
-                int htx[QC], hty[QC], htz[QC], hnt[QC];
-                CT hc[QC];
 #pragma unroll
-                for (int r = 0; r < QC; ++r) {
-                    const int q = q0 + r;
-                    const int qs = q < cnt ? q : 0;
-                    const int okq = __shfl((int)ok, qs, G);
-                    hok[r] = q < cnt && okq != 0;
-                    hu[r] = (uint32_t)__shfl((int)u2, qs, G);
-                    const uint32_t bt = (uint32_t)__shfl((int)tp, qs, G);
-                    htx[r] = bt & 1023u;
-                    hty[r] = (bt >> 10) & 1023u;
-                    htz[r] = (bt >> 20) & 1023u;
-                    hnt[r] = __shfl(nt2, qs, G);
-                    hc[r] = (CT)__shfl(coef, qs, G);
-                    const CT jz = (CT)__shfl(jzv, qs, G);
-                    if (hok[r]) dz += jz;
-                }
-                C2 x[QC][BPL];
-                double2 ph[QC][BPL];
-#pragma unroll
-                for (int r = 0; r < QC; ++r) {
-#pragma unroll
-                    for (int i = 0; i < BPL; ++i) {
-                        const int b = lane + i * G;
-                        bool use = hok[r] && bval[i];
-                        if (use && hnt[r] >= 0) use = A.compat_nt[(size_t)hnt[r] * B + b] != 0;
-                        int P = kx[i] * htx[r] + ky[i] * hty[r] + kz[i] * htz[r];
-                        const int qq = (int)((double)P * A.invM);
-                        P -= qq * A.M;
-                        P += (P < 0) ? A.M : 0;
-                        P -= (P >= A.M) ? A.M : 0;
-                        const uint64_t idx = use ? (uint64_t)hu[r] * B + b : 0;
-                        x[r][i] = v[idx];
-                        ph[r][i] = A.phase[use ? P : 0];
-                        if (!use) {
-                            x[r][i].x = 0;
-                            x[r][i].y = 0;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < QC; ++r) {
-#pragma unroll
-                    for (int i = 0; i < BPL; ++i) {
-                        const CT pr = hc[r] * (CT)ph[r][i].x, pi = hc[r] * (CT)ph[r][i].y;
-                        accr[i] += pr * x[r][i].x - pi * x[r][i].y;
-                        acci[i] += pr * x[r][i].y + pi * x[r][i].x;
-                    }
-                }
+            for (int r = 0; r < QC; ++r) {
+                if (!hok[r]) continue;
+                const int e = he[r];
+                dz += (CT)(UNIF ? A.L.u_jz_h : A.L.jz_h[e]);
+                // a target whose stabiliser is incompatible with k is not in the sector
+                if (s2[r] > 1 && !A.compat_nt[A.nt_of[hu[r]]]) continue;
+                const double jxy = UNIF ? A.L.u_jxy_h : A.L.jxy_h[e];
+                const CT hc = (CT)(jxy * (s2[r] == 1 ? 1.0 : A.L.sqrt_tab[s2[r]]) * (double)isq);
+                const CT pr = hc * (CT)ph[r].x, pi = hc * (CT)ph[r].y;
+                accr += pr * x[r].x - pi * x[r].y;
+                acci += pr * x[r].y + pi * x[r].x;
             }
         }
         const CT diag = (CT)A.L.ez4 - dz;
-        O2 *wrow = w + u * B;
-        const C2 *vself = v + u * B;
+        const C2 xs = v[u];
+        O2 o;
+        o.x = (OT)(diag * xs.x + accr);
+        o.y = (OT)(diag * xs.y + acci);
+        w[u] = o;
+    }
+}
+
+// A single momentum sector with per-representative hop lists on a lattice with
+// one exchange and one Ising constant: a row needs neither its state nor the
+// lattice tables, its hop-list entries (target representative and
+// translation, ~0 for an occupied target) give every term.  All of a row's
+// entries are loaded at once (16-byte loads when rows start 16-byte aligned),
+// then the stabiliser and v gathers of every hop of the row, so a row waits
+// for two memory round trips; the phases e^{2 pi i P / M} come from LDS and
+// the stabiliser factor sqrt(s) is read only for the rare s > 1 (sqrt(1) is
+// 1 exactly).  Same terms, order and arithmetic as k_hv_one and k_hv_batch.
+template <typename CT, typename OT, int HM>
+__global__ __launch_bounds__(256) void k_hv_one_lists(BatchArgs A,
+                                                      const typename Cplx<CT>::type *__restrict__ v,
+                                                      typename Cplx<OT>::type *__restrict__ w) {
+    using C2 = typename Cplx<CT>::type;
+    using O2 = typename Cplx<OT>::type;
+    __shared__ double2 s_ph[PHASE_LDS];
+    if (A.active && !A.active[0]) return;  // an inactive sector's rows stay untouched
+    for (int i = threadIdx.x; i < A.M; i += blockDim.x) s_ph[i] = A.phase[i];
+    __syncthreads();
+    const int kx = A.kmul[0], ky = A.kmul[1], kz = A.kmul[2];
+    const int hmax = A.hmax;
+    const CT jz = (CT)A.L.u_jz_h;
+    const double jxy = A.L.u_jxy_h;
+    const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
+    const uint64_t ntiles = (A.n_reps + 255) / 256;
+    const uint64_t t0 = ntiles * lb / gridDim.x, t1 = ntiles * (lb + 1) / gridDim.x;
+    for (uint64_t tile = t0; tile < t1; ++tile) {
+        const uint64_t u = tile * 256 + threadIdx.x;
+        if (u >= A.n_reps) break;
+        const uint64_t *hrow = A.hops + u * (uint64_t)hmax;
+        uint64_t ent[HM];
+        if ((hmax & 1) == 0) {
+            const uint4 *p = (const uint4 *)hrow;
 #pragma unroll
-        for (int i = 0; i < BPL; ++i) {
-            if (!bval[i]) continue;
-            const int b = lane + i * G;
-            const bool okr = ntu < 0 || A.compat_nt[(size_t)ntu * B + b];
-            O2 o;
-            if (okr) {
-                C2 x = vself[b];
-                o.x = (OT)(diag * x.x + accr[i]);
-                o.y = (OT)(diag * x.y + acci[i]);
-            } else {
-                o.x = 0;
-                o.y = 0;
+            for (int i = 0; i < HM / 2; ++i) {
+                uint4 q = make_uint4(~0u, ~0u, ~0u, ~0u);
+                if (2 * i < hmax) q = p[i];
+                ent[2 * i] = (uint64_t)q.x | ((uint64_t)q.y << 32);
+                ent[2 * i + 1] = (uint64_t)q.z | ((uint64_t)q.w << 32);
             }
-            wrow[b] = o;
+        } else {
+#pragma unroll
+            for (int h = 0; h < HM; ++h) ent[h] = h < hmax ? hrow[h] : ~0ull;
         }
+        const int su = A.stab[u];
+        const C2 xs = v[u];
+        bool hok[HM];
+        uint32_t hu[HM];
+        int s2[HM];
+        C2 x[HM];
+#pragma unroll
+        for (int h = 0; h < HM; ++h) {
+            hok[h] = ent[h] != ~0ull;
+            hu[h] = hok[h] ? (uint32_t)ent[h] : (uint32_t)u;
+        }
+        // every gather of the row in flight together
+#pragma unroll
+        for (int h = 0; h < HM; ++h) {
+            s2[h] = A.stab[hu[h]];
+            x[h] = v[hu[h]];
+        }
+        if (su > 1 && !A.compat_nt[A.nt_of[u]]) {
+            w[u] = O2{0, 0};
+            continue;
+        }
+        const double sqs = su == 1 ? 1.0 : A.L.sqrt_tab[su];
+        const CT isq = (CT)(1.0 / sqs);
+        CT accr = 0, acci = 0, dz = 0;
+#pragma unroll
+        for (int h = 0; h < HM; ++h) {
+            if (!hok[h]) continue;
+            dz += jz;
+            // a target whose stabiliser is incompatible with k is not in the sector
+            if (s2[h] > 1 && !A.compat_nt[A.nt_of[hu[h]]]) continue;
+            const uint32_t t = (uint32_t)(ent[h] >> 32);
+            int p = kx * (int)(t & 1023u) + ky * (int)((t >> 10) & 1023u) + kz * (int)((t >> 20) & 1023u);
+            const int qq = (int)((double)p * A.invM);
+            p -= qq * A.M;
+            p += (p < 0) ? A.M : 0;
+            p -= (p >= A.M) ? A.M : 0;
+            const double2 ph = s_ph[p];
+            const double sq2 = s2[h] == 1 ? 1.0 : A.L.sqrt_tab[s2[h]];
+            const CT hc = (CT)(jxy * sq2 * (double)isq);
+            const CT pr = hc * (CT)ph.x, pi = hc * (CT)ph.y;
+            accr += pr * x[h].x - pi * x[h].y;
+            acci += pr * x[h].y + pi * x[h].x;
+        }
+        const CT diag = (CT)A.L.ez4 - dz;
+        O2 o;
+        o.x = (OT)(diag * xs.x + accr);
+        o.y = (OT)(diag * xs.y + acci);
+        w[u] = o;
     }
 }
 

@@ -31,6 +31,7 @@ struct BatchArgs {
     double invM;
     const double2 *phase;  // e^{2 pi i P / M}
     const uint8_t *active;  // per sector, or null: rows of inactive sectors are left untouched
+    int ph_lds_off;         // byte offset of the phase table in dynamic LDS, or -1 (global)
 };
 
 struct BuildArgs {
@@ -59,6 +60,7 @@ int lanczos_small(qs3_lattice *lat, int K, const BinomTable *bt, qs3_batch *bat,
 template <int K>
 int lanczos_small_K(qs3_lattice *lat, const BinomTable *bt, qs3_batch *bat, const SmallArgs &S, hipStream_t s);
 int grid_for(qs3_ctx *ctx, uint64_t tiles);
+int grid_cover(qs3_ctx *ctx, uint64_t tiles);
 
 template <int K>
 int hv_u1_K(qs3_sector *sec, const void *v, int vtype, void *w, int wtype, hipStream_t s);
