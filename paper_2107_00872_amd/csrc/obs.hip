@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <complex>
+#include <cstring>
 #include <map>
 #include <numeric>
 #include <unordered_map>
@@ -402,6 +403,52 @@ int qs3_sq_apply(qs3_sector *from, const void *vec_from, qs3_sector *to, int op,
     return QS3_OK;
 }
 
+}  // extern "C"
+
+namespace qs3 {
+
+struct CfArgs {
+    int n_q, n_omega;
+    const double *alpha, *beta;  // [x][q]: the Lanczos coefficients of column q
+    const double *weight, *triv; // per q: |psi'|^2, weight of the trivial q = 0 pole (or 0)
+    const int32_t *m;            // per q: levels taken (0: no weight)
+    const double *omega;
+    double zshift, eta;          // z = omega + zshift + i eta
+};
+
+// Eq. (cfe), one thread per (q, omega): G(z) by the backward recurrence
+// g_i = 1 / (z - alpha_i - beta_i^2 g_{i+1}) from the innermost level out,
+// S = -Im(weight g_0) / pi, minus the trivial Lorentzian where asked.
+__global__ __launch_bounds__(256) void k_cfrac(CfArgs C, double *__restrict__ S) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (uint64_t)C.n_q * C.n_omega) return;
+    const int q = (int)(t / C.n_omega), k = (int)(t % C.n_omega);
+    const double pi = 3.141592653589793;
+    const double om = C.omega[k];
+    const double tr = C.triv[q] != 0.0 ? C.triv[q] * C.eta / (pi * (om * om + C.eta * C.eta)) : 0.0;
+    const int m = C.m[q];
+    if (m == 0) {
+        S[t] = -tr;
+        return;
+    }
+    const double zr = om + C.zshift, zi = C.eta;
+    double gr = 0.0, gi = 0.0;
+    for (int i = m - 1; i >= 0; --i) {
+        const double b = i < m - 1 ? C.beta[(size_t)i * C.n_q + q] : 0.0;
+        const double b2 = b * b;
+        const double dr = zr - C.alpha[(size_t)i * C.n_q + q] - b2 * gr;
+        const double di = zi - b2 * gi;
+        const double inv = 1.0 / (dr * dr + di * di);
+        gr = dr * inv;
+        gi = -di * inv;
+    }
+    S[t] = -(C.weight[q] * gi) / pi - tr;
+}
+
+}  // namespace qs3
+
+extern "C" {
+
 int qs3_smq(qs3_sector *from, const void *vec_from, qs3_sector *to, const int32_t *qvec, void *vec_to,
             void *stream) {
     return qs3_sq_apply(from, vec_from, to, QS3_OP_SMINUS, qvec, vec_to, stream);
@@ -469,39 +516,53 @@ int qs3_dsf(qs3_sector *gs, const void *gs_vec, double e0, int n_q, const int32_
     std::vector<double> a, bb, n0;
     std::vector<int> done;
     QS3_TRY(run_lanczos(E, psi.as<double>(), steps, a, bb, n0, done));
-    const double pi = std::acos(-1.0);
     // the field moves the poles by the Zeeman change of the operator
     const double shift = op == QS3_OP_SMINUS ? opts->field : (op == QS3_OP_SPLUS ? -opts->field : 0.0);
     const double Mz = 0.5 * lat->N - gs->K;
+    std::vector<double> wq(n_q), triv_w(n_q);
+    std::vector<int32_t> mq(n_q);
     for (int q = 0; q < n_q; ++q) {
         bool q0 = true;
         for (int a = 0; a < 3; ++a) q0 &= (((qvecs[3 * q + a] % L[a]) + L[a]) % L[a]) == 0;
         const bool trivial = op == QS3_OP_SZ && opts->subtract_trivial && q0;
-        const double w = n0[q] * n0[q] / g2;
-        if (weight) weight[q] = w;
+        wq[q] = n0[q] * n0[q] / g2;
+        triv_w[q] = trivial ? Mz * Mz / lat->N : 0.0;
+        mq[q] = (wq[q] > 0) ? done[q] : 0;
+        if (weight) weight[q] = wq[q];
         if (alpha)
             for (int x = 0; x < steps; ++x) alpha[(size_t)q * steps + x] = a[(size_t)q * steps + x];
         if (beta)
             for (int x = 0; x < steps; ++x) beta[(size_t)q * steps + x] = bb[(size_t)q * steps + x];
-        const int m = (w > 0) ? done[q] : 0;
-        for (int k = 0; k < n_omega; ++k) {
-            const double triv = trivial ? (Mz * Mz / lat->N) * opts->eta /
-                                              (pi * (omega[k] * omega[k] + opts->eta * opts->eta))
-                                        : 0.0;
-            if (m == 0) {
-                S[(size_t)q * n_omega + k] = -triv;
-                continue;
-            }
-            const std::complex<double> z(omega[k] - shift + e0, opts->eta);
-            std::complex<double> g = 0.0;
-            for (int i = m - 1; i >= 0; --i) {
-                const std::complex<double> tail =
-                    (i < m - 1) ? bb[(size_t)q * steps + i] * bb[(size_t)q * steps + i] * g : 0.0;
-                g = 1.0 / (z - a[(size_t)q * steps + i] - tail);
-            }
-            S[(size_t)q * n_omega + k] = -(w * g).imag() / pi - triv;
-        }
     }
+    if (n_omega == 0) return QS3_OK;
+    // Eq. (cfe) for every (q, omega) on the device, from the coefficient
+    // history the Lanczos run left there
+    DevBuf par, dom, dS;
+    QS3_TRY(par.alloc(lat->ctx, sizeof(double) * 2 * n_q + sizeof(int32_t) * n_q));
+    QS3_TRY(dom.alloc(lat->ctx, sizeof(double) * n_omega));
+    QS3_TRY(dS.alloc(lat->ctx, sizeof(double) * (size_t)n_q * n_omega));
+    std::vector<char> hp(sizeof(double) * 2 * n_q + sizeof(int32_t) * n_q);
+    std::memcpy(hp.data(), wq.data(), sizeof(double) * n_q);
+    std::memcpy(hp.data() + sizeof(double) * n_q, triv_w.data(), sizeof(double) * n_q);
+    std::memcpy(hp.data() + sizeof(double) * 2 * n_q, mq.data(), sizeof(int32_t) * n_q);
+    QS3_HIP(hipMemcpyAsync(par.ptr, hp.data(), hp.size(), hipMemcpyHostToDevice, s));
+    QS3_HIP(hipMemcpyAsync(dom.ptr, omega, sizeof(double) * n_omega, hipMemcpyHostToDevice, s));
+    CfArgs C;
+    C.n_q = n_q;
+    C.n_omega = n_omega;
+    C.alpha = E.ab_hist.as<double>();
+    C.beta = E.ab_hist.as<double>() + (size_t)E.slots * n_q;
+    C.weight = par.as<double>();
+    C.triv = par.as<double>() + n_q;
+    C.m = (const int32_t *)(par.as<double>() + 2 * n_q);
+    C.omega = dom.as<double>();
+    C.zshift = e0 - shift;
+    C.eta = opts->eta;
+    const uint64_t nt = (uint64_t)n_q * n_omega;
+    hipLaunchKernelGGL(k_cfrac, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, C, dS.as<double>());
+    QS3_HIP(hipGetLastError());
+    QS3_HIP(hipMemcpyAsync(S, dS.ptr, sizeof(double) * nt, hipMemcpyDeviceToHost, s));
+    QS3_HIP(hipStreamSynchronize(s));
     return QS3_OK;
 }
 
