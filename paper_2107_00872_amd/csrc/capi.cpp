@@ -744,6 +744,11 @@ int qs3_lanczos(qs3_sector *sec, const void *v0, int steps, int precision, int r
     std::vector<double> a, b, n0;
     std::vector<int> dn;
     QS3_TRY(run_lanczos(E, vb.as<double>(), steps, a, b, n0, dn));
+    // a zero or non-finite start vector (or coefficients that turned
+    // non-finite) leaves the outputs untouched
+    QS3_REQUIRE(std::isfinite(n0[0]) && n0[0] > 0.0, QS3_ENUMERIC, "zero or non-finite start vector");
+    for (int x = 0; x < dn[0]; ++x)
+        QS3_REQUIRE(std::isfinite(a[x]) && std::isfinite(b[x]), QS3_ENUMERIC, "non-finite Lanczos coefficient");
     for (int x = 0; x < steps; ++x) {
         alpha[x] = a[x];
         beta[x] = b[x];
