@@ -325,3 +325,61 @@ def _union_ranks(qs3, ctx, L, K, lat):
         sec.close()
         _UNI[key] = r
     return _UNI[key]
+
+
+# Wide batches: more sectors than one wavefront of lanes, so each lane owns
+# several sectors (ceil(B / 64) per lane, rounded up to 2, 4, 8, 16 or 32),
+# the instances the full momentum sweeps launch (10x10: 100 sectors, 2 per
+# lane; 10^3: 1000 sectors, 16 per lane).
+WIDE = [(wl.square(10), 3, None), (wl.square(12), 2, None), (wl.square(20), 2, 24),
+        (wl.cube(10), 2, 20), (wl.cube(12), 2, 10)]
+
+
+def _wide_batch(qs3, c, lat, K, n_sample):
+    L = qs3.Lattice.of(c, lat)
+    ks = wl.all_momenta(lat)
+    bat = qs3.Batch(L, K, ks)
+    per = -(-bat.B // 64)
+    assert bat.B > 64 and per >= 2
+    B = orc.Bonds.of(lat)
+    rng = np.random.default_rng(3)
+    vh = rng.uniform(-1, 1, size=(bat.rows, bat.B)) + 1j * rng.uniform(-1, 1, size=(bat.rows, bat.B))
+    v = torch.from_numpy(vh).cuda()
+    w = torch.empty_like(v)
+    bat.matvec(v, w)
+    wh = w.cpu().numpy()
+    # the union of representatives: every orbit minimum, i.e. the k = 0 sector
+    sig0, _ = orc.mk_list(lat.dims, K, (0, 0, 0))
+    assert bat.rows == len(sig0)
+    pick = range(bat.B) if n_sample is None else sorted(
+        set(rng.choice(bat.B, n_sample, replace=False).tolist()) | {0, bat.B - 1})
+    for b in pick:
+        Kv = ks[b]
+        sigma, R = orc.mk_list(lat.dims, K, Kv)
+        assert bat.dims[b] == len(sigma)
+        pos = np.searchsorted(sig0, sigma)
+        assert np.array_equal(sig0[pos], sigma)
+        ref = orc.hv_k(lat.dims, K, Kv, B, sigma, R, vh[pos, b])
+        assert np.abs(wh[pos, b] - ref).max() <= hv_tol(lat, 1.5), (Kv, per)
+        mask = np.ones(bat.rows, bool)
+        mask[pos] = False
+        assert np.all(wh[mask, b] == 0)
+    bat.close()
+    L.close()
+
+
+@pytest.mark.parametrize("lat,K,n_sample", WIDE, ids=lambda x: getattr(x, "name", str(x)))
+def test_batch_wide_hop_lists(qs3, ctx_hops, lat, K, n_sample):
+    """Every sector (or a seeded sample of them) of a wide batch against the
+    oracle's Alg. 9, element by element, hops through hop lists."""
+    _wide_batch(qs3, ctx_hops, lat, K, n_sample)
+
+
+@pytest.mark.parametrize("lat,K,n_sample", WIDE, ids=lambda x: getattr(x, "name", str(x)))
+def test_batch_wide_rank_table(qs3, ctx_table, lat, K, n_sample):
+    _wide_batch(qs3, ctx_table, lat, K, n_sample)
+
+
+@pytest.mark.parametrize("lat,K,n_sample", WIDE[:2] + WIDE[3:4], ids=lambda x: getattr(x, "name", str(x)))
+def test_batch_wide_on_the_fly(qs3, ctx_fly, lat, K, n_sample):
+    _wide_batch(qs3, ctx_fly, lat, K, n_sample)
