@@ -155,6 +155,21 @@ int qs3_matvec(qs3_sector *sec, const void *v, void *w, int dtype, void *stream)
  * them (down spins ascending, then the site's bonds in bond order).  cols are
  * basis indices; vals is re/im interleaved for momentum sectors.  *nnz may
  * exceed cap (then only cap entries are written).  Host outputs. */
+/* The same product as qs3_matvec, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): it allocates nothing.  A momentum sector whose basis is
+ * smaller than the union of representatives is multiplied through two
+ * union-layout vectors; qs3_matvec allocates them on the sector's first call,
+ * this entry point takes them from one device array of 64 MiB that the
+ * library holds on every device it runs on until the process ends.  Sectors
+ * of more than 2,097,152 representatives return QS3_EINVAL (nothing is
+ * launched); fixed-N_down sectors, and momentum sectors in QS3_C128 whose
+ * basis is the whole union, need no scratch.  Every call on a device shares
+ * that device's array and leaves its last contents there: calls that overlap
+ * on one GPU (two streams, two threads) race, so serialise them.  Same
+ * arguments, layouts and results as qs3_matvec (bit for bit). */
+int qs3_matvec_noalloc(qs3_sector *sec, const void *v, void *w, int dtype, void *stream);
+
 int qs3_row(qs3_sector *sec, uint64_t row, int cap, int64_t *cols, double *vals, double *diag,
             int *nnz);
 

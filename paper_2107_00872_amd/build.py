@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libqs3.so")
-SOURCES = ["capi.cpp", "hv.hip", "krylov.hip", "obs.hip", "server.cpp", "full.hip", "pg.hip"]
+SOURCES = ["capi.cpp", "hv.hip", "krylov.hip", "obs.hip", "server.cpp", "full.hip", "pg.hip", "noalloc.hip"]
 # H.v / structure kernels: one translation unit per N_down
 INST = [("hv_inst.hip", k) for k in range(0, 9)]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -207,6 +207,7 @@ int qs3_ctx_create(int device, uint64_t hbm_budget_bytes, qs3_ctx **out) {
     QS3_HIP(hipMemGetInfo(&fr, &tot));
     hipDeviceProp_t prop;
     QS3_HIP(hipGetDeviceProperties(&prop, device));
+    QS3_TRY(qs3::noalloc_init(device));
     auto *c = new qs3_ctx();
     c->device = device;
     c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * fr);

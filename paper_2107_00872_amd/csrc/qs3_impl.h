@@ -215,6 +215,9 @@ int build_kstruct(qs3_lattice *lat, int K, KStructure *ks, hipStream_t s);
 int start_vector_u1(qs3_sector *sec, uint64_t seed, void *v, int dtype, hipStream_t s);
 int start_vector_batch(qs3_batch *bat, const uint64_t *seeds, double *v, hipStream_t s);
 int scatter_compact(qs3_sector *sec, const double *src, double *dst_union, hipStream_t s);
+// device address of the allocation-free matvec's scratch array on `device`
+// (looked up once per device; the device must be current)
+int noalloc_init(int device);
 int gather_compact(qs3_sector *sec, const double *src_union, double *dst, hipStream_t s);
 
 }  // namespace qs3

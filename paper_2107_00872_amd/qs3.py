@@ -81,6 +81,7 @@ SIGNATURES = [
     ("qs3_sector_basis", ctypes.c_int, [P, P, P]),
     ("qs3_sector_start_vector", ctypes.c_int, [P, u64, P, ctypes.c_int, P]),
     ("qs3_matvec", ctypes.c_int, [P, P, P, ctypes.c_int, P]),
+    ("qs3_matvec_noalloc", ctypes.c_int, [P, P, P, ctypes.c_int, P]),
     ("qs3_row", ctypes.c_int, [P, u64, ctypes.c_int, P, P, P, P]),
     ("qs3_eigs", ctypes.c_int, [P, P, P, P, P, P]),
     ("qs3_lanczos", ctypes.c_int, [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, u64, P, P, P, P, P]),
