@@ -194,8 +194,8 @@ int qs3_row(qs3_sector *sec, uint64_t row, int cap, int64_t *cols, double *vals,
 typedef struct {
     int alg;            /* QS3_ALG_LANCZOS or QS3_ALG_TRL */
     int nev;            /* wanted number of distinct lowest levels */
-    int nk;             /* TRL: kept Ritz vectors N_K (0 = nev + 5) */
-    int nm;             /* TRL: Krylov size N_M (0 = max(2 nk, 20)) */
+    int nk;             /* TRL: kept Ritz vectors N_K (0 = max(nev + 5, 8)) */
+    int nm;             /* TRL: Krylov size N_M (0 = max(2 nk, 24)) */
     int max_restarts;   /* TRL: I_M (0 = 2000) */
     int steps;          /* LANCZOS: number of steps (0 = 100) */
     double tol;         /* residual tolerance, relative to the scale below

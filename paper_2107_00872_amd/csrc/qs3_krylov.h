@@ -179,10 +179,14 @@ struct BatchOp : Operator {
     int subset(const std::vector<int> &cols, std::unique_ptr<Operator> *out) override;
 };
 
+// default thick-restart sizes: N_K kept Ritz vectors, N_M Krylov vectors
+inline int default_nk(int nev) { return std::max(nev + 5, 8); }
+inline int default_nm(int nk) { return std::max(2 * nk, 24); }
+
 inline int fill_opts(qs3_eigs_opts &o, uint64_t min_dim) {
     if (o.nev <= 0) o.nev = 1;
-    if (o.nk <= 0) o.nk = o.nev + 5;
-    if (o.nm <= 0) o.nm = std::max(2 * o.nk, 20);
+    if (o.nk <= 0) o.nk = default_nk(o.nev);
+    if (o.nm <= 0) o.nm = default_nm(o.nk);
     if (o.max_restarts <= 0) o.max_restarts = 2000;
     if (o.steps <= 0) o.steps = 100;
     if (!(o.tol > 0)) o.tol = o.precision == QS3_PREC_F32MV ? 1e-6 : 1e-10;

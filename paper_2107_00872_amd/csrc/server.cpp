@@ -77,9 +77,13 @@ static double binom_d(int n, int k) {
 
 // Device bytes a request needs: Krylov basis (N_M + 1 + N_K vectors), work
 // and start vectors, the float32 copy, reduction scratch, and for momentum
-// sectors the representative list, stabilisers, directory and (when it is
-// built) the rank -> representative table.
-static uint64_t footprint(const qs3_request &q, const qs3_eigs_opts &o) {
+// sectors the representative list, stabilisers, directory and the two hop
+// stores the structure build makes when they fit the context's limits: the
+// rank -> representative table (8 B per rank) and the per-representative
+// hop lists (8 B per representative and hop slot, N_down x the largest
+// degree slots).
+static uint64_t footprint(const qs3_request &q, const qs3_eigs_opts &o, int max_degree,
+                          const qs3_ctx *ctx) {
     const int N = q.lx * q.ly * q.lz;
     const double D = binom_d(N, q.n_down);
     const double rows = q.use_k ? D / N * 1.05 + 64 : D;
@@ -89,7 +93,9 @@ static uint64_t footprint(const qs3_request &q, const qs3_eigs_opts &o) {
     double bytes = rows * elem * slots + 4.0 * 1024 * 1024;
     if (q.use_k) {
         bytes += rows * (8 + 2 + 4) + 4.0 * (1 << 24);
-        if (D * 8 <= 16.0 * (1ull << 30)) bytes += D * 8;
+        if (D * 8 <= (double)ctx->table_limit) bytes += D * 8;
+        const double hops = rows * (double)q.n_down * max_degree * 8;
+        if (hops <= (double)ctx->hop_list_limit) bytes += hops;
     }
     if (!(bytes < 1.8e19)) return ~0ull;
     return (uint64_t)bytes;
@@ -287,9 +293,18 @@ int qs3_submit(qs3_server *S, const qs3_request *q, uint64_t *ticket) {
     r->opts.precision = q->precision;
     r->opts.reorth = 1;
     qs3_eigs_opts est = r->opts;
-    est.nk = est.nev + 5;
-    est.nm = std::max(2 * est.nk, 20);
-    r->footprint = footprint(r->req, est);
+    est.nk = default_nk(est.nev);
+    est.nm = default_nm(est.nk);
+    std::vector<int> deg((size_t)std::max(q->lx * q->ly * q->lz, 1), 0);
+    int max_degree = 0;
+    for (size_t b = 0; b < r->bi.size(); ++b) {
+        const int i = r->bi[b], j = r->bj[b];
+        if (i >= 0 && j >= 0 && i < (int)deg.size() && j < (int)deg.size() && i != j) {
+            max_degree = std::max(max_degree, ++deg[i]);
+            max_degree = std::max(max_degree, ++deg[j]);
+        }
+    }
+    r->footprint = footprint(r->req, est, max_degree, S->ctx);
     r->res.footprint_bytes = r->footprint;
     std::lock_guard<std::mutex> lk(S->mu);
     r->ticket = S->next_ticket++;

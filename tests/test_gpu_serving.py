@@ -91,3 +91,40 @@ def test_admission_rejects_oversize_and_cancel(qs3, ctx):
     with pytest.raises(qs3.QS3Error):
         srv.poll(999999)
     srv.close()
+
+
+def test_tight_budget_large_momentum_requests(qs3):
+    """Several large momentum requests (10^3 cube, N_down = 3: a 1.3 GB rank
+    table and per-representative hop lists each) under a context budget that
+    holds two of them: the footprint used for admission covers every store
+    the structure build makes, so no request fails for memory -- all finish
+    with QS3_OK, at most two at a time, with the levels of an unconstrained
+    run."""
+    lat = wl.cube(10)
+    ks = [(0, 0, 0), (1, 0, 0), (3, 6, 0), (5, 5, 5), (2, 7, 1)]
+    probe_ctx = qs3.Context(0)
+    srv = qs3.Server(probe_ctx, max_active=1)
+    ref = {}
+    for k in ks:
+        r = srv.wait(srv.submit(lat, 3, k, nev=1, seed=4))
+        assert r.status == 0
+        ref[k] = (r.evals[0], r.footprint_bytes)
+    srv.close()
+    probe_ctx.close()
+    F = max(f for _, f in ref.values())
+    tight = qs3.Context(0, budget_bytes=int(2.3 * F))
+    srv = qs3.Server(tight, max_active=4)
+    tickets = [srv.submit(lat, 3, k, nev=1, seed=4) for k in ks]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    for k, r in zip(ks, res):
+        assert r.status == 0, (k, r.status, qs3.lib().qs3_last_error())
+        assert abs(r.evals[0] - ref[k][0]) <= 1e-12 * abs(ref[k][0])
+    # never more than two running at once
+    ev = sorted([(r.t_start, 1) for r in res] + [(r.t_done, -1) for r in res])
+    run = peak = 0
+    for _, d in ev:
+        run += d
+        peak = max(peak, run)
+    assert peak <= 2
+    tight.close()
