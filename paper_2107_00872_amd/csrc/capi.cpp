@@ -222,6 +222,13 @@ int qs3_ctx_destroy(qs3_ctx *ctx) {
     return QS3_OK;
 }
 
+int qs3_ctx_set_schedule(qs3_ctx *ctx, int use_graphs, int autotune) {
+    QS3_REQUIRE(ctx, QS3_EINVAL, "ctx is NULL");
+    ctx->use_graphs = use_graphs ? 1 : 0;
+    ctx->autotune = autotune ? 1 : 0;
+    return QS3_OK;
+}
+
 int qs3_ctx_set_structure_limits(qs3_ctx *ctx, uint64_t table_max_bytes, uint64_t hop_list_max_bytes) {
     QS3_REQUIRE(ctx, QS3_EINVAL, "ctx is NULL");
     ctx->table_limit = table_max_bytes;

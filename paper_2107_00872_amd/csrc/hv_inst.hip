@@ -250,6 +250,93 @@ int lanczos_small_K<KI>(qs3_lattice *lat, const BinomTable *bt, qs3_batch *bat, 
 
 #if QS3_INST_K <= 6
 // ------------------------------------------------------------------ momentum batches
+// One launch of the batched kernel with G lanes per row and `bpc` blocks
+// per CU (at most 8 sectors per lane and pass, several passes beyond that).
+template <typename RT, typename CT, typename OT, int MODE>
+static int launch_batch_g(qs3_batch *bat, BatchArgs A, int G, int bpc, const void *v, void *w,
+                          hipStream_t s) {
+    A.G = G;
+    size_t sh = lds_need<RT>(bat->lat, KI);
+    // the phase table after the lattice tables, when it fits
+    const size_t ph_off = (sh + 15) & ~size_t(15);
+    if (A.M <= 4096 && ph_off + 16 * (size_t)A.M <= 64 * 1024) {
+        A.ph_lds_off = (int)ph_off;
+        sh = ph_off + 16 * (size_t)A.M;
+    }
+    QS3_REQUIRE(sh <= 160 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
+    const int per = (A.B + A.G - 1) / A.G;
+    const uint64_t rows_per_tile = 256 / A.G;
+    const uint64_t tiles = (A.n_reps + rows_per_tile - 1) / rows_per_tile;
+    uint64_t g = std::min<uint64_t>(tiles, (uint64_t)bat->lat->ctx->n_cu * bpc);
+    if (g >= 8) g &= ~uint64_t(7);
+    const int grid = (int)std::max<uint64_t>(g, 1);
+    const RT *tab = bat->bt->dev.as<RT>();
+    using C2 = typename Cplx<CT>::type;
+    using O2 = typename Cplx<OT>::type;
+#define QS3_LB(BPL, NP)                                                                             \
+    hipLaunchKernelGGL((k_hv_batch<KI, RT, CT, OT, MODE, BPL, NP>), dim3(grid), dim3(256), sh, s, A, \
+                       tab, (const C2 *)v, (O2 *)w)
+    if (per <= 1) QS3_LB(1, 1);
+    else if (per <= 2) QS3_LB(2, 1);
+    else if (per <= 4) QS3_LB(4, 1);
+    else if (per <= 8) QS3_LB(8, 1);
+    else if (per <= 16) QS3_LB(8, 2);
+    else if (per <= 32) QS3_LB(8, 4);
+    else {
+        set_error("batch larger than 2048 sectors");
+        return QS3_EINVAL;
+    }
+#undef QS3_LB
+    QS3_HIP(hipGetLastError());
+    return QS3_OK;
+}
+
+// Times the candidate schedules on the caller's vectors (every launch writes
+// the same w) and returns the fastest: first G in {8, 16, 32, 64} (at most 32
+// sectors per lane) at 8 blocks per CU, then 4, 8 and 16 blocks per CU.
+template <typename RT, typename CT, typename OT, int MODE>
+static int tune_batch(qs3_batch *bat, const BatchArgs &A, const void *v, void *w, hipStream_t s, int *G_out,
+                      int *bpc_out) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    QS3_HIP(hipEventCreate(&e0));
+    QS3_HIP(hipEventCreate(&e1));
+    auto timed = [&](int G, int bpc, float *ms) -> int {
+        QS3_TRY((launch_batch_g<RT, CT, OT, MODE>(bat, A, G, bpc, v, w, s)));  // warm-up
+        QS3_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 2; ++r) QS3_TRY((launch_batch_g<RT, CT, OT, MODE>(bat, A, G, bpc, v, w, s)));
+        QS3_HIP(hipEventRecord(e1, s));
+        QS3_HIP(hipEventSynchronize(e1));
+        QS3_HIP(hipEventElapsedTime(ms, e0, e1));
+        return QS3_OK;
+    };
+    int rc = QS3_OK, bestG = 0, bestB = 8;
+    float best = 0;
+    for (int G = 8; G <= 64 && rc == QS3_OK; G <<= 1) {
+        if ((A.B + G - 1) / G > 32) continue;
+        float ms = 0;
+        rc = timed(G, 8, &ms);
+        if (rc == QS3_OK && (bestG == 0 || ms < best)) {
+            best = ms;
+            bestG = G;
+        }
+    }
+    for (int bpc : {4, 16}) {
+        if (rc != QS3_OK) break;
+        float ms = 0;
+        rc = timed(bestG, bpc, &ms);
+        if (rc == QS3_OK && ms < best) {
+            best = ms;
+            bestB = bpc;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != QS3_OK) return rc;
+    *G_out = bestG;
+    *bpc_out = bestB;
+    return QS3_OK;
+}
+
 template <typename RT, typename CT, typename OT, int MODE>
 static int launch_batch(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
     BatchArgs A = batch_args(bat);
@@ -280,44 +367,39 @@ static int launch_batch(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
         QS3_HIP(hipGetLastError());
         return QS3_OK;
     }
-    // a narrow batch (the few sectors a solve has left) takes 8 lanes per
-    // row: its hops are resolved 8 at a time and 8 gathers stay in flight;
-    // every sector sums its hops in the same order.  A single sector keeps
-    // one lane per row (its gathers would leave the other lanes idle).
-    if (A.B > 1 && A.G < 8) A.G = 8;
-    size_t sh = lds_need<RT>(bat->lat, KI);
-    // the phase table after the lattice tables, when it fits
-    const size_t ph_off = (sh + 15) & ~size_t(15);
-    if (A.M <= 4096 && ph_off + 16 * (size_t)A.M <= 64 * 1024) {
-        A.ph_lds_off = (int)ph_off;
-        sh = ph_off + 16 * (size_t)A.M;
+    // Schedule: G lanes per row (a power of two, 8..64) and blocks per CU.
+    // The rule: G = the smallest power of two >= B (at least 8, at most 64),
+    // so a narrow batch (the few sectors a solve has left) still resolves 8
+    // hops at a time with 8 gathers in flight, and 8 blocks per CU.  With
+    // autotuning on, the first launch of each width class (B rounded up to a
+    // power of two), element type and hop store times every G with at most
+    // 32 sectors per lane, then 4, 8 and 16 blocks per CU at the best G, and
+    // keeps the fastest in the structure's cache.  Every schedule sums each
+    // sector's hops in hop order, so the choice does not change results.
+    int G = 8;
+    while (G < A.B && G < 64) G <<= 1;
+    int bpc = 8;
+    qs3_ctx *ctx = bat->lat->ctx;
+    if (ctx->autotune) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        QS3_HIP(hipStreamIsCapturing(s, &cs));
+        if (cs == hipStreamCaptureStatusNone) {
+            int cls = 0;
+            while ((1 << cls) < A.B) ++cls;
+            const uint32_t key = ((uint32_t)cls << 8) | ((uint32_t)sizeof(CT) << 4) | (uint32_t)MODE;
+            KStructure &ks = *bat->ks;
+            std::lock_guard<std::mutex> lk(ks.tune_mu);
+            auto it = ks.tuned.find(key);
+            if (it != ks.tuned.end()) {
+                G = it->second.first;
+                bpc = it->second.second;
+            } else {
+                QS3_TRY((tune_batch<RT, CT, OT, MODE>(bat, A, v, w, s, &G, &bpc)));
+                ks.tuned[key] = {G, bpc};
+            }
+        }
     }
-    QS3_REQUIRE(sh <= 160 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
-    const int per = (A.B + A.G - 1) / A.G;
-    uint64_t rows_per_tile = 256 / A.G;
-    uint64_t tiles = (A.n_reps + rows_per_tile - 1) / rows_per_tile;
-    int grid = grid_for(bat->lat->ctx, tiles);
-    const RT *tab = bat->bt->dev.as<RT>();
-    using C2 = typename Cplx<CT>::type;
-    using O2 = typename Cplx<OT>::type;
-#define QS3_LB(BPL, NP)                                                                             \
-    hipLaunchKernelGGL((k_hv_batch<KI, RT, CT, OT, MODE, BPL, NP>), dim3(grid), dim3(256), sh, s, A, \
-                       tab, (const C2 *)v, (O2 *)w)
-    // a lane's sectors: at most 8 per pass (accumulators and gathers in few
-    // registers), several passes for wider batches
-    if (per <= 1) QS3_LB(1, 1);
-    else if (per <= 2) QS3_LB(2, 1);
-    else if (per <= 4) QS3_LB(4, 1);
-    else if (per <= 8) QS3_LB(8, 1);
-    else if (per <= 16) QS3_LB(8, 2);
-    else if (per <= 32) QS3_LB(8, 4);
-    else {
-        set_error("batch larger than 2048 sectors");
-        return QS3_EINVAL;
-    }
-#undef QS3_LB
-    QS3_HIP(hipGetLastError());
-    return QS3_OK;
+    return launch_batch_g<RT, CT, OT, MODE>(bat, A, G, bpc, v, w, s);
 }
 
 template <typename RT, typename CT, typename OT>

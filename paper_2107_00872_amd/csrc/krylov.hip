@@ -779,7 +779,9 @@ void sym_eig(int n, std::vector<double> &A, std::vector<double> &e, std::vector<
 }
 
 // ------------------------------------------------------------------ engine
-Engine::~Engine() = default;
+Engine::~Engine() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+}
 
 int Engine::init(qs3_ctx *c, Operator *o, int slots_, int precision_, int reorth_, hipStream_t s) {
     ctx = c;
@@ -1075,7 +1077,42 @@ int Engine::gather_columns_into(Engine &dst, int from_slot, int to_slot, const i
 }
 
 void Engine::release() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
     for (DevBuf *b : {&Psi, &W, &X32, &partial, &hvec, &alpha, &nrm2, &ab_hist, &act, &om}) b->release();
+}
+
+int Engine::cycle_replay(int x0, int x1, int prev_first) {
+    if (!ctx->use_graphs || st == nullptr) return cycle(x0, x1, prev_first);
+    if (gexec && g_x0 == x0 && g_x1 == x1 && g_pf == prev_first && g_mask == colmask) {
+        QS3_HIP(hipGraphLaunch(gexec, st));
+        n_matvec += x1 - x0;
+        ++graph_launches;
+        return QS3_OK;
+    }
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+    // capture records the launches without running them (and counts the
+    // steps once); the graph then runs them
+    QS3_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int rc = cycle(x0, x1, prev_first);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    if (rc != QS3_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    QS3_HIP(ec);
+    const hipError_t ei = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    QS3_HIP(ei);
+    g_x0 = x0;
+    g_x1 = x1;
+    g_pf = prev_first;
+    g_mask = colmask;
+    QS3_HIP(hipGraphLaunch(gexec, st));
+    ++graph_launches;
+    return QS3_OK;
 }
 
 // ------------------------------------------------------------------ host-side solver logic
@@ -1409,6 +1446,7 @@ int SolveRun::compact(const uint8_t *keep, bool *compacted) {
     for (int j = 0; j < nb; ++j) nmap[j] = col(sel[j]);
     // the previous engine's memory is released below: let the copies finish
     QS3_HIP(hipStreamSynchronize(E.st));
+    graph_prev += E.graph_launches;
     if (!narrow) root.release();
     narrow = std::move(ne);
     narrow_op = std::move(nop);
@@ -1530,6 +1568,7 @@ int SolveRun::advance(bool *done) {
         info[c].n_restarts = restarts;
         info[c].n_matvec = E.n_matvec;
         info[c].width = Bc;
+        info[c].graph_cycles = graph_prev + E.graph_launches;
         final_lv[c] = lv;
         if (allc) info[c].converged = 1;
     });
@@ -1577,7 +1616,7 @@ int SolveRun::advance(bool *done) {
     // the first step has no three-term partner (the couplings to the kept
     // Ritz vectors are removed by the full reorthogonalisation), then
     // x = NK+1..NM-1
-    QS3_TRY(En.cycle(NK, NM, -1));
+    QS3_TRY(En.cycle_replay(NK, NM, -1));
     QS3_TRY(enqueue_ab_copy(NK, NM));
     first = false;
     ++restarts;

@@ -76,6 +76,8 @@ struct qs3_ctx {
     std::mutex mu;
     void *blas = nullptr;  // rocBLAS handle, created on first use
     std::mutex blas_mu;    // held while a call is bound to the handle
+    int use_graphs = 0;    // replay thick-restart cycles from captured graphs
+    int autotune = 1;      // time the batched H.v's schedules once per width class
 };
 
 namespace qs3 {
@@ -115,6 +117,10 @@ struct KStructure {
     std::vector<uint32_t> nt_u;
     std::vector<std::vector<int>> nt_trans;  // packed tx | ty<<10 | tz<<20
     DevBuf nt_of;  // int32 [n_reps]: index into nt_u or -1
+    // the batched H.v's tuned schedule per (width class, element type, hop
+    // store): lanes per row and blocks per CU (see hv_inst.hip)
+    std::mutex tune_mu;
+    std::map<uint32_t, std::pair<int, int>> tuned;
 };
 
 }  // namespace qs3

@@ -73,6 +73,15 @@ struct Engine {
     int step(int x, int prev);
     // steps x0..x1-1 (step x0's three-term partner is slot prev_first or none)
     int cycle(int x0, int x1, int prev_first);
+    // the same, from a graph of the cycle's launches captured on its first
+    // call and replayed afterwards (when the context allows graphs and the
+    // stream can be captured); the launches of a cycle do not change between
+    // the restarts of one engine
+    int cycle_replay(int x0, int x1, int prev_first);
+    hipGraphExec_t gexec = nullptr;
+    int g_x0 = -1, g_x1 = -1, g_pf = -2;
+    const uint8_t *g_mask = nullptr;
+    int graph_launches = 0;
     int normalize_into_slot0(const double *v0, std::vector<double> *norms0);
     int read_ab(int x0, int x1, std::vector<double> &a, std::vector<double> &b);
     int rotate_dev(int from_slot, int NX, const double *dC, int NY, int to_slot, const uint8_t *act_dev);
@@ -101,6 +110,7 @@ struct SolveRun {
     int B = 1;
     bool want_vecs = false;
     int phase = 0;  // 1 first cycle, 2 restart cycle, 3 final rotation, 4 done
+    int graph_prev = 0;  // graph replays of the engines before the current one
     bool first = true;
     int restarts = 0;
     double *hab = nullptr, *hC = nullptr;

@@ -35,7 +35,7 @@ class EigsOpts(ctypes.Structure):
 class EigsInfo(ctypes.Structure):
     _fields_ = [("converged", ctypes.c_int), ("n_restarts", ctypes.c_int), ("n_matvec", ctypes.c_int),
                 ("n_found", ctypes.c_int), ("max_residual", dbl), ("seconds", dbl),
-                ("width", ctypes.c_int)]
+                ("width", ctypes.c_int), ("graph_cycles", ctypes.c_int)]
 
 
 class DsfOpts(ctypes.Structure):
@@ -69,6 +69,7 @@ SIGNATURES = [
     ("qs3_ctx_destroy", ctypes.c_int, [P]),
     ("qs3_ctx_memory", ctypes.c_int, [P, P, P]),
     ("qs3_ctx_set_structure_limits", ctypes.c_int, [P, u64, u64]),
+    ("qs3_ctx_set_schedule", ctypes.c_int, [P, ctypes.c_int, ctypes.c_int]),
     ("qs3_lattice_create", ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P]),
     ("qs3_lattice_create_cells", ctypes.c_int,
      [P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P, P, P]),
@@ -183,6 +184,11 @@ class Context:
         table_max_bytes, else hop lists up to hop_list_max_bytes, else
         canonicalise on the fly (0 turns a store off)."""
         check(lib().qs3_ctx_set_structure_limits(self.h, int(table_max_bytes), int(hop_list_max_bytes)))
+
+    def set_schedule(self, use_graphs: bool = True, autotune: bool = True):
+        """Graph replay of restart cycles and autotuned batched H.v schedules
+        (results do not depend on either)."""
+        check(lib().qs3_ctx_set_schedule(self.h, int(use_graphs), int(autotune)))
 
     def memory(self):
         u, b = u64(), u64()
