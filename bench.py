@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="skip the one-sector-at-a-time comparison (shorter profiles)")
     ap.add_argument("--no-c2", action="store_true", help="skip the secondary 10x10 figures")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="only the batched H.v launches and the calibration copy (counter profiles)")
     ap.add_argument("--requests", type=int, default=0, help="c5: number of requests (default 200)")
     ap.add_argument("--cells", default="both", choices=["kagome", "pyrochlore", "both"],
                     help="cells: which unit-cell lattice to run (default both)")
@@ -199,6 +201,8 @@ def main():
 
     print(f"c3: {bat.rows} representatives x {bat.B} sectors, set-up {t_setup:.2f} s", file=sys.stderr,
           flush=True)
+    if args.matvec_only:
+        args.steps = args.warmup = 0
     for w in range(args.warmup):
         one_step(100 + w)
         print(f"warmup {w + 1}/{args.warmup}", file=sys.stderr, flush=True)
@@ -215,9 +219,6 @@ def main():
         last = (ev, infos, rc)
         print(f"step {s + 1}/{args.steps}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
     t_all = time.perf_counter() - t_all0
-    ms_per_step = 1e3 * t_all / args.steps
-    ev, infos, rc = last
-    mv = np.array([i.n_matvec for i in infos])
 
     # ---- roofline of the batched H.v over all 1000 sectors, timed with events
     # recorded on the stream the kernel runs on
@@ -246,6 +247,42 @@ def main():
     nh = hops_per_sector(lat, K)
     alg_bytes = 16.0 * (2 * bat.rows + nh) * bat.B
     achieved = alg_bytes / t_mv / 1e9
+    G, bpc = bat.schedule()
+    per = -(-bat.B // G)
+    bpl, npass = (per, 1) if per <= 8 else (8, -(-per // 8))
+    bpl = 1 << (bpl - 1).bit_length()
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(),
+                "kernel": f"k_hv_batch<3,uint32,double,double,HOP_LISTS,{bpl},{npass}>",
+                "schedule": {"lanes_per_row": G, "blocks_per_cu": bpc},
+                "alg_bytes_per_launch": alg_bytes, "launch_s": t_mv}
+    # the single-sector product (one lane per row) on one of the sectors
+    one = qs3.Sector(L, K, (3, 6, 0))
+    v1 = torch.empty(one.dim, dtype=torch.complex128, device="cuda")
+    one.start_vector(1, v1, stream=stream)
+    w1 = torch.empty_like(v1)
+    for _ in range(2):
+        one.matvec(v1, w1, stream=stream)
+    e0.record(stream)
+    for _ in range(20):
+        one.matvec(v1, w1, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    t1 = e0.elapsed_time(e1) / 1e3 / 20
+    # per row: own v and w, one gather per hop (16 B each), the representative
+    # rank (8 B) and stabiliser size (2 B)
+    alg1 = (16.0 * (2 + nh / bat.rows) + 10.0) * one.dim
+    one_sector = {"kernel": "k_hv_one_lists<double,double,18>", "rows": one.dim, "launch_us": t1 * 1e6,
+                  "achieved_GBs": alg1 / t1 / 1e9, "frac": alg1 / t1 / 1e9 / HBM_PEAK_GBS,
+                  "alg_bytes_per_launch": alg1}
+    one.close()
+    del v1, w1
+    if args.matvec_only:
+        print(json.dumps({"workload": "c3 batched H.v only", "roofline": roofline, "one_sector_hv": one_sector}))
+        return
+    ms_per_step = 1e3 * t_all / args.steps
+    ev, infos, rc = last
+    mv = np.array([i.n_matvec for i in infos])
 
     # ---- the plain float64 path one sector at a time on a seeded sample, the
     # batch's seeds (sector b of the batch uses seed + b)
@@ -296,10 +333,7 @@ def main():
                                "all 1000 momentum sectors (166,167 representatives each) in one batched "
                                "thick-restart solve, float64",
                    "sectors": bat.B, "rows_per_sector": int(bat.rows)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(),
-                     "kernel": "k_hv_batch<3,uint32,double,double,HOP_LISTS,16>",
-                     "alg_bytes_per_launch": alg_bytes, "launch_s": t_mv},
+        "roofline": roofline,
         "solves_per_s": bat.B / (t_all / args.steps),
         "step_ms_p50": 1e3 * float(np.percentile(times, 50)),
         "step_ms_max": 1e3 * float(np.max(times)),
@@ -308,6 +342,7 @@ def main():
         "results": {"E_min": float(ev[:, 0].min()), "E_gamma": float(ev[ks.index((0, 0, 0)), 0]),
                     "all_converged": bool(rc == 0 and all(i.converged for i in infos))},
         "one_at_a_time_f64": serial,
+        "one_sector_hv": one_sector,
         "f32mv": f32mv,
         "accuracy_vs_oracle": accuracy_vs_golden(ks, ev[:, 0]),
     }

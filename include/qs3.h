@@ -355,6 +355,10 @@ int qs3_batch_create(qs3_lattice *lat, int n_down, int n_sectors, const int32_t 
 int qs3_batch_destroy(qs3_batch *bat);
 /* rows: union size; dims[b]: dimension of sector b.  Host outputs. */
 int qs3_batch_dims(const qs3_batch *bat, uint64_t *rows, uint64_t *dims);
+/* The schedule of the batch's last batched H.v launch (see
+ * qs3_ctx_set_schedule): lanes per representative row and blocks per CU; 0
+ * before the first launch and for a batch of one sector (one lane per row). */
+int qs3_batch_schedule(const qs3_batch *bat, int *lanes_per_row, int *blocks_per_cu);
 int qs3_batch_matvec(qs3_batch *bat, const void *v, void *w, int dtype, void *stream);
 /* Per-sector lowest levels (evals[b*nev + y]) and info[b]; every sector runs
  * its own Lanczos state inside the shared launches and stops updating when it

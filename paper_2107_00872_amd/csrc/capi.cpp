@@ -502,6 +502,13 @@ int qs3_batch_dims(const qs3_batch *bat, uint64_t *rows, uint64_t *dims) {
     return QS3_OK;
 }
 
+int qs3_batch_schedule(const qs3_batch *bat, int *lanes_per_row, int *blocks_per_cu) {
+    QS3_REQUIRE(bat, QS3_EINVAL, "batch is NULL");
+    if (lanes_per_row) *lanes_per_row = bat->last_G;
+    if (blocks_per_cu) *blocks_per_cu = bat->last_bpc;
+    return QS3_OK;
+}
+
 int qs3_batch_matvec(qs3_batch *bat, const void *v, void *w, int dtype, void *stream) {
     QS3_REQUIRE(bat && v && w, QS3_EINVAL, "NULL argument");
     QS3_REQUIRE(v != w, QS3_EINVAL, "v and w must not alias");

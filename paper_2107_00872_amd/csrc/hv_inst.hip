@@ -276,6 +276,8 @@ static int launch_batch_g(qs3_batch *bat, BatchArgs A, int G, int bpc, const voi
 #define QS3_LB(BPL, NP)                                                                             \
     hipLaunchKernelGGL((k_hv_batch<KI, RT, CT, OT, MODE, BPL, NP>), dim3(grid), dim3(256), sh, s, A, \
                        tab, (const C2 *)v, (O2 *)w)
+    bat->last_G = G;
+    bat->last_bpc = bpc;
     if (per <= 1) QS3_LB(1, 1);
     else if (per <= 2) QS3_LB(2, 1);
     else if (per <= 4) QS3_LB(4, 1);

@@ -185,6 +185,7 @@ struct qs3_batch {
     qs3::DevBuf kmul;             // int32 [3*B]: K_a * (M / L_a) mod M
     qs3::DevBuf phase;            // double2 [M]: e^{2 pi i P / M}
     qs3::DevBuf compat_nt;        // uint8 [n_nt * B]
+    int last_G = 0, last_bpc = 0;  // schedule of the last batched H.v launch
     std::vector<uint8_t> h_compat_nt;
     std::vector<uint64_t> dims;   // per sector
     const uint8_t *active_dev = nullptr;  // device mask set by the solver while it applies H

@@ -98,6 +98,7 @@ SIGNATURES = [
     ("qs3_batch_create", ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, P]),
     ("qs3_batch_destroy", ctypes.c_int, [P]),
     ("qs3_batch_dims", ctypes.c_int, [P, P, P]),
+    ("qs3_batch_schedule", ctypes.c_int, [P, P, P]),
     ("qs3_batch_matvec", ctypes.c_int, [P, P, P, ctypes.c_int, P]),
     ("qs3_batch_eigs", ctypes.c_int, [P, P, P, P, P]),
     ("qs3_server_create", ctypes.c_int, [P, P, P]),
@@ -394,6 +395,12 @@ class Batch:
         check(lib().qs3_batch_dims(self.h, ctypes.byref(rows), _ptr(dims)))
         self.rows = rows.value
         self.dims = dims
+
+    def schedule(self):
+        """(lanes per row, blocks per CU) of the last batched H.v launch."""
+        g, b = ctypes.c_int(), ctypes.c_int()
+        check(lib().qs3_batch_schedule(self.h, ctypes.byref(g), ctypes.byref(b)))
+        return g.value, b.value
 
     def matvec(self, v, w, stream=None):
         check(lib().qs3_batch_matvec(self.h, _ptr(v), _ptr(w), _dtype_code(v), _stream(stream)))
