@@ -458,6 +458,28 @@ int qs3_batch_create(qs3_lattice *lat, int n_down, int n_sectors, const int32_t 
     QS3_HIP(hipMemcpy(bat->kmul.ptr, kmul.data(), sizeof(int32_t) * kmul.size(), hipMemcpyHostToDevice));
     QS3_HIP(hipMemcpy(bat->phase.ptr, ph.data(), sizeof(double) * ph.size(), hipMemcpyHostToDevice));
     QS3_HIP(hipMemcpy(bat->compat_nt.ptr, bat->h_compat_nt.data(), bat->h_compat_nt.size(), hipMemcpyHostToDevice));
+    if (n_sectors == 1 && lat->uniform && M <= 65536) {
+        // the single-sector hop-list product reads e^{ik.t} per translation t
+        // and the k-dependent stabiliser factors per representative
+        const int nt = lat->lx * lat->ly * lat->lz;
+        std::vector<uint16_t> tP(nt);
+        for (int t = 0; t < nt; ++t) {
+            const int tx = t % lat->lx, ty = (t / lat->lx) % lat->ly, tz = t / (lat->lx * lat->ly);
+            tP[t] = (uint16_t)(((long)kmul[0] * tx + (long)kmul[1] * ty + (long)kmul[2] * tz) % M);
+        }
+        QS3_TRY(bat->tP.alloc(ctx, sizeof(uint16_t) * nt));
+        QS3_HIP(hipMemcpy(bat->tP.ptr, tP.data(), sizeof(uint16_t) * nt, hipMemcpyHostToDevice));
+        if (nnt > 0) {
+            // a stabiliser acts freely on the N_down down spins, so s <= N_down
+            std::vector<uint8_t> g(bat->ks->n_reps, 1);
+            for (size_t q = 0; q < nnt; ++q) {
+                const uint32_t u = bat->ks->nt_u[q];
+                g[u] = bat->h_compat_nt[q] ? (uint8_t)bat->ks->h_stab[u] : 0;
+            }
+            QS3_TRY(bat->gcls.alloc(ctx, g.size()));
+            QS3_HIP(hipMemcpy(bat->gcls.ptr, g.data(), g.size(), hipMemcpyHostToDevice));
+        }
+    }
     *out = bat.release();
     return QS3_OK;
 }

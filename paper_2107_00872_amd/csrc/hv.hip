@@ -56,6 +56,8 @@ BatchArgs batch_args(qs3_batch *bat) {
     A.phase = bat->phase.as<double2>();
     A.active = bat->active_dev;
     A.ph_lds_off = -1;
+    A.tP = bat->tP.as<uint16_t>();
+    A.gcls = bat->gcls.as<uint8_t>();
     return A;
 }
 

@@ -343,14 +343,32 @@ template <typename RT, typename CT, typename OT, int MODE>
 static int launch_batch(qs3_batch *bat, const void *v, void *w, hipStream_t s) {
     BatchArgs A = batch_args(bat);
     if (A.B == 1) {
-        // a single sector: one lane per row, the hops of a chunk in flight together
+        // a single sector: one or two lanes per row, all of its hops in flight together
         using C2 = typename Cplx<CT>::type;
         using O2 = typename Cplx<OT>::type;
-        if (MODE == HOP_LISTS && A.L.uniform && A.hmax <= 24 && A.M <= PHASE_LDS) {
+        // LDS of the hop-list kernel: per cell translation t, (J_xy/2) e^{ik.t}
+        // and its phase index; the phase table
+        const int ntr = bat->lat->lx * bat->lat->ly * bat->lat->lz;
+        const size_t lds1 = ((sizeof(C2) * (size_t)ntr + 15) & ~size_t(15)) + sizeof(double2) * (size_t)A.M +
+                            sizeof(double) * 16 + sizeof(uint16_t) * (size_t)ntr;
+        const bool factors = bat->ks->nt_u.empty() || A.gcls;
+        if (MODE == HOP_LISTS && A.tP && factors && A.L.uniform && A.hmax <= 24 && lds1 <= 64 * 1024) {
             // hop lists with one exchange constant: the entries give every term
+            // two lanes per row while the sector is small enough for its rows
+            // to be resident at once; one lane per row (more registers per
+            // lane, fewer instructions per row) for larger ones
+            const bool two = A.n_reps <= (2ull << 20);
             const int g1 = grid_cover(bat->lat->ctx, (A.n_reps + 255) / 256);
-#define QS3_L1(HM)                                                                                         \
-    hipLaunchKernelGGL((k_hv_one_lists<CT, OT, HM>), dim3(g1), dim3(256), 0, s, A, (const C2 *)v, (O2 *)w)
+            const int g2 = grid_cover(bat->lat->ctx, (A.n_reps + 127) / 128);
+#define QS3_L1(HM)                                                                                           \
+    do {                                                                                                     \
+        if (two)                                                                                             \
+            hipLaunchKernelGGL((k_hv_one_lists<CT, OT, HM, 2>), dim3(g2), dim3(256), lds1, s, A, (const C2 *)v, \
+                               (O2 *)w);                                                                     \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_hv_one_lists<CT, OT, HM, 1>), dim3(g1), dim3(256), lds1, s, A, (const C2 *)v, \
+                               (O2 *)w);                                                                     \
+    } while (0)
             if (A.hmax <= 6) QS3_L1(6);
             else if (A.hmax <= 8) QS3_L1(8);
             else if (A.hmax <= 12) QS3_L1(12);
@@ -745,6 +763,7 @@ static int build_t(qs3_lattice *lat, const BinomTable &bt, KStructure *ks, hipSt
         HA.L = L;
         HA.n_reps = tot;
         HA.reps = ks->reps.as<uint64_t>();
+        HA.stab = ks->stab.as<uint16_t>();
         HA.dir = ks->dir.as<uint32_t>();
         HA.dir_shift = ks->dir_shift;
         hipLaunchKernelGGL((k_hoplist<K, RT>), dim3((tot + 255) / 256), dim3(256), 0, s, HA, tab, ks->hmax,

@@ -301,12 +301,13 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                     hop_of<K>(h, off, c, ptr, &m, &e);
                     const int j = nbr[e];
                     RT rp;
-                    bool hop = true;
+                    bool hop = true, ntf = true;
                     int tx = 0, ty = 0, tz = 0;
                     if (MODE == HOP_LISTS) {
                         // resolved once at structure build: occupied targets are ~0
                         const uint64_t ent = A.hops[u * (uint64_t)A.hmax + h];
                         hop = ent != ~0ull;
+                        ntf = (ent & HOP_NT_BIT) != 0;
                         u2 = (uint32_t)ent;
                         const uint32_t t = (uint32_t)(ent >> 32);
                         tx = t & 1023u;
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                         if (hop) resolve_hop<K, RT, MODE == HOP_TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
                     }
                     if (hop) {
-                        const int s2 = A.stab[u2];
+                        const int s2 = ntf ? A.stab[u2] : 1;
                         nt2 = s2 > 1 ? A.nt_of[u2] : -1;
                         tp = (uint32_t)(tx | (ty << 10) | (tz << 20));
                         const double jxy = UNIF ? A.L.u_jxy_h : A.L.jxy_h[e];
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(256) void k_hv_one(BatchArgs A, const RT *__restric
         const uint64_t *hrow = MODE == HOP_LISTS ? A.hops + u * (uint64_t)A.hmax : nullptr;
         CT accr = 0, acci = 0, dz = 0;
         for (int h0 = 0; h0 < nh; h0 += QC) {
-            bool hok[QC];
+            bool hok[QC], hnt[QC];
             uint32_t hu[QC];
             int he[QC], P[QC];
 #pragma unroll
@@ -500,10 +501,11 @@ __global__ __launch_bounds__(256) void k_hv_one(BatchArgs A, const RT *__restric
                 he[r] = e;
                 uint32_t u2 = 0;
                 int tx = 0, ty = 0, tz = 0;
-                bool ok = false;
+                bool ok = false, ntf = true;
                 if (MODE == HOP_LISTS) {
                     const uint64_t ent = h < nh ? hrow[h] : ~0ull;
                     ok = ent != ~0ull;
+                    ntf = (ent & HOP_NT_BIT) != 0;
                     u2 = (uint32_t)ent;
                     const uint32_t t = (uint32_t)(ent >> 32);
                     tx = t & 1023u;
@@ -516,6 +518,7 @@ __global__ __launch_bounds__(256) void k_hv_one(BatchArgs A, const RT *__restric
                     if (ok) resolve_hop<K, RT, MODE == HOP_TABLE>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
                 }
                 hok[r] = ok;
+                hnt[r] = ok && ntf;
                 hu[r] = ok ? u2 : (uint32_t)u;
                 int p = kx * tx + ky * ty + kz * tz;
                 const int qq = (int)((double)p * A.invM);
@@ -530,7 +533,7 @@ __global__ __launch_bounds__(256) void k_hv_one(BatchArgs A, const RT *__restric
             double2 ph[QC];
 #pragma unroll
             for (int r = 0; r < QC; ++r) {
-                s2[r] = A.stab[hu[r]];
+                s2[r] = hnt[r] ? A.stab[hu[r]] : 1;
                 x[r] = v[hu[r]];
                 ph[r] = A.phase[P[r]];
             }
@@ -560,38 +563,63 @@ __global__ __launch_bounds__(256) void k_hv_one(BatchArgs A, const RT *__restric
 // A single momentum sector with per-representative hop lists on a lattice with
 // one exchange and one Ising constant: a row needs neither its state nor the
 // lattice tables, its hop-list entries (target representative and
-// translation, ~0 for an occupied target) give every term.  All of a row's
-// entries are loaded at once (16-byte loads when rows start 16-byte aligned),
-// then the stabiliser and v gathers of every hop of the row, so a row waits
-// for two memory round trips; the phases e^{2 pi i P / M} come from LDS and
-// the stabiliser factor sqrt(s) is read only for the rare s > 1 (sqrt(1) is
-// 1 exactly).  Same terms, order and arithmetic as k_hv_one and k_hv_batch.
-template <typename CT, typename OT, int HM>
+// translation, ~0 for an occupied target) give every term.  A lane loads its
+// row's entries (16-byte loads), then issues the v gathers of every hop of the
+// row together, so a row waits for two memory round trips.  Rows whose own
+// stabiliser and whose targets' stabilisers are all trivial (no entry carries
+// HOP_NT_BIT) -- every row of a lattice whose orbits are all full -- take each
+// term as one LDS read of (J_xy/2) e^{ik.t}, staged per cell translation t
+// (from A.tP, the phase index of t, and the phase table), in a branch-free
+// loop (an empty slot is dropped by a select).  For a flagged target the
+// class byte A.gcls (its stabiliser size s, 0 when it is not in the sector) is
+// gathered with v, and a wavefront holding such rows evaluates every term as
+// (J_xy/2) sqrt(s_b) / sqrt(s_a) e^{ik.t} instead.  LPR = 2 splits a row's
+// slots between two neighbouring lanes (half the registers per lane, so a
+// sector of a few hundred thousand rows is resident in one wave of the
+// machine), each summing its half in hop order, and the first half's sums
+// are added to the second's.  The phase indices, the phase table and the
+// first row's entries share one memory round trip.
+// Dynamic LDS: the staged terms (N_T CT pairs), the phase table (M double2),
+// sqrt(0..15) and the phase indices (N_T uint16).  The terms and their
+// arithmetic are those of k_hv_one and k_hv_batch (with sqrt(1) = 1 exactly,
+// (CT)(J_xy/2 * 1 * 1) * (CT)phase is the staged term), and with LPR = 1 so is
+// their order.
+template <typename CT, typename OT, int HM, int LPR>
 __global__ __launch_bounds__(256) void k_hv_one_lists(BatchArgs A,
                                                       const typename Cplx<CT>::type *__restrict__ v,
                                                       typename Cplx<OT>::type *__restrict__ w) {
     using C2 = typename Cplx<CT>::type;
     using O2 = typename Cplx<OT>::type;
-    __shared__ double2 s_ph[PHASE_LDS];
+    static_assert(LPR == 1 || LPR == 2, "one or two lanes per row");
+    constexpr int HH = HM / LPR;      // hop slots per lane
+    constexpr int RPB = 256 / LPR;    // rows per block and tile
+    extern __shared__ __align__(16) unsigned char smem[];
     if (A.active && !A.active[0]) return;  // an inactive sector's rows stay untouched
-    for (int i = threadIdx.x; i < A.M; i += blockDim.x) s_ph[i] = A.phase[i];
-    __syncthreads();
-    const int kx = A.kmul[0], ky = A.kmul[1], kz = A.kmul[2];
+    const int lx = A.L.lx, lxy = A.L.lx * A.L.ly;
+    const int nt = lxy * A.L.lz;
+    const int M = A.M;
+    C2 *s_pt = (C2 *)smem;
+    double2 *s_phase = (double2 *)(smem + (((size_t)nt * sizeof(C2) + 15) & ~size_t(15)));
+    double *s_sq = (double *)(s_phase + M);
+    uint16_t *s_P = (uint16_t *)(s_sq + 16);
+    const double jxy = A.L.u_jxy_h;
     const int hmax = A.hmax;
     const CT jz = (CT)A.L.u_jz_h;
-    const double jxy = A.L.u_jxy_h;
+    const int sub = LPR == 1 ? 0 : (int)(threadIdx.x & 1u);  // which half of the row's slots
+    const int rl = (int)threadIdx.x / LPR;
     const uint32_t lb = xcd_block(blockIdx.x, gridDim.x);
-    const uint64_t ntiles = (A.n_reps + 255) / 256;
+    const uint64_t ntiles = (A.n_reps + RPB - 1) / RPB;
     const uint64_t t0 = ntiles * lb / gridDim.x, t1 = ntiles * (lb + 1) / gridDim.x;
-    for (uint64_t tile = t0; tile < t1; ++tile) {
-        const uint64_t u = tile * 256 + threadIdx.x;
-        if (u >= A.n_reps) break;
+    uint64_t ent[HH];
+    int su = 1;
+    C2 xs = C2{0, 0};
+    // the lane's slots of a row's entries, the row's stabiliser and own element
+    auto load_row = [&](uint64_t u) {
         const uint64_t *hrow = A.hops + u * (uint64_t)hmax;
-        uint64_t ent[HM];
-        if ((hmax & 1) == 0) {
+        if (LPR == 1 && (hmax & 1) == 0) {
             const uint4 *p = (const uint4 *)hrow;
 #pragma unroll
-            for (int i = 0; i < HM / 2; ++i) {
+            for (int i = 0; i < HH / 2; ++i) {
                 uint4 q = make_uint4(~0u, ~0u, ~0u, ~0u);
                 if (2 * i < hmax) q = p[i];
                 ent[2 * i] = (uint64_t)q.x | ((uint64_t)q.y << 32);
@@ -599,56 +627,113 @@ __global__ __launch_bounds__(256) void k_hv_one_lists(BatchArgs A,
             }
         } else {
 #pragma unroll
-            for (int h = 0; h < HM; ++h) ent[h] = h < hmax ? hrow[h] : ~0ull;
+            for (int j = 0; j < HH; ++j) {
+                const int h = sub * HH + j;
+                ent[j] = h < hmax ? hrow[h] : ~0ull;
+            }
         }
-        const int su = A.stab[u];
-        const C2 xs = v[u];
-        bool hok[HM];
-        uint32_t hu[HM];
-        int s2[HM];
-        C2 x[HM];
+        su = A.stab[u];
+        xs = v[u];
+    };
+    // ---- one round trip: phase indices (first 1024), phase table (first 256),
+    // sqrt(0..15) and the first row's entries
+    uint16_t rP[4];
 #pragma unroll
-        for (int h = 0; h < HM; ++h) {
-            hok[h] = ent[h] != ~0ull;
-            hu[h] = hok[h] ? (uint32_t)ent[h] : (uint32_t)u;
-        }
-        // every gather of the row in flight together
+    for (int j = 0; j < 4; ++j) {
+        const int t = threadIdx.x + 256 * j;
+        rP[j] = t < nt ? A.tP[t] : 0;
+    }
+    double2 rph = make_double2(0.0, 0.0);
+    if ((int)threadIdx.x < M) rph = A.phase[threadIdx.x];
+    const double rsq = threadIdx.x < 16 ? A.L.sqrt_tab[threadIdx.x < (unsigned)A.L.N ? threadIdx.x : 0] : 0.0;
+    const uint64_t u0 = t0 * RPB + rl;
+    if (t0 < t1 && u0 < A.n_reps) load_row(u0);
+    if ((int)threadIdx.x < M) s_phase[threadIdx.x] = rph;
+    for (int i = threadIdx.x + 256; i < M; i += 256) s_phase[i] = A.phase[i];
+    if (threadIdx.x < 16) s_sq[threadIdx.x] = rsq;
 #pragma unroll
-        for (int h = 0; h < HM; ++h) {
-            s2[h] = A.stab[hu[h]];
-            x[h] = v[hu[h]];
+    for (int j = 0; j < 4; ++j) {
+        const int t = threadIdx.x + 256 * j;
+        if (t < nt) s_P[t] = rP[j];
+    }
+    for (int t = threadIdx.x + 1024; t < nt; t += 256) s_P[t] = A.tP[t];
+    __syncthreads();
+    for (int t = threadIdx.x; t < nt; t += 256) {
+        const double2 ph = s_phase[s_P[t]];
+        const CT hc = (CT)jxy;
+        s_pt[t] = C2{hc * (CT)ph.x, hc * (CT)ph.y};
+    }
+    __syncthreads();
+    for (uint64_t tile = t0; tile < t1; ++tile) {
+        const uint64_t u = tile * RPB + rl;
+        if (u >= A.n_reps) break;  // both lanes of a row leave together
+        if (tile != t0) load_row(u);
+        uint32_t hu[HH];
+        int ti[HH];
+        uint32_t okm = 0, flm = 0;  // bit j: slot j is a hop; its target's stabiliser is non-trivial
+#pragma unroll
+        for (int j = 0; j < HH; ++j) {
+            const bool ok = ent[j] != ~0ull;
+            hu[j] = ok ? (uint32_t)ent[j] : (uint32_t)u;
+            okm |= ok ? (1u << j) : 0u;
+            flm |= (ok && (ent[j] & HOP_NT_BIT)) ? (1u << j) : 0u;
+            const uint32_t t = (uint32_t)(ent[j] >> 32);
+            ti[j] = ok ? (int)(t & 1023u) + lx * (int)((t >> 10) & 1023u) + lxy * (int)((t >> 20) & 1023u) : 0;
         }
-        if (su > 1 && !A.compat_nt[A.nt_of[u]]) {
-            w[u] = O2{0, 0};
-            continue;
+        // every gather of the lane's slots in flight together, with the class
+        // of each flagged target and of the row itself
+        C2 x[HH];
+        int cl[HH];
+#pragma unroll
+        for (int j = 0; j < HH; ++j) {
+            x[j] = v[hu[j]];
+            cl[j] = ((flm >> j) & 1u) ? (int)A.gcls[hu[j]] : 1;
         }
-        const double sqs = su == 1 ? 1.0 : A.L.sqrt_tab[su];
-        const CT isq = (CT)(1.0 / sqs);
+        const int cu = su > 1 ? (int)A.gcls[u] : 1;
         CT accr = 0, acci = 0, dz = 0;
+        if (!__any(su > 1 || flm != 0)) {
 #pragma unroll
-        for (int h = 0; h < HM; ++h) {
-            if (!hok[h]) continue;
-            dz += jz;
-            // a target whose stabiliser is incompatible with k is not in the sector
-            if (s2[h] > 1 && !A.compat_nt[A.nt_of[hu[h]]]) continue;
-            const uint32_t t = (uint32_t)(ent[h] >> 32);
-            int p = kx * (int)(t & 1023u) + ky * (int)((t >> 10) & 1023u) + kz * (int)((t >> 20) & 1023u);
-            const int qq = (int)((double)p * A.invM);
-            p -= qq * A.M;
-            p += (p < 0) ? A.M : 0;
-            p -= (p >= A.M) ? A.M : 0;
-            const double2 ph = s_ph[p];
-            const double sq2 = s2[h] == 1 ? 1.0 : A.L.sqrt_tab[s2[h]];
-            const CT hc = (CT)(jxy * sq2 * (double)isq);
-            const CT pr = hc * (CT)ph.x, pi = hc * (CT)ph.y;
-            accr += pr * x[h].x - pi * x[h].y;
-            acci += pr * x[h].y + pi * x[h].x;
+            for (int j = 0; j < HH; ++j) {
+                const bool ok = (okm >> j) & 1u;
+                const C2 pt = s_pt[ti[j]];
+                const CT ar = accr + (pt.x * x[j].x - pt.y * x[j].y);
+                const CT ai = acci + (pt.x * x[j].y + pt.y * x[j].x);
+                accr = ok ? ar : accr;
+                acci = ok ? ai : acci;
+                dz = ok ? dz + jz : dz;
+            }
+        } else {
+            // a target outside the sector (class 0) contributes only to the diagonal
+            const CT isq = (CT)(1.0 / s_sq[cu > 0 ? cu : 1]);
+#pragma unroll
+            for (int j = 0; j < HH; ++j) {
+                const bool ok = (okm >> j) & 1u;
+                const bool use = ok && cl[j] != 0;
+                const double2 ph = s_phase[s_P[ti[j]]];
+                const CT hc = (CT)(jxy * s_sq[cl[j]] * (double)isq);
+                const CT pr = hc * (CT)ph.x, pi = hc * (CT)ph.y;
+                const CT ar = accr + (pr * x[j].x - pi * x[j].y);
+                const CT ai = acci + (pr * x[j].y + pi * x[j].x);
+                accr = use ? ar : accr;
+                acci = use ? ai : acci;
+                dz = ok ? dz + jz : dz;
+            }
         }
-        const CT diag = (CT)A.L.ez4 - dz;
-        O2 o;
-        o.x = (OT)(diag * xs.x + accr);
-        o.y = (OT)(diag * xs.y + acci);
-        w[u] = o;
+        if (LPR == 2) {
+            // first half's sums plus the second half's, in that order on both lanes
+            const CT orr = __shfl_xor(accr, 1), oi = __shfl_xor(acci, 1), od = __shfl_xor(dz, 1);
+            accr = sub == 0 ? accr + orr : orr + accr;
+            acci = sub == 0 ? acci + oi : oi + acci;
+            dz = sub == 0 ? dz + od : od + dz;
+        }
+        if (sub == 0) {
+            const bool zero = cu == 0;  // the row's own orbit is not in the sector
+            const CT diag = (CT)A.L.ez4 - dz;
+            O2 o;
+            o.x = zero ? (OT)0 : (OT)(diag * xs.x + accr);
+            o.y = zero ? (OT)0 : (OT)(diag * xs.y + acci);
+            w[u] = o;
+        }
     }
 }
 
@@ -847,8 +932,9 @@ __global__ __launch_bounds__(256) void k_table(BuildArgs A, const RT *__restrict
 
 // Hop lists: for representative u, entry h (the row's hops in the kernel's
 // order: down spins ascending, each site's bonds in order) is the packed
-// (representative index, translation) of the hop's target, or ~0 when the
-// target site is occupied; entries nh..hmax-1 are ~0.
+// (representative index, translation) of the hop's target, with HOP_NT_BIT
+// when the target's stabiliser is non-trivial, or ~0 when the target site is
+// occupied; entries nh..hmax-1 are ~0.  A.stab must be complete.
 template <int K, typename RT>
 __global__ __launch_bounds__(256) void k_hoplist(BatchArgs A, const RT *__restrict__ binom_g, int hmax,
                                                  uint64_t *__restrict__ hops) {
@@ -873,7 +959,7 @@ __global__ __launch_bounds__(256) void k_hoplist(BatchArgs A, const RT *__restri
                 uint32_t u2;
                 int tx, ty, tz;
                 resolve_hop<K, RT, false>(A, Bn, g, c, m, j, rp, &u2, &tx, &ty, &tz);
-                ent = pack_ent(u2, tx, ty, tz);
+                ent = pack_ent(u2, tx, ty, tz) | (A.stab[u2] > 1 ? HOP_NT_BIT : 0ull);
             }
             out[h] = ent;
         }

@@ -231,6 +231,12 @@ __host__ __device__ __forceinline__ uint64_t pack_ent(uint32_t u, int tx, int ty
     return (uint64_t)u | ((uint64_t)(tx | (ty << 10) | (tz << 20)) << 32);
 }
 
+// Bit 62 of a hop-list entry marks a target representative with a
+// non-trivial stabiliser (its size and k-compatibility have to be read);
+// decoders mask the translation to its three 10-bit fields, and bit 63 is
+// clear in every entry, so ~0 still marks an empty slot.
+constexpr uint64_t HOP_NT_BIT = 1ull << 62;
+
 // SplitMix64 (Steele, Lea, Flood 2014), output `counter` of the stream `seed`.
 __host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t counter) {
     uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;

@@ -32,6 +32,12 @@ struct BatchArgs {
     const double2 *phase;  // e^{2 pi i P / M}
     const uint8_t *active;  // per sector, or null: rows of inactive sectors are left untouched
     int ph_lds_off;         // byte offset of the phase table in dynamic LDS, or -1 (global)
+    // a batch of one sector with uniform couplings: the phase index of e^{ik.t}
+    // per cell translation, and the class of every representative in the
+    // sector (stabiliser size, 0 outside it; null when every stabiliser is
+    // trivial); both null otherwise
+    const uint16_t *tP;
+    const uint8_t *gcls;
 };
 
 struct BuildArgs {

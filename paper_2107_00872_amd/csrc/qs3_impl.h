@@ -185,6 +185,13 @@ struct qs3_batch {
     qs3::DevBuf kmul;             // int32 [3*B]: K_a * (M / L_a) mod M
     qs3::DevBuf phase;            // double2 [M]: e^{2 pi i P / M}
     qs3::DevBuf compat_nt;        // uint8 [n_nt * B]
+    // a batch of one sector on a lattice with one exchange constant: the
+    // phase-table index P of e^{ik.t} per cell translation t = tx + lx (ty +
+    // ly tz) (uint16 [N_T]), and where the structure has non-trivial
+    // stabilisers the class of every representative in this sector (uint8
+    // [n_reps]): its stabiliser size s when k is compatible with it (1 for a
+    // trivial stabiliser), 0 when it is not in the sector; empty otherwise
+    qs3::DevBuf tP, gcls;
     int last_G = 0, last_bpc = 0;  // schedule of the last batched H.v launch
     std::vector<uint8_t> h_compat_nt;
     std::vector<uint64_t> dims;   // per sector

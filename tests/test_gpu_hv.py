@@ -199,6 +199,43 @@ def test_k_sector_64bit_ranks_cube10_k4(qs3, ctx):
     sec.close()
 
 
+def test_k_sector_large_hop_lists_vs_on_the_fly(qs3, ctx, ctx_fly):
+    """A momentum sector of 41,417,000 representatives (10^3 cube, N_down = 4,
+    k = (5, 0, 0)) takes the single-sector hop-list product with one lane per
+    row; k = (5, 0, 0) excludes the orbits whose stabiliser holds a translation
+    with odd x component, so rows and targets of class 0 occur.  Its H.v
+    (float64 and float32 rows) must equal the product that canonicalises
+    every hop on the fly -- the kernel checked element by element against
+    Alg. 9 on every lattice of K_CASES -- within rounding, and be Hermitian."""
+    lat = wl.cube(10)
+    Kv = (5, 0, 0)
+    sec = qs3.Sector(qs3.Lattice.of(ctx, lat), 4, Kv)
+    fly = qs3.Sector(qs3.Lattice.of(ctx_fly, lat), 4, Kv)
+    assert sec.dim == fly.dim and sec.dim > (2 << 20)
+    r1, s1 = sec.basis()
+    r2, s2 = fly.basis()
+    assert np.array_equal(r1, r2) and np.array_equal(s1, s2)
+    assert (s1 > 1).any()
+    v = torch.empty(sec.dim, dtype=torch.complex128, device="cuda")
+    sec.start_vector(9, v)
+    w, wf = torch.empty_like(v), torch.empty_like(v)
+    sec.matvec(v, w)
+    fly.matvec(v, wf)
+    vmax = v.abs().max().item()
+    assert (w - wf).abs().max().item() <= hv_tol(lat, vmax * 1.5)
+    w32 = torch.empty(sec.dim, dtype=torch.complex64, device="cuda")
+    sec.matvec(v.to(torch.complex64), w32)
+    assert (w32.to(torch.complex128) - wf).abs().max().item() <= hv_tol32(lat, vmax * 1.5, 4)
+    u = torch.empty_like(v)
+    sec.start_vector(10, u)
+    hu = torch.empty_like(u)
+    sec.matvec(u, hu)
+    lhs, rhs = torch.vdot(u, w).item(), torch.vdot(hu, v).item()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    sec.close()
+    fly.close()
+
+
 @pytest.fixture(scope="module")
 def ctx_fly(qs3):
     """A context that never builds rank tables: every hop is resolved by
