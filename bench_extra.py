@@ -635,8 +635,10 @@ def c2(args):
     t_all = time.perf_counter() - t_all0
     ms_per_step = 1e3 * t_all / args.steps
 
-    # ---- roofline of the dominant kernel: fixed-N_down H.v on the full sector,
-    # timed with events recorded on the stream the kernel runs on
+    # ---- roofline of the fixed-N_down H.v on the full sector (the method's hot
+    # operation; in the step its kernel time is a minority share beside the
+    # multi-dot and Gram-Schmidt kernels of the reorthogonalisation), timed
+    # with events recorded on the stream the kernel runs on
     v = torch.empty(d, dtype=torch.float64, device="cuda")
     w = torch.empty_like(v)
     full.start_vector(7, v, stream=stream)
