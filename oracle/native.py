@@ -26,12 +26,23 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+def build_sanitized(out: str) -> str:
+    """The same C file under AddressSanitizer and UndefinedBehaviorSanitizer
+    (any report aborts the process); loaded in place of the plain build when
+    QS3_ORACLE_LIB names it, in a process that preloads the ASan runtime."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=all", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                           "-D_GNU_SOURCE", SRC, "-o", out, "-lm"])
+    return out
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        path = os.environ.get("QS3_ORACLE_LIB") or LIB
+        if path == LIB and not os.path.exists(LIB):
             build()
-        L = ctypes.CDLL(LIB)
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
         L.orc_binom.restype = u64
