@@ -231,7 +231,26 @@ static int small_t(qs3_lattice *lat, const BinomTable *bt, qs3_batch *bat, const
     else A.L = lat_args(lat);
     const size_t sh = lds_need<RT>(lat, KI);
     QS3_REQUIRE(sh <= 64 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
-    hipLaunchKernelGGL((k_lanczos_small<KI, RT, CPLX, TABLE>), dim3(1), dim3(1024), sh, s, S, A, bt->dev.as<RT>());
+    // fixed N_down on a regular lattice with one coupling: the unrolled row
+    const int z = (lat->uniform && lat->regular) ? lat->max_degree : 0;
+    if constexpr (!CPLX) {
+        if (z == 2 && KI * 2 <= 24)
+            hipLaunchKernelGGL((k_lanczos_small<KI, RT, CPLX, TABLE, 2>), dim3(1), dim3(1024), sh, s, S, A,
+                               bt->dev.as<RT>());
+        else if (z == 4 && KI * 4 <= 24)
+            hipLaunchKernelGGL((k_lanczos_small<KI, RT, CPLX, TABLE, 4>), dim3(1), dim3(1024), sh, s, S, A,
+                               bt->dev.as<RT>());
+        else if (z == 6 && KI * 6 <= 24)
+            hipLaunchKernelGGL((k_lanczos_small<KI, RT, CPLX, TABLE, 6>), dim3(1), dim3(1024), sh, s, S, A,
+                               bt->dev.as<RT>());
+        else
+            hipLaunchKernelGGL((k_lanczos_small<KI, RT, CPLX, TABLE, 0>), dim3(1), dim3(1024), sh, s, S, A,
+                               bt->dev.as<RT>());
+    } else {
+        (void)z;
+        hipLaunchKernelGGL((k_lanczos_small<KI, RT, CPLX, TABLE, 0>), dim3(1), dim3(1024), sh, s, S, A,
+                           bt->dev.as<RT>());
+    }
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }

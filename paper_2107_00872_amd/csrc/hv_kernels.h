@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <type_traits>
 
 #include "qs3_device.h"
 #include "qs3_impl.h"
@@ -1191,10 +1192,18 @@ __device__ __forceinline__ double2 block_sum_all(double2 v, double2 *red) {
 // the three-term update, classical Gram-Schmidt against every earlier vector
 // (the second pass where the first cancelled more than half of |w|^2) and the
 // normalisation, with the Krylov basis in global memory (it stays in L2 for
-// the sizes this kernel is used for).  CPLX: momentum sector (union layout),
-// else fixed-N_down.
-template <int K, typename RT, bool CPLX, bool TABLE>
+// the sizes this kernel is used for).  A single workgroup is bound by the
+// latency of its loads from L2, so every pass keeps many independent loads in
+// flight: the Gram-Schmidt dot products take VPI basis vectors per wavefront
+// at a time (their loads issued together, their wavefront sums interleaved),
+// and the update prefetches UC basis elements of a row before subtracting
+// them in slot order.  CPLX: momentum sector (union layout), else fixed-N_down
+// (ZM > 0: the unrolled all-hops-in-flight row of k_hv_u1).
+template <int K, typename RT, bool CPLX, bool TABLE, int ZM>
 __global__ __launch_bounds__(1024) void k_lanczos_small(SmallArgs S, BatchArgs A, const RT *__restrict__ binom_g) {
+    using ET = typename std::conditional<CPLX, double2, double>::type;
+    constexpr int VPI = CPLX ? 2 : 4;  // basis vectors per wavefront per round of the dot products
+    constexpr int UC = CPLX ? 16 : 32; // basis elements prefetched per row in the update
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double2 red[16];
     __shared__ double2 hsh[520];
@@ -1207,84 +1216,106 @@ __global__ __launch_bounds__(1024) void k_lanczos_small(SmallArgs S, BatchArgs A
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
     const uint64_t n = S.n;
-    auto P = [&](int j) { return S.Psi + (size_t)j * S.stride; };
+    auto P = [&](int j) { return (ET *)(S.Psi + (size_t)j * S.stride); };
+    ET *W = (ET *)S.W;
     for (int x = S.x0; x < S.x1; ++x) {
         const int prev = (x == S.x0) ? S.prev_first : x - 1;
         // ---- W = H psi_x
-        if (CPLX) {
-            const double2 *px = (const double2 *)P(x);
-            for (uint64_t r = tid; r < n; r += nt)
-                ((double2 *)S.W)[r] = hv_row_k1<K, RT, TABLE>(A, Bn, g, ptr, nbr, r, px);
+        if constexpr (CPLX) {
+            const double2 *px = P(x);
+            for (uint64_t r = tid; r < n; r += nt) W[r] = hv_row_k1<K, RT, TABLE>(A, Bn, g, ptr, nbr, r, px);
         } else {
             const double *px = P(x);
-            for (uint64_t r = tid; r < n; r += nt) S.W[r] = hv_row_u1<K, RT, double, 0>(A.L, Bn, ptr, nbr, (RT)r, px);
+            for (uint64_t r = tid; r < n; r += nt) W[r] = hv_row_u1<K, RT, double, ZM>(A.L, Bn, ptr, nbr, (RT)r, px);
         }
         __syncthreads();
         // ---- alpha = Re <psi_x, W>; W -= alpha psi_x + beta_prev psi_prev
         double2 s = make_double2(0.0, 0.0);
-        for (uint64_t r = tid; r < n; r += nt) {
-            if (CPLX) dot_acc(((const double2 *)P(x))[r], ((const double2 *)S.W)[r], s);
-            else dot_acc(P(x)[r], S.W[r], s);
-        }
+        for (uint64_t r = tid; r < n; r += nt) dot_acc(P(x)[r], W[r], s);
         const double a = block_sum_all(s, red).x;
         const double bp = prev >= 0 ? S.ab[S.slots + prev] : 0.0;
         for (uint64_t r = tid; r < n; r += nt) {
-            if (CPLX) {
-                double2 w = ((double2 *)S.W)[r];
-                const double2 p0 = ((const double2 *)P(x))[r];
+            if constexpr (CPLX) {
+                double2 w = W[r];
+                const double2 p0 = P(x)[r];
                 w.x -= a * p0.x;
                 w.y -= a * p0.y;
                 if (prev >= 0) {
-                    const double2 p1 = ((const double2 *)P(prev))[r];
+                    const double2 p1 = P(prev)[r];
                     w.x -= bp * p1.x;
                     w.y -= bp * p1.y;
                 }
-                ((double2 *)S.W)[r] = w;
+                W[r] = w;
             } else {
-                double w = S.W[r] - a * P(x)[r];
+                double w = W[r] - a * P(x)[r];
                 if (prev >= 0) w -= bp * P(prev)[r];
-                S.W[r] = w;
+                W[r] = w;
             }
         }
         if (tid == 0) S.ab[x] = a;
         __syncthreads();
         // ---- classical Gram-Schmidt against slots 0..x: one pass, and a
-        // second where the first cancelled more than half of |W|^2
+        // second where the first cancelled more than half of |W|^2.  Dot
+        // products: wavefront q takes slots q, q + nw, ... VPI at a time (slot
+        // x + 1 stands for W itself, giving |W|^2); each sum runs over rows
+        // lane, lane + 64, ... and then a fixed shuffle tree.
         auto cgs_dots = [&](bool self) {
-            for (int j = wave; j <= x + (self ? 1 : 0); j += nw) {
-                double2 h = make_double2(0.0, 0.0);
+            const int jmax = x + (self ? 1 : 0);
+            for (int j0 = wave; j0 <= jmax; j0 += nw * VPI) {
+                double2 h[VPI];
+#pragma unroll
+                for (int c = 0; c < VPI; ++c) h[c] = make_double2(0.0, 0.0);
                 for (uint64_t r = lane; r < n; r += 64) {
-                    if (CPLX) {
-                        const double2 w = ((const double2 *)S.W)[r];
-                        dot_acc(j <= x ? ((const double2 *)P(j))[r] : w, w, h);
-                    } else {
-                        const double w = S.W[r];
-                        dot_acc(j <= x ? P(j)[r] : w, w, h);
+                    const ET w = W[r];
+                    ET xv[VPI];
+#pragma unroll
+                    for (int c = 0; c < VPI; ++c) {
+                        const int j = j0 + c * nw;
+                        xv[c] = j <= x ? P(j)[r] : w;
+                    }
+#pragma unroll
+                    for (int c = 0; c < VPI; ++c) dot_acc(xv[c], w, h[c]);
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+                    for (int c = 0; c < VPI; ++c) {
+                        h[c].x += __shfl_down(h[c].x, off, 64);
+                        h[c].y += __shfl_down(h[c].y, off, 64);
                     }
                 }
-                h = wave_sum2(h);
-                if (lane == 0) hsh[j] = h;
+                if (lane == 0) {
+#pragma unroll
+                    for (int c = 0; c < VPI; ++c)
+                        if (j0 + c * nw <= jmax) hsh[j0 + c * nw] = h[c];
+                }
             }
             __syncthreads();
         };
         auto cgs_update = [&]() -> double {
             double2 acc = make_double2(0.0, 0.0);
             for (uint64_t r = tid; r < n; r += nt) {
-                if (CPLX) {
-                    double2 w = ((double2 *)S.W)[r];
-                    for (int j = 0; j <= x; ++j) {
-                        const double2 xj = ((const double2 *)P(j))[r], c = hsh[j];
-                        w.x -= xj.x * c.x - xj.y * c.y;
-                        w.y -= xj.x * c.y + xj.y * c.x;
+                ET w = W[r];
+                for (int j0 = 0; j0 <= x; j0 += UC) {
+                    ET pv[UC];
+#pragma unroll
+                    for (int c = 0; c < UC; ++c)
+                        if (j0 + c <= x) pv[c] = P(j0 + c)[r];
+#pragma unroll
+                    for (int c = 0; c < UC; ++c) {
+                        if (j0 + c > x) break;
+                        const double2 hc = hsh[j0 + c];
+                        if constexpr (CPLX) {
+                            w.x -= pv[c].x * hc.x - pv[c].y * hc.y;
+                            w.y -= pv[c].x * hc.y + pv[c].y * hc.x;
+                        } else {
+                            w -= pv[c] * hc.x;
+                        }
                     }
-                    ((double2 *)S.W)[r] = w;
-                    acc.x += w.x * w.x + w.y * w.y;
-                } else {
-                    double w = S.W[r];
-                    for (int j = 0; j <= x; ++j) w -= P(j)[r] * hsh[j].x;
-                    S.W[r] = w;
-                    acc.x += w * w;
                 }
+                W[r] = w;
+                if constexpr (CPLX) acc.x += w.x * w.x + w.y * w.y;
+                else acc.x += w * w;
             }
             return block_sum_all(acc, red).x;
         };
@@ -1300,20 +1331,17 @@ __global__ __launch_bounds__(1024) void k_lanczos_small(SmallArgs S, BatchArgs A
             }
         } else {
             double2 acc = make_double2(0.0, 0.0);
-            for (uint64_t r = tid; r < n; r += nt) {
-                if (CPLX) dot_acc(((const double2 *)S.W)[r], ((const double2 *)S.W)[r], acc);
-                else dot_acc(S.W[r], S.W[r], acc);
-            }
+            for (uint64_t r = tid; r < n; r += nt) dot_acc(W[r], W[r], acc);
             nrm2 = block_sum_all(acc, red).x;
         }
         const double beta = sqrt(fmax(nrm2, 0.0));
         const double sc = beta > 0.0 ? 1.0 / beta : 0.0;
         for (uint64_t r = tid; r < n; r += nt) {
-            if (CPLX) {
-                const double2 w = ((const double2 *)S.W)[r];
-                ((double2 *)P(x + 1))[r] = make_double2(w.x * sc, w.y * sc);
+            if constexpr (CPLX) {
+                const double2 w = W[r];
+                P(x + 1)[r] = make_double2(w.x * sc, w.y * sc);
             } else {
-                P(x + 1)[r] = S.W[r] * sc;
+                P(x + 1)[r] = W[r] * sc;
             }
         }
         if (tid == 0) S.ab[S.slots + x] = beta;
