@@ -43,12 +43,6 @@ struct Cplx<float> {
 // phase tables of at most this many entries are staged in LDS
 constexpr int PHASE_LDS = 2048;
 
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
-    // gfx950 dispatches workgroup b to XCD b % 8; give each XCD one contiguous
-    // slice of the logical block range so its L2 sees neighbouring rows.
-    return (n % 8u == 0u) ? (b % 8u) * (n / 8u) + b / 8u : b;
-}
-
 template <typename RT>
 __device__ __forceinline__ void load_lds_tables(unsigned char *smem, const LatArgs &L,
                                                 const RT *binom_g, int K, const RT **tab,

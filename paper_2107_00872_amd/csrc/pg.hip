@@ -249,6 +249,36 @@ __global__ void k_pg_spmv_packed(const uint32_t *__restrict__ col, const double 
     y[a] = diag[a] * x[a] + scale[a] * acc;
 }
 
+// The packed product with every slot of a row in flight at once (WM >= width
+// slots, padding dropped by a select): the row's column loads, then all of its
+// gathers, so a row waits for two memory round trips instead of two per chunk
+// of eight.  XT: element type of x and the staged R o x, AT: accumulator (the
+// float32 form accumulates in float32); same terms and order as the chunked
+// kernels.
+template <typename XT, typename AT, int WM>
+__global__ __launch_bounds__(256) void k_pg_spmv_packed_w(const uint32_t *__restrict__ col,
+                                                          const XT *__restrict__ xr,
+                                                          const double *__restrict__ scale,
+                                                          const double *__restrict__ diag, uint64_t dim, int width,
+                                                          const XT *__restrict__ x, double *__restrict__ y) {
+    const uint64_t a = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= dim) return;
+    uint32_t cb[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) cb[i] = i < width ? col[(uint64_t)i * dim + a] : 0xffffffffu;
+    XT t[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) t[i] = xr[cb[i] == 0xffffffffu ? 0u : (cb[i] & 0x7fffffffu)];
+    AT acc = 0;
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+        const AT v = (AT)t[i];
+        acc = cb[i] == 0xffffffffu ? acc : acc + ((cb[i] >> 31) ? -v : v);
+    }
+    if constexpr (sizeof(AT) == 8) y[a] = diag[a] * (double)x[a] + scale[a] * (double)acc;
+    else y[a] = (double)((float)diag[a] * (float)x[a] + (float)scale[a] * (float)acc);
+}
+
 // The momentum-sector amplitudes of sum_a x_a |a, k, chi>: grouping the
 // space-group sum by point operation, T-sum of P_p a = T^{-t} u is
 // e^{i k.t} sqrt(N_T s_u) |u, k>, so u (compact index i) receives
@@ -593,14 +623,31 @@ int pg_build(qs3_pg_sector *sec) {
     return QS3_OK;
 }
 
+// the all-slots kernel for widths up to 36 (false: the caller takes the chunked one)
+template <typename XT, typename AT>
+bool packed_w(qs3_pg_sector *sec, const XT *xr, const XT *x, double *y, hipStream_t s) {
+    const dim3 g(blocks_for(sec->dim, 256)), b(256);
+    const uint32_t *col = sec->col.as<uint32_t>();
+    const double *sc = sec->scale.as<double>(), *dg = sec->diag.as<double>();
+    const int w = sec->width;
+    if (w <= 8) hipLaunchKernelGGL((k_pg_spmv_packed_w<XT, AT, 8>), g, b, 0, s, col, xr, sc, dg, sec->dim, w, x, y);
+    else if (w <= 12) hipLaunchKernelGGL((k_pg_spmv_packed_w<XT, AT, 12>), g, b, 0, s, col, xr, sc, dg, sec->dim, w, x, y);
+    else if (w <= 16) hipLaunchKernelGGL((k_pg_spmv_packed_w<XT, AT, 16>), g, b, 0, s, col, xr, sc, dg, sec->dim, w, x, y);
+    else if (w <= 24) hipLaunchKernelGGL((k_pg_spmv_packed_w<XT, AT, 24>), g, b, 0, s, col, xr, sc, dg, sec->dim, w, x, y);
+    else if (w <= 36) hipLaunchKernelGGL((k_pg_spmv_packed_w<XT, AT, 36>), g, b, 0, s, col, xr, sc, dg, sec->dim, w, x, y);
+    else return false;
+    return true;
+}
+
 int pg_apply(qs3_pg_sector *sec, const double *x, double *y, hipStream_t s) {
     if (sec->dim == 0) return QS3_OK;
     if (sec->packed) {
         hipLaunchKernelGGL(k_pg_prescale, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s, sec->rnorm.as<double>(),
                            sec->dim, x, sec->xr.as<double>());
-        hipLaunchKernelGGL(k_pg_spmv_packed, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s,
-                           sec->col.as<uint32_t>(), sec->xr.as<double>(), sec->scale.as<double>(),
-                           sec->diag.as<double>(), sec->dim, sec->width, x, y);
+        if (!packed_w<double, double>(sec, sec->xr.as<double>(), x, y, s))
+            hipLaunchKernelGGL(k_pg_spmv_packed, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s,
+                               sec->col.as<uint32_t>(), sec->xr.as<double>(), sec->scale.as<double>(),
+                               sec->diag.as<double>(), sec->dim, sec->width, x, y);
     } else
         hipLaunchKernelGGL(k_pg_spmv, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s, sec->col.as<uint32_t>(),
                            sec->val.as<double>(), sec->diag.as<double>(), sec->dim, sec->width, x, y);
@@ -613,9 +660,10 @@ int pg_apply_f32(qs3_pg_sector *sec, const float *x, double *y, hipStream_t s) {
     if (sec->packed) {
         hipLaunchKernelGGL(k_pg_prescale_f32, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s,
                            sec->rnorm.as<double>(), sec->dim, x, sec->xr32.as<float>());
-        hipLaunchKernelGGL(k_pg_spmv_packed_f32, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s,
-                           sec->col.as<uint32_t>(), sec->xr32.as<float>(), sec->scale.as<double>(),
-                           sec->diag.as<double>(), sec->dim, sec->width, x, y);
+        if (!packed_w<float, float>(sec, sec->xr32.as<float>(), x, y, s))
+            hipLaunchKernelGGL(k_pg_spmv_packed_f32, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s,
+                               sec->col.as<uint32_t>(), sec->xr32.as<float>(), sec->scale.as<double>(),
+                               sec->diag.as<double>(), sec->dim, sec->width, x, y);
     } else {
         hipLaunchKernelGGL(k_pg_spmv_f32, dim3(blocks_for(sec->dim, 256)), dim3(256), 0, s, sec->col.as<uint32_t>(),
                            sec->val.as<double>(), sec->diag.as<double>(), sec->dim, sec->width, x, y);

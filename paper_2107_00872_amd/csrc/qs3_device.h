@@ -226,6 +226,12 @@ __host__ __device__ __forceinline__ int64_t find_rep(const uint64_t *__restrict_
     return lo;
 }
 
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t n) {
+    // gfx950 dispatches workgroup b to XCD b % 8; give each XCD one contiguous
+    // slice of the logical block range so its L2 sees neighbouring rows.
+    return (n % 8u == 0u) ? (b % 8u) * (n / 8u) + b / 8u : b;
+}
+
 // Packed structure-table entry: union index (32 bits) | tx | ty<<10 | tz<<20 (<<32).
 __host__ __device__ __forceinline__ uint64_t pack_ent(uint32_t u, int tx, int ty, int tz) {
     return (uint64_t)u | ((uint64_t)(tx | (ty << 10) | (tz << 20)) << 32);
