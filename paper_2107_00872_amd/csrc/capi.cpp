@@ -354,6 +354,8 @@ int qs3_lattice_create_cells(qs3_ctx *ctx, int n_sub, int lx, int ly, int lz, in
     QS3_TRY(lat->d_jxy_h.alloc(ctx, sizeof(double) * ne));
     QS3_TRY(lat->d_jz_h.alloc(ctx, sizeof(double) * ne));
     QS3_TRY(lat->d_jxy_hf.alloc(ctx, sizeof(float) * ne));
+    QS3_TRY(lat->d_jp_h.alloc(ctx, sizeof(double) * 2 * ne));
+    QS3_TRY(lat->d_jp_hf.alloc(ctx, sizeof(float) * 2 * ne));
     QS3_TRY(lat->d_jz_hf.alloc(ctx, sizeof(float) * ne));
     QS3_TRY(lat->d_coords.alloc(ctx, sizeof(uint32_t) * N));
     QS3_TRY(lat->d_sqrt.alloc(ctx, sizeof(double) * (N + 1)));
@@ -363,6 +365,16 @@ int qs3_lattice_create_cells(qs3_ctx *ctx, int n_sub, int lx, int ly, int lz, in
         QS3_HIP(hipMemcpy(lat->d_jxy_h.ptr, lat->h_jxy_h.data(), sizeof(double) * lat->h_nbr.size(), hipMemcpyHostToDevice));
         QS3_HIP(hipMemcpy(lat->d_jz_h.ptr, lat->h_jz_h.data(), sizeof(double) * lat->h_nbr.size(), hipMemcpyHostToDevice));
         QS3_HIP(hipMemcpy(lat->d_jxy_hf.ptr, jxyf.data(), sizeof(float) * lat->h_nbr.size(), hipMemcpyHostToDevice));
+        std::vector<double> jp(2 * lat->h_nbr.size());
+        std::vector<float> jpf(2 * lat->h_nbr.size());
+        for (size_t e = 0; e < lat->h_nbr.size(); ++e) {
+            jp[2 * e] = lat->h_jxy_h[e];
+            jp[2 * e + 1] = lat->h_jz_h[e];
+            jpf[2 * e] = jxyf[e];
+            jpf[2 * e + 1] = jzf[e];
+        }
+        QS3_HIP(hipMemcpy(lat->d_jp_h.ptr, jp.data(), sizeof(double) * jp.size(), hipMemcpyHostToDevice));
+        QS3_HIP(hipMemcpy(lat->d_jp_hf.ptr, jpf.data(), sizeof(float) * jpf.size(), hipMemcpyHostToDevice));
         QS3_HIP(hipMemcpy(lat->d_jz_hf.ptr, jzf.data(), sizeof(float) * lat->h_nbr.size(), hipMemcpyHostToDevice));
     }
     QS3_HIP(hipMemcpy(lat->d_coords.ptr, coords.data(), sizeof(uint32_t) * N, hipMemcpyHostToDevice));

@@ -23,6 +23,8 @@ LatArgs lat_args(const qs3_lattice *lat) {
     L.jz_h = lat->d_jz_h.as<double>();
     L.jxy_hf = lat->d_jxy_hf.as<float>();
     L.jz_hf = lat->d_jz_hf.as<float>();
+    L.jp_h = lat->d_jp_h.as<double2>();
+    L.jp_hf = lat->d_jp_hf.as<float2>();
     L.n_edges = (int)lat->h_nbr.size();
     L.uniform = lat->uniform ? 1 : 0;
     L.u_jxy_h = lat->u_jxy_h;

@@ -27,7 +27,7 @@ static size_t lds_need(const qs3_lattice *lat, int K) {
 }
 
 // ------------------------------------------------------------------ U(1)
-template <typename RT, typename VT, typename OT, int ZM>
+template <typename RT, typename VT, typename OT, int ZM, int UM>
 static int launch_u1_z(qs3_sector *sec, const void *v, void *w, hipStream_t s) {
     qs3_lattice *lat = sec->lat;
     LatArgs L = lat_args(lat);
@@ -35,23 +35,29 @@ static int launch_u1_z(qs3_sector *sec, const void *v, void *w, hipStream_t s) {
     QS3_REQUIRE(sh <= 160 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
     uint64_t tiles = (sec->dim + 255) / 256;
     int grid = grid_for(lat->ctx, tiles);
-    hipLaunchKernelGGL((k_hv_u1<KI, RT, VT, OT, ZM>), dim3(grid), dim3(256), sh, s, L,
+    hipLaunchKernelGGL((k_hv_u1<KI, RT, VT, OT, ZM, UM>), dim3(grid), dim3(256), sh, s, L,
                        sec->bt->dev.as<RT>(), (RT)sec->dim, (const VT *)v, (OT *)w);
     QS3_HIP(hipGetLastError());
     return QS3_OK;
 }
 
-// the unrolled all-hops-in-flight row for uniform couplings on lattices where
-// every site has 2, 4 or 6 neighbours (chains, square and cubic lattices)
+// the unrolled all-hops-in-flight row on lattices where every site has 2, 4
+// or 6 neighbours (chains, square and cubic lattices, with any couplings)
 // while K * degree stays within the registers; the plain loop otherwise
 template <typename RT, typename VT, typename OT>
 static int launch_u1(qs3_sector *sec, const void *v, void *w, hipStream_t s) {
     const qs3_lattice *lat = sec->lat;
-    const int z = (lat->uniform && lat->regular) ? lat->max_degree : 0;
-    if (z == 2 && KI * 2 <= 24) return launch_u1_z<RT, VT, OT, 2>(sec, v, w, s);
-    if (z == 4 && KI * 4 <= 24) return launch_u1_z<RT, VT, OT, 4>(sec, v, w, s);
-    if (z == 6 && KI * 6 <= 24) return launch_u1_z<RT, VT, OT, 6>(sec, v, w, s);
-    return launch_u1_z<RT, VT, OT, 0>(sec, v, w, s);
+    const int z = lat->regular ? lat->max_degree : 0;
+    if (lat->uniform) {
+        if (z == 2 && KI * 2 <= 24) return launch_u1_z<RT, VT, OT, 2, 1>(sec, v, w, s);
+        if (z == 4 && KI * 4 <= 24) return launch_u1_z<RT, VT, OT, 4, 1>(sec, v, w, s);
+        if (z == 6 && KI * 6 <= 24) return launch_u1_z<RT, VT, OT, 6, 1>(sec, v, w, s);
+    } else {
+        if (z == 2 && KI * 2 <= 24) return launch_u1_z<RT, VT, OT, 2, 2>(sec, v, w, s);
+        if (z == 4 && KI * 4 <= 24) return launch_u1_z<RT, VT, OT, 4, 2>(sec, v, w, s);
+        if (z == 6 && KI * 6 <= 24) return launch_u1_z<RT, VT, OT, 6, 2>(sec, v, w, s);
+    }
+    return launch_u1_z<RT, VT, OT, 0, 0>(sec, v, w, s);
 }
 
 template <typename RT>
@@ -231,8 +237,8 @@ static int small_t(qs3_lattice *lat, const BinomTable *bt, qs3_batch *bat, const
     else A.L = lat_args(lat);
     const size_t sh = lds_need<RT>(lat, KI);
     QS3_REQUIRE(sh <= 64 * 1024, QS3_EINVAL, "lattice tables exceed LDS");
-    // fixed N_down on a regular lattice with one coupling: the unrolled row
-    const int z = (lat->uniform && lat->regular) ? lat->max_degree : 0;
+    // fixed N_down on a regular lattice: the unrolled row
+    const int z = lat->regular ? lat->max_degree : 0;
     if constexpr (!CPLX) {
         if (z == 2 && KI * 2 <= 24)
             hipLaunchKernelGGL((k_lanczos_small<KI, RT, CPLX, TABLE, 2>), dim3(1), dim3(1024), sh, s, S, A,

@@ -72,13 +72,17 @@ static size_t lds_bytes(const qs3_lattice *lat, int K) {
 // the Ising diagonal E_FM - sum over (down site, up neighbour) of Jz/2, and
 // Jxy/2 v[rank'] for every hop of a down spin to an up neighbour.
 //
-// ZM > 0 (uniform couplings, every site has exactly ZM neighbours, stored
-// contiguously from ZM * site): all K*ZM candidate hops are ranked first and
-// their gathers issued together (a slot that is no hop reads the row's own
-// element and is dropped by a select), so a row waits for one memory latency
-// instead of one per hop and carries no divergent branches.  ZM = 0: a plain
-// loop over each down spin's neighbours (any degree, any couplings).
-template <int K, typename RT, typename VT, int ZM>
+// ZM > 0 (every site has exactly ZM neighbours, stored contiguously from
+// ZM * site): all K*ZM candidate hops are ranked first and their gathers
+// issued together (a slot that is no hop reads the row's own element and is
+// dropped by a select), so a row waits for one memory latency instead of one
+// per hop and carries no divergent branches; site-dependent couplings come
+// with them, one (J_xy/2, J_z/2) pair per edge, and are summed in the plain
+// loop's order.  ZM = 0: a plain loop over each down spin's neighbours (any
+// degree, any couplings).
+// UM (with ZM > 0): 1 one coupling constant, 2 site-dependent couplings, 0
+// decided at run time from L.uniform.
+template <int K, typename RT, typename VT, int ZM, int UM = 0>
 __device__ __forceinline__ VT hv_row_u1(const LatArgs &L, const Binom<RT> &Bn, const int *ptr,
                                         const uint16_t *nbr, RT row, const VT *__restrict__ v) {
     int c[K > 0 ? K : 1];
@@ -100,11 +104,35 @@ __device__ __forceinline__ VT hv_row_u1(const LatArgs &L, const Binom<RT> &Bn, c
                 x[m * ZM + q] = v[up ? rp : row];
             }
         });
-        VT acc = 0;
+        if (UM == 1 || (UM == 0 && L.uniform)) {
+            VT acc = 0;
 #pragma unroll
-        for (int h = 0; h < NH; ++h) acc += ((okm >> h) & 1u) ? x[h] : (VT)0;
-        const VT diag = (VT)L.ez4 - (VT)L.u_jz_h * (VT)__popcll(okm);
-        return diag * v[row] + (VT)L.u_jxy_h * acc;
+            for (int h = 0; h < NH; ++h) acc += ((okm >> h) & 1u) ? x[h] : (VT)0;
+            const VT diag = (VT)L.ez4 - (VT)L.u_jz_h * (VT)__popcll(okm);
+            return diag * v[row] + (VT)L.u_jxy_h * acc;
+        }
+        VT acc = 0, dz = 0;
+        StaticFor<0, K>::run([&](auto mc) {
+            constexpr int m = decltype(mc)::value;
+            const int e0 = c[m] * ZM;
+#pragma unroll
+            for (int q = 0; q < ZM; ++q) {
+                const bool up = (okm >> (m * ZM + q)) & 1u;
+                VT jx, jzv;
+                if constexpr (sizeof(VT) == 8) {
+                    const double2 jp = L.jp_h[e0 + q];
+                    jx = (VT)jp.x;
+                    jzv = (VT)jp.y;
+                } else {
+                    const float2 jp = L.jp_hf[e0 + q];
+                    jx = (VT)jp.x;
+                    jzv = (VT)jp.y;
+                }
+                acc = up ? acc + jx * x[m * ZM + q] : acc;
+                dz = up ? dz + jzv : dz;
+            }
+        });
+        return ((VT)L.ez4 - dz) * v[row] + acc;
     }
     const bool UNIF = L.uniform != 0;
     VT acc = 0, dz = 0;
@@ -141,7 +169,7 @@ __device__ __forceinline__ VT hv_row_u1(const LatArgs &L, const Binom<RT> &Bn, c
     return diag * v[row] + off;
 }
 
-template <int K, typename RT, typename VT, typename OT, int ZM>
+template <int K, typename RT, typename VT, typename OT, int ZM, int UM>
 __global__ __launch_bounds__(256) void k_hv_u1(LatArgs L, const RT *__restrict__ binom_g, RT D,
                                                const VT *__restrict__ v, OT *__restrict__ w) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -157,7 +185,7 @@ __global__ __launch_bounds__(256) void k_hv_u1(LatArgs L, const RT *__restrict__
     for (uint64_t tile = t0; tile < t1; ++tile) {
         const uint64_t row64 = tile * 256 + threadIdx.x;
         if (row64 >= (uint64_t)D) break;
-        w[row64] = (OT)hv_row_u1<K, RT, VT, ZM>(L, Bn, ptr, nbr, (RT)row64, v);
+        w[row64] = (OT)hv_row_u1<K, RT, VT, ZM, UM>(L, Bn, ptr, nbr, (RT)row64, v);
     }
 }
 

@@ -143,7 +143,7 @@ struct qs3_lattice {
     bool uniform = false;
     double u_jxy_h = 0, u_jz_h = 0;
     double ez4 = 0;  // sum_b Jz_b / 4
-    qs3::DevBuf d_ptr, d_nbr, d_jxy_h, d_jz_h, d_jxy_hf, d_jz_hf, d_coords, d_sqrt;
+    qs3::DevBuf d_ptr, d_nbr, d_jxy_h, d_jz_h, d_jxy_hf, d_jz_hf, d_jp_h, d_jp_hf, d_coords, d_sqrt;
     std::map<int, std::shared_ptr<qs3::BinomTable>> binoms;
     std::map<int, std::shared_ptr<qs3::KStructure>> kstructs;
     std::mutex mu;
@@ -162,6 +162,8 @@ struct LatArgs {
     const uint16_t *nbr;
     const double *jxy_h, *jz_h;
     const float *jxy_hf, *jz_hf;
+    const double2 *jp_h;  // per edge (J_xy/2, J_z/2): one load for both
+    const float2 *jp_hf;
     int n_edges;
     int uniform;
     double u_jxy_h, u_jz_h, ez4;
