@@ -134,11 +134,16 @@ static int pm_gram(qs3_sector *sec, const double *phi, int npairs, const int32_t
     for (int a = 0; a < nt; ++a)
         for (int b = a; b < nt; ++b) tiles.push_back(make_int2(a, b));
     const int ntp = (int)tiles.size();
-    const int max_chunks = std::max(1, 2048 / ntp);
-    DevBuf U, G, P, T;
+    // about four blocks per CU for the tile kernel; the chunk partials are
+    // summed in order in groups of GS chunks, then the group sums
+    const int max_chunks = std::max(1, 4 * ctx->n_cu / ntp);
+    constexpr int GS = 16;
+    const int max_groups = (max_chunks + GS - 1) / GS;
+    DevBuf U, G, P, P2, T;
     QS3_TRY(U.alloc(ctx, sizeof(double) * nc * N));
     QS3_TRY(G.alloc(ctx, sizeof(double) * (size_t)N * N));
     QS3_TRY(P.alloc(ctx, sizeof(double) * 4096 * (size_t)ntp * max_chunks));
+    QS3_TRY(P2.alloc(ctx, sizeof(double) * 4096 * (size_t)ntp * max_groups));
     QS3_TRY(T.alloc(ctx, sizeof(int2) * (size_t)ntp));
     QS3_HIP(hipMemcpyAsync(T.ptr, tiles.data(), sizeof(int2) * ntp, hipMemcpyHostToDevice, s));
     std::vector<double> acc((size_t)N * N, 0.0), hG((size_t)N * N);
@@ -154,8 +159,13 @@ static int pm_gram(qs3_sector *sec, const double *phi, int npairs, const int32_t
         hipLaunchKernelGGL(k_gram_tiles<64>, dim3(nchunk, ntp), dim3(256), 0, s, U.as<double>(), m, N, rc,
                            T.as<int2>(), ntp, P.as<double>());
         QS3_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_gram_reduce<64>, dim3((unsigned)(((uint64_t)ntp * 4096 + 255) / 256)), dim3(256), 0, s,
-                           P.as<double>(), nchunk, T.as<int2>(), ntp, N, G.as<double>());
+        const unsigned eb = (unsigned)(((uint64_t)ntp * 4096 + 255) / 256);
+        const int ngroup = (nchunk + GS - 1) / GS;
+        hipLaunchKernelGGL(k_gram_group<64>, dim3(eb, ngroup), dim3(256), 0, s, P.as<double>(), nchunk, ntp, GS,
+                           P2.as<double>());
+        QS3_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_gram_reduce<64>, dim3(eb), dim3(256), 0, s, P2.as<double>(), ngroup, T.as<int2>(), ntp, N,
+                           G.as<double>());
         QS3_HIP(hipGetLastError());
         QS3_HIP(hipMemcpyAsync(hG.data(), G.ptr, sizeof(double) * hG.size(), hipMemcpyDeviceToHost, s));
         QS3_HIP(hipStreamSynchronize(s));

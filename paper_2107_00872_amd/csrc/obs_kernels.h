@@ -165,25 +165,32 @@ __global__ __launch_bounds__(256) void k_pm_rows(int N, const RT *__restrict__ b
 
 // Gram matrix of the factor above, split over row chunks: block (c, t) takes
 // rows [c * rc, (c + 1) * rc) of U (nc x N, column major) and the 64 x 64 tile
-// pair t = (ti <= tj) of G = U^T U, 16 x 16 threads with 4 x 4 outputs each,
-// staging 16 rows of both column panels in LDS per pass.
+// pair t = (ti <= tj) of G = U^T U on the matrix cores: 16-row panels of both
+// column blocks are staged in LDS, and each of the four wavefronts forms one
+// 32 x 32 quadrant as 2 x 2 blocks of v_mfma_f64_16x16x4 (A: lane l holds
+// A[l % 16][l / 16], B: lane l holds B[l / 16][l % 16], D: element r of lane l
+// is D[4 r + l / 16][l % 16]), four k-steps of 4 per panel.
 // part[((c * ntp + t) * 64 + i) * 64 + j] = the chunk's sum for G[64 ti + i][64 tj + j].
 template <int TS>
 __global__ __launch_bounds__(256) void k_gram_tiles(const double *__restrict__ U, uint64_t nc, int N, uint64_t rc,
                                                     const int2 *__restrict__ tiles, int ntp,
                                                     double *__restrict__ part) {
-    static_assert(TS == 64, "one thread per 4 x 4 outputs of a 64 x 64 tile");
-    __shared__ double As[16][64], Bs[16][64];
+    static_assert(TS == 64, "four wavefronts of 32 x 32 outputs per 64 x 64 tile");
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    constexpr int LD = 64 + 4;  // padded panel rows
+    __shared__ double As[16][LD], Bs[16][LD];
     const int2 tp = tiles[blockIdx.y];
     const int i0 = tp.x * 64, j0 = tp.y * 64;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
     const uint64_t r0 = (uint64_t)blockIdx.x * rc;
     const uint64_t r1 = r0 + rc < nc ? r0 + rc : nc;
-    double acc[4][4];
+    d4 acc[2][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
     for (uint64_t k0 = r0; k0 < r1; k0 += 16) {
         // 2 x 16 x 64 loads by 256 threads: k fastest, so 16 consecutive rows
         // of one column are contiguous
@@ -198,29 +205,48 @@ __global__ __launch_bounds__(256) void k_gram_tiles(const double *__restrict__ U
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            double a[4], b[4];
+        for (int kk = 0; kk < 16; kk += 4) {
+            double a[2], b[2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = As[k][ty * 4 + q];
-                b[q] = Bs[k][tx * 4 + q];
+            for (int q = 0; q < 2; ++q) {
+                a[q] = As[kk + lk][wi + q * 16 + li];
+                b[q] = Bs[kk + lk][wj + q * 16 + li];
             }
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
+            for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+                for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
         }
         __syncthreads();
     }
     double *out = part + ((size_t)blockIdx.x * ntp + blockIdx.y) * 4096;
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) out[(ty * 4 + x) * 64 + tx * 4 + y] = acc[x][y];
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                out[(wi + x * 16 + 4 * r + lk) * 64 + wj + y * 16 + li] = acc[x][y][r];
 }
 
 // G[i + j N] (and G[j + i N]) = sum over the chunks, in chunk order, of the
 // tile partials: one thread per element of every tile pair.
+// First stage of the ordered sum over chunks: group g of gsz consecutive
+// chunks, one thread per element of every tile pair, summed in chunk order
+// into part2[(g * ntp + t) * 4096 + w] (the layout of the chunk partials).
+template <int TS>
+__global__ __launch_bounds__(256) void k_gram_group(const double *__restrict__ part, int nchunk, int ntp, int gsz,
+                                                    double *__restrict__ part2) {
+    static_assert(TS == 64, "64 x 64 tiles");
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (uint64_t)ntp * 4096) return;
+    const int g = blockIdx.y;
+    const int c0 = g * gsz, c1 = c0 + gsz < nchunk ? c0 + gsz : nchunk;
+    double s = 0.0;
+    for (int c = c0; c < c1; ++c) s += part[(size_t)c * ntp * 4096 + e];
+    part2[(size_t)g * ntp * 4096 + e] = s;
+}
+
 template <int TS>
 __global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ part, int nchunk,
                                                      const int2 *__restrict__ tiles, int ntp, int N,
