@@ -66,11 +66,15 @@ __device__ __forceinline__ void cdot_acc(double2 x, double2 y, double &sr, doubl
 // ------------------------------------------------------------------ kernels
 // The three-term part of a Lanczos step, applied on the fly (never stored):
 // Y - alpha_b P0 - beta_b P1 per column, in the order a separate update pass
-// would use.  P0 == null: Y unchanged; P1 == null: no beta term.
+// would use.  P0 == null: Y unchanged; P1 == null: no beta term.  i0 / i1:
+// the slot indices of P0 / P1 among the basis vectors X_j of the same pass
+// (-1 if they are not among them), so that a kernel holding P0 and P1 in
+// registers does not read those slots a second time.
 struct ThreeTerm {
     const double *P0 = nullptr, *P1 = nullptr;
     const double2 *alpha = nullptr;
     const double *beta = nullptr;
+    int i0 = -1, i1 = -1;
 };
 
 __device__ __forceinline__ double three_term(double w, uint64_t e, const ThreeTerm &f, double a, double be) {
@@ -84,6 +88,22 @@ __device__ __forceinline__ double2 three_term(double2 w, uint64_t e, const Three
     w.y -= a * p0.y;
     if (f.P1) {
         const double2 p1 = ((const double2 *)f.P1)[e];
+        w.x -= be * p1.x;
+        w.y -= be * p1.y;
+    }
+    return w;
+}
+
+// The three-term part on values already loaded (the arithmetic of three_term).
+__device__ __forceinline__ double sub_three(double w, double p0, double p1, bool has1, double a, double be) {
+    w -= a * p0;
+    if (has1) w -= be * p1;
+    return w;
+}
+__device__ __forceinline__ double2 sub_three(double2 w, double2 p0, double2 p1, bool has1, double a, double be) {
+    w.x -= a * p0.x;
+    w.y -= a * p0.y;
+    if (has1) {
         w.x -= be * p1.x;
         w.y -= be * p1.y;
     }
@@ -169,6 +189,85 @@ __global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__res
     }
 }
 
+// The same multi-dot for many outputs with Y' read from memory once per G *
+// JPL outputs instead of once per 4: G thread groups cover the same (row,
+// column) elements, group gi taking outputs j0 + gi * JPL .. + JPL - 1.
+// With TC * G <= 64 the groups sit in one wavefront, so their loads of Y, P0
+// and P1 are the same addresses in the same instructions (one request per
+// cache line); with TC = 64 they are the waves of the block.  The slots that
+// are P0 or P1 come from the registers that formed Y'.  Threads are (column
+// c < TC, group gi < G, row lane rr < TR) with c fastest; each thread sums
+// its rows in row order, then a fixed tree over rr.  Partials as in
+// k_multidot.
+template <bool CPLX, int G, int JPL>
+__global__ __launch_bounds__(256) void k_multidot_g(RedGeom g, const double *__restrict__ X,
+                                                    uint64_t stride, int J, int selfdot,
+                                                    const double *__restrict__ Y, ThreeTerm f,
+                                                    const uint8_t *__restrict__ mask,
+                                                    double2 *__restrict__ partial) {
+    using T = typename Elem<CPLX>::T;
+    const int c = threadIdx.x % g.TC, gi = (threadIdx.x / g.TC) % G, rr = threadIdx.x / (g.TC * G);
+    const int b = blockIdx.y * g.TC + c;
+    const uint64_t r0 = (uint64_t)blockIdx.x * g.RC;
+    const uint64_t r1 = min(g.n, r0 + g.RC);
+    const int JO = J + selfdot;
+    const bool on = b < g.B && (!mask || mask[b]);
+    const double fa = (on && f.P0) ? f.alpha[b].x : 0.0;
+    const double fb = (on && f.P0 && f.P1) ? f.beta[b] : 0.0;
+    __shared__ double2 red[256][JPL];
+    const T *Yt = (const T *)Y;
+    for (int j0 = blockIdx.z * G * JPL; j0 < JO; j0 += G * JPL * gridDim.z) {
+        const int jb = j0 + gi * JPL;  // this group's first output
+        double sr[JPL], si[JPL];
+#pragma unroll
+        for (int q = 0; q < JPL; ++q) sr[q] = si[q] = 0.0;
+        if (on) {
+            for (uint64_t r = r0 + rr; r < r1; r += (uint64_t)g.TR) {
+                const uint64_t e = r * g.B + b;
+                T y = Yt[e], p0{}, p1{};
+                if (f.P0) {
+                    p0 = ((const T *)f.P0)[e];
+                    if (f.P1) p1 = ((const T *)f.P1)[e];
+                    y = sub_three(y, p0, p1, f.P1 != nullptr, fa, fb);
+                }
+                T xv[JPL];
+#pragma unroll
+                for (int q = 0; q < JPL; ++q) {
+                    const int jj = jb + q;
+                    if (jj == f.i0) xv[q] = p0;
+                    else if (jj == f.i1) xv[q] = p1;
+                    else if (jj < J) xv[q] = ((const T *)(X + (size_t)jj * stride))[e];
+                    else xv[q] = y;  // the self-dot (jj == J) or unused
+                }
+#pragma unroll
+                for (int q = 0; q < JPL; ++q) {
+                    const int jj = jb + q;
+                    if (jj < J || (jj == J && selfdot)) cdot_acc(xv[q], y, sr[q], si[q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < JPL; ++q) red[threadIdx.x][q] = make_double2(sr[q], si[q]);
+        __syncthreads();
+        for (int s2 = g.TR / 2; s2 > 0; s2 >>= 1) {
+            if (rr < s2) {
+#pragma unroll
+                for (int q = 0; q < JPL; ++q) {
+                    const double2 a = red[threadIdx.x][q], o = red[threadIdx.x + s2 * g.TC * G][q];
+                    red[threadIdx.x][q] = make_double2(a.x + o.x, a.y + o.y);
+                }
+            }
+            __syncthreads();
+        }
+        if (rr == 0 && b < g.B) {
+#pragma unroll
+            for (int q = 0; q < JPL; ++q)
+                if (jb + q < JO) partial[((size_t)blockIdx.x * JO + jb + q) * g.B + b] = red[threadIdx.x][q];
+        }
+        __syncthreads();
+    }
+}
+
 // W := W' - sum_{j<J} X_j h[j * B + b] on the columns with mask[b] != 0 (all
 // when mask is null), W' = W after the three-term part f, and
 // partial[chunk * B + b] = sum over the chunk's rows of |W|^2 after the
@@ -192,17 +291,43 @@ __global__ __launch_bounds__(256) void k_cgs_update_norm(RedGeom g, double *__re
         for (uint64_t r = r0 + tr; CPLX && r < r1; r += 2 * (uint64_t)g.TR) {
             const uint64_t e = r * g.B + b, e2 = (r + g.TR) * g.B + b;
             const bool two = r + g.TR < r1;
+            const double2 z2 = make_double2(0.0, 0.0);
             double2 w = ((double2 *)W)[e];
-            double2 w2 = two ? ((double2 *)W)[e2] : make_double2(0.0, 0.0);
+            double2 w2 = two ? ((double2 *)W)[e2] : z2;
+            double2 p0 = z2, p0b = z2, p1 = z2, p1b = z2;
             if (f.P0) {
-                w = three_term(w, e, f, fa, fb);
-                if (two) w2 = three_term(w2, e2, f, fa, fb);
+                p0 = ((const double2 *)f.P0)[e];
+                if (two) p0b = ((const double2 *)f.P0)[e2];
+                if (f.P1) {
+                    p1 = ((const double2 *)f.P1)[e];
+                    if (two) p1b = ((const double2 *)f.P1)[e2];
+                }
+                // the three-term part, in the order of three_term()
+                w.x -= fa * p0.x;
+                w.y -= fa * p0.y;
+                w2.x -= fa * p0b.x;
+                w2.y -= fa * p0b.y;
+                if (f.P1) {
+                    w.x -= fb * p1.x;
+                    w.y -= fb * p1.y;
+                    w2.x -= fb * p1b.x;
+                    w2.y -= fb * p1b.y;
+                }
             }
             for (int jj = 0; jj < J; ++jj) {
                 const double2 *xj = (const double2 *)(X + (size_t)jj * stride);
                 const double2 c = h[(size_t)jj * g.B + b];
-                const double2 x = xj[e];
-                const double2 x2 = two ? xj[e2] : make_double2(0.0, 0.0);
+                double2 x, x2;
+                if (jj == f.i0) {
+                    x = p0;
+                    x2 = p0b;
+                } else if (jj == f.i1) {
+                    x = p1;
+                    x2 = p1b;
+                } else {
+                    x = xj[e];
+                    x2 = two ? xj[e2] : z2;
+                }
                 w.x -= x.x * c.x - x.y * c.y;
                 w.y -= x.x * c.y + x.y * c.x;
                 w2.x -= x2.x * c.x - x2.y * c.y;
@@ -219,15 +344,37 @@ __global__ __launch_bounds__(256) void k_cgs_update_norm(RedGeom g, double *__re
             const uint64_t e = r * g.B + b, e2 = (r + g.TR) * g.B + b;
             const bool two = r + g.TR < r1;
             double w = W[e], w2 = two ? W[e2] : 0.0;
+            double p0 = 0.0, p0b = 0.0, p1 = 0.0, p1b = 0.0;
             if (f.P0) {
-                w = three_term(w, e, f, fa, fb);
-                if (two) w2 = three_term(w2, e2, f, fa, fb);
+                p0 = f.P0[e];
+                if (two) p0b = f.P0[e2];
+                if (f.P1) {
+                    p1 = f.P1[e];
+                    if (two) p1b = f.P1[e2];
+                }
+                w -= fa * p0;
+                w2 -= fa * p0b;
+                if (f.P1) {
+                    w -= fb * p1;
+                    w2 -= fb * p1b;
+                }
             }
             for (int jj = 0; jj < J; ++jj) {
                 const double c = h[(size_t)jj * g.B + b].x;
                 const double *xj = X + (size_t)jj * stride;
-                w -= xj[e] * c;
-                if (two) w2 -= xj[e2] * c;
+                double x, x2;
+                if (jj == f.i0) {
+                    x = p0;
+                    x2 = p0b;
+                } else if (jj == f.i1) {
+                    x = p1;
+                    x2 = p1b;
+                } else {
+                    x = xj[e];
+                    x2 = two ? xj[e2] : 0.0;
+                }
+                w -= x * c;
+                if (two) w2 -= x2 * c;
             }
             W[e] = w;
             acc += w * w;
@@ -842,24 +989,71 @@ static RedGeom dot_geom(const RedGeom &rg, int JO) {
     return g;
 }
 
+// Geometry of k_multidot_g with G groups of JPL outputs: TC columns (a power
+// of two) x G groups x TR row lanes per block, about 2048 blocks, and chunks
+// no shorter than the engine's own (so the chunk count fits its partial
+// buffer).  in_lanes: TC * G <= 64, so the groups share each wavefront's
+// loads of Y, P0 and P1; otherwise TC <= 64 and the groups are the waves of
+// a block, which read the same lines within a short time (through L1/L2),
+// with longer contiguous runs per vector.
+static RedGeom dot_geom_g(const RedGeom &rg, int JO, int G, int JPL, bool in_lanes) {
+    RedGeom g = rg;
+    g.TC = 1;
+    while (g.TC < rg.B && g.TC < 64 && (!in_lanes || g.TC * G < 64)) g.TC <<= 1;
+    g.TR = 256 / (g.TC * G);
+    g.ncoltile = (rg.B + g.TC - 1) / g.TC;
+    const int nz = (JO + G * JPL - 1) / (G * JPL);
+    const uint64_t want = std::max<uint64_t>(1, (2048 + (uint64_t)g.ncoltile * nz - 1) / ((uint64_t)g.ncoltile * nz));
+    uint64_t rc = std::max<uint64_t>((uint64_t)g.TR, (g.n + want - 1) / want);
+    rc = std::max<uint64_t>(rc, rg.RC);
+    rc = (rc + g.TR - 1) / g.TR * g.TR;
+    g.RC = rc;
+    g.nchunk = (int)std::max<uint64_t>(1, (g.n + rc - 1) / rc);
+    return g;
+}
+
 template <bool CPLX>
-static void launch_multidot(const RedGeom &g, hipStream_t st, const double *X, uint64_t stride, int J,
-                            int selfdot, const double *Y, const ThreeTerm &f, const uint8_t *mask,
-                            double2 *partial) {
+static RedGeom launch_multidot(const RedGeom &rg, hipStream_t st, const double *X, uint64_t stride, int J,
+                               int selfdot, const double *Y, const ThreeTerm &f, const uint8_t *mask,
+                               double2 *partial) {
     const int JO = J + selfdot;
-    dim3 grid(g.nchunk, g.ncoltile, (JO + 3) / 4);
-    hipLaunchKernelGGL((k_multidot<CPLX, 4>), grid, dim3(256), 0, st, g, X, stride, J, selfdot, Y, f, mask,
-                       partial);
+    constexpr int JPL = 8;
+    // Few outputs, or vectors small enough for the caches to serve the
+    // per-group re-reads of Y: groups of 4 outputs, each block group
+    // re-reading Y (more blocks for short vectors).  Vectors beyond the
+    // last-level cache (256 MB): the groups share loads inside a
+    // wavefront.  In between: the groups are the waves of a block.
+    const uint64_t elems = rg.n * (uint64_t)rg.B;
+    if (JO <= 4 || elems < (1ull << 20)) {
+        const RedGeom g = dot_geom(rg, JO);
+        dim3 grid(g.nchunk, g.ncoltile, (JO + 3) / 4);
+        hipLaunchKernelGGL((k_multidot<CPLX, 4>), grid, dim3(256), 0, st, g, X, stride, J, selfdot, Y, f, mask,
+                           partial);
+        return g;
+    }
+    const int G = JO <= JPL ? 1 : (JO <= 2 * JPL ? 2 : 4);
+    const bool in_lanes = elems * (CPLX ? 16 : 8) > (256ull << 20);
+    const RedGeom g = dot_geom_g(rg, JO, G, JPL, in_lanes);
+    dim3 grid(g.nchunk, g.ncoltile, (JO + G * JPL - 1) / (G * JPL));
+    if (G == 1)
+        hipLaunchKernelGGL((k_multidot_g<CPLX, 1, JPL>), grid, dim3(256), 0, st, g, X, stride, J, selfdot, Y, f,
+                           mask, partial);
+    else if (G == 2)
+        hipLaunchKernelGGL((k_multidot_g<CPLX, 2, JPL>), grid, dim3(256), 0, st, g, X, stride, J, selfdot, Y, f,
+                           mask, partial);
+    else
+        hipLaunchKernelGGL((k_multidot_g<CPLX, 4, JPL>), grid, dim3(256), 0, st, g, X, stride, J, selfdot, Y, f,
+                           mask, partial);
+    return g;
 }
 
 int Engine::multidot(const double *X, int J, const double *Y, double2 *out, int selfdot,
                      const uint8_t *mask, const ThreeTerm *f, double *re_out) {
     const ThreeTerm none{};
-    const RedGeom g = dot_geom(rg, J + selfdot);
-    if (cplx)
-        launch_multidot<true>(g, st, X, stride, J, selfdot, Y, f ? *f : none, mask, partial.as<double2>());
-    else
-        launch_multidot<false>(g, st, X, stride, J, selfdot, Y, f ? *f : none, mask, partial.as<double2>());
+    const RedGeom g = cplx ? launch_multidot<true>(rg, st, X, stride, J, selfdot, Y, f ? *f : none, mask,
+                                                   partial.as<double2>())
+                           : launch_multidot<false>(rg, st, X, stride, J, selfdot, Y, f ? *f : none, mask,
+                                                    partial.as<double2>());
     QS3_HIP(hipGetLastError());
     const int JB = (J + selfdot) * B;
     hipLaunchKernelGGL(k_reduce_chunks, dim3((JB + 3) / 4), dim3(256), 0, st, partial.as<double2>(),
@@ -912,6 +1106,8 @@ int Engine::step(int x, int prev) {
         f.P1 = prev >= 0 ? slot(prev) : nullptr;
         f.alpha = alpha.as<double2>();
         f.beta = betap;
+        f.i0 = x;  // P0 and P1 are slots x and prev of the basis the passes read
+        f.i1 = prev;
         QS3_TRY(multidot(slot(0), x + 1, W.as<double>(), h, 1, colmask, &f));
         uint8_t *flag = act.as<uint8_t>() + 8 + B;
         // the norm's reduction also sets the second-pass flags

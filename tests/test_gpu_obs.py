@@ -231,11 +231,16 @@ def test_dsf_small_vs_oracle(qs3, ctx):
 
 def test_dsf_partial_reorthogonalisation(qs3, ctx):
     """S^-(q, omega) on the 10x10 square from the N_down = 2 ground state, 150
-    levels for all 100 q: partial reorthogonalisation gives the same weights
-    and a spectrum within 5e-5 of its maximum of the fully reorthogonalised one
-    (measured 8e-6 at eta = 0.05; the coefficients themselves differ once Ritz
-    values have converged, semi-orthogonality keeps the Ritz values, not the
-    basis, at working accuracy)."""
+    levels for all 100 q: partial reorthogonalisation gives the same weights,
+    the same Lanczos coefficients to 1e-10 over the first 40 levels (q != 0;
+    at q = 0 the start vector is an eigenvector and the recurrence stops after
+    one level), and a spectrum within 2e-4 of its maximum of the fully
+    reorthogonalised one.  The late coefficients are fixed only to rounding:
+    semi-orthogonality keeps the Ritz values, not the basis, at working
+    accuracy, and even two fully reorthogonalised runs whose dot products sum
+    in a different order agree to 1e-13 up to about level 85 and then drift
+    apart exponentially, which moves S by 3e-5 of its maximum (partial against
+    full: 4.6e-5 and 5.6e-5 with those two summation orders)."""
     lat = wl.square(10)
     L = qs3.Lattice.of(ctx, lat)
     ks = wl.all_momenta(lat)
@@ -243,10 +248,12 @@ def test_dsf_partial_reorthogonalisation(qs3, ctx):
     X = torch.empty(gs.dim, dtype=torch.complex128, device="cuda")
     e0 = gs.eigs(nev=1, evecs=X, seed=3).evals[0]
     omega = np.linspace(0, 8, 801)
-    Sf, _, _, wf = gs.dsf(X, e0, ks, omega, steps=150, eta=0.05, field=4.0, reorth=qs3.REORTH_FULL)
-    Sp, _, _, wp = gs.dsf(X, e0, ks, omega, steps=150, eta=0.05, field=4.0, reorth=qs3.REORTH_PARTIAL)
+    Sf, af, bf, wf = gs.dsf(X, e0, ks, omega, steps=150, eta=0.05, field=4.0, reorth=qs3.REORTH_FULL)
+    Sp, ap, bp, wp = gs.dsf(X, e0, ks, omega, steps=150, eta=0.05, field=4.0, reorth=qs3.REORTH_PARTIAL)
     assert np.abs(wp - wf).max() < 1e-13
-    assert np.abs(Sp - Sf).max() < 5e-5 * np.abs(Sf).max()
+    assert np.abs(ap[1:, :40] - af[1:, :40]).max() < 1e-10
+    assert np.abs(bp[1:, :39] - bf[1:, :39]).max() < 1e-10
+    assert np.abs(Sp - Sf).max() < 2e-4 * np.abs(Sf).max()
 
 
 SQ_CASES = [(wl.square(4), 2), (wl.chain(8), 3), (wl.hypercubic(4, 2, 1), 3), (wl.cube(3), 2), (wl.chain(6), 1)]
