@@ -153,6 +153,9 @@ def main():
     ap.add_argument("--no-one-at-a-time", action="store_true",
                     help="skip the one-sector-at-a-time comparison (shorter profiles)")
     ap.add_argument("--no-c2", action="store_true", help="skip the secondary 10x10 figures")
+    ap.add_argument("--krylov-only", action="store_true",
+                    help="only two restart cycles of the batched solve at full width (every sector "
+                         "iterating) and the calibration copy (counter profiles of the Krylov kernels)")
     ap.add_argument("--matvec-only", action="store_true",
                     help="only the batched H.v launches and the calibration copy (counter profiles)")
     ap.add_argument("--requests", type=int, default=0, help="c5: number of requests (default 200)")
@@ -201,6 +204,22 @@ def main():
 
     print(f"c3: {bat.rows} representatives x {bat.B} sectors, set-up {t_setup:.2f} s", file=sys.stderr,
           flush=True)
+    if args.krylov_only:
+        # two thick-restart cycles (at most one restart) of the float64 solve,
+        # twice: the first call also times the H.v schedules
+        for rep in range(2):
+            t0 = time.perf_counter()
+            ev, infos, rc = bat.eigs(nev=1, seed=1, stream=stream, max_restarts=1)
+            torch.cuda.synchronize()
+            print(f"two cycles: {time.perf_counter() - t0:.3f} s, {max(int(i.n_matvec) for i in infos)} steps",
+                  file=sys.stderr, flush=True)
+        cal_src = torch.empty(1 << 26, dtype=torch.float64, device="cuda")
+        cal_src.fill_(1.0)
+        cal_dst = torch.empty_like(cal_src)
+        cal_dst.copy_(cal_src)
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": "c3 Krylov cycles only"}))
+        return
     if args.matvec_only:
         args.steps = args.warmup = 0
     for w in range(args.warmup):
