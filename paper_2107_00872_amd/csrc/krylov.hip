@@ -1015,16 +1015,18 @@ static RedGeom dot_geom_g(const RedGeom &rg, int JO, int G, int JPL, bool in_lan
 template <bool CPLX>
 static RedGeom launch_multidot(const RedGeom &rg, hipStream_t st, const double *X, uint64_t stride, int J,
                                int selfdot, const double *Y, const ThreeTerm &f, const uint8_t *mask,
-                               double2 *partial) {
+                               double2 *partial, bool dense) {
     const int JO = J + selfdot;
     constexpr int JPL = 8;
-    // Few outputs, or vectors small enough for the caches to serve the
-    // per-group re-reads of Y: groups of 4 outputs, each block group
-    // re-reading Y (more blocks for short vectors).  Vectors beyond the
-    // last-level cache (256 MB): the groups share loads inside a
-    // wavefront.  In between: the groups are the waves of a block.
+    // Few outputs, vectors small enough for the caches to serve the
+    // per-group re-reads of Y, or a mask that may leave only a few columns
+    // (a second or partial Gram-Schmidt pass, where short row chunks keep
+    // the few active threads' loops short): groups of 4 outputs, each block
+    // group re-reading Y.  Otherwise vectors beyond the last-level cache
+    // (256 MB) share loads inside a wavefront, smaller ones across the
+    // waves of a block.
     const uint64_t elems = rg.n * (uint64_t)rg.B;
-    if (JO <= 4 || elems < (1ull << 20)) {
+    if (JO <= 4 || elems < (1ull << 20) || !dense) {
         const RedGeom g = dot_geom(rg, JO);
         dim3 grid(g.nchunk, g.ncoltile, (JO + 3) / 4);
         hipLaunchKernelGGL((k_multidot<CPLX, 4>), grid, dim3(256), 0, st, g, X, stride, J, selfdot, Y, f, mask,
@@ -1050,10 +1052,13 @@ static RedGeom launch_multidot(const RedGeom &rg, hipStream_t st, const double *
 int Engine::multidot(const double *X, int J, const double *Y, double2 *out, int selfdot,
                      const uint8_t *mask, const ThreeTerm *f, double *re_out) {
     const ThreeTerm none{};
+    // the first pass of a step (the one with the three-term part) takes
+    // every column still iterating
+    const bool dense = f != nullptr;
     const RedGeom g = cplx ? launch_multidot<true>(rg, st, X, stride, J, selfdot, Y, f ? *f : none, mask,
-                                                   partial.as<double2>())
+                                                   partial.as<double2>(), dense)
                            : launch_multidot<false>(rg, st, X, stride, J, selfdot, Y, f ? *f : none, mask,
-                                                    partial.as<double2>());
+                                                    partial.as<double2>(), dense);
     QS3_HIP(hipGetLastError());
     const int JB = (J + selfdot) * B;
     hipLaunchKernelGGL(k_reduce_chunks, dim3((JB + 3) / 4), dim3(256), 0, st, partial.as<double2>(),
