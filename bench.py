@@ -49,7 +49,7 @@ HBM_PEAK_GBS = 8000.0
 # that define that kernel: the profile's traffic holds while they are unchanged
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hv_batch_cube10_N3_1000k.md")
 KERNEL_SOURCES = ["paper_2107_00872_amd/csrc/hv_kernels.h", "paper_2107_00872_amd/csrc/qs3_device.h",
-                  "paper_2107_00872_amd/csrc/hv_inst.hip"]
+                  "paper_2107_00872_amd/csrc/hv_inst.hip", "paper_2107_00872_amd/csrc/qs3_hv.h"]
 GOLDEN = os.path.join(ROOT, "tests", "golden", "full_size_levels.json")
 
 
@@ -264,17 +264,22 @@ def main():
     del cal_src, cal_dst, v, w
     torch.cuda.empty_cache()
     nh = hops_per_sector(lat, K)
-    alg_bytes = 16.0 * (2 * bat.rows + nh) * bat.B
-    achieved = alg_bytes / t_mv / 1e9
+    # the product runs as `ngr` equal launches over `gw` sectors each (wide
+    # batches of long vectors go in groups of at most 256 sectors)
+    ngr, gw = bat.groups()
+    alg_bytes = 16.0 * (2 * bat.rows + nh) * gw
+    t_launch = t_mv / ngr
+    achieved = alg_bytes / t_launch / 1e9
     G, bpc = bat.schedule()
-    per = -(-bat.B // G)
+    per = -(-gw // G)
     bpl, npass = (per, 1) if per <= 8 else (8, -(-per // 8))
     bpl = 1 << (bpl - 1).bit_length()
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(),
                 "kernel": f"k_hv_batch<3,uint32,double,double,HOP_LISTS,{bpl},{npass}>",
-                "schedule": {"lanes_per_row": G, "blocks_per_cu": bpc},
-                "alg_bytes_per_launch": alg_bytes, "launch_s": t_mv}
+                "schedule": {"lanes_per_row": G, "blocks_per_cu": bpc, "launches_per_product": ngr,
+                             "sectors_per_launch": gw},
+                "alg_bytes_per_launch": alg_bytes, "launch_s": t_launch, "product_s": t_mv}
     # the single-sector product (one lane per row) on one of the sectors
     one = qs3.Sector(L, K, (3, 6, 0))
     v1 = torch.empty(one.dim, dtype=torch.complex128, device="cuda")

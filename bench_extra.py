@@ -508,7 +508,7 @@ def pg(args):
 # that define that kernel: the profile's traffic holds while they are unchanged
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hv_u1_square10x10_N4.md")
 KERNEL_SOURCES = ["paper_2107_00872_amd/csrc/hv_kernels.h", "paper_2107_00872_amd/csrc/qs3_device.h",
-                  "paper_2107_00872_amd/csrc/hv_inst.hip"]
+                  "paper_2107_00872_amd/csrc/hv_inst.hip", "paper_2107_00872_amd/csrc/qs3_hv.h"]
 
 
 def kernel_sources_digest():

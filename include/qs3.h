@@ -359,6 +359,12 @@ int qs3_batch_dims(const qs3_batch *bat, uint64_t *rows, uint64_t *dims);
  * qs3_ctx_set_schedule): lanes per representative row and blocks per CU; 0
  * before the first launch and for a batch of one sector (one lane per row). */
 int qs3_batch_schedule(const qs3_batch *bat, int *lanes_per_row, int *blocks_per_cu);
+/* How the batch's last batched H.v was split: `groups` consecutive launches
+ * over at most `sectors_per_group` sectors each (a wide batch of long
+ * vectors runs in groups of at most 256 sectors, whose share of v the caches
+ * serve better; every sector's sum is the same either way); 0 before the
+ * first launch.  Host outputs, either may be null. */
+int qs3_batch_groups(const qs3_batch *bat, int *groups, int *sectors_per_group);
 int qs3_batch_matvec(qs3_batch *bat, const void *v, void *w, int dtype, void *stream);
 /* Per-sector lowest levels (evals[b*nev + y]) and info[b]; every sector runs
  * its own Lanczos state inside the shared launches and stops updating when it

@@ -543,6 +543,13 @@ int qs3_batch_schedule(const qs3_batch *bat, int *lanes_per_row, int *blocks_per
     return QS3_OK;
 }
 
+int qs3_batch_groups(const qs3_batch *bat, int *groups, int *sectors_per_group) {
+    QS3_REQUIRE(bat, QS3_EINVAL, "batch is NULL");
+    if (groups) *groups = bat->last_groups;
+    if (sectors_per_group) *sectors_per_group = bat->last_group_width;
+    return QS3_OK;
+}
+
 int qs3_batch_matvec(qs3_batch *bat, const void *v, void *w, int dtype, void *stream) {
     QS3_REQUIRE(bat && v && w, QS3_EINVAL, "NULL argument");
     QS3_REQUIRE(v != w, QS3_EINVAL, "v and w must not alias");

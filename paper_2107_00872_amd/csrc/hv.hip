@@ -50,6 +50,7 @@ BatchArgs batch_args(qs3_batch *bat) {
     A.dir = bat->ks->dir.as<uint32_t>();
     A.dir_shift = bat->ks->dir_shift;
     A.B = bat->B;
+    A.ld = bat->B;
     A.G = 1;
     while (A.G < bat->B && A.G < 64) A.G <<= 1;
     A.kmul = bat->kmul.as<int32_t>();

@@ -266,6 +266,7 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
 
     const int G = A.G, B = A.B;
+    const uint64_t LD = (uint64_t)A.ld;
     const bool UNIF = A.L.uniform != 0;
     const int lane = threadIdx.x % G;
     const int slot = threadIdx.x / G;
@@ -366,12 +367,12 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                         const CT bc = (CT)__shfl(coef, q, G);
                         dz += (CT)__shfl(jzv, q, G);
                         const int tx = bt & 1023u, ty = (bt >> 10) & 1023u, tz = (bt >> 20) & 1023u;
-                        const C2 *vrow = v + (uint64_t)bu * B;
+                        const C2 *vrow = v + (uint64_t)bu * LD;
 #pragma unroll
                         for (int i = 0; i < BPL; ++i) {
                             if (!bval[i]) continue;
                             const int b = lane + (pass * BPL + i) * G;
-                            if (bnt >= 0 && !A.compat_nt[(size_t)bnt * B + b]) continue;
+                            if (bnt >= 0 && !A.compat_nt[(size_t)bnt * LD + b]) continue;
                             int P = kx[i] * tx + ky[i] * ty + kz[i] * tz;
                             const int qq = (int)((double)P * A.invM);
                             P -= qq * A.M;
@@ -415,13 +416,13 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                         for (int i = 0; i < BPL; ++i) {
                             const int b = lane + (pass * BPL + i) * G;
                             bool use = hok[r] && bval[i];
-                            if (use && hnt[r] >= 0) use = A.compat_nt[(size_t)hnt[r] * B + b] != 0;
+                            if (use && hnt[r] >= 0) use = A.compat_nt[(size_t)hnt[r] * LD + b] != 0;
                             int P = kx[i] * htx[r] + ky[i] * hty[r] + kz[i] * htz[r];
                             const int qq = (int)((double)P * A.invM);
                             P -= qq * A.M;
                             P += (P < 0) ? A.M : 0;
                             P -= (P >= A.M) ? A.M : 0;
-                            const uint64_t idx = use ? (uint64_t)hu[r] * B + b : 0;
+                            const uint64_t idx = use ? (uint64_t)hu[r] * LD + b : 0;
                             x[r][i] = v[idx];
                             Pi[r][i] = use ? P : 0;
                             if (!use) {
@@ -443,13 +444,13 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                 }
             }
             const CT diag = (CT)A.L.ez4 - dz;
-            O2 *wrow = w + u * B;
-            const C2 *vself = v + u * B;
+            O2 *wrow = w + u * LD;
+            const C2 *vself = v + u * LD;
 #pragma unroll
             for (int i = 0; i < BPL; ++i) {
                 if (!bval[i]) continue;
                 const int b = lane + (pass * BPL + i) * G;
-                const bool okr = ntu < 0 || A.compat_nt[(size_t)ntu * B + b];
+                const bool okr = ntu < 0 || A.compat_nt[(size_t)ntu * LD + b];
                 O2 o;
                 if (okr) {
                     C2 x = vself[b];

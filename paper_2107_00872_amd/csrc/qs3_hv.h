@@ -26,6 +26,7 @@ struct BatchArgs {
     const uint32_t *dir;
     int dir_shift;
     int B, G;
+    int ld;  // row stride of v, w and compat_nt in sectors (B, or the whole batch for a group of its sectors)
     const int32_t *kmul;  // 3*B: K_a * (M / L_a) mod M
     int M;
     double invM;

@@ -195,6 +195,7 @@ struct qs3_batch {
     // trivial stabiliser), 0 when it is not in the sector; empty otherwise
     qs3::DevBuf tP, gcls;
     int last_G = 0, last_bpc = 0;  // schedule of the last batched H.v launch
+    int last_groups = 0, last_group_width = 0;  // and its split into sector groups
     std::vector<uint8_t> h_compat_nt;
     std::vector<uint64_t> dims;   // per sector
     const uint8_t *active_dev = nullptr;  // device mask set by the solver while it applies H

@@ -99,6 +99,7 @@ SIGNATURES = [
     ("qs3_batch_destroy", ctypes.c_int, [P]),
     ("qs3_batch_dims", ctypes.c_int, [P, P, P]),
     ("qs3_batch_schedule", ctypes.c_int, [P, P, P]),
+    ("qs3_batch_groups", ctypes.c_int, [P, P, P]),
     ("qs3_batch_matvec", ctypes.c_int, [P, P, P, ctypes.c_int, P]),
     ("qs3_batch_eigs", ctypes.c_int, [P, P, P, P, P]),
     ("qs3_server_create", ctypes.c_int, [P, P, P]),
@@ -400,6 +401,12 @@ class Batch:
         """(lanes per row, blocks per CU) of the last batched H.v launch."""
         g, b = ctypes.c_int(), ctypes.c_int()
         check(lib().qs3_batch_schedule(self.h, ctypes.byref(g), ctypes.byref(b)))
+        return g.value, b.value
+
+    def groups(self):
+        """(launches, sectors per launch) of the last batched H.v."""
+        g, b = ctypes.c_int(), ctypes.c_int()
+        check(lib().qs3_batch_groups(self.h, ctypes.byref(g), ctypes.byref(b)))
         return g.value, b.value
 
     def matvec(self, v, w, stream=None):

@@ -275,6 +275,11 @@ static void check_momentum(qs3_ctx *ctx, hipStream_t s) {
     CHECK(qs3_batch_eigs(bat, &o, bev.data(), binfo.data(), s) == QS3_OK && all_finite(bev.data(), 36));
     int G = 0, bpc = 0;
     CHECK(qs3_batch_schedule(bat, &G, &bpc) == QS3_OK && G > 0);
+    {
+        int ng = -1, gw = -1;
+        CHECK(qs3_batch_groups(bat, &ng, &gw) == QS3_OK && ng >= 1 && gw >= 1);
+        CHECK(qs3_batch_groups(nullptr, &ng, &gw) == QS3_EINVAL);
+    }
     HIPOK(hipFree(bv));
     HIPOK(hipFree(bw));
     qs3_batch_destroy(bat);

@@ -236,6 +236,44 @@ def test_k_sector_large_hop_lists_vs_on_the_fly(qs3, ctx, ctx_fly):
     fly.close()
 
 
+def test_wide_batch_in_sector_groups(qs3, ctx):
+    """The 1000 momentum sectors of the 10^3 cube at N_down = 3 (a 2.66 GB
+    vector) run their batched H.v as four launches over 250 sectors each with
+    the whole batch's row stride.  Every float64 column must equal, bit for
+    bit, the same sector's column from a 64-sector batch that runs in one
+    launch: every schedule sums a sector's hops in hop order.  Float32 rows
+    agree within their rounding bound (instances of other widths may contract
+    the complex multiply-adds differently)."""
+    lat = wl.cube(10)
+    L = qs3.Lattice.of(ctx, lat)
+    ks = wl.all_momenta(lat)
+    pick = sorted(np.random.default_rng(11).choice(len(ks), 64, replace=False).tolist())
+    big = qs3.Batch(L, 3, ks)
+    small = qs3.Batch(L, 3, [ks[i] for i in pick])
+    assert big.rows == small.rows
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    v = torch.complex(torch.rand(big.rows, big.B, dtype=torch.float64, device="cuda", generator=gen) - 0.5,
+                      torch.rand(big.rows, big.B, dtype=torch.float64, device="cuda", generator=gen) - 0.5)
+    idx = torch.tensor(pick, device="cuda")
+    vs = v.index_select(1, idx).contiguous()
+    for dt in (torch.complex128, torch.complex64):
+        w = torch.empty(big.rows, big.B, dtype=dt, device="cuda")
+        ws = torch.empty(small.rows, small.B, dtype=dt, device="cuda")
+        big.matvec(v.to(dt), w)
+        assert big.groups() == (4, 250)
+        small.matvec(vs.to(dt), ws)
+        assert small.groups() == (1, 64)
+        if dt == torch.complex128:
+            assert torch.equal(w.index_select(1, idx), ws)
+        else:
+            d = (w.index_select(1, idx) - ws).abs().max().item()
+            assert math.isfinite(d)
+            assert d <= hv_tol32(lat, 0.75, 3), d
+        del w, ws
+    big.close()
+    small.close()
+
+
 @pytest.fixture(scope="module")
 def ctx_fly(qs3):
     """A context that never builds rank tables: every hop is resolved by
