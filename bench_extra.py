@@ -311,7 +311,7 @@ def thermal(args):
 def c5(args):
     import sys
     ctx = _ctx()
-    n = int(getattr(args, "requests", 0) or 40)
+    n = int(getattr(args, "requests", 0) or 200)
     probe = wl.serving_stream(n, seed=7, rate=1.0)
     # one-at-a-time service times (FP64, same requests)
     srv = qs3.Server(ctx, max_active=1)
