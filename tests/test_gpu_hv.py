@@ -236,17 +236,19 @@ def test_k_sector_large_hop_lists_vs_on_the_fly(qs3, ctx, ctx_fly):
     fly.close()
 
 
-def test_wide_batch_in_sector_groups(qs3, ctx):
-    """The 1000 momentum sectors of the 10^3 cube at N_down = 3 (a 2.66 GB
-    vector) run their batched H.v as four launches over 250 sectors each with
-    the whole batch's row stride.  Every float64 column must equal, bit for
-    bit, the same sector's column from a 64-sector batch that runs in one
+@pytest.mark.parametrize("nsec,split", [(1000, (4, 250)), (601, (3, 201))], ids=["1000-sectors", "601-ragged"])
+def test_wide_batch_in_sector_groups(qs3, ctx, nsec, split):
+    """The momentum sectors of the 10^3 cube at N_down = 3 (2.66 GB vectors
+    for all 1000 of them) run their batched H.v as launches over groups of at
+    most 256 sectors with the whole batch's row stride: 4 x 250 for 1000
+    sectors, 201 + 201 + 199 for 601.  Every float64 column must equal, bit
+    for bit, the same sector's column from a 64-sector batch that runs in one
     launch: every schedule sums a sector's hops in hop order.  Float32 rows
     agree within their rounding bound (instances of other widths may contract
     the complex multiply-adds differently)."""
     lat = wl.cube(10)
     L = qs3.Lattice.of(ctx, lat)
-    ks = wl.all_momenta(lat)
+    ks = wl.all_momenta(lat)[:nsec]
     pick = sorted(np.random.default_rng(11).choice(len(ks), 64, replace=False).tolist())
     big = qs3.Batch(L, 3, ks)
     small = qs3.Batch(L, 3, [ks[i] for i in pick])
@@ -260,7 +262,7 @@ def test_wide_batch_in_sector_groups(qs3, ctx):
         w = torch.empty(big.rows, big.B, dtype=dt, device="cuda")
         ws = torch.empty(small.rows, small.B, dtype=dt, device="cuda")
         big.matvec(v.to(dt), w)
-        assert big.groups() == (4, 250)
+        assert big.groups() == split
         small.matvec(vs.to(dt), ws)
         assert small.groups() == (1, 64)
         if dt == torch.complex128:
