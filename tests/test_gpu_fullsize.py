@@ -113,6 +113,25 @@ def test_c3_all_sectors_default_solver(qs3, ctx):
     bat.close()
 
 
+def test_c3_all_sectors_float32_products(qs3, ctx):
+    """The 1000-sector solve with float32 products (float64 recurrences; the
+    batched H.v in four float32 launches over 250 sectors): rounding v to
+    float32 perturbs H.v by at most about eps32 * ||H|| ||v||, so by Weyl's
+    inequality every level moves by at most about 6e-8 of the spectrum's
+    scale (|E| ~ 730 here, ||H|| <= 750); the stored oracle levels are met
+    within 2e-7 relative."""
+    g = GOLD["c3"]
+    lat = wl.cube(10)
+    L = qs3.Lattice.of(ctx, lat)
+    ks = wl.all_momenta(lat)
+    bat = qs3.Batch(L, 3, ks)
+    ev, infos, rc = bat.eigs(nev=1, seed=1, precision=qs3.PREC_F32MV)
+    assert rc == qs3.QS3_OK and all(i.converged for i in infos)
+    errs = {tuple(s["k"]): _rel(ev[ks.index(tuple(s["k"])), 0], s["levels"][0]) for s in g["sectors"]}
+    assert max(errs.values()) <= 2e-7, errs
+    bat.close()
+
+
 def test_c3_single_sectors_default_solver(qs3, ctx):
     """The plain one-sector path (one lane per row) on the stored sectors."""
     g = GOLD["c3"]
