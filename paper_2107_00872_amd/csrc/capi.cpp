@@ -19,6 +19,45 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 
 DevBuf::~DevBuf() { release(); }
 
+// pinned host buffers up to 16 MB are pooled, up to 64 MB in all
+static constexpr size_t PIN_POOL_MAX_BUF = 16u << 20, PIN_POOL_MAX = 64u << 20;
+
+int pinned_get(qs3_ctx *c, size_t bytes, void **p, size_t *cap) {
+    size_t k = std::max<size_t>(bytes, 1);
+    if (k <= PIN_POOL_MAX_BUF) {
+        size_t q = 4096;
+        while (q < k) q <<= 1;
+        k = q;
+        std::lock_guard<std::mutex> lk(c->pin_mu);
+        auto it = c->pin_pool.find(k);
+        if (it != c->pin_pool.end()) {
+            *p = it->second;
+            *cap = k;
+            c->pin_pool_bytes -= k;
+            c->pin_pool.erase(it);
+            return QS3_OK;
+        }
+    }
+    void *q = nullptr;
+    QS3_HIP(hipHostMalloc(&q, k, hipHostMallocDefault));
+    *p = q;
+    *cap = k;
+    return QS3_OK;
+}
+
+void pinned_put(qs3_ctx *c, void *p, size_t cap) {
+    if (!p) return;
+    if (cap <= PIN_POOL_MAX_BUF) {
+        std::lock_guard<std::mutex> lk(c->pin_mu);
+        if (c->pin_pool_bytes + cap <= PIN_POOL_MAX) {
+            c->pin_pool.emplace(cap, p);
+            c->pin_pool_bytes += cap;
+            return;
+        }
+    }
+    (void)hipHostFree(p);
+}
+
 int DevBuf::alloc(qs3_ctx *c, size_t n) {
     release();
     ctx = c;
@@ -214,6 +253,10 @@ int qs3_ctx_create(int device, uint64_t hbm_budget_bytes, qs3_ctx **out) {
     c->n_cu = prop.multiProcessorCount;
     *out = c;
     return QS3_OK;
+}
+
+qs3_ctx::~qs3_ctx() {
+    for (auto &e : pin_pool) (void)hipHostFree(e.second);
 }
 
 int qs3_ctx_destroy(qs3_ctx *ctx) {

@@ -1539,19 +1539,24 @@ int run_lanczos(Engine &E, const double *v0, int steps, std::vector<double> &a_o
 
 // ------------------------------------------------------------------ resumable solver
 template <typename T>
-static int pinned(T **p, size_t n) {
+static int pinned(qs3_ctx *c, T **p, size_t n, size_t *cap) {
     void *q = nullptr;
-    QS3_HIP(hipHostMalloc(&q, sizeof(T) * std::max<size_t>(n, 1), hipHostMallocDefault));
+    QS3_TRY(pinned_get(c, sizeof(T) * n, &q, cap));
     *p = (T *)q;
     return QS3_OK;
 }
 
 SolveRun::~SolveRun() {
     if (ev) (void)hipEventDestroy(ev);
-    if (hab) (void)hipHostFree(hab);
-    if (hC) (void)hipHostFree(hC);
-    if (hact) (void)hipHostFree(hact);
-    if (hidx) (void)hipHostFree(hidx);
+    // no copy through the host buffers may still be queued when they go
+    // back to the pool (an error can end a run mid-cycle)
+    if (pctx) {
+        (void)hipStreamSynchronize(root.st);
+        pinned_put(pctx, hab, cap_hab);
+        pinned_put(pctx, hC, cap_hC);
+        pinned_put(pctx, hact, cap_hact);
+        pinned_put(pctx, hidx, cap_hidx);
+    }
 }
 
 int SolveRun::slots_for(const qs3_eigs_opts &o) {
@@ -1566,10 +1571,11 @@ int SolveRun::init(qs3_ctx *ctx, Operator *op, const qs3_eigs_opts &opts, hipStr
     B = root.B;
     const int NX = o.alg == QS3_ALG_TRL ? o.nm : o.steps;
     const int NY = o.alg == QS3_ALG_TRL ? o.nk : o.nev;
-    QS3_TRY(pinned(&hab, 2 * (size_t)root.slots * B));
-    QS3_TRY(pinned(&hC, (size_t)B * NX * NY));
-    QS3_TRY(pinned(&hact, 2 * (size_t)B));
-    QS3_TRY(pinned(&hidx, (size_t)B));
+    pctx = ctx;
+    QS3_TRY(pinned(ctx, &hab, 2 * (size_t)root.slots * B, &cap_hab));
+    QS3_TRY(pinned(ctx, &hC, (size_t)B * NX * NY, &cap_hC));
+    QS3_TRY(pinned(ctx, &hact, 2 * (size_t)B, &cap_hact));
+    QS3_TRY(pinned(ctx, &hidx, (size_t)B, &cap_hidx));
     QS3_TRY(dC.alloc(ctx, sizeof(double) * (size_t)B * NX * NY));
     QS3_TRY(dact.alloc(ctx, 2 * (size_t)B));
     QS3_TRY(didx.alloc(ctx, sizeof(int32_t) * (size_t)B));

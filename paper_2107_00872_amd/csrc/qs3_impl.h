@@ -78,9 +78,26 @@ struct qs3_ctx {
     std::mutex blas_mu;    // held while a call is bound to the handle
     int use_graphs = 0;    // replay thick-restart cycles from captured graphs
     int autotune = 1;      // time the batched H.v's schedules once per width class
+    // small pinned host buffers kept for reuse (power-of-two capacities): a
+    // solve's host staging comes from here, not from hipHostMalloc and
+    // hipHostFree per solve (tens of microseconds each)
+    std::mutex pin_mu;
+    std::multimap<size_t, void *> pin_pool;
+    size_t pin_pool_bytes = 0;
+    qs3_ctx() = default;
+    qs3_ctx(const qs3_ctx &) = delete;
+    qs3_ctx &operator=(const qs3_ctx &) = delete;
+    ~qs3_ctx();
 };
 
 namespace qs3 {
+
+// A pinned host buffer of at least `bytes` from the context's pool (or a new
+// one); *cap is its capacity, to be handed back with pinned_put.
+int pinned_get(qs3_ctx *c, size_t bytes, void **p, size_t *cap);
+// Returns a buffer to the pool (freed instead beyond the pool's limit).  The
+// caller must have finished every copy into or out of it.
+void pinned_put(qs3_ctx *c, void *p, size_t cap);
 
 // Binomial columns for one (N, K): see Binom<RT> in qs3_device.h.
 struct BinomTable {

@@ -116,6 +116,8 @@ struct SolveRun {
     double *hab = nullptr, *hC = nullptr;
     uint8_t *hact = nullptr;
     int32_t *hidx = nullptr;
+    qs3_ctx *pctx = nullptr;  // the pool the host buffers return to
+    size_t cap_hab = 0, cap_hC = 0, cap_hact = 0, cap_hidx = 0;
     DevBuf dC, dact, didx;
     hipEvent_t ev = nullptr;
     std::vector<std::vector<double>> al, be, coup;
