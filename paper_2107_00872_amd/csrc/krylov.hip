@@ -194,7 +194,8 @@ __global__ __launch_bounds__(256) void k_multidot(RedGeom g, const double *__res
 // column) elements, group gi taking outputs j0 + gi * JPL .. + JPL - 1.
 // With TC * G <= 64 the groups sit in one wavefront, so their loads of Y, P0
 // and P1 are the same addresses in the same instructions (one request per
-// cache line); with TC = 64 they are the waves of the block.  The slots that
+// cache line); with TC * G > 64 they are spread over the waves of the block,
+// which read the same lines within a short time.  The slots that
 // are P0 or P1 come from the registers that formed Y'.  Threads are (column
 // c < TC, group gi < G, row lane rr < TR) with c fastest; each thread sums
 // its rows in row order, then a fixed tree over rr.  Partials as in
