@@ -258,9 +258,14 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
     const int *ptr;
     const uint16_t *nbr;
     const bool ph_lds = A.ph_lds_off >= 0;
-    double2 *s_ph = (double2 *)(smem + (ph_lds ? A.ph_lds_off : 0));
+    // the phase table in the element type (float32 products read 8-byte
+    // entries and skip a conversion per term; the values are the same)
+    C2 *s_ph = (C2 *)(smem + (ph_lds ? A.ph_lds_off : 0));
     if (ph_lds)
-        for (int i = threadIdx.x; i < A.M; i += blockDim.x) s_ph[i] = A.phase[i];
+        for (int i = threadIdx.x; i < A.M; i += blockDim.x) {
+            const double2 q = A.phase[i];
+            s_ph[i] = C2{(CT)q.x, (CT)q.y};
+        }
     load_lds_tables<RT>(smem, A.L, binom_g, K, &tab, &ptr, &nbr);
     Binom<RT> Bn{tab, binom_shift(A.L.N)};
     Geom g{A.L.lx, A.L.ly, A.L.lz, A.L.lx * A.L.ly, A.L.coords, A.L.ns};
@@ -378,9 +383,9 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                             P -= qq * A.M;
                             P += (P < 0) ? A.M : 0;
                             P -= (P >= A.M) ? A.M : 0;
-                            const double2 ph = ph_lds ? s_ph[P] : A.phase[P];
+                            const C2 ph = ph_lds ? s_ph[P] : C2{(CT)A.phase[P].x, (CT)A.phase[P].y};
                             const C2 x = vrow[b];
-                            const CT pr = bc * (CT)ph.x, pi = bc * (CT)ph.y;
+                            const CT pr = bc * ph.x, pi = bc * ph.y;
                             accr[i] += pr * x.x - pi * x.y;
                             acci[i] += pr * x.y + pi * x.x;
                         }
@@ -435,8 +440,9 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                     for (int r = 0; r < QC; ++r) {
 #pragma unroll
                         for (int i = 0; i < BPL; ++i) {
-                            const double2 ph = ph_lds ? s_ph[Pi[r][i]] : A.phase[Pi[r][i]];
-                            const CT pr = hc[r] * (CT)ph.x, pi = hc[r] * (CT)ph.y;
+                            const C2 ph = ph_lds ? s_ph[Pi[r][i]]
+                                                 : C2{(CT)A.phase[Pi[r][i]].x, (CT)A.phase[Pi[r][i]].y};
+                            const CT pr = hc[r] * ph.x, pi = hc[r] * ph.y;
                             accr[i] += pr * x[r][i].x - pi * x[r][i].y;
                             acci[i] += pr * x[r][i].y + pi * x[r][i].x;
                         }
