@@ -258,13 +258,15 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
     const int *ptr;
     const uint16_t *nbr;
     const bool ph_lds = A.ph_lds_off >= 0;
-    // the phase table in the element type (float32 products read 8-byte
-    // entries and skip a conversion per term; the values are the same)
-    C2 *s_ph = (C2 *)(smem + (ph_lds ? A.ph_lds_off : 0));
+    // the phase table in LDS; float32 products stage it as float2 (8-byte
+    // entries, no conversion per term; the values are the same)
+    constexpr bool F32 = std::is_same<CT, float>::value;
+    double2 *s_ph = (double2 *)(smem + (ph_lds ? A.ph_lds_off : 0));
+    float2 *s_phf = (float2 *)s_ph;
     if (ph_lds)
         for (int i = threadIdx.x; i < A.M; i += blockDim.x) {
-            const double2 q = A.phase[i];
-            s_ph[i] = C2{(CT)q.x, (CT)q.y};
+            if constexpr (F32) s_phf[i] = make_float2((float)A.phase[i].x, (float)A.phase[i].y);
+            else s_ph[i] = A.phase[i];
         }
     load_lds_tables<RT>(smem, A.L, binom_g, K, &tab, &ptr, &nbr);
     Binom<RT> Bn{tab, binom_shift(A.L.N)};
@@ -383,9 +385,19 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                             P -= qq * A.M;
                             P += (P < 0) ? A.M : 0;
                             P -= (P >= A.M) ? A.M : 0;
-                            const C2 ph = ph_lds ? s_ph[P] : C2{(CT)A.phase[P].x, (CT)A.phase[P].y};
+                            CT phx, phy;
+                            if constexpr (F32) {
+                                const float2 q = ph_lds ? s_phf[P]
+                                                        : make_float2((float)A.phase[P].x, (float)A.phase[P].y);
+                                phx = q.x;
+                                phy = q.y;
+                            } else {
+                                const double2 ph = ph_lds ? s_ph[P] : A.phase[P];
+                                phx = (CT)ph.x;
+                                phy = (CT)ph.y;
+                            }
                             const C2 x = vrow[b];
-                            const CT pr = bc * ph.x, pi = bc * ph.y;
+                            const CT pr = bc * phx, pi = bc * phy;
                             accr[i] += pr * x.x - pi * x.y;
                             acci[i] += pr * x.y + pi * x.x;
                         }
@@ -440,9 +452,19 @@ __global__ __launch_bounds__(256) void k_hv_batch(BatchArgs A, const RT *__restr
                     for (int r = 0; r < QC; ++r) {
 #pragma unroll
                         for (int i = 0; i < BPL; ++i) {
-                            const C2 ph = ph_lds ? s_ph[Pi[r][i]]
-                                                 : C2{(CT)A.phase[Pi[r][i]].x, (CT)A.phase[Pi[r][i]].y};
-                            const CT pr = hc[r] * ph.x, pi = hc[r] * ph.y;
+                            CT phx, phy;
+                            if constexpr (F32) {
+                                const int Pq = Pi[r][i];
+                                const float2 q = ph_lds ? s_phf[Pq]
+                                                        : make_float2((float)A.phase[Pq].x, (float)A.phase[Pq].y);
+                                phx = q.x;
+                                phy = q.y;
+                            } else {
+                                const double2 ph = ph_lds ? s_ph[Pi[r][i]] : A.phase[Pi[r][i]];
+                                phx = (CT)ph.x;
+                                phy = (CT)ph.y;
+                            }
+                            const CT pr = hc[r] * phx, pi = hc[r] * phy;
                             accr[i] += pr * x[r][i].x - pi * x[r][i].y;
                             acci[i] += pr * x[r][i].y + pi * x[r][i].x;
                         }
